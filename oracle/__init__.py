@@ -1,0 +1,258 @@
+"""FP64 CPU oracle for the P3T long-range tree force -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
+leg may import this package.  The product library never links or calls it; the
+two share no code.  ``p3t_oracle.c`` holds the tree method written out step by
+step (its header lists the conventions); ``direct.py`` holds the plain O(N^2)
+definitions the tree method reduces to.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "p3t_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+          "-fPIC", "-shared", "-Wall", "-Wno-unknown-pragmas"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Params(C.Structure):
+    _fields_ = [("eps", C.c_double), ("r_in", C.c_double), ("r_out", C.c_double),
+                ("theta", C.c_double), ("r_search", C.c_double), ("n_crit", C.c_int32),
+                ("n_leaf", C.c_int32), ("use_quadrupole", C.c_int32), ("precision", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        L.or_build.argtypes = [C.c_int64, P, P, C.POINTER(_Params), C.POINTER(C.c_void_p)]
+        L.or_build.restype = C.c_int
+        L.or_free.argtypes = [P]
+        L.or_force.argtypes = [P, P, P]
+        L.or_neighbors.argtypes = [P, P, P]
+        L.or_vjp.argtypes = [P, P, P, P, P]
+        L.or_refresh.argtypes = [P, P, P]
+        for f in ("or_n_nodes", "or_n_groups"):
+            getattr(L, f).argtypes = [P]
+            getattr(L, f).restype = C.c_int64
+        L.or_root.argtypes = [P, P]
+        L.or_counts.argtypes = [P, P]
+        L.or_get_keys.argtypes = [P, P, P]
+        L.or_get_nodes.argtypes = [P] * 8
+        L.or_get_moments.argtypes = [P] * 7
+        L.or_get_groups.argtypes = [P, P]
+        L.or_get_lists.argtypes = [P] * 5
+        for f in ("or_K", "or_dK", "or_W", "or_W_over_y"):
+            getattr(L, f).argtypes = [C.c_double, C.c_double]
+            getattr(L, f).restype = C.c_double
+        L.or_C.argtypes = [C.c_double]
+        L.or_C.restype = C.c_double
+        L.or_morton.argtypes = [C.c_double, C.c_double, C.c_double, P, C.c_double]
+        L.or_morton.restype = C.c_uint64
+        L.or_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def K(y, gamma):
+    """Cutoff function K(y) of the oracle (scalar or array)."""
+    f = np.vectorize(lambda v: lib().or_K(float(v), float(gamma)))
+    return f(y)
+
+
+def dK(y, gamma):
+    f = np.vectorize(lambda v: lib().or_dK(float(v), float(gamma)))
+    return f(y)
+
+
+def W(y, gamma):
+    f = np.vectorize(lambda v: lib().or_W(float(v), float(gamma)))
+    return f(y)
+
+
+def W_over_y(y, gamma):
+    f = np.vectorize(lambda v: lib().or_W_over_y(float(v), float(gamma)))
+    return f(y)
+
+
+def C_gamma(gamma):
+    return lib().or_C(float(gamma))
+
+
+def morton(p, lo, L):
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    return int(lib().or_morton(float(p[0]), float(p[1]), float(p[2]), _ptr(lo), float(L)))
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
+@dataclass
+class Params:
+    eps: float
+    r_in: float
+    r_out: float
+    theta: float
+    r_search: float
+    n_crit: int = 64
+    n_leaf: int = 16
+    use_quadrupole: int = 1
+
+    def c(self) -> _Params:
+        return _Params(self.eps, self.r_in, self.r_out, self.theta, self.r_search,
+                       self.n_crit, self.n_leaf, self.use_quadrupole, 0)
+
+
+class Tree:
+    """Oracle tree for one particle set: every step of the method, inspectable."""
+
+    def __init__(self, pos, mass, params: Params | dict):
+        if isinstance(params, dict):
+            params = Params(**{k: v for k, v in params.items() if k in Params.__annotations__})
+        self.params = params
+        self.pos = np.ascontiguousarray(pos, dtype=np.float64)
+        self.mass = np.ascontiguousarray(mass, dtype=np.float64)
+        self.n = self.mass.shape[0]
+        assert self.pos.shape == (self.n, 3)
+        L = lib()
+        h = C.c_void_p()
+        cp = params.c()
+        rc = L.or_build(self.n, _ptr(self.pos), _ptr(self.mass), C.byref(cp), C.byref(h))
+        if rc != 0:
+            raise ValueError("oracle build failed")
+        self._h = h
+        self._cache = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().or_free(h)
+            self._h = None
+
+    # -- tree data --------------------------------------------------------
+    @property
+    def n_nodes(self) -> int:
+        return int(lib().or_n_nodes(self._h))
+
+    @property
+    def n_groups(self) -> int:
+        return int(lib().or_n_groups(self._h))
+
+    def root(self):
+        out = np.zeros(4)
+        lib().or_root(self._h, _ptr(out))
+        return out[:3].copy(), float(out[3])
+
+    def keys(self):
+        key = np.zeros(self.n, np.uint64)
+        perm = np.zeros(self.n, np.int64)
+        lib().or_get_keys(self._h, _ptr(key), _ptr(perm))
+        return key, perm
+
+    def nodes(self) -> dict:
+        nn = self.n_nodes
+        d = dict(level=np.zeros(nn, np.int32), first=np.zeros(nn, np.int64),
+                 count=np.zeros(nn, np.int64), child_first=np.zeros(nn, np.int64),
+                 n_child=np.zeros(nn, np.int32), prefix=np.zeros(nn, np.uint64),
+                 parent=np.zeros(nn, np.int64))
+        lib().or_get_nodes(self._h, *[_ptr(d[k]) for k in
+                                      ("level", "first", "count", "child_first", "n_child",
+                                       "prefix", "parent")])
+        return d
+
+    def moments(self) -> dict:
+        nn = self.n_nodes
+        d = dict(M=np.zeros(nn), com=np.zeros((nn, 3)), Q=np.zeros((nn, 6)),
+                 blo=np.zeros((nn, 3)), bhi=np.zeros((nn, 3)), side=np.zeros(nn))
+        lib().or_get_moments(self._h, *[_ptr(d[k]) for k in ("M", "com", "Q", "blo", "bhi", "side")])
+        return d
+
+    def groups(self) -> np.ndarray:
+        g = np.zeros(self.n_groups, np.int64)
+        lib().or_get_groups(self._h, _ptr(g))
+        return g
+
+    def counts(self) -> dict:
+        out = np.zeros(4, np.int64)
+        lib().or_counts(self._h, _ptr(out))
+        return dict(n_cells=int(out[0]), n_parts=int(out[1]), n_pc=int(out[2]), n_pp=int(out[3]))
+
+    def lists(self) -> dict:
+        ng = self.n_groups
+        cnt = self.counts()
+        d = dict(c_off=np.zeros(ng + 1, np.int64), c_idx=np.zeros(cnt["n_cells"], np.int64),
+                 p_off=np.zeros(ng + 1, np.int64), p_idx=np.zeros(cnt["n_parts"], np.int64))
+        lib().or_get_lists(self._h, *[_ptr(d[k]) for k in ("c_off", "c_idx", "p_off", "p_idx")])
+        return d
+
+    # -- results ----------------------------------------------------------
+    def force(self):
+        """(acc [n,3], pot [n]) in original particle order."""
+        if "force" not in self._cache:
+            acc = np.zeros((self.n, 3))
+            pot = np.zeros(self.n)
+            lib().or_force(self._h, _ptr(acc), _ptr(pot))
+            self._cache["force"] = (acc, pot)
+        return self._cache["force"]
+
+    def neighbors(self):
+        """(offsets [n+1], idx [nnz]) CSR, original indices ascending per row."""
+        off = np.zeros(self.n + 1, np.int64)
+        lib().or_neighbors(self._h, _ptr(off), None)
+        idx = np.zeros(int(off[-1]), np.int64)
+        lib().or_neighbors(self._h, _ptr(off), _ptr(idx))
+        return off, idx
+
+    def refresh(self, pos, mass):
+        """Move particles / change masses with keys, topology and lists frozen."""
+        self.pos = np.ascontiguousarray(pos, dtype=np.float64)
+        self.mass = np.ascontiguousarray(mass, dtype=np.float64)
+        lib().or_refresh(self._h, _ptr(self.pos), _ptr(self.mass))
+        self._cache = {}
+
+    def vjp(self, w, c=None):
+        """(dL/dpos [n,3], dL/dmass [n]) for L = sum w.acc + sum c.pot, lists frozen."""
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        cc = None if c is None else np.ascontiguousarray(c, dtype=np.float64)
+        gp = np.zeros((self.n, 3))
+        gm = np.zeros(self.n)
+        lib().or_vjp(self._h, _ptr(w), None if cc is None else _ptr(cc), _ptr(gp), _ptr(gm))
+        return gp, gm
+
+
+def group_lists(tree: Tree):
+    """Per group (ordered by first particle): (node id, sorted P set, sorted C set)."""
+    g = tree.groups()
+    L = tree.lists()
+    out = []
+    for k in range(len(g)):
+        out.append((int(g[k]), L["p_idx"][L["p_off"][k]:L["p_off"][k + 1]],
+                    L["c_idx"][L["c_off"][k]:L["c_off"][k + 1]]))
+    return out
