@@ -1,0 +1,236 @@
+"""Benchmark: leapfrog steps of the soft (long-range) part on one MI355X.
+
+A step is one shared-timestep kick-drift-kick of the soft Hamiltonian
+(Section 2.1 splitting; the hard Hermite part is not part of this path):
+  v += dt/2 a;  x += dt v;  rebuild tree + groups + lists;  long-range force and
+  potential;  neighbour lists within h;  v += dt/2 a.
+Default workload: King W0 = 9, N = 2^20 equal-mass stars (seeded synthetic
+sample of the model), theta = 0.5, n_crit = 256, r_out = 0.002, r_in = 0.1 r_out,
+h = 1.1 r_out, eps = 4/N, dt = 1/256, mixed precision.
+
+Prints ONE JSON line.  ``value`` is long-range interactions per second over
+whole steps (interactions counted from the walk's lists: sum over groups of
+n_g (|P_g| + |C_g|)).  The same steps are also run with the FP64 interaction
+kernel; the roofline object describes the dominant kernel (the interaction
+kernel), timed with HIP events on the stream it runs on.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "long-range interactions/s & ms per leapfrog step at N=1M, FP32 vs FP64, RMS err"
+PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}     # MI355X vector FP32 (packed) / FP64
+# Algorithmic flops per interaction of the common path (FMA = 2, add/sub/mul = 1,
+# rsqrt = 4); see the design doc for the itemisation.
+F_PP = 23
+F_PC_QUAD = 58
+F_PC_MONO = 22
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_steps(ctx, pos0, vel0, mass, params, dt, steps, warmup, collect_first=False):
+    import torch
+    pos = pos0.clone()
+    vel = vel0.clone()
+    acc = torch.empty_like(pos)
+    pot = torch.empty_like(mass)
+    ctx.build_tree(pos, mass, **params)
+    ctx.long_force(acc, pot)
+    first = None
+    if collect_first:
+        first = (acc.clone(), pot.clone(), ctx.stats())
+    rec = []
+
+    def step():
+        ctx.kick_drift(pos, vel, acc, 0.5 * dt, dt)
+        ctx.build_tree(pos, mass, **params)
+        ctx.long_force(acc, pot)
+        ctx.neighbors()
+        ctx.kick_drift(pos, vel, acc, 0.5 * dt, 0.0)
+        return ctx.stats()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rec.append(step())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0), rec, first
+
+
+def summarize(rec, seconds, steps, quad):
+    inter = sum(s["n_pp"] + s["n_pc"] for s in rec)
+    force_ms = [s["ms_force"] for s in rec]
+    flops = [s["n_pp"] * F_PP + s["n_pc"] * (F_PC_QUAD if quad else F_PC_MONO) for s in rec]
+    avg_force_ms = float(np.mean(force_ms))
+    avg_flops = float(np.mean(flops))
+    return dict(
+        ms_per_step=1e3 * seconds / steps,
+        interactions_per_step=inter / steps,
+        interactions_per_s=inter / seconds,
+        force_ms=avg_force_ms,
+        build_ms=float(np.mean([s["ms_build"] for s in rec])),
+        neighbors_ms=float(np.mean([s["ms_neighbors"] for s in rec])),
+        force_tflops=avg_flops / (avg_force_ms * 1e-3) / 1e12,
+        flops_per_launch=avg_flops,
+        n_pp=float(np.mean([s["n_pp"] for s in rec])),
+        n_pc=float(np.mean([s["n_pc"] for s in rec])),
+        n_groups=float(np.mean([s["n_groups"] for s in rec])),
+        nnz=float(np.mean([s["nnz"] for s in rec])),
+    )
+
+
+def cpu_baseline(pos, mass, params, gpu_first, target_s=12.0, seed=3):
+    """The oracle on sampled groups of the step-0 tree: force rate on host cores,
+    plus the RMS error of the GPU forces on those groups."""
+    import oracle
+    t0 = time.perf_counter()
+    tree = oracle.Tree(pos, mass, params)
+    t_build = time.perf_counter() - t0
+    L = tree.lists()
+    nd = tree.nodes()
+    g = tree.groups()
+    G = len(g)
+    work = (nd["count"][g] * (np.diff(L["p_off"]) + np.diff(L["c_off"]))).astype(np.int64)
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(G)
+    # calibrate on a small batch, then size the sample for ~target_s of CPU work
+    first = order[:16]
+    t0 = time.perf_counter()
+    tree.force_groups(first)
+    t_cal = time.perf_counter() - t0
+    rate = work[first].sum() / max(t_cal, 1e-6)
+    budget = rate * target_s
+    cum = np.cumsum(work[order[16:]])
+    take = order[16:16 + int(np.searchsorted(cum, budget)) + 1]
+    t0 = time.perf_counter()
+    acc, pot = tree.force_groups(take)
+    t_force = time.perf_counter() - t0
+    rows = np.nonzero(~np.isnan(pot))[0]
+    n_int = int(work[take].sum())
+    out = dict(value=n_int / t_force, unit="interactions/s", cores=oracle.num_threads(),
+               kind="oracle",
+               sample=(f"force+potential of {len(take)} random groups of {G} "
+                       f"({n_int} interactions, {len(rows)} particles) of the step-0 tree; "
+                       f"oracle tree build (single-threaded, excluded) took {t_build:.1f} s"))
+    errs = {}
+    for name, (ga, gp) in gpu_first.items():
+        ga, gp = ga[rows], gp[rows]
+        errs[name] = dict(
+            acc_rel_rms=float(np.sqrt(((ga - acc[rows]) ** 2).sum() / (acc[rows] ** 2).sum())),
+            pot_rel_rms=float(np.sqrt(((gp - pot[rows]) ** 2).sum() / (pot[rows] ** 2).sum())),
+            acc_max_rel=float((np.linalg.norm(ga - acc[rows], axis=1)
+                               / np.linalg.norm(acc[rows], axis=1)).max()))
+    return out, errs
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=16)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="king9_1m")
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from inputs import WORKLOADS, make_cluster
+    from paper_1506_04553_amd import P3T
+
+    w = WORKLOADS[args.workload]
+    dt = w.extra.get("dt", 1.0 / 256)
+    log(f"bench: generating {w.name} N={w.n} seed={args.seed}")
+    c = make_cluster(w, seed=args.seed)
+    dev = torch.device("cuda", 0)
+    pos0 = torch.from_numpy(c.pos).to(dev)
+    vel0 = torch.from_numpy(c.vel).to(dev)
+    mass = torch.from_numpy(c.mass).to(dev)
+    ctx = P3T(0)
+    quad = True
+    results, firsts = {}, {}
+    precs = [args.precision] + ([] if args.no_fp64 else
+                                [p for p in ("mixed", "fp64") if p != args.precision])
+    for prec in precs:
+        params = w.params(precision=prec)
+        log(f"bench: {prec}: {args.warmup} warmup + {args.steps} timed steps")
+        secs, rec, first = run_steps(ctx, pos0, vel0, mass, params, dt, args.steps, args.warmup,
+                                     collect_first=True)
+        results[prec] = summarize(rec, secs, args.steps, quad)
+        firsts[prec] = (first[0].cpu().numpy(), first[1].cpu().numpy())
+        log(f"bench: {prec}: {json.dumps(results[prec])}")
+    head = results[args.precision]
+    peak = PEAK_TFLOPS[args.precision]
+    out = {
+        "metric": METRIC,
+        "value": head["interactions_per_s"],
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "distribution": "King W0=9" if w.model == "king9"
+                   else "Plummer", "imf": w.imf, "theta": w.theta, "n_crit": w.n_crit,
+                   "n_leaf": w.n_leaf, "r_out": w.r_out, "r_in": w.r_in, "r_search": w.r_search,
+                   "eps": w.eps, "dt": dt, "precision": args.precision, "seed": args.seed},
+        "roofline": {"bound": "alu", "kernel": f"k_force<{'float' if args.precision == 'mixed' else 'double'}>",
+                     "achieved": head["force_tflops"], "peak": peak, "unit": "TFLOP/s",
+                     "frac": head["force_tflops"] / peak, "traffic": None,
+                     "flops_per_launch": head["flops_per_launch"],
+                     "avg_launch_ms": head["force_ms"],
+                     "flops_per_interaction": {"pp": F_PP, "pc": F_PC_QUAD}},
+        "phase_ms": {"build": head["build_ms"], "force": head["force_ms"],
+                     "neighbors": head["neighbors_ms"]},
+        "interactions_per_step": head["interactions_per_step"],
+        "n_groups": head["n_groups"],
+        "neighbour_pairs": head["nnz"],
+    }
+    if "fp64" in results and args.precision != "fp64":
+        f64 = results["fp64"]
+        out["fp64"] = {"ms_per_step": f64["ms_per_step"], "interactions_per_s": f64["interactions_per_s"],
+                       "force_ms": f64["force_ms"], "force_tflops": f64["force_tflops"],
+                       "force_frac_of_fp64_peak": f64["force_tflops"] / PEAK_TFLOPS["fp64"]}
+        out["speedup_mixed_vs_fp64"] = {"force_kernel": f64["force_ms"] / head["force_ms"],
+                                        "step": f64["ms_per_step"] / head["ms_per_step"]}
+        a32, p32 = firsts["mixed"]
+        a64, p64 = firsts["fp64"]
+        out["mixed_vs_fp64_gpu"] = {
+            "acc_rel_rms": float(np.sqrt(((a32 - a64) ** 2).sum() / (a64 ** 2).sum())),
+            "pot_rel_rms": float(np.sqrt(((p32 - p64) ** 2).sum() / (p64 ** 2).sum()))}
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle baseline on sampled groups")
+        cb, errs = cpu_baseline(c.pos, c.mass, w.params(), firsts)
+        out["cpu_baseline"] = cb
+        out["rms_err_vs_oracle"] = errs
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * p3t.h -- C ABI of the MI355X (gfx950) long-range tree-force library.
+ *
+ * The library computes, for N particles, the long-range ("soft") part of the
+ * gravitational force of the P3T scheme (Iwasawa, Portegies Zwart & Makino,
+ * Section 2.1): the acceleration a_i = sum_j m_j K(s_ij) d_ij / s_ij^3 and the
+ * potential phi_i = -sum_j m_j W(s_ij) / s_ij, with d_ij = x_j - x_i, Plummer
+ * softened distance s_ij = sqrt(|d_ij|^2 + eps^2), and the changeover functions
+ * K and W of Section 2.1 (inner cutoff r_in, outer cutoff r_out, gamma = r_in /
+ * r_out).  The sum is evaluated with a Barnes-Hut octree with moments up to
+ * the quadrupole (Section 2.2), walked once per group of at most n_crit
+ * particles; the same walk yields, for every particle, the list of particles
+ * within distance h (Section 2.2, "neighbour sphere" plus "buffer shell"),
+ * which feeds the host-side Hermite integrator of the hard part.
+ *
+ * Conventions shared by every call:
+ *   - all particle arrays are in the caller's ORIGINAL particle order;
+ *   - pointers documented "device" are hipMalloc'd (or torch-allocated) memory
+ *     on the context's device; "host" pointers are ordinary host memory;
+ *   - positions/accelerations are row-major [n][3] float64, masses/potentials
+ *     [n] float64, whatever the precision mode;
+ *   - all work is enqueued on the context's stream; calls that must read a
+ *     size back (p3t_build_tree, p3t_neighbors) synchronise that stream;
+ *   - a context is not thread-safe; use one per host thread;
+ *   - every call returns P3T_OK (0) or a negative P3T_E* status; on error the
+ *     caller's output buffers are left untouched and p3t_last_error() holds a
+ *     message.  No C++ exception crosses this interface.
+ */
+#ifndef P3T_H
+#define P3T_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define P3T_OK 0
+#define P3T_EINVAL (-1)    /* invalid argument or parameter */
+#define P3T_ENOMEM (-2)    /* device allocation failed */
+#define P3T_ECAPACITY (-3) /* caller buffer too small; required size reported */
+#define P3T_ESTATE (-4)    /* call out of order (e.g. force before build) */
+#define P3T_EHIP (-5)      /* HIP runtime error */
+
+#define P3T_PREC_FP64 0    /* every interaction in FP64 */
+#define P3T_PREC_MIXED 1   /* FP64 group-relative offsets, FP32 interactions, compensated sums */
+
+/* Method parameters (Section 2.1, Table 1 symbols).
+ *   eps        Plummer softening length (>= 0)
+ *   r_in       inner cutoff of K and W (0 <= r_in < r_out); gamma = r_in / r_out
+ *   r_out      outer cutoff r_cut (> 0)
+ *   theta      opening angle (>= 0); a cell of side l with centre of mass at
+ *              distance D from a group's box is used as a multipole iff
+ *              theta * D > l and the cell's box is at least h away from it
+ *   r_search   neighbour radius h (> 0), h = r_cut + buffer width
+ *   n_crit     maximum group size (>= n_leaf)
+ *   n_leaf     maximum leaf size (>= 1); leaves at depth 21 may hold more
+ *   use_quadrupole  1: monopole + quadrupole, 0: monopole only
+ *   precision  P3T_PREC_FP64 or P3T_PREC_MIXED */
+typedef struct {
+    double eps, r_in, r_out, theta, r_search;
+    int32_t n_crit, n_leaf, use_quadrupole, precision;
+} p3t_params;
+
+/* Counters of the last calls. */
+typedef struct {
+    int64_t n, n_nodes, n_leaves, n_groups, depth;
+    int64_t n_cell_entries;   /* sum over groups of |C_g| (accepted cells) */
+    int64_t n_part_entries;   /* sum over groups of |P_g| (particles of opened leaves) */
+    int64_t n_near_entries;   /* sum over groups of leaves within h of the group box */
+    int64_t n_pc, n_pp;       /* interactions: sum_g n_g |C_g|, sum_g n_g |P_g| */
+    int64_t nnz;              /* neighbour pairs found by the last p3t_neighbors */
+    int32_t walk_global_stack;/* 1 if the walk needed its global-memory stack */
+    int32_t pad_;
+    double ms_build, ms_force, ms_neighbors, ms_vjp; /* GPU time of the last calls */
+} p3t_stats;
+
+/* Optional device allocator (e.g. a framework's caching allocator). */
+typedef void *(*p3t_alloc_fn)(size_t bytes, void *user);
+typedef void (*p3t_free_fn)(void *ptr, void *user);
+
+typedef struct p3t_ctx p3t_ctx;
+
+/* Create a context on HIP device `device` whose work goes to `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  `alloc`/`free_` may both be NULL
+ * (hipMalloc/hipFree are used) or both set; the context owns every internal
+ * workspace.  *out receives the context.  Errors: EINVAL, EHIP. */
+int p3t_create(p3t_ctx **out, int device, void *hip_stream, p3t_alloc_fn alloc,
+               p3t_free_fn free_, void *alloc_user);
+
+/* Release every workspace and the context (NULL is ignored). */
+void p3t_destroy(p3t_ctx *ctx);
+
+/* Host-only parameter check (no device access): P3T_OK or P3T_EINVAL. */
+int p3t_check_params(const p3t_params *p);
+
+/* Build the tree, groups and interaction lists (Section 2.2) for n particles.
+ *   pos   device [n][3] float64, mass device [n] float64 (> 0, finite)
+ * The positions and masses are copied (sorted) into the context, so the caller
+ * may reuse its buffers afterwards.  Synchronises the stream to size the lists.
+ * Errors: EINVAL (bad n, parameters, non-finite positions or non-positive
+ * masses), ENOMEM, EHIP. */
+int p3t_build_tree(p3t_ctx *ctx, int64_t n, const double *pos, const double *mass,
+                   const p3t_params *p);
+
+/* Long-range acceleration and potential (Section 2.1 soft force, Section 2.2
+ * tree) of every particle of the last build.
+ *   acc  device [n][3] float64 out;  pot  device [n] float64 out, or NULL
+ * Errors: ESTATE (no tree), EINVAL, EHIP. */
+int p3t_long_force(p3t_ctx *ctx, double *acc, double *pot);
+
+/* For every particle i, the particles j != i with |x_j - x_i| < h (Section 2.2),
+ * as CSR in original indices, ascending within each row; particle i is
+ * isolated iff offsets[i+1] == offsets[i].
+ *   offsets  device [n+1] int64 out;  idx  device [cap] int32 out
+ *   nnz      host out: number of pairs (set also when ECAPACITY is returned)
+ * Synchronises the stream.  Errors: ESTATE, EINVAL, ECAPACITY (cap < nnz:
+ * offsets and idx untouched), EHIP. */
+int p3t_neighbors(p3t_ctx *ctx, int64_t *offsets, int32_t *idx, int64_t cap, int64_t *nnz);
+
+/* Vector-Jacobian product of L = sum_i w_i . a_i + c_i phi_i with respect to
+ * positions and masses, with the tree, groups and lists of the last build held
+ * fixed (the derivative ignores changes of list membership).
+ *   w  device [n][3] float64; c device [n] float64 or NULL (taken as 0)
+ *   gpos device [n][3] float64 out; gmass device [n] float64 out
+ * Errors: ESTATE, EINVAL, ENOMEM, EHIP. */
+int p3t_long_force_vjp(p3t_ctx *ctx, const double *w, const double *c, double *gpos,
+                       double *gmass);
+
+/* Leapfrog helpers of the shared-timestep soft step (Section 2.1, kick under
+ * H_soft; drift): v += dt_kick * a, then x += dt_drift * v, elementwise over
+ * [n][3] device arrays.  Errors: EINVAL, EHIP. */
+int p3t_kick_drift(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const double *acc,
+                   double dt_kick, double dt_drift);
+
+/* Statistics of the last calls.  Errors: EINVAL. */
+int p3t_get_stats(p3t_ctx *ctx, p3t_stats *out);
+
+/* Inspection of the last build, for tests and tools: copies an internal array
+ * into HOST memory `dst` of `bytes` bytes (synchronous).  Array ids and element
+ * types are listed below; the element count of each is given by p3t_get_stats
+ * (n, n_nodes, n_groups, list sizes).  Errors: ESTATE, EINVAL (unknown id or
+ * bytes not the array's size), EHIP. */
+enum {
+    P3T_ARR_SORTED_KEYS = 0,   /* uint64 [n]   Morton keys in sorted order */
+    P3T_ARR_PERM = 1,          /* int32  [n]   sorted position -> original index */
+    P3T_ARR_NODE_LEVEL = 2,    /* int32  [n_nodes] */
+    P3T_ARR_NODE_FIRST = 3,    /* int32  [n_nodes] first sorted particle */
+    P3T_ARR_NODE_COUNT = 4,    /* int32  [n_nodes] */
+    P3T_ARR_NODE_CHILD = 5,    /* int32  [n_nodes] first child id */
+    P3T_ARR_NODE_NCHILD = 6,   /* int32  [n_nodes] 0 for leaves */
+    P3T_ARR_NODE_PARENT = 7,   /* int32  [n_nodes] -1 for the root */
+    P3T_ARR_NODE_PREFIX = 8,   /* uint64 [n_nodes] key prefix at the node's level */
+    P3T_ARR_NODE_MASS = 9,     /* double [n_nodes] */
+    P3T_ARR_NODE_COM = 10,     /* double [n_nodes][3] */
+    P3T_ARR_NODE_QUAD = 11,    /* double [n_nodes][6] xx yy zz xy xz yz */
+    P3T_ARR_NODE_BOX = 12,     /* double [n_nodes][6] lo xyz, hi xyz */
+    P3T_ARR_GROUP_NODE = 13,   /* int32  [n_groups] node id, ordered by first particle */
+    P3T_ARR_CELL_OFF = 14,     /* int64  [n_groups+1] */
+    P3T_ARR_CELL_IDX = 15,     /* int32  [n_cell_entries] node ids */
+    P3T_ARR_PART_OFF = 16,     /* int64  [n_groups+1] */
+    P3T_ARR_PART_IDX = 17,     /* int32  [n_part_entries] sorted particle indices */
+    P3T_ARR_ROOT = 18          /* double [4] lo xyz, side L */
+};
+int p3t_copy_array(p3t_ctx *ctx, int which, void *dst, int64_t bytes);
+
+/* Human-readable status, and the context's last error message. */
+const char *p3t_status_string(int status);
+const char *p3t_last_error(p3t_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* P3T_H */

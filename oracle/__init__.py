@@ -54,6 +54,7 @@ def lib():
         L.or_neighbors.argtypes = [P, P, P]
         L.or_vjp.argtypes = [P, P, P, P, P]
         L.or_refresh.argtypes = [P, P, P]
+        L.or_force_groups.argtypes = [P, P, C.c_int64, P, P]
         for f in ("or_n_nodes", "or_n_groups"):
             getattr(L, f).argtypes = [P]
             getattr(L, f).restype = C.c_int64
@@ -221,6 +222,14 @@ class Tree:
             lib().or_force(self._h, _ptr(acc), _ptr(pot))
             self._cache["force"] = (acc, pot)
         return self._cache["force"]
+
+    def force_groups(self, gids):
+        """Forces for the members of the given groups (index into groups()); NaN elsewhere."""
+        gids = np.ascontiguousarray(gids, dtype=np.int64)
+        acc = np.full((self.n, 3), np.nan)
+        pot = np.full(self.n, np.nan)
+        lib().or_force_groups(self._h, _ptr(gids), len(gids), _ptr(acc), _ptr(pot))
+        return acc, pot
 
     def neighbors(self):
         """(offsets [n+1], idx [nnz]) CSR, original indices ascending per row."""

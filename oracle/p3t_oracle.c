@@ -577,6 +577,29 @@ int or_force(const or_tree *t, double *acc, double *pot)
     return 0;
 }
 
+/* Forces of the members of the listed groups only (rows of other particles
+ * are left untouched); used to sample large problems. */
+int or_force_groups(const or_tree *t, const int64_t *gids, int64_t ng, double *acc, double *pot)
+{
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < ng; k++) {
+        int64_t gi = gids[k];
+        int64_t g = t->grp[gi];
+        for (int64_t i = t->first[g]; i < t->first[g] + t->count[g]; i++) {
+            double a[3] = {0, 0, 0}, ph = 0.0;
+            for (int64_t q = t->p_off[gi]; q < t->p_off[gi + 1]; q++) {
+                int64_t j = t->p_idx[q];
+                if (j != i) pp_term(t, i, j, a, &ph);
+            }
+            for (int64_t q = t->c_off[gi]; q < t->c_off[gi + 1]; q++) pc_term(t, i, t->c_idx[q], a, &ph);
+            int64_t o = t->perm[i];
+            acc[3 * o] = a[0]; acc[3 * o + 1] = a[1]; acc[3 * o + 2] = a[2];
+            if (pot) pot[o] = ph;
+        }
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Neighbour lists: CSR in original order, ascending original indices.        */
 /* ------------------------------------------------------------------------ */

@@ -1,0 +1,135 @@
+// internal.h -- data layout and launch interfaces shared by the library's
+// translation units (not part of the public ABI; see include/p3t.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "p3t.h"
+
+namespace p3t {
+
+constexpr int kMaxLevel = 21;        // 63-bit keys, 3 bits per level
+constexpr int kLevels = kMaxLevel + 1;
+
+// Root cube of the last build (device resident).
+struct RootInfo {
+    double lo[3];
+    double L;          // power-of-two side
+    double scale;      // 2^21 / L
+    int32_t bad_input; // non-finite position or non-positive mass seen
+    int32_t pad;
+};
+
+// Per-node record read by the tree walk (96 bytes, one read per visit).
+struct NodeWalk {
+    double cx, cy, cz;      // centre of mass
+    double l2;              // squared cell side (L 2^-level)^2
+    double lo[3], hi[3];    // tight member box
+    int32_t child_first, n_child, first, count;
+};
+
+// Per-node multipole read by the interaction kernels (80 bytes).
+struct NodeMP {
+    double cx, cy, cz, M;
+    double q[6];            // traceless quadrupole xx yy zz xy xz yz about the com
+};
+
+// Per-group record, groups ordered by first particle.
+struct GroupInfo {
+    double lo[3], hi[3];    // member box
+    double c[3];            // box centre, origin of the FP32 offsets
+    int32_t first, count, node, pad;
+};
+
+// Changeover constants for a given gamma = r_in / r_out.
+struct Changeover {
+    double r_out, inv_rout, gamma, inv_1mg;   // 1 / (1 - gamma)
+    double C;                                  // W/y below r_in
+    // W(y)/y on [gamma, 1): w6 y^6 + w5 y^5 + ... + w1 y + w0 + wl ln(y) + wm / y
+    double w[7];
+    double wl, wm;
+};
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace p3t
+
+struct p3t_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    p3t_alloc_fn alloc = nullptr;
+    p3t_free_fn free_ = nullptr;
+    void *user = nullptr;
+    char err[512] = {0};
+
+    int built = 0;
+    int64_t n = 0;
+    p3t_params prm{};
+    p3t::Changeover chg{};
+
+    int64_t n_nodes = 0, n_groups = 0, n_leaves = 0, depth = 0;
+    int64_t n_cell_entries = 0, n_part_entries = 0, n_near_entries = 0;
+    int64_t n_pc = 0, n_pp = 0, nnz = 0;
+    int64_t level_start[p3t::kLevels + 2] = {0};
+    int walk_global = 0;
+    double ms_build = 0, ms_force = 0, ms_nbr = 0, ms_vjp = 0;
+    hipEvent_t ev[8] = {nullptr};  // start/end pairs: build, force, neighbours, vjp
+    int64_t *hpin = nullptr;      // pinned host readback area (64 int64)
+
+    p3t::DevBuf root, keys[2], vals[2], hist, histc, x, y, z, m;
+    p3t::DevBuf lvlrange, tblk, tblk_off;
+    p3t::DevBuf node_level, node_first, node_count, node_child, node_nchild, node_parent,
+        node_prefix, node_S, node_walk, node_mp;
+    p3t::DevBuf gflag, gscan, grp;
+    p3t::DevBuf cnt, off, c_idx, p_idx, n_idx;
+    p3t::DevBuf wstack, dflags, readback, scan_tmp, nbr_cnt;
+    p3t::DevBuf vjp_gx, vjp_gm, vjp_cell, bbox;
+};
+
+namespace p3t {
+
+// Allocation helpers (context allocator or hipMalloc); return 0 or P3T_ENOMEM.
+int ensure(p3t_ctx *ctx, DevBuf &b, size_t bytes);
+void release(p3t_ctx *ctx, DevBuf &b);
+int set_error(p3t_ctx *ctx, int status, const char *fmt, ...);
+int check_hip(p3t_ctx *ctx, hipError_t e, const char *what);
+
+// Device-wide exclusive prefix sum (out may alias in).  `total` (device, may be
+// null) receives the sum of all n inputs.
+int scan_exclusive_i64(p3t_ctx *ctx, const int64_t *in, int64_t *out, int64_t n, int64_t *total);
+int scan_exclusive_i32(p3t_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, int32_t *total);
+
+// Tree build stages (tree.hip).
+int build_root_keys(p3t_ctx *ctx, const double *pos, const double *mass, int64_t n);
+int radix_sort_keys(p3t_ctx *ctx, int64_t n);   // sorts keys[0]/vals[0] -> keys[0]/vals[0]
+int gather_sorted(p3t_ctx *ctx, const double *pos, const double *mass, int64_t n);
+int build_topology(p3t_ctx *ctx, int64_t n);    // sets ctx->n_nodes, level_start, depth
+int build_moments(p3t_ctx *ctx);
+int build_groups(p3t_ctx *ctx);                 // sets ctx->n_groups
+
+// Walk (walk.hip): counts, offsets, list emission; sets list sizes.
+int build_lists(p3t_ctx *ctx);
+
+// Interactions (force.hip).
+int launch_force(p3t_ctx *ctx, double *acc, double *pot);
+
+// Neighbour lists (neighbors.hip).
+int launch_neighbors(p3t_ctx *ctx, int64_t *offsets, int32_t *idx, int64_t cap, int64_t *nnz);
+
+// VJP (vjp.hip).
+int launch_vjp(p3t_ctx *ctx, const double *w, const double *c, double *gpos, double *gmass);
+
+// Elementwise leapfrog helper (force.hip).
+int launch_kick_drift(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const double *acc,
+                      double dt_kick, double dt_drift);
+
+template <class T>
+inline T *ptr(const DevBuf &b) { return static_cast<T *>(b.p); }
+
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace p3t

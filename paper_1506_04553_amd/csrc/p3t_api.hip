@@ -1,0 +1,332 @@
+// p3t_api.hip -- the C ABI (include/p3t.h): context, workspaces, parameter
+// validation, stage sequencing, statistics and inspection.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "internal.h"
+
+using namespace p3t;
+
+namespace p3t {
+
+int set_error(p3t_ctx *ctx, int status, const char *fmt, ...) {
+    if (ctx) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(ctx->err, sizeof(ctx->err), fmt, ap);
+        va_end(ap);
+    }
+    return status;
+}
+
+int check_hip(p3t_ctx *ctx, hipError_t e, const char *what) {
+    if (e == hipSuccess) return P3T_OK;
+    return set_error(ctx, P3T_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int ensure(p3t_ctx *ctx, DevBuf &b, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (b.p && b.bytes >= bytes) return P3T_OK;
+    release(ctx, b);
+    size_t cap = bytes + bytes / 8;   // headroom: sizes drift from step to step
+    cap = (cap + 255) & ~(size_t)255;
+    void *p = nullptr;
+    if (ctx->alloc) {
+        p = ctx->alloc(cap, ctx->user);
+        if (!p) return set_error(ctx, P3T_ENOMEM, "allocator returned NULL for %zu bytes", cap);
+    } else {
+        hipError_t e = hipMalloc(&p, cap);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(ctx, P3T_ENOMEM, "hipMalloc(%zu): %s", cap, hipGetErrorString(e));
+        }
+    }
+    b.p = p;
+    b.bytes = cap;
+    return P3T_OK;
+}
+
+void release(p3t_ctx *ctx, DevBuf &b) {
+    if (!b.p) return;
+    if (ctx->free_) ctx->free_(b.p, ctx->user);
+    else (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+// Constants of K and W for gamma = r_in / r_out (Section 2.1, G with
+// denominator (gamma - 1)^7).
+static Changeover make_changeover(double r_in, double r_out) {
+    Changeover c{};
+    const double g = r_in / r_out;
+    c.r_out = r_out;
+    c.inv_rout = 1.0 / r_out;
+    c.gamma = g;
+    c.inv_1mg = 1.0 / (1.0 - g);
+    const double g2 = g * g, g3 = g2 * g, g4 = g3 * g, g5 = g4 * g, g6 = g5 * g, g7 = g6 * g;
+    const double D = pow(g - 1.0, 7);
+    const double glog = (g > 0.0) ? g3 * log(g) : 0.0;
+    c.C = 7.0 * (g6 - 9.0 * g5 + 45.0 * g4 - 60.0 * glog - 45.0 * g2 + 9.0 * g - 1.0) / (3.0 * D);
+    const double a7 = -10.0 / 3.0, a6 = 14.0 * (g + 1.0), a5 = -21.0 * (g2 + 3.0 * g + 1.0),
+                 a4 = 35.0 * (g3 + 9.0 * g2 + 9.0 * g + 1.0) / 3.0,
+                 a3 = -70.0 * (g3 + 3.0 * g2 + g), a2 = 210.0 * (g3 + g2), al = -140.0 * g3,
+                 a0 = g7 - 7.0 * g6 + 21.0 * g5 - 35.0 * g4;
+    const double G1 = (a7 + a6 + a5 + a4 + a3 + a2 + a0) / D;
+    // W/y = G(y)/y + 1 - G(1)
+    c.w[6] = a7 / D;
+    c.w[5] = a6 / D;
+    c.w[4] = a5 / D;
+    c.w[3] = a4 / D;
+    c.w[2] = a3 / D;
+    c.w[1] = a2 / D;
+    c.w[0] = 1.0 - G1;
+    c.wl = al / D;
+    c.wm = a0 / D;
+    return c;
+}
+
+}  // namespace p3t
+
+static const char *kStatus[] = {"ok", "invalid argument", "out of device memory",
+                                "capacity exceeded", "call out of order", "HIP error"};
+
+extern "C" const char *p3t_status_string(int s) {
+    if (s <= 0 && s >= -5) return kStatus[-s];
+    return "unknown status";
+}
+
+extern "C" const char *p3t_last_error(p3t_ctx *ctx) { return ctx ? ctx->err : "null context"; }
+
+extern "C" int p3t_check_params(const p3t_params *p) {
+    if (!p) return P3T_EINVAL;
+    const double v[5] = {p->eps, p->r_in, p->r_out, p->theta, p->r_search};
+    for (double d : v)
+        if (!isfinite(d)) return P3T_EINVAL;
+    if (p->eps < 0.0 || !(p->r_out > 0.0) || p->r_in < 0.0 || !(p->r_in < p->r_out)) return P3T_EINVAL;
+    if (p->theta < 0.0 || !(p->r_search > 0.0)) return P3T_EINVAL;
+    if (p->n_leaf < 1 || p->n_crit < p->n_leaf) return P3T_EINVAL;
+    if (p->use_quadrupole != 0 && p->use_quadrupole != 1) return P3T_EINVAL;
+    if (p->precision != P3T_PREC_FP64 && p->precision != P3T_PREC_MIXED) return P3T_EINVAL;
+    return P3T_OK;
+}
+
+extern "C" int p3t_create(p3t_ctx **out, int device, void *hip_stream, p3t_alloc_fn alloc,
+                          p3t_free_fn free_, void *alloc_user) {
+    if (!out) return P3T_EINVAL;
+    *out = nullptr;
+    if ((alloc == nullptr) != (free_ == nullptr)) return P3T_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        (void)hipGetLastError();
+        return P3T_EINVAL;
+    }
+    if (hipSetDevice(device) != hipSuccess) return P3T_EHIP;
+    p3t_ctx *ctx = new (std::nothrow) p3t_ctx();
+    if (!ctx) return P3T_ENOMEM;
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->alloc = alloc;
+    ctx->free_ = free_;
+    ctx->user = alloc_user;
+    hipError_t e = hipHostMalloc((void **)&ctx->hpin, 64 * sizeof(int64_t), hipHostMallocDefault);
+    for (int k = 0; k < 8 && e == hipSuccess; ++k) e = hipEventCreate(&ctx->ev[k]);
+    if (e != hipSuccess) {
+        p3t_destroy(ctx);
+        return P3T_EHIP;
+    }
+    *out = ctx;
+    return P3T_OK;
+}
+
+extern "C" void p3t_destroy(p3t_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    DevBuf *bufs[] = {&ctx->root, &ctx->keys[0], &ctx->keys[1], &ctx->vals[0], &ctx->vals[1],
+                      &ctx->hist, &ctx->histc, &ctx->x, &ctx->y, &ctx->z, &ctx->m, &ctx->lvlrange,
+                      &ctx->tblk, &ctx->tblk_off, &ctx->node_level, &ctx->node_first,
+                      &ctx->node_count, &ctx->node_child, &ctx->node_nchild, &ctx->node_parent,
+                      &ctx->node_prefix, &ctx->node_S, &ctx->node_walk, &ctx->node_mp, &ctx->gflag,
+                      &ctx->gscan, &ctx->grp, &ctx->cnt, &ctx->off, &ctx->c_idx, &ctx->p_idx,
+                      &ctx->n_idx, &ctx->wstack, &ctx->dflags, &ctx->readback, &ctx->scan_tmp,
+                      &ctx->nbr_cnt, &ctx->vjp_gx, &ctx->vjp_gm, &ctx->vjp_cell, &ctx->bbox};
+    for (DevBuf *b : bufs) release(ctx, *b);
+    if (ctx->hpin) (void)hipHostFree(ctx->hpin);
+    for (int k = 0; k < 8; ++k)
+        if (ctx->ev[k]) (void)hipEventDestroy(ctx->ev[k]);
+    delete ctx;
+}
+
+enum { EV_BUILD = 0, EV_FORCE = 2, EV_NBR = 4, EV_VJP = 6 };
+
+static int mark(p3t_ctx *ctx, int ev) {
+    return check_hip(ctx, hipEventRecord(ctx->ev[ev], ctx->stream), "event record");
+}
+
+static int elapsed_ms(p3t_ctx *ctx, int pair, double *out) {
+    float ms = 0.f;
+    int rc = check_hip(ctx, hipEventSynchronize(ctx->ev[pair + 1]), "event sync");
+    if (rc) return rc;
+    rc = check_hip(ctx, hipEventElapsedTime(&ms, ctx->ev[pair], ctx->ev[pair + 1]), "event time");
+    if (rc) return rc;
+    *out = ms;
+    return P3T_OK;
+}
+
+extern "C" int p3t_build_tree(p3t_ctx *ctx, int64_t n, const double *pos, const double *mass,
+                              const p3t_params *p) {
+    if (!ctx) return P3T_EINVAL;
+    if (n < 1 || n > (int64_t)INT32_MAX - 1 || !pos || !mass)
+        return set_error(ctx, P3T_EINVAL, "bad particle arrays (n = %lld)", (long long)n);
+    if (p3t_check_params(p) != P3T_OK) return set_error(ctx, P3T_EINVAL, "invalid parameters");
+    int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
+    if (rc) return rc;
+    ctx->built = 0;
+    ctx->n = n;
+    ctx->prm = *p;
+    ctx->chg = make_changeover(p->r_in, p->r_out);
+    if ((rc = ensure(ctx, ctx->readback, 64 * sizeof(int64_t)))) return rc;
+    if ((rc = mark(ctx, EV_BUILD))) return rc;
+    if ((rc = build_root_keys(ctx, pos, mass, n))) return rc;
+    if ((rc = radix_sort_keys(ctx, n))) return rc;
+    if ((rc = gather_sorted(ctx, pos, mass, n))) return rc;
+    if ((rc = build_topology(ctx, n))) return rc;
+    if ((rc = build_moments(ctx))) return rc;
+    if ((rc = build_groups(ctx))) return rc;
+    if ((rc = build_lists(ctx))) return rc;
+    if ((rc = mark(ctx, EV_BUILD + 1))) return rc;
+    ctx->ms_build = -1.0;   // resolved lazily by p3t_get_stats
+    ctx->ms_force = ctx->ms_nbr = ctx->ms_vjp = 0.0;
+    ctx->built = 1;
+    return P3T_OK;
+}
+
+extern "C" int p3t_long_force(p3t_ctx *ctx, double *acc, double *pot) {
+    if (!ctx) return P3T_EINVAL;
+    if (!ctx->built) return set_error(ctx, P3T_ESTATE, "p3t_long_force before p3t_build_tree");
+    if (!acc) return set_error(ctx, P3T_EINVAL, "acc is NULL");
+    int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
+    if (rc) return rc;
+    if ((rc = mark(ctx, EV_FORCE))) return rc;
+    if ((rc = launch_force(ctx, acc, pot))) return rc;
+    if ((rc = mark(ctx, EV_FORCE + 1))) return rc;
+    ctx->ms_force = -1.0;   // resolved lazily by p3t_get_stats
+    return P3T_OK;
+}
+
+extern "C" int p3t_neighbors(p3t_ctx *ctx, int64_t *offsets, int32_t *idx, int64_t cap, int64_t *nnz) {
+    if (!ctx) return P3T_EINVAL;
+    if (!ctx->built) return set_error(ctx, P3T_ESTATE, "p3t_neighbors before p3t_build_tree");
+    if (!offsets || !nnz || cap < 0 || (cap > 0 && !idx))
+        return set_error(ctx, P3T_EINVAL, "bad neighbour buffers");
+    int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
+    if (rc) return rc;
+    if ((rc = mark(ctx, EV_NBR))) return rc;
+    if ((rc = launch_neighbors(ctx, offsets, idx, cap, nnz))) return rc;
+    if ((rc = mark(ctx, EV_NBR + 1))) return rc;
+    ctx->ms_nbr = -1.0;
+    return P3T_OK;
+}
+
+extern "C" int p3t_long_force_vjp(p3t_ctx *ctx, const double *w, const double *c, double *gpos,
+                                  double *gmass) {
+    if (!ctx) return P3T_EINVAL;
+    if (!ctx->built) return set_error(ctx, P3T_ESTATE, "p3t_long_force_vjp before p3t_build_tree");
+    if (!w || !gpos || !gmass) return set_error(ctx, P3T_EINVAL, "bad VJP buffers");
+    int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
+    if (rc) return rc;
+    if ((rc = mark(ctx, EV_VJP))) return rc;
+    if ((rc = launch_vjp(ctx, w, c, gpos, gmass))) return rc;
+    if ((rc = mark(ctx, EV_VJP + 1))) return rc;
+    ctx->ms_vjp = -1.0;
+    return P3T_OK;
+}
+
+extern "C" int p3t_kick_drift(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const double *acc,
+                              double dt_kick, double dt_drift) {
+    if (!ctx || n < 0 || (n > 0 && (!pos || !vel || !acc)) || !isfinite(dt_kick) || !isfinite(dt_drift))
+        return ctx ? set_error(ctx, P3T_EINVAL, "bad kick/drift arguments") : P3T_EINVAL;
+    int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
+    if (rc) return rc;
+    return launch_kick_drift(ctx, n, pos, vel, acc, dt_kick, dt_drift);
+}
+
+extern "C" int p3t_get_stats(p3t_ctx *ctx, p3t_stats *out) {
+    if (!ctx || !out) return P3T_EINVAL;
+    if (ctx->ms_build < 0.0 && elapsed_ms(ctx, EV_BUILD, &ctx->ms_build)) ctx->ms_build = 0.0;
+    if (ctx->ms_force < 0.0 && elapsed_ms(ctx, EV_FORCE, &ctx->ms_force)) ctx->ms_force = 0.0;
+    if (ctx->ms_nbr < 0.0 && elapsed_ms(ctx, EV_NBR, &ctx->ms_nbr)) ctx->ms_nbr = 0.0;
+    if (ctx->ms_vjp < 0.0 && elapsed_ms(ctx, EV_VJP, &ctx->ms_vjp)) ctx->ms_vjp = 0.0;
+    memset(out, 0, sizeof(*out));
+    out->n = ctx->n;
+    out->n_nodes = ctx->n_nodes;
+    out->n_leaves = ctx->n_leaves;
+    out->n_groups = ctx->n_groups;
+    out->depth = ctx->depth;
+    out->n_cell_entries = ctx->n_cell_entries;
+    out->n_part_entries = ctx->n_part_entries;
+    out->n_near_entries = ctx->n_near_entries;
+    out->n_pc = ctx->n_pc;
+    out->n_pp = ctx->n_pp;
+    out->nnz = ctx->nnz;
+    out->walk_global_stack = ctx->walk_global;
+    out->ms_build = ctx->ms_build;
+    out->ms_force = ctx->ms_force;
+    out->ms_neighbors = ctx->ms_nbr;
+    out->ms_vjp = ctx->ms_vjp;
+    return P3T_OK;
+}
+
+extern "C" int p3t_copy_array(p3t_ctx *ctx, int which, void *dst, int64_t bytes) {
+    if (!ctx || !dst || bytes < 0) return P3T_EINVAL;
+    if (!ctx->built) return set_error(ctx, P3T_ESTATE, "no tree");
+    int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
+    if (rc) return rc;
+    if ((rc = check_hip(ctx, hipStreamSynchronize(ctx->stream), "sync"))) return rc;
+    const int64_t n = ctx->n, nn = ctx->n_nodes, G = ctx->n_groups, stride = nn + 1;
+    const void *src = nullptr;
+    int64_t size = 0, pitch = 0, spitch = 0, rows = 0;   // strided copies of node records
+    switch (which) {
+    case P3T_ARR_SORTED_KEYS: src = ctx->keys[0].p; size = n * 8; break;
+    case P3T_ARR_PERM: src = ctx->vals[0].p; size = n * 4; break;
+    case P3T_ARR_NODE_LEVEL: src = ctx->node_level.p; size = nn * 4; break;
+    case P3T_ARR_NODE_FIRST: src = ctx->node_first.p; size = nn * 4; break;
+    case P3T_ARR_NODE_COUNT: src = ctx->node_count.p; size = nn * 4; break;
+    case P3T_ARR_NODE_CHILD: src = ctx->node_child.p; size = nn * 4; break;
+    case P3T_ARR_NODE_NCHILD: src = ctx->node_nchild.p; size = nn * 4; break;
+    case P3T_ARR_NODE_PARENT: src = ctx->node_parent.p; size = nn * 4; break;
+    case P3T_ARR_NODE_PREFIX: src = ctx->node_prefix.p; size = nn * 8; break;
+    case P3T_ARR_NODE_MASS:
+        src = (const char *)ctx->node_mp.p + offsetof(NodeMP, M); pitch = 8; spitch = sizeof(NodeMP);
+        rows = nn; break;
+    case P3T_ARR_NODE_COM:
+        src = ctx->node_mp.p; pitch = 24; spitch = sizeof(NodeMP); rows = nn; break;
+    case P3T_ARR_NODE_QUAD:
+        src = (const char *)ctx->node_mp.p + offsetof(NodeMP, q); pitch = 48; spitch = sizeof(NodeMP);
+        rows = nn; break;
+    case P3T_ARR_NODE_BOX:
+        src = (const char *)ctx->node_walk.p + offsetof(NodeWalk, lo); pitch = 48;
+        spitch = sizeof(NodeWalk); rows = nn; break;
+    case P3T_ARR_GROUP_NODE:
+        src = (const char *)ctx->grp.p + offsetof(GroupInfo, node); pitch = 4;
+        spitch = sizeof(GroupInfo); rows = G; break;
+    case P3T_ARR_CELL_OFF: src = ctx->off.p; size = (G + 1) * 8; break;
+    case P3T_ARR_CELL_IDX: src = ctx->c_idx.p; size = ctx->n_cell_entries * 4; break;
+    case P3T_ARR_PART_OFF: src = (const int64_t *)ctx->off.p + stride; size = (G + 1) * 8; break;
+    case P3T_ARR_PART_IDX: src = ctx->p_idx.p; size = ctx->n_part_entries * 4; break;
+    case P3T_ARR_ROOT: src = ctx->root.p; size = 32; break;
+    default: return set_error(ctx, P3T_EINVAL, "unknown array id %d", which);
+    }
+    if (rows) size = rows * pitch;
+    if (bytes != size)
+        return set_error(ctx, P3T_EINVAL, "array %d holds %lld bytes, %lld requested", which,
+                         (long long)size, (long long)bytes);
+    if (size == 0) return P3T_OK;
+    if (rows)
+        return check_hip(ctx, hipMemcpy2D(dst, pitch, src, spitch, pitch, rows, hipMemcpyDeviceToHost),
+                         "copy array");
+    return check_hip(ctx, hipMemcpy(dst, src, size, hipMemcpyDeviceToHost), "copy array");
+}

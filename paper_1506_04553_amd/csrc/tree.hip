@@ -1,0 +1,649 @@
+// tree.hip -- octree construction on the GPU: root cube, Morton keys, LSD
+// radix sort, sorted SoA gather, particle-parallel octree topology, bottom-up
+// moments (monopole + quadrupole, Section 2.2 "up to the quadrupole moment")
+// and group selection.
+//
+// Every quantity that feeds a discrete decision (keys, node boundaries,
+// centre of mass, boxes) is a fixed IEEE FP64 operation sequence: this file is
+// compiled with -ffp-contract=off, so no multiply-add is fused.
+//
+// Conventions (the method leaves them open):
+//   root cube  lo_a = min_i x_ia, L = 2^ceil(log2(max_a extent_a)), L = 1 if 0;
+//   key        q_a = min(floor((x_a - lo_a) * (2^21 / L)), 2^21 - 1) interleaved
+//              x,y,z from the most significant bit of each 3-bit level digit;
+//   order      ascending key, ties by original index (stable sort of 0..n-1);
+//   node       (level l, key prefix) range; split into its non-empty octants
+//              iff count > n_leaf and l < 21; numbered breadth first;
+//   moments    M, S = sum m x folded in member order (leaves) or child order
+//              (internal), com = S / M; box = member min/max;
+//   groups     nodes with (count <= n_crit or leaf) whose ancestors all have
+//              count > n_crit, ordered by first particle.
+#include <math.h>
+
+#include "device_util.h"
+#include "internal.h"
+
+namespace p3t {
+
+// ---------------------------------------------------------------------------
+// Root cube
+// ---------------------------------------------------------------------------
+constexpr int kRedThreads = 256;
+
+__global__ __launch_bounds__(kRedThreads) void k_bbox_partial(const double *__restrict__ pos,
+                                                              const double *__restrict__ mass,
+                                                              int64_t n, double *partial,
+                                                              int32_t *bad) {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int flag = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double v = pos[3 * i + a];
+            flag |= !isfinite(v);
+            lo[a] = fmin(lo[a], v);
+            hi[a] = fmax(hi[a], v);
+        }
+        double mm = mass[i];
+        flag |= !(isfinite(mm) && mm > 0.0);
+    }
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fmin(lo[a], __shfl_xor(lo[a], d, kWave));
+            hi[a] = fmax(hi[a], __shfl_xor(hi[a], d, kWave));
+        }
+        flag |= __shfl_xor(flag, d, kWave);
+    }
+    __shared__ double s[kRedThreads / kWave][6];
+    __shared__ int sf[kRedThreads / kWave];
+    const int w = threadIdx.x / kWave;
+    if (threadIdx.x % kWave == 0) {
+        for (int a = 0; a < 3; ++a) { s[w][a] = lo[a]; s[w][3 + a] = hi[a]; }
+        sf[w] = flag;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < kRedThreads / kWave; ++k) {
+            for (int a = 0; a < 3; ++a) {
+                s[0][a] = fmin(s[0][a], s[k][a]);
+                s[0][3 + a] = fmax(s[0][3 + a], s[k][3 + a]);
+            }
+            sf[0] |= sf[k];
+        }
+        for (int a = 0; a < 6; ++a) partial[6 * blockIdx.x + a] = s[0][a];
+        if (sf[0]) atomicOr(bad, 1);
+    }
+}
+
+__global__ void k_bbox_final(const double *partial, int nb, const int32_t *bad, RootInfo *root) {
+    if (threadIdx.x != 0) return;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int b = 0; b < nb; ++b)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fmin(lo[a], partial[6 * b + a]);
+            hi[a] = fmax(hi[a], partial[6 * b + 3 + a]);
+        }
+    double ext = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double e = hi[a] - lo[a];
+        if (e > ext) ext = e;
+    }
+    double L = 1.0;
+    if (ext > 0.0) {
+        int e;
+        double f = frexp(ext, &e);
+        L = (f == 0.5) ? ldexp(1.0, e - 1) : ldexp(1.0, e);
+    }
+    for (int a = 0; a < 3; ++a) root->lo[a] = lo[a];
+    root->L = L;
+    root->scale = ldexp(1.0, kMaxLevel) / L;
+    root->bad_input = *bad;
+}
+
+// ---------------------------------------------------------------------------
+// Morton keys
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t spread_bits3(uint64_t v) {
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+__global__ void k_keys(const double *__restrict__ pos, int64_t n, const RootInfo *__restrict__ root,
+                       uint64_t *__restrict__ keys, int32_t *__restrict__ idx) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double scale = root->scale;
+    uint64_t q[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double t = floor((pos[3 * i + a] - root->lo[a]) * scale);
+        uint64_t v = (uint64_t)t;
+        q[a] = v > 0x1fffffull ? 0x1fffffull : v;
+    }
+    keys[i] = (spread_bits3(q[0]) << 2) | (spread_bits3(q[1]) << 1) | spread_bits3(q[2]);
+    idx[i] = (int32_t)i;
+}
+
+int build_root_keys(p3t_ctx *ctx, const double *pos, const double *mass, int64_t n) {
+    int rc;
+    const int nb = (int)std::min<int64_t>(1024, (n + kRedThreads - 1) / kRedThreads);
+    if ((rc = ensure(ctx, ctx->root, sizeof(RootInfo)))) return rc;
+    if ((rc = ensure(ctx, ctx->dflags, 16 * sizeof(int32_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->bbox, 6 * nb * sizeof(double)))) return rc;
+    if ((rc = ensure(ctx, ctx->keys[0], n * sizeof(uint64_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->keys[1], n * sizeof(uint64_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->vals[0], n * sizeof(int32_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->vals[1], n * sizeof(int32_t)))) return rc;
+    int32_t *flags = ptr<int32_t>(ctx->dflags);
+    if ((rc = check_hip(ctx, hipMemsetAsync(flags, 0, 16 * sizeof(int32_t), ctx->stream), "memset")))
+        return rc;
+    double *partial = ptr<double>(ctx->bbox);
+    k_bbox_partial<<<nb, kRedThreads, 0, ctx->stream>>>(pos, mass, n, partial, flags);
+    k_bbox_final<<<1, 64, 0, ctx->stream>>>(partial, nb, flags, ptr<RootInfo>(ctx->root));
+    k_keys<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(pos, n, ptr<RootInfo>(ctx->root),
+                                                         ptr<uint64_t>(ctx->keys[0]),
+                                                         ptr<int32_t>(ctx->vals[0]));
+    return check_hip(ctx, hipGetLastError(), "root/keys");
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort of (key, index), 8 passes of 8 bits.
+// ---------------------------------------------------------------------------
+constexpr int kRsThreads = 256;
+constexpr int kRsRounds = 8;
+constexpr int kRsTile = kRsThreads * kRsRounds;   // 2048 keys per block
+constexpr int kRsWaves = kRsThreads / kWave;
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t *__restrict__ keys, int64_t n,
+                                                        int shift, int32_t *__restrict__ counts,
+                                                        int nb) {
+    __shared__ int32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    for (int r = 0; r < kRsRounds; ++r) {
+        int64_t i = base + r * kRsThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255], 1);
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
+    const uint64_t *__restrict__ kin, const int32_t *__restrict__ vin, uint64_t *__restrict__ kout,
+    int32_t *__restrict__ vout, int64_t n, int shift, const int32_t *__restrict__ counts,
+    const int32_t *__restrict__ offsets, int nb) {
+    __shared__ uint64_t s_key[kRsTile];
+    __shared__ int32_t s_val[kRsTile];
+    __shared__ int32_t s_start[256], s_run[256];
+    __shared__ int32_t s_wcnt[kRsWaves][256], s_woff[kRsWaves][256];
+    __shared__ int32_t s_wsum[kRsWaves];
+    const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    const int64_t tile_n = std::min<int64_t>(kRsTile, n - base);
+
+    // digit starts inside this tile: exclusive scan of the tile histogram
+    {
+        int c = counts[(int64_t)tid * nb + blockIdx.x];
+        int incl = wave_incl_scan(c);
+        if (lane == kWave - 1) s_wsum[w] = incl;
+        __syncthreads();
+        int wb = 0;
+        for (int k = 0; k < w; ++k) wb += s_wsum[k];
+        s_start[tid] = wb + incl - c;
+        s_run[tid] = 0;
+    }
+    for (int r = 0; r < kRsRounds; ++r) {
+        for (int k = 0; k < kRsWaves; ++k) s_wcnt[k][tid] = 0;
+        __syncthreads();
+        const int64_t i = base + r * kRsThreads + tid;
+        const bool valid = i < n;
+        const uint64_t key = valid ? kin[i] : 0ull;
+        const int d = (int)((key >> shift) & 255);
+        uint64_t same = ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1;
+            const uint64_t bb = ballot(bit);
+            same &= bit ? bb : ~bb;
+        }
+        const int rank_w = count_below(same);
+        if (valid && rank_w == 0) s_wcnt[w][d] = __popcll(same);
+        __syncthreads();
+        {
+            int run = s_run[tid];
+#pragma unroll
+            for (int k = 0; k < kRsWaves; ++k) {
+                s_woff[k][tid] = run;
+                run += s_wcnt[k][tid];
+            }
+            s_run[tid] = run;
+        }
+        __syncthreads();
+        if (valid) {
+            const int p = s_start[d] + s_woff[w][d] + rank_w;
+            s_key[p] = key;
+            s_val[p] = vin[i];
+        }
+        __syncthreads();
+    }
+    for (int p = tid; p < tile_n; p += kRsThreads) {
+        const uint64_t key = s_key[p];
+        const int d = (int)((key >> shift) & 255);
+        const int64_t o = (int64_t)offsets[(int64_t)d * nb + blockIdx.x] + (p - s_start[d]);
+        kout[o] = key;
+        vout[o] = s_val[p];
+    }
+}
+
+int radix_sort_keys(p3t_ctx *ctx, int64_t n) {
+    int rc;
+    const int nb = (int)((n + kRsTile - 1) / kRsTile);
+    if ((rc = ensure(ctx, ctx->hist, (size_t)256 * nb * sizeof(int32_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->histc, (size_t)256 * nb * sizeof(int32_t)))) return rc;
+    int32_t *cnt = ptr<int32_t>(ctx->histc), *off = ptr<int32_t>(ctx->hist);
+    int src = 0;
+    for (int pass = 0; pass < 8; ++pass) {
+        const int shift = 8 * pass;
+        uint64_t *kin = ptr<uint64_t>(ctx->keys[src]), *kout = ptr<uint64_t>(ctx->keys[1 - src]);
+        int32_t *vin = ptr<int32_t>(ctx->vals[src]), *vout = ptr<int32_t>(ctx->vals[1 - src]);
+        k_rs_hist<<<nb, kRsThreads, 0, ctx->stream>>>(kin, n, shift, cnt, nb);
+        if ((rc = check_hip(ctx, hipGetLastError(), "radix hist"))) return rc;
+        if ((rc = scan_exclusive_i32(ctx, cnt, off, (int64_t)256 * nb, nullptr))) return rc;
+        k_rs_scatter<<<nb, kRsThreads, 0, ctx->stream>>>(kin, vin, kout, vout, n, shift, cnt, off, nb);
+        if ((rc = check_hip(ctx, hipGetLastError(), "radix scatter"))) return rc;
+        src = 1 - src;
+    }
+    return P3T_OK;  // 8 passes: the result is back in keys[0] / vals[0]
+}
+
+// ---------------------------------------------------------------------------
+// Sorted SoA copy of positions and masses
+// ---------------------------------------------------------------------------
+__global__ void k_gather(const double *__restrict__ pos, const double *__restrict__ mass,
+                         const int32_t *__restrict__ perm, int64_t n, double *__restrict__ x,
+                         double *__restrict__ y, double *__restrict__ z, double *__restrict__ m) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int64_t o = perm[s];
+    x[s] = pos[3 * o];
+    y[s] = pos[3 * o + 1];
+    z[s] = pos[3 * o + 2];
+    m[s] = mass[o];
+}
+
+int gather_sorted(p3t_ctx *ctx, const double *pos, const double *mass, int64_t n) {
+    int rc;
+    for (p3t::DevBuf *b : {&ctx->x, &ctx->y, &ctx->z, &ctx->m})
+        if ((rc = ensure(ctx, *b, n * sizeof(double)))) return rc;
+    k_gather<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(pos, mass, ptr<int32_t>(ctx->vals[0]), n,
+                                                           ptr<double>(ctx->x), ptr<double>(ctx->y),
+                                                           ptr<double>(ctx->z), ptr<double>(ctx->m));
+    return check_hip(ctx, hipGetLastError(), "gather");
+}
+
+// ---------------------------------------------------------------------------
+// Octree topology from sorted keys, in parallel over particles.
+//
+// With c(a) = common levels of keys a-1 and a, position a starts the nodes of
+// levels c(a)+1 .. e(a) (all levels 0.. for a = 0), provided the level-c(a)
+// node containing a has more than n_leaf particles; e(a) is the first of those
+// levels whose node does not split.  A node starting at a at level l has more
+// than n_leaf particles iff key a+n_leaf shares its level-l prefix.  Breadth
+// first ids follow from per-level ranks of the start positions.
+// ---------------------------------------------------------------------------
+constexpr int kTopoThreads = 256;
+constexpr int kTopoWaves = kTopoThreads / kWave;
+
+__device__ __forceinline__ int64_t lower_bound_key(const uint64_t *keys, int64_t lo, int64_t hi,
+                                                   uint64_t v) {
+    while (lo < hi) {
+        int64_t mid = lo + ((hi - lo) >> 1);
+        if (keys[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int64_t upper_bound_key(const uint64_t *keys, int64_t lo, int64_t hi,
+                                                   uint64_t v) {
+    while (lo < hi) {
+        int64_t mid = lo + ((hi - lo) >> 1);
+        if (keys[mid] <= v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// range code: lo | hi << 8, or -1 when no node starts at a
+__global__ __launch_bounds__(kTopoThreads) void k_topo_ranges(const uint64_t *__restrict__ keys,
+                                                              int64_t n, int n_leaf,
+                                                              int32_t *__restrict__ range,
+                                                              int32_t *__restrict__ blk, int nb) {
+    __shared__ int32_t cnt[kLevels];
+    if (threadIdx.x < kLevels) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t a = (int64_t)blockIdx.x * kTopoThreads + threadIdx.x;
+    int lo = 1, hi = 0;
+    if (a < n) {
+        const uint64_t ka = keys[a];
+        const int c = (a == 0) ? -1 : common_levels(keys[a - 1], ka);
+        const int m = (a + n_leaf < n) ? common_levels(ka, keys[a + n_leaf]) : -1;
+        bool exists;
+        if (a == 0) {
+            exists = true;
+        } else if (c >= kMaxLevel) {
+            exists = false;   // duplicate key: no node starts here
+        } else {
+            // the level-c node containing a must have more than n_leaf particles
+            const int sh = 3 * (kMaxLevel - c);
+            const uint64_t base = (sh >= 64) ? 0ull : ((ka >> sh) << sh);
+            const int64_t p = lower_bound_key(keys, 0, a, base);
+            exists = (p + n_leaf < n) && common_levels(keys[p], keys[p + n_leaf]) >= c;
+        }
+        if (exists) {
+            lo = c + 1;
+            const int msplit = m < 20 ? m : 20;
+            hi = (msplit + 1 > lo) ? msplit + 1 : lo;
+        }
+        range[a] = exists ? (lo | (hi << 8)) : -1;
+        for (int l = lo; l <= hi; ++l) atomicAdd(&cnt[l], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < kLevels) blk[(int64_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ void k_topo_level_starts(const int32_t *__restrict__ blk_off, int nb, const int32_t *total,
+                                    int64_t *__restrict__ out) {
+    const int l = threadIdx.x;
+    if (l < kLevels) out[l] = blk_off[(int64_t)l * nb];
+    if (l == kLevels) out[l] = *total;
+}
+
+__global__ __launch_bounds__(kTopoThreads) void k_topo_emit(
+    const uint64_t *__restrict__ keys, int64_t n, const int32_t *__restrict__ range,
+    const int32_t *__restrict__ blk_off, int nb, int32_t *__restrict__ level, int32_t *__restrict__ first,
+    int32_t *__restrict__ count, int32_t *__restrict__ child, int32_t *__restrict__ nchild,
+    uint64_t *__restrict__ prefix) {
+    __shared__ uint64_t s_ball[kLevels][kTopoWaves];
+    __shared__ int32_t s_wc[kLevels][kTopoWaves];
+    const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+    const int64_t a = (int64_t)blockIdx.x * kTopoThreads + tid;
+    const int32_t code = (a < n) ? range[a] : -1;
+    const int lo = code < 0 ? 1 : (code & 255), hi = code < 0 ? 0 : (code >> 8);
+    // all lanes: per-level membership masks of this wave
+    for (int l = 0; l < kLevels; ++l) {
+        const uint64_t b = ballot(l >= lo && l <= hi);
+        if (lane == 0) {
+            s_ball[l][w] = b;
+            s_wc[l][w] = __popcll(b);
+        }
+    }
+    __syncthreads();
+    if (code < 0) return;
+    const uint64_t ka = keys[a];
+    // number of level-l starts before position a, plus the level's first id
+    auto rank_at = [&](int l) -> int32_t {
+        int base = blk_off[(int64_t)l * nb + blockIdx.x];
+        for (int k = 0; k < w; ++k) base += s_wc[l][k];
+        return base + count_below(s_ball[l][w]);
+    };
+    int32_t id = rank_at(lo);
+    for (int l = lo; l <= hi; ++l) {
+        const int32_t next = (l < kMaxLevel) ? rank_at(l + 1) : 0;
+        const int sh = 3 * (kMaxLevel - l);
+        const uint64_t kmax = ka | ((sh >= 64) ? ~0ull : ((1ull << sh) - 1ull));
+        const int64_t ub = upper_bound_key(keys, a + 1, n, kmax);
+        level[id] = l;
+        first[id] = (int32_t)a;
+        count[id] = (int32_t)(ub - a);
+        child[id] = next;
+        nchild[id] = (l == hi) ? 0 : -1;
+        prefix[id] = (sh >= 64) ? 0ull : (ka >> sh);
+        id = next;
+    }
+}
+
+// children are contiguous: n_child = (first child of the next node at this level)
+// - (own first child); parents from the children ranges.
+__global__ void k_topo_links(int64_t n_nodes, const int32_t *__restrict__ level,
+                             const int32_t *__restrict__ child, int32_t *__restrict__ nchild,
+                             int32_t *__restrict__ parent, const int64_t *__restrict__ level_start) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n_nodes) return;
+    if (id == 0) parent[0] = -1;
+    if (nchild[id] != -1) return;
+    const int l = level[id];
+    const int64_t next = (id + 1 < level_start[l + 1]) ? child[id + 1] : level_start[l + 2];
+    const int32_t cf = child[id];
+    const int32_t nc = (int32_t)(next - cf);
+    nchild[id] = nc;
+    for (int k = 0; k < nc; ++k) parent[cf + k] = (int32_t)id;
+}
+
+int build_topology(p3t_ctx *ctx, int64_t n) {
+    int rc;
+    const int nb = (int)((n + kTopoThreads - 1) / kTopoThreads);
+    if ((rc = ensure(ctx, ctx->lvlrange, n * sizeof(int32_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->tblk, (size_t)kLevels * nb * sizeof(int32_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->tblk_off, ((size_t)kLevels * nb + 1) * sizeof(int32_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->readback, 64 * sizeof(int64_t)))) return rc;
+    const uint64_t *keys = ptr<uint64_t>(ctx->keys[0]);
+    int32_t *blk = ptr<int32_t>(ctx->tblk), *blk_off = ptr<int32_t>(ctx->tblk_off);
+    int64_t *rb = ptr<int64_t>(ctx->readback);
+    k_topo_ranges<<<nb, kTopoThreads, 0, ctx->stream>>>(keys, n, ctx->prm.n_leaf,
+                                                        ptr<int32_t>(ctx->lvlrange), blk, nb);
+    if ((rc = check_hip(ctx, hipGetLastError(), "topology ranges"))) return rc;
+    int32_t *total = blk_off + (size_t)kLevels * nb;
+    if ((rc = scan_exclusive_i32(ctx, blk, blk_off, (int64_t)kLevels * nb, total))) return rc;
+    k_topo_level_starts<<<1, 64, 0, ctx->stream>>>(blk_off, nb, total, rb);
+    if ((rc = check_hip(ctx, hipGetLastError(), "topology level starts"))) return rc;
+    // one read-back: node count, level starts and the input check
+    if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin, rb, (kLevels + 1) * sizeof(int64_t),
+                                            hipMemcpyDeviceToHost, ctx->stream), "readback")))
+        return rc;
+    if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + 32, (const char *)ctx->root.p +
+                                                offsetof(RootInfo, bad_input),
+                                            sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream),
+                        "readback")))
+        return rc;
+    if ((rc = check_hip(ctx, hipStreamSynchronize(ctx->stream), "sync"))) return rc;
+    if (*(int32_t *)(ctx->hpin + 32))
+        return set_error(ctx, P3T_EINVAL, "non-finite position or non-positive/non-finite mass");
+    for (int l = 0; l <= kLevels; ++l) ctx->level_start[l] = ctx->hpin[l];
+    ctx->n_nodes = ctx->level_start[kLevels];
+    ctx->depth = 0;
+    for (int l = 0; l < kLevels; ++l)
+        if (ctx->level_start[l + 1] > ctx->level_start[l]) ctx->depth = l;
+    const int64_t nn = ctx->n_nodes;
+    for (p3t::DevBuf *b : {&ctx->node_level, &ctx->node_first, &ctx->node_count, &ctx->node_child,
+                           &ctx->node_nchild, &ctx->node_parent})
+        if ((rc = ensure(ctx, *b, nn * sizeof(int32_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->node_prefix, nn * sizeof(uint64_t)))) return rc;
+    k_topo_emit<<<nb, kTopoThreads, 0, ctx->stream>>>(
+        keys, n, ptr<int32_t>(ctx->lvlrange), blk_off, nb, ptr<int32_t>(ctx->node_level),
+        ptr<int32_t>(ctx->node_first), ptr<int32_t>(ctx->node_count), ptr<int32_t>(ctx->node_child),
+        ptr<int32_t>(ctx->node_nchild), ptr<uint64_t>(ctx->node_prefix));
+    if ((rc = check_hip(ctx, hipGetLastError(), "topology emit"))) return rc;
+    k_topo_links<<<blocks_for(nn, 256), 256, 0, ctx->stream>>>(
+        nn, ptr<int32_t>(ctx->node_level), ptr<int32_t>(ctx->node_child),
+        ptr<int32_t>(ctx->node_nchild), ptr<int32_t>(ctx->node_parent), rb);
+    return check_hip(ctx, hipGetLastError(), "topology links");
+}
+
+// ---------------------------------------------------------------------------
+// Moments, one launch per level from the deepest up.
+// ---------------------------------------------------------------------------
+__global__ void k_moments_level(int64_t begin, int64_t end, int lev, const RootInfo *__restrict__ root,
+                                const double *__restrict__ x, const double *__restrict__ y,
+                                const double *__restrict__ z, const double *__restrict__ m,
+                                const int32_t *__restrict__ first, const int32_t *__restrict__ count,
+                                const int32_t *__restrict__ child, const int32_t *__restrict__ nchild,
+                                double *__restrict__ S, NodeWalk *__restrict__ nw,
+                                NodeMP *__restrict__ mp, int64_t n_nodes) {
+    const int64_t id = begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= end) return;
+    const int nc = nchild[id];
+    const int32_t f = first[id], cnt = count[id];
+    double M = 0.0, Sx = 0.0, Sy = 0.0, Sz = 0.0;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double q[6] = {0, 0, 0, 0, 0, 0};
+    if (nc == 0) {
+        for (int32_t k = f; k < f + cnt; ++k) {
+            const double mk = m[k], xk = x[k], yk = y[k], zk = z[k];
+            M = M + mk;
+            Sx = Sx + mk * xk;
+            Sy = Sy + mk * yk;
+            Sz = Sz + mk * zk;
+            lo[0] = fmin(lo[0], xk); lo[1] = fmin(lo[1], yk); lo[2] = fmin(lo[2], zk);
+            hi[0] = fmax(hi[0], xk); hi[1] = fmax(hi[1], yk); hi[2] = fmax(hi[2], zk);
+        }
+        const double cx = Sx / M, cy = Sy / M, cz = Sz / M;
+        for (int32_t k = f; k < f + cnt; ++k) {
+            const double mk = m[k];
+            const double dx = x[k] - cx, dy = y[k] - cy, dz = z[k] - cz;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            q[0] += mk * (3.0 * dx * dx - r2);
+            q[1] += mk * (3.0 * dy * dy - r2);
+            q[2] += mk * (3.0 * dz * dz - r2);
+            q[3] += mk * 3.0 * dx * dy;
+            q[4] += mk * 3.0 * dx * dz;
+            q[5] += mk * 3.0 * dy * dz;
+        }
+    } else {
+        const int32_t cf = child[id];
+        for (int k = cf; k < cf + nc; ++k) {
+            M = M + mp[k].M;
+            Sx = Sx + S[k];
+            Sy = Sy + S[n_nodes + k];
+            Sz = Sz + S[2 * n_nodes + k];
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = fmin(lo[a], nw[k].lo[a]);
+                hi[a] = fmax(hi[a], nw[k].hi[a]);
+            }
+        }
+        const double cx = Sx / M, cy = Sy / M, cz = Sz / M;
+        // parallel-axis shift of the children's quadrupoles to this centre
+        for (int k = cf; k < cf + nc; ++k) {
+            const NodeMP c = mp[k];
+            const double dx = c.cx - cx, dy = c.cy - cy, dz = c.cz - cz;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            q[0] += c.q[0] + c.M * (3.0 * dx * dx - r2);
+            q[1] += c.q[1] + c.M * (3.0 * dy * dy - r2);
+            q[2] += c.q[2] + c.M * (3.0 * dz * dz - r2);
+            q[3] += c.q[3] + c.M * 3.0 * dx * dy;
+            q[4] += c.q[4] + c.M * 3.0 * dx * dz;
+            q[5] += c.q[5] + c.M * 3.0 * dy * dz;
+        }
+    }
+    const double cx = Sx / M, cy = Sy / M, cz = Sz / M;
+    S[id] = Sx;
+    S[n_nodes + id] = Sy;
+    S[2 * n_nodes + id] = Sz;
+    const double side = ldexp(root->L, -lev);
+    NodeWalk o;
+    o.cx = cx; o.cy = cy; o.cz = cz;
+    o.l2 = side * side;
+    for (int a = 0; a < 3; ++a) { o.lo[a] = lo[a]; o.hi[a] = hi[a]; }
+    o.child_first = nc ? child[id] : -1;
+    o.n_child = nc;
+    o.first = f;
+    o.count = cnt;
+    nw[id] = o;
+    NodeMP p;
+    p.cx = cx; p.cy = cy; p.cz = cz; p.M = M;
+    for (int a = 0; a < 6; ++a) p.q[a] = q[a];
+    mp[id] = p;
+}
+
+int build_moments(p3t_ctx *ctx) {
+    int rc;
+    const int64_t nn = ctx->n_nodes;
+    if ((rc = ensure(ctx, ctx->node_S, 3 * nn * sizeof(double)))) return rc;
+    if ((rc = ensure(ctx, ctx->node_walk, nn * sizeof(NodeWalk)))) return rc;
+    if ((rc = ensure(ctx, ctx->node_mp, nn * sizeof(NodeMP)))) return rc;
+    for (int l = kMaxLevel; l >= 0; --l) {
+        const int64_t b = ctx->level_start[l], e = ctx->level_start[l + 1];
+        if (e <= b) continue;
+        k_moments_level<<<blocks_for(e - b, 128), 128, 0, ctx->stream>>>(
+            b, e, l, ptr<RootInfo>(ctx->root), ptr<double>(ctx->x), ptr<double>(ctx->y),
+            ptr<double>(ctx->z), ptr<double>(ctx->m), ptr<int32_t>(ctx->node_first),
+            ptr<int32_t>(ctx->node_count), ptr<int32_t>(ctx->node_child),
+            ptr<int32_t>(ctx->node_nchild), ptr<double>(ctx->node_S), ptr<NodeWalk>(ctx->node_walk),
+            ptr<NodeMP>(ctx->node_mp), nn);
+        if ((rc = check_hip(ctx, hipGetLastError(), "moments"))) return rc;
+    }
+    return P3T_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Groups: flag the first particle of every group node, compact in particle order.
+// ---------------------------------------------------------------------------
+__global__ void k_group_mark(int64_t n_nodes, const int32_t *__restrict__ count,
+                             const int32_t *__restrict__ nchild, const int32_t *__restrict__ parent,
+                             const int32_t *__restrict__ first, int n_crit, int32_t *__restrict__ flag,
+                             int32_t *__restrict__ node_at, unsigned long long *__restrict__ n_leaves) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n_nodes) return;
+    if (nchild[id] == 0) atomicAdd(n_leaves, 1ull);
+    const bool cand = count[id] <= n_crit || nchild[id] == 0;
+    const bool top = (id == 0) || count[parent[id]] > n_crit;
+    if (cand && top) {
+        flag[first[id]] = 1;
+        node_at[first[id]] = (int32_t)id;
+    }
+}
+
+__global__ void k_group_compact(int64_t n, const int32_t *__restrict__ flag,
+                                const int32_t *__restrict__ slot, const int32_t *__restrict__ node_at,
+                                const NodeWalk *__restrict__ nw, GroupInfo *__restrict__ grp) {
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n || !flag[a]) return;
+    const int32_t id = node_at[a];
+    const NodeWalk nd = nw[id];
+    GroupInfo g;
+    for (int k = 0; k < 3; ++k) {
+        g.lo[k] = nd.lo[k];
+        g.hi[k] = nd.hi[k];
+        g.c[k] = (nd.lo[k] + nd.hi[k]) * 0.5;
+    }
+    g.first = nd.first;
+    g.count = nd.count;
+    g.node = id;
+    g.pad = 0;
+    grp[slot[a]] = g;
+}
+
+int build_groups(p3t_ctx *ctx) {
+    int rc;
+    const int64_t n = ctx->n, nn = ctx->n_nodes;
+    if ((rc = ensure(ctx, ctx->gflag, (n + 1) * sizeof(int32_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->gscan, (n + 1) * sizeof(int32_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->lvlrange, (n + 1) * sizeof(int32_t)))) return rc;   // reused: node_at
+    if ((rc = ensure(ctx, ctx->grp, (nn + 1) * sizeof(GroupInfo)))) return rc;
+    int32_t *flag = ptr<int32_t>(ctx->gflag), *slot = ptr<int32_t>(ctx->gscan);
+    int32_t *node_at = ptr<int32_t>(ctx->lvlrange);
+    if ((rc = check_hip(ctx, hipMemsetAsync(flag, 0, (n + 1) * sizeof(int32_t), ctx->stream), "memset")))
+        return rc;
+    if ((rc = check_hip(ctx, hipMemsetAsync(ptr<int64_t>(ctx->readback) + 32, 0, sizeof(int64_t),
+                                            ctx->stream), "memset")))
+        return rc;
+    k_group_mark<<<blocks_for(nn, 256), 256, 0, ctx->stream>>>(
+        nn, ptr<int32_t>(ctx->node_count), ptr<int32_t>(ctx->node_nchild),
+        ptr<int32_t>(ctx->node_parent), ptr<int32_t>(ctx->node_first), ctx->prm.n_crit, flag, node_at,
+        (unsigned long long *)(ptr<int64_t>(ctx->readback) + 32));
+    if ((rc = check_hip(ctx, hipGetLastError(), "group mark"))) return rc;
+    // slot[n] = number of groups (device), read back together with the list sizes
+    if ((rc = scan_exclusive_i32(ctx, flag, slot, n + 1, nullptr))) return rc;
+    k_group_compact<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(
+        n, flag, slot, node_at, ptr<NodeWalk>(ctx->node_walk), ptr<GroupInfo>(ctx->grp));
+    return check_hip(ctx, hipGetLastError(), "group compact");
+}
+
+}  // namespace p3t

@@ -1,0 +1,262 @@
+"""ctypes binding of ``libp3t.so`` (the C ABI declared in ``include/p3t.h``).
+
+Argument marshalling only: tensors are checked (device, dtype, shape,
+contiguity) and handed to the library as raw device pointers; every step of the
+computation runs in the library's HIP kernels.  PyTorch supplies device memory
+(its caching allocator serves the library's workspaces) and the stream.
+
+If the library is missing this module raises; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libp3t.so")
+
+P3T_OK, P3T_EINVAL, P3T_ENOMEM, P3T_ECAPACITY, P3T_ESTATE, P3T_EHIP = 0, -1, -2, -3, -4, -5
+PREC_FP64, PREC_MIXED = 0, 1
+
+ARRAYS = {  # id, dtype, per-row shape, size key
+    "sorted_keys": (0, np.uint64, (), "n"),
+    "perm": (1, np.int32, (), "n"),
+    "node_level": (2, np.int32, (), "n_nodes"),
+    "node_first": (3, np.int32, (), "n_nodes"),
+    "node_count": (4, np.int32, (), "n_nodes"),
+    "node_child": (5, np.int32, (), "n_nodes"),
+    "node_nchild": (6, np.int32, (), "n_nodes"),
+    "node_parent": (7, np.int32, (), "n_nodes"),
+    "node_prefix": (8, np.uint64, (), "n_nodes"),
+    "node_mass": (9, np.float64, (), "n_nodes"),
+    "node_com": (10, np.float64, (3,), "n_nodes"),
+    "node_quad": (11, np.float64, (6,), "n_nodes"),
+    "node_box": (12, np.float64, (6,), "n_nodes"),
+    "group_node": (13, np.int32, (), "n_groups"),
+    "cell_off": (14, np.int64, (), "n_groups+1"),
+    "cell_idx": (15, np.int32, (), "n_cell_entries"),
+    "part_off": (16, np.int64, (), "n_groups+1"),
+    "part_idx": (17, np.int32, (), "n_part_entries"),
+    "root": (18, np.float64, (), "4"),
+}
+
+
+class P3TError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"p3t status {status}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("eps", C.c_double), ("r_in", C.c_double), ("r_out", C.c_double),
+                ("theta", C.c_double), ("r_search", C.c_double), ("n_crit", C.c_int32),
+                ("n_leaf", C.c_int32), ("use_quadrupole", C.c_int32), ("precision", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("n", "n_nodes", "n_leaves", "n_groups", "depth",
+                                         "n_cell_entries", "n_part_entries", "n_near_entries",
+                                         "n_pc", "n_pp", "nnz")] + \
+               [("walk_global_stack", C.c_int32), ("pad_", C.c_int32)] + \
+               [(k, C.c_double) for k in ("ms_build", "ms_force", "ms_neighbors", "ms_vjp")]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+_lib = None
+
+EXPORTS = ("p3t_create", "p3t_destroy", "p3t_check_params", "p3t_build_tree", "p3t_long_force",
+           "p3t_neighbors", "p3t_long_force_vjp", "p3t_kick_drift", "p3t_get_stats",
+           "p3t_copy_array", "p3t_status_string", "p3t_last_error")
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libp3t.so and declare its signatures (no device access)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is not built; run paper_1506_04553_amd/build.py")
+    L = C.CDLL(path)
+    V = C.c_void_p
+    L.p3t_create.argtypes = [C.POINTER(V), C.c_int, V, ALLOC_FN, FREE_FN, V]
+    L.p3t_destroy.argtypes = [V]
+    L.p3t_destroy.restype = None
+    L.p3t_check_params.argtypes = [C.POINTER(Params)]
+    L.p3t_build_tree.argtypes = [V, C.c_int64, V, V, C.POINTER(Params)]
+    L.p3t_long_force.argtypes = [V, V, V]
+    L.p3t_neighbors.argtypes = [V, V, V, C.c_int64, C.POINTER(C.c_int64)]
+    L.p3t_long_force_vjp.argtypes = [V, V, V, V, V]
+    L.p3t_kick_drift.argtypes = [V, C.c_int64, V, V, V, C.c_double, C.c_double]
+    L.p3t_get_stats.argtypes = [V, C.POINTER(Stats)]
+    L.p3t_copy_array.argtypes = [V, C.c_int, V, C.c_int64]
+    L.p3t_status_string.argtypes = [C.c_int]
+    L.p3t_status_string.restype = C.c_char_p
+    L.p3t_last_error.argtypes = [V]
+    L.p3t_last_error.restype = C.c_char_p
+    for f in EXPORTS:
+        if f not in ("p3t_destroy", "p3t_status_string", "p3t_last_error"):
+            getattr(L, f).restype = C.c_int
+    _lib = L
+    return L
+
+
+def make_params(eps, r_in, r_out, theta, r_search, n_crit=64, n_leaf=16, use_quadrupole=1,
+                precision=PREC_FP64, **_ignored) -> Params:
+    if isinstance(precision, str):
+        precision = {"fp64": PREC_FP64, "mixed": PREC_MIXED}[precision]
+    return Params(float(eps), float(r_in), float(r_out), float(theta), float(r_search),
+                  int(n_crit), int(n_leaf), int(use_quadrupole), int(precision))
+
+
+def check_params(**kw) -> int:
+    p = make_params(**kw)
+    return int(load_library().p3t_check_params(C.byref(p)))
+
+
+def _dptr(t: torch.Tensor | None):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class P3T:
+    """One library context on one device and stream (not thread-safe)."""
+
+    def __init__(self, device: int | None = None, stream: torch.cuda.Stream | None = None,
+                 use_torch_allocator: bool = True):
+        self._L = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible")
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        self._allocs = {}
+        if use_torch_allocator:
+            dev, st = self.device, self.stream
+
+            def _alloc(nbytes, _user):
+                try:
+                    p = torch.cuda.caching_allocator_alloc(int(nbytes), dev, st)
+                except Exception:       # out of memory: the library reports ENOMEM
+                    return None
+                return p
+
+            def _free(p, _user):
+                torch.cuda.caching_allocator_delete(int(p))
+
+            self._alloc_cb, self._free_cb = ALLOC_FN(_alloc), FREE_FN(_free)
+        else:
+            self._alloc_cb, self._free_cb = ALLOC_FN(0), FREE_FN(0)
+        h = C.c_void_p()
+        rc = self._L.p3t_create(C.byref(h), self.device, C.c_void_p(self.stream.cuda_stream),
+                                self._alloc_cb, self._free_cb, None)
+        if rc != P3T_OK:
+            raise P3TError(rc, "p3t_create failed")
+        self._h = h
+        self.n = 0
+        self.params = None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.p3t_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int):
+        if rc != P3T_OK:
+            msg = self._L.p3t_last_error(self._h).decode(errors="replace")
+            raise P3TError(rc, msg)
+
+    def _tensor(self, t, shape, name):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+            raise TypeError(f"{name} must be a float64 tensor on the GPU")
+        if t.device.index != self.device:
+            raise ValueError(f"{name} is on device {t.device}, context on cuda:{self.device}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t
+
+    # -- the four calls of the method --------------------------------------
+    def build_tree(self, pos: torch.Tensor, mass: torch.Tensor, **params):
+        n = int(mass.shape[0]) if mass.dim() == 1 else -1
+        self._tensor(pos, (n, 3), "pos")
+        self._tensor(mass, (n,), "mass")
+        p = make_params(**params)
+        self._check(self._L.p3t_build_tree(self._h, n, _dptr(pos), _dptr(mass), C.byref(p)))
+        self.n = n
+        self.params = p
+
+    def long_force(self, acc: torch.Tensor | None = None, pot: torch.Tensor | None = None,
+                   want_pot: bool = True):
+        dev = torch.device("cuda", self.device)
+        if acc is None:
+            acc = torch.empty((self.n, 3), dtype=torch.float64, device=dev)
+        if pot is None and want_pot:
+            pot = torch.empty((self.n,), dtype=torch.float64, device=dev)
+        self._tensor(acc, (self.n, 3), "acc")
+        if pot is not None:
+            self._tensor(pot, (self.n,), "pot")
+        self._check(self._L.p3t_long_force(self._h, _dptr(acc), _dptr(pot)))
+        return acc, pot
+
+    def neighbors(self, cap: int | None = None):
+        """(offsets int64 [n+1], idx int32 [nnz]) on the GPU."""
+        dev = torch.device("cuda", self.device)
+        off = torch.empty((self.n + 1,), dtype=torch.int64, device=dev)
+        cap = max(1024, self.n // 4) if cap is None else int(cap)
+        while True:
+            idx = torch.empty((max(cap, 1),), dtype=torch.int32, device=dev)
+            nnz = C.c_int64(0)
+            rc = self._L.p3t_neighbors(self._h, _dptr(off), _dptr(idx), cap, C.byref(nnz))
+            if rc == P3T_ECAPACITY:
+                cap = int(nnz.value)
+                continue
+            self._check(rc)
+            return off, idx[:nnz.value]
+
+    def long_force_vjp(self, w: torch.Tensor, c: torch.Tensor | None = None):
+        dev = torch.device("cuda", self.device)
+        self._tensor(w, (self.n, 3), "w")
+        if c is not None:
+            self._tensor(c, (self.n,), "c")
+        gpos = torch.empty((self.n, 3), dtype=torch.float64, device=dev)
+        gmass = torch.empty((self.n,), dtype=torch.float64, device=dev)
+        self._check(self._L.p3t_long_force_vjp(self._h, _dptr(w), _dptr(c), _dptr(gpos),
+                                               _dptr(gmass)))
+        return gpos, gmass
+
+    def kick_drift(self, pos, vel, acc, dt_kick: float, dt_drift: float):
+        n = int(pos.shape[0])
+        for t, nm in ((pos, "pos"), (vel, "vel"), (acc, "acc")):
+            self._tensor(t, (n, 3), nm)
+        self._check(self._L.p3t_kick_drift(self._h, n, _dptr(pos), _dptr(vel), _dptr(acc),
+                                           float(dt_kick), float(dt_drift)))
+
+    # -- inspection ---------------------------------------------------------
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(self._L.p3t_get_stats(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats._fields_ if k != "pad_"}
+
+    def copy_array(self, name: str) -> np.ndarray:
+        aid, dt, row, key = ARRAYS[name]
+        st = self.stats()
+        if key == "4":
+            count = 4
+        elif key.endswith("+1"):
+            count = st[key[:-2]] + 1
+        else:
+            count = st[key]
+        out = np.empty((count, *row), dtype=dt)
+        self._check(self._L.p3t_copy_array(self._h, aid, out.ctypes.data_as(C.c_void_p),
+                                           out.nbytes))
+        return out

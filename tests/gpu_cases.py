@@ -1,0 +1,90 @@
+"""Shared helpers for the GPU parity tests: run the HIP path through the C ABI
+and compare every stage with the oracle on the same seeded inputs."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+import oracle
+
+
+def log(msg: str):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_rms(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = float((b ** 2).sum())
+    return float(np.sqrt(((a - b) ** 2).sum() / den)) if den > 0 else float(np.abs(a - b).max())
+
+
+def gpu_run(ctx, pos, mass, params, want_neighbors=True, want_arrays=True):
+    """Build + force (+ neighbours) on the GPU; returns host numpy results."""
+    import torch
+    dev = torch.device("cuda", ctx.device)
+    tp = torch.from_numpy(np.ascontiguousarray(pos)).to(dev)
+    tm = torch.from_numpy(np.ascontiguousarray(mass)).to(dev)
+    ctx.build_tree(tp, tm, **params)
+    acc, pot = ctx.long_force()
+    out = {"acc": acc.cpu().numpy(), "pot": pot.cpu().numpy(), "stats": ctx.stats()}
+    if want_neighbors:
+        off, idx = ctx.neighbors()
+        out["nbr_off"] = off.cpu().numpy()
+        out["nbr_idx"] = idx.cpu().numpy().astype(np.int64)
+    if want_arrays:
+        for k in ("sorted_keys", "perm", "node_level", "node_first", "node_count", "node_child",
+                  "node_nchild", "node_parent", "node_prefix", "node_mass", "node_com",
+                  "node_quad", "node_box", "group_node", "cell_off", "cell_idx", "part_off",
+                  "part_idx", "root"):
+            out[k] = ctx.copy_array(k)
+    return out
+
+
+def compare_tree(g, t: oracle.Tree, groups_sample=None):
+    """Keys, order, topology, moments, groups and lists must match bit for bit."""
+    key, perm = t.keys()
+    lo, L = t.root()
+    assert np.array_equal(g["root"][:3], lo) and g["root"][3] == L
+    np.testing.assert_array_equal(g["perm"].astype(np.int64), perm)
+    np.testing.assert_array_equal(g["sorted_keys"], key[perm])
+    nd = t.nodes()
+    assert len(g["node_level"]) == t.n_nodes, (len(g["node_level"]), t.n_nodes)
+    np.testing.assert_array_equal(g["node_level"], nd["level"])
+    np.testing.assert_array_equal(g["node_first"], nd["first"])
+    np.testing.assert_array_equal(g["node_count"], nd["count"])
+    np.testing.assert_array_equal(g["node_nchild"], nd["n_child"])
+    internal = nd["n_child"] > 0
+    np.testing.assert_array_equal(g["node_child"][internal], nd["child_first"][internal])
+    np.testing.assert_array_equal(g["node_parent"], nd["parent"])
+    np.testing.assert_array_equal(g["node_prefix"], nd["prefix"])
+    mo = t.moments()
+    np.testing.assert_array_equal(g["node_mass"], mo["M"])          # decision-feeding: exact
+    np.testing.assert_array_equal(g["node_com"], mo["com"])
+    np.testing.assert_array_equal(g["node_box"][:, :3], mo["blo"])
+    np.testing.assert_array_equal(g["node_box"][:, 3:], mo["bhi"])
+    qs = np.abs(mo["Q"]).max(axis=1, keepdims=True) + 1e-300
+    assert np.all(np.abs(g["node_quad"] - mo["Q"]) <= 1e-11 * qs + 1e-300)
+    np.testing.assert_array_equal(g["group_node"].astype(np.int64), t.groups())
+    ol = t.lists()
+    G = t.n_groups
+    gs = range(G) if groups_sample is None else groups_sample
+    st = g["stats"]
+    assert st["n_cell_entries"] == ol["c_off"][-1] and st["n_part_entries"] == ol["p_off"][-1]
+    np.testing.assert_array_equal(g["cell_off"], ol["c_off"])
+    np.testing.assert_array_equal(g["part_off"], ol["p_off"])
+    for k in gs:
+        a, b = ol["c_off"][k], ol["c_off"][k + 1]
+        np.testing.assert_array_equal(np.sort(g["cell_idx"][a:b]), ol["c_idx"][a:b])
+        a, b = ol["p_off"][k], ol["p_off"][k + 1]
+        np.testing.assert_array_equal(np.sort(g["part_idx"][a:b]), ol["p_idx"][a:b])
+    cnt = t.counts()
+    assert st["n_pc"] == cnt["n_pc"] and st["n_pp"] == cnt["n_pp"]
+
+
+def compare_neighbors(g, t: oracle.Tree):
+    off, idx = t.neighbors()
+    np.testing.assert_array_equal(g["nbr_off"], off)
+    np.testing.assert_array_equal(g["nbr_idx"], idx)

@@ -1,0 +1,229 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Keys, order, topology, centres of mass, boxes, groups, interaction lists and
+neighbour lists must match bit for bit.  Forces: the FP64 path within 1e-12
+relative RMS (the terms are the same; only rsqrt rounding and summation order
+differ, ~1e-16 per term), the mixed path within the 1e-4 relative RMS bar.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from inputs import WORKLOADS, make_cluster, plummer
+from tests.gpu_cases import compare_neighbors, compare_tree, gpu_run, log, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+MIXED_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1506_04553_amd import P3T
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    c = P3T(0)
+    yield c
+    c.close()
+
+
+def _params(w, **over):
+    p = w.params(**over)
+    return p
+
+
+def _check_forces(g, acc, pot, tol, label, rows=None):
+    ga, gp = g["acc"], g["pot"]
+    if rows is not None:
+        ga, gp, acc, pot = ga[rows], gp[rows], acc[rows], pot[rows]
+    ea, ep = rel_rms(ga, acc), rel_rms(gp, pot)
+    log(f"{label}: acc rel-RMS {ea:.3e}  pot rel-RMS {ep:.3e}")
+    assert ea <= tol and ep <= tol, (ea, ep)
+    return ea, ep
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_plummer4k(ctx, prec):
+    w = WORKLOADS["plummer4k"]
+    c = make_cluster(w, seed=1)
+    p = _params(w, precision=prec)
+    log(f"case plummer4k {prec}")
+    g = gpu_run(ctx, c.pos, c.mass, p)
+    t = oracle.Tree(c.pos, c.mass, p)
+    compare_tree(g, t)
+    acc, pot = t.force()
+    _check_forces(g, acc, pot, FP64_TOL if prec == "fp64" else MIXED_TOL, f"plummer4k {prec}")
+    compare_neighbors(g, t)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_plummer64k_salpeter(ctx, prec):
+    w = WORKLOADS["plummer64k_salpeter"]
+    c = make_cluster(w, seed=1)
+    p = _params(w, precision=prec)
+    log(f"case plummer64k_salpeter {prec}")
+    g = gpu_run(ctx, c.pos, c.mass, p)
+    t = oracle.Tree(c.pos, c.mass, p)
+    compare_tree(g, t)
+    acc, pot = t.force()
+    _check_forces(g, acc, pot, FP64_TOL if prec == "fp64" else MIXED_TOL, f"plummer64k {prec}")
+    compare_neighbors(g, t)
+
+
+def _sampled_neighbors(pos, h, rows):
+    """Exact neighbour rows for a sample of particles: KD-tree candidates, then the
+    FP64 test dx*dx + dy*dy + dz*dz < h*h."""
+    from scipy.spatial import cKDTree
+    kd = cKDTree(pos)
+    out = {}
+    for i in rows:
+        cand = np.array(sorted(kd.query_ball_point(pos[i], h * (1 + 1e-9))), dtype=np.int64)
+        d = pos[cand] - pos[i]
+        r2 = d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] + d[:, 2] * d[:, 2]
+        out[i] = cand[(r2 < h * h) & (cand != i)]
+    return out
+
+
+@pytest.mark.parametrize("name,prec", [("plummer256k", "mixed"), ("king9_1m", "mixed"),
+                                       ("king9_1m", "fp64")])
+def test_large_sampled(ctx, name, prec):
+    w = WORKLOADS[name]
+    c = make_cluster(w, seed=1)
+    p = _params(w, precision=prec)
+    log(f"case {name} {prec} n={w.n}")
+    g = gpu_run(ctx, c.pos, c.mass, p)
+    t = oracle.Tree(c.pos, c.mass, p)
+    rng = np.random.default_rng(5)
+    G = t.n_groups
+    sample = np.unique(np.concatenate([[0, G - 1], rng.choice(G, min(G, 48), replace=False)]))
+    compare_tree(g, t, groups_sample=sample)
+    acc, pot = t.force_groups(sample)
+    rows = np.nonzero(~np.isnan(pot))[0]
+    _check_forces(g, acc, pot, FP64_TOL if prec == "fp64" else MIXED_TOL, f"{name} {prec}", rows)
+    # neighbour rows of particles in the sampled groups against an independent search
+    off, idx = g["nbr_off"], g["nbr_idx"]
+    check = rows[:: max(1, len(rows) // 3000)]
+    ref = _sampled_neighbors(c.pos, p["r_search"], check)
+    for i in check:
+        np.testing.assert_array_equal(idx[off[i]:off[i + 1]], ref[i])
+    # symmetry of the whole CSR
+    rws = np.repeat(np.arange(len(c.mass)), np.diff(off))
+    a = np.sort(rws * len(c.mass) + idx)
+    b = np.sort(idx * len(c.mass) + rws)
+    np.testing.assert_array_equal(a, b)
+
+
+def _edge_cases():
+    rng = np.random.default_rng(11)
+    base = dict(eps=1e-3, r_in=0.002, r_out=0.02, theta=0.5, r_search=0.022, n_crit=64, n_leaf=16)
+    cases = {}
+    cases["n1"] = (np.array([[0.3, -0.2, 0.1]]), np.array([1.0]), base)
+    cases["n2"] = (np.array([[0.0, 0.0, 0.0], [0.01, 0.0, 0.0]]), np.array([0.5, 0.5]), base)
+    cases["coincident"] = (np.full((50, 3), 0.125), np.full(50, 0.02), base)
+    dup = np.repeat(rng.uniform(-1, 1, (40, 3)), 9, axis=0)
+    cases["duplicates"] = (dup, np.full(len(dup), 1.0 / len(dup)), base)
+    big_leaf = np.concatenate([np.full((600, 3), 0.3), rng.normal(0, 0.5, (400, 3))])
+    cases["leaf_over_block"] = (big_leaf, np.full(1000, 1e-3), dict(base, n_crit=32, n_leaf=8))
+    line = np.stack([np.linspace(0, 1, 3000) ** 2, np.zeros(3000), np.zeros(3000)], 1)
+    cases["collinear"] = (line, np.full(3000, 1 / 3000), base)
+    pc = plummer(4097, 12)
+    cases["ragged_4097"] = (pc.pos, pc.mass, dict(base, n_crit=100))
+    cases["leaf1_group1"] = (plummer(700, 13).pos, np.full(700, 1 / 700),
+                             dict(base, n_crit=1, n_leaf=1))
+    cases["theta0"] = (plummer(1500, 14).pos, np.full(1500, 1 / 1500), dict(base, theta=0.0))
+    cases["one_group"] = (plummer(900, 15).pos, np.full(900, 1 / 900), dict(base, n_crit=5000))
+    cases["monopole_rin0"] = (plummer(2500, 16).pos, np.full(2500, 1 / 2500),
+                              dict(base, use_quadrupole=0, r_in=0.0))
+    cases["big_h"] = (plummer(2000, 17).pos, np.full(2000, 1 / 2000),
+                      dict(base, r_out=0.2, r_in=0.02, r_search=0.3, theta=0.7))
+    cases["large_theta"] = (plummer(3000, 18).pos, np.full(3000, 1 / 3000), dict(base, theta=1.5))
+    return cases
+
+
+EDGE = _edge_cases()
+
+
+@pytest.mark.parametrize("name", list(EDGE))
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_edge_cases(ctx, name, prec):
+    pos, mass, p = EDGE[name]
+    p = dict(p, precision=prec)
+    log(f"edge case {name} {prec} n={len(mass)}")
+    g = gpu_run(ctx, pos, mass, p)
+    t = oracle.Tree(pos, mass, p)
+    compare_tree(g, t)
+    acc, pot = t.force()
+    tol = FP64_TOL if prec == "fp64" else MIXED_TOL
+    if np.all(acc == 0) and np.all(pot == 0):
+        assert np.all(g["acc"] == 0) and np.all(g["pot"] == 0)
+    else:
+        _check_forces(g, acc, pot, tol, f"{name} {prec}")
+    compare_neighbors(g, t)
+
+
+def test_forward_is_deterministic(ctx):
+    w = WORKLOADS["plummer64k_salpeter"]
+    c = make_cluster(w, seed=2)
+    for prec in ("fp64", "mixed"):
+        p = _params(w, precision=prec)
+        a = gpu_run(ctx, c.pos, c.mass, p, want_arrays=False)
+        b = gpu_run(ctx, c.pos, c.mass, p, want_arrays=False)
+        assert np.array_equal(a["acc"], b["acc"]) and np.array_equal(a["pot"], b["pot"])
+        assert np.array_equal(a["nbr_idx"], b["nbr_idx"])
+
+
+def test_errors_and_capacity(ctx):
+    import torch
+    from paper_1506_04553_amd import P3T, P3TError
+    from paper_1506_04553_amd.p3t import P3T_ECAPACITY, P3T_EINVAL, P3T_ESTATE
+    fresh = P3T(0)
+    with pytest.raises(P3TError) as e:
+        fresh.long_force(torch.empty((0, 3), dtype=torch.float64, device="cuda"))
+    assert e.value.status in (P3T_ESTATE, P3T_EINVAL)
+    fresh.n = 0
+    import ctypes as C
+    rc = fresh._L.p3t_long_force(fresh._h, None, None)
+    assert rc == P3T_ESTATE
+    c = plummer(3000, 19)
+    pos = torch.from_numpy(c.pos).cuda()
+    mass = torch.from_numpy(c.mass).cuda()
+    p = dict(eps=1e-3, r_in=0.005, r_out=0.05, theta=0.5, r_search=0.055, n_crit=64, n_leaf=16)
+    fresh.build_tree(pos, mass, **p)
+    off, idx = fresh.neighbors()
+    nnz = len(idx)
+    assert nnz > 10
+    o2 = torch.full((3001,), -7, dtype=torch.int64, device="cuda")
+    i2 = torch.empty((5,), dtype=torch.int32, device="cuda")
+    got = C.c_int64(0)
+    rc = fresh._L.p3t_neighbors(fresh._h, C.c_void_p(o2.data_ptr()), C.c_void_p(i2.data_ptr()), 5,
+                                C.byref(got))
+    assert rc == P3T_ECAPACITY and got.value == nnz
+    assert torch.all(o2 == -7)             # untouched on error
+    bad = pos.clone()
+    bad[17, 1] = float("nan")
+    with pytest.raises(P3TError) as e:
+        fresh.build_tree(bad, mass, **p)
+    assert e.value.status == P3T_EINVAL
+    badm = mass.clone()
+    badm[3] = 0.0
+    with pytest.raises(P3TError):
+        fresh.build_tree(pos, badm, **p)
+    with pytest.raises(P3TError):
+        fresh.build_tree(pos, mass, **dict(p, r_in=0.06))
+    # the context stays usable after errors
+    fresh.build_tree(pos, mass, **p)
+    a, _ = fresh.long_force()
+    assert torch.isfinite(a).all()
+    fresh.close()
+
+
+def test_kick_drift(ctx):
+    import torch
+    rng = np.random.default_rng(3)
+    x, v, a = (rng.normal(size=(1001, 3)) for _ in range(3))
+    tx, tv, ta = (torch.from_numpy(q.copy()).cuda() for q in (x, v, a))
+    ctx.kick_drift(tx, tv, ta, 0.125, 0.25)
+    v2 = v + 0.125 * a
+    x2 = x + 0.25 * v2
+    assert np.array_equal(tv.cpu().numpy(), v2) and np.array_equal(tx.cpu().numpy(), x2)
