@@ -67,8 +67,10 @@ typedef struct {
 typedef struct {
     int64_t n, n_nodes, n_leaves, n_groups, depth;
     int64_t n_cell_entries;   /* sum over groups of |C_g| (accepted cells) */
-    int64_t n_part_entries;   /* sum over groups of |P_g| (particles of opened leaves) */
-    int64_t n_near_entries;   /* sum over groups of leaves within h of the group box */
+    int64_t n_part_entries;   /* sum over groups of |F_g|: particles of opened leaves whose box
+                                 is at least max(h, r_out) from the group box */
+    int64_t n_near_entries;   /* sum over groups of |N_g|: particles of the other opened leaves;
+                                 the walk's particle list is P_g = F_g + N_g */
     int64_t n_pc, n_pp;       /* interactions: sum_g n_g |C_g|, sum_g n_g |P_g| */
     int64_t nnz;              /* neighbour pairs found by the last p3t_neighbors */
     int32_t walk_global_stack;/* 1 if the walk needed its global-memory stack */
@@ -159,9 +161,11 @@ enum {
     P3T_ARR_GROUP_NODE = 13,   /* int32  [n_groups] node id, ordered by first particle */
     P3T_ARR_CELL_OFF = 14,     /* int64  [n_groups+1] */
     P3T_ARR_CELL_IDX = 15,     /* int32  [n_cell_entries] node ids */
-    P3T_ARR_PART_OFF = 16,     /* int64  [n_groups+1] */
-    P3T_ARR_PART_IDX = 17,     /* int32  [n_part_entries] sorted particle indices */
-    P3T_ARR_ROOT = 18          /* double [4] lo xyz, side L */
+    P3T_ARR_PART_OFF = 16,     /* int64  [n_groups+1] offsets of F_g */
+    P3T_ARR_PART_IDX = 17,     /* int32  [n_part_entries] sorted particle indices of F_g */
+    P3T_ARR_ROOT = 18,         /* double [4] lo xyz, side L */
+    P3T_ARR_NEAR_OFF = 19,     /* int64  [n_groups+1] offsets of N_g */
+    P3T_ARR_NEAR_IDX = 20      /* int32  [n_near_entries] sorted particle indices of N_g */
 };
 int p3t_copy_array(p3t_ctx *ctx, int which, void *dst, int64_t bytes);
 

@@ -7,19 +7,25 @@
 // with s the softened distance, y = s / r_out, K and W the changeover functions
 // of Section 2.1 (denominator of G read as (gamma - 1)^7).
 //
-// Kernel design (one 256-thread block per group):
-//  * group members are split over the block as (i, slice): a group of n_g
-//    members padded to the next power of two p uses 256/p slices, each slice
-//    walking every (256/p)-th entry of a list tile, so small groups still fill
-//    the block; slice partial sums are reduced in FP64 at the end;
-//  * list entries are staged through LDS in tiles of 256, each entry fetched
-//    from HBM once per group; positions are shifted to the group's box centre
-//    in FP64 while staging (the mixed path then rounds the offsets to FP32);
-//  * K and W differ from 1 only when s < r_out.  The common case evaluates the
-//    plain softened term; a wave-uniform branch, taken only when some lane of
-//    the wave has s < r_out, evaluates K, W and the j == i exclusion.  W's
+// Kernel design (one 256-thread block = 4 wavefronts per group):
+//  * a wavefront lane is (i, slice): 64/s group members times s slices, each
+//    slice taking every s-th entry of a list tile; s (a power of two) is chosen
+//    per group to minimise padded lane work, so groups of any size keep the
+//    lanes busy.  Each lane carries two i-particles (two "virtual wavefronts")
+//    that share every LDS read; slice partial sums are reduced in FP64 with
+//    cross-lane shuffles in a fixed order;
+//  * list entries are staged through LDS in tiles of 256, the next tile being
+//    fetched into registers while the current one is consumed; positions are
+//    shifted to the group's box centre in FP64 while staging (the mixed path
+//    then rounds the offsets to FP32);
+//  * K and W differ from 1 only when s < r_out.  The walk splits the particle
+//    list into far particles (leaf box at least max(h, r_out) from the group
+//    box: K = W = 1, never i itself), evaluated as plain softened terms with no
+//    test at all, and near particles, where a wave-uniform branch taken only
+//    when some lane has s < r_out evaluates K, W and the j == i exclusion.  W's
 //    middle branch is evaluated in FP64 in both paths (its monomial form
-//    cancels by two orders of magnitude);
+//    cancels by two orders of magnitude).  Accepted cells lie at least h from
+//    the group, so their K = W = 1 is tested only when h < r_out;
 //  * the mixed path accumulates each tile in FP32 and adds tile partials to a
 //    compensated (Kahan) FP32 sum per particle and component.
 #include <math.h>
@@ -70,11 +76,6 @@ __device__ __forceinline__ void changeover(R r2, R rinv, const ForceParams &fp, 
     }
 }
 
-template <class R>
-struct Acc4 {
-    R ax = 0, ay = 0, az = 0, ph = 0;
-};
-
 // compensated accumulation of tile partials (FP32); FP64 adds directly
 template <class R>
 struct Sum {
@@ -94,144 +95,297 @@ struct Sum<double> {
     __device__ __forceinline__ double value() const { return s; }
 };
 
+// LDS records: one 128-bit (float) or 2x128-bit (double) read per particle,
+// three / five per cell.
 template <class R>
+struct alignas(4 * sizeof(R)) PJ {
+    R x, y, z, m;
+};
+template <class R>
+struct alignas(4 * sizeof(R)) CJ {
+    R x, y, z, M, qxx, qyy, qzz, qxy, qxz, qyz, pad0, pad1;
+};
+
+// i-particle slot: position offset, tile partials and compensated sums
+template <class R>
+struct Slot {
+    R x, y, z;
+    R ax, ay, az, ph;
+    Sum<R> sx, sy, sz, sp;
+    int32_t i;
+    __device__ __forceinline__ void flush() {
+        sx.add(ax); sy.add(ay); sz.add(az); sp.add(ph);
+        ax = ay = az = ph = R(0);
+    }
+};
+
+template <class R>
+__device__ __forceinline__ void pp_fast(Slot<R> &q, const PJ<R> &j, R eps2) {
+    const R dx = j.x - q.x, dy = j.y - q.y, dz = j.z - q.z;
+    const R r2 = fmaR(dx, dx, fmaR(dy, dy, fmaR(dz, dz, eps2)));
+    const R rinv = rsq(r2);
+    const R mr = j.m * rinv;
+    const R f = mr * (rinv * rinv);
+    q.ax = fmaR(f, dx, q.ax);
+    q.ay = fmaR(f, dy, q.ay);
+    q.az = fmaR(f, dz, q.az);
+    q.ph -= mr;
+}
+
+template <class R>
+__device__ __forceinline__ void pp_full(Slot<R> &q, const PJ<R> &j, int32_t jid, R eps2,
+                                        const ForceParams &fp) {
+    const R dx = j.x - q.x, dy = j.y - q.y, dz = j.z - q.z;
+    const R r2 = fmaR(dx, dx, fmaR(dy, dy, fmaR(dz, dz, eps2)));
+    const R rinv = rsq(r2);
+    R K, Ws;
+    changeover<R>(r2, rinv, fp, K, Ws);
+    if (jid == q.i) { K = R(0); Ws = R(0); }
+    const R f = j.m * K * (rinv * rinv * rinv);
+    q.ax = fmaR(f, dx, q.ax);
+    q.ay = fmaR(f, dy, q.ay);
+    q.az = fmaR(f, dz, q.az);
+    q.ph = fmaR(-j.m, Ws, q.ph);
+}
+
+// cell term; with B = (r.Q.r)/s^4:
+//   phi += -(M + B/2)/s,  a += -(M + 5B/2) r/s^3 + Q r/s^5
+template <class R, bool QUAD, bool CHECK_K>
+__device__ __forceinline__ void pc_term(Slot<R> &q, const CJ<R> &c, R eps2, R rout2,
+                                        const ForceParams &fp) {
+    const R rx = q.x - c.x, ry = q.y - c.y, rz = q.z - c.z;
+    const R r2 = fmaR(rx, rx, fmaR(ry, ry, fmaR(rz, rz, eps2)));
+    const R rinv = rsq(r2);
+    const R u = rinv * rinv;
+    const R rinv3 = rinv * u;
+    R cr, cq = R(0), pot;
+    R Qx = R(0), Qy = R(0), Qz = R(0);
+    if (QUAD) {
+        Qx = fmaR(c.qxx, rx, fmaR(c.qxy, ry, c.qxz * rz));
+        Qy = fmaR(c.qxy, rx, fmaR(c.qyy, ry, c.qyz * rz));
+        Qz = fmaR(c.qxz, rx, fmaR(c.qyz, ry, c.qzz * rz));
+        const R rQr = fmaR(rx, Qx, fmaR(ry, Qy, rz * Qz));
+        const R B = rQr * (u * u);
+        pot = fmaR(B, R(-0.5), -c.M) * rinv;
+        cr = fmaR(B, R(2.5), c.M) * (-rinv3);
+        cq = rinv3 * u;
+    } else {
+        pot = -c.M * rinv;
+        cr = -c.M * rinv3;
+    }
+    if (CHECK_K) {
+        if (ballot(r2 < rout2)) {
+            R K, Ws;
+            changeover<R>(r2, rinv, fp, K, Ws);
+            const R W = Ws * r2 * rinv;   // W(y) = (W/s) s
+            cr *= K;
+            cq *= K;
+            pot *= W;
+        }
+    }
+    if (QUAD) {
+        q.ax = fmaR(cr, rx, fmaR(cq, Qx, q.ax));
+        q.ay = fmaR(cr, ry, fmaR(cq, Qy, q.ay));
+        q.az = fmaR(cr, rz, fmaR(cq, Qz, q.az));
+    } else {
+        q.ax = fmaR(cr, rx, q.ax);
+        q.ay = fmaR(cr, ry, q.ay);
+        q.az = fmaR(cr, rz, q.az);
+    }
+    q.ph += pot;
+}
+
+// Per-tile loops of one wavefront over its slice of the staged entries, for
+// one or two active i-slots (TWO), so that the loop bodies carry no branch on
+// the slot count.
+template <class R, bool TWO>
+__device__ __forceinline__ void far_tile(Slot<R> *q, const PJ<R> *sp, int tl, int slice, int ns,
+                                         R eps2) {
+    for (int k = slice; k < tl; k += ns) {
+        const PJ<R> pj = sp[k];
+        pp_fast<R>(q[0], pj, eps2);
+        if (TWO) pp_fast<R>(q[1], pj, eps2);
+    }
+}
+
+template <class R, bool TWO>
+__device__ __forceinline__ void near_tile(Slot<R> *q, const PJ<R> *sp, const int32_t *sj, int tl,
+                                          int slice, int ns, R eps2, R rout2,
+                                          const ForceParams &fp) {
+    for (int k = slice; k < tl; k += ns) {
+        const PJ<R> pj = sp[k];
+        const R dx0 = pj.x - q[0].x, dy0 = pj.y - q[0].y, dz0 = pj.z - q[0].z;
+        bool nr = fmaR(dx0, dx0, fmaR(dy0, dy0, fmaR(dz0, dz0, eps2))) < rout2;
+        if (TWO) {
+            const R dx1 = pj.x - q[1].x, dy1 = pj.y - q[1].y, dz1 = pj.z - q[1].z;
+            nr = nr | (fmaR(dx1, dx1, fmaR(dy1, dy1, fmaR(dz1, dz1, eps2))) < rout2);
+        }
+        if (ballot(nr)) {
+            const int32_t jid = sj[k];
+            pp_full<R>(q[0], pj, jid, eps2, fp);
+            if (TWO) pp_full<R>(q[1], pj, jid, eps2, fp);
+        } else {
+            pp_fast<R>(q[0], pj, eps2);
+            if (TWO) pp_fast<R>(q[1], pj, eps2);
+        }
+    }
+}
+
+template <class R, bool QUAD, bool CHECK_K, bool TWO>
+__device__ __forceinline__ void cell_tile(Slot<R> *q, const CJ<R> *sc, int tl, int slice, int ns,
+                                          R eps2, R rout2, const ForceParams &fp) {
+    for (int k = slice; k < tl; k += ns) {
+        const CJ<R> cj = sc[k];
+        pc_term<R, QUAD, CHECK_K>(q[0], cj, eps2, rout2, fp);
+        if (TWO) pc_term<R, QUAD, CHECK_K>(q[1], cj, eps2, rout2, fp);
+    }
+}
+
+// Slices per wavefront for a group of n members: s slices of 64/s i-particles,
+// V = ceil(n s / 64) virtual wavefronts, 8 per round (4 wavefronts x 2 slots);
+// minimise issued lane work V * 64 / s, with a small charge per extra round.
+__device__ __forceinline__ int choose_log2_slices(int n) {
+    int best = 0;
+    float best_cost = 1e30f;
+    for (int ls = 0; ls <= 6; ++ls) {
+        const int nw = kWave >> ls;
+        const int V = (n + nw - 1) / nw;
+        const int rounds = (V + 7) / 8;
+        const float cost = (float)V * (float)nw * (1.0f + 0.05f * (float)(rounds - 1));
+        if (cost < best_cost - 1e-3f) {
+            best_cost = cost;
+            best = ls;
+        }
+    }
+    return best;
+}
+
+template <class R, bool QUAD, bool CHECK_K>
 __global__ __launch_bounds__(kForceThreads) void k_force(
     const GroupInfo *__restrict__ grp, const int64_t *__restrict__ p_off,
-    const int32_t *__restrict__ p_idx, const int64_t *__restrict__ c_off,
+    const int32_t *__restrict__ p_idx, const int64_t *__restrict__ n_off,
+    const int32_t *__restrict__ n_idx, const int64_t *__restrict__ c_off,
     const int32_t *__restrict__ c_idx, const double *__restrict__ x, const double *__restrict__ y,
     const double *__restrict__ z, const double *__restrict__ m, const NodeMP *__restrict__ mp,
     const int32_t *__restrict__ perm, ForceParams fp, double *__restrict__ acc,
     double *__restrict__ pot) {
-    __shared__ R s_px[kTile], s_py[kTile], s_pz[kTile], s_pm[kTile];
+    __shared__ PJ<R> s_p[kTile];
     __shared__ int32_t s_jid[kTile];
-    __shared__ R s_c[10][kTile];
-    __shared__ double s_red[4][kForceThreads];
+    __shared__ CJ<R> s_c[kTile];
 
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
     const GroupInfo gi = grp[blockIdx.x];
     const double gcx = gi.c[0], gcy = gi.c[1], gcz = gi.c[2];
     const int64_t pb = p_off[blockIdx.x], pe = p_off[blockIdx.x + 1];
+    const int64_t nb = n_off[blockIdx.x], ne = n_off[blockIdx.x + 1];
     const int64_t cb = c_off[blockIdx.x], ce = c_off[blockIdx.x + 1];
     const R eps2 = (R)fp.eps2, rout2 = (R)fp.rout2;
 
-    for (int chunk = 0; chunk < gi.count; chunk += kForceThreads) {
-        const int nc = min(kForceThreads, gi.count - chunk);
-        int lg = 0;
-        while ((1 << lg) < nc) ++lg;
-        const int pad = 1 << lg;
-        const int nslice = kForceThreads >> lg;
-        const int li = tid & (pad - 1), slice = tid >> lg;
-        const bool ivalid = li < nc;
-        const int32_t i = gi.first + chunk + (ivalid ? li : 0);
-        // far-away dummy position for padding lanes: every term is ~0 and stays finite
-        const R xi = ivalid ? (R)(x[i] - gcx) : R(1e18), yi = ivalid ? (R)(y[i] - gcy) : R(1e18),
-                zi = ivalid ? (R)(z[i] - gcz) : R(1e18);
-        Sum<R> sx, sy, sz, sp;
+    const int ls = choose_log2_slices(gi.count);
+    const int ns = 1 << ls;
+    const int nw = kWave >> ls;                 // i-particles per virtual wavefront
+    const int il = lane & (nw - 1), slice = lane >> (6 - ls);
+    const int V = (gi.count + nw - 1) / nw;
 
-        // ---- particle-particle terms ----
-        for (int64_t t0 = pb; t0 < pe; t0 += kTile) {
-            const int tl = (int)min<int64_t>(kTile, pe - t0);
-            __syncthreads();
-            if (tid < tl) {
-                const int32_t j = p_idx[t0 + tid];
-                s_px[tid] = (R)(x[j] - gcx);
-                s_py[tid] = (R)(y[j] - gcy);
-                s_pz[tid] = (R)(z[j] - gcz);
-                s_pm[tid] = (R)m[j];
-                s_jid[tid] = j;
-            }
-            __syncthreads();
-            Acc4<R> a;
-            for (int k = slice; k < tl; k += nslice) {
-                const R dx = s_px[k] - xi, dy = s_py[k] - yi, dz = s_pz[k] - zi;
-                const R mj = s_pm[k];
-                const R r2 = fmaR(dx, dx, fmaR(dy, dy, fmaR(dz, dz, eps2)));
-                const R rinv = rsq(r2);
-                if (ballot(r2 < rout2)) {
-                    R K, Ws;
-                    changeover<R>(r2, rinv, fp, K, Ws);
-                    if (s_jid[k] == i) { K = R(0); Ws = R(0); }
-                    const R f = mj * K * rinv * rinv * rinv;
-                    a.ax = fmaR(f, dx, a.ax);
-                    a.ay = fmaR(f, dy, a.ay);
-                    a.az = fmaR(f, dz, a.az);
-                    a.ph = fmaR(-mj, Ws, a.ph);
-                } else {
-                    const R mr = mj * rinv;
-                    const R f = mr * rinv * rinv;
-                    a.ax = fmaR(f, dx, a.ax);
-                    a.ay = fmaR(f, dy, a.ay);
-                    a.az = fmaR(f, dz, a.az);
-                    a.ph -= mr;
-                }
-            }
-            sx.add(a.ax); sy.add(a.ay); sz.add(a.az); sp.add(a.ph);
+    for (int v0 = 0; v0 < V; v0 += 8) {
+        // this wavefront's two virtual wavefronts in this round
+        const bool act0 = v0 + w < V, act1 = v0 + 4 + w < V;
+        Slot<R> q[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int v = v0 + 4 * k + w;
+            const int li = v * nw + il;
+            const bool valid = (k == 0 ? act0 : act1) && li < gi.count;
+            const int32_t i = gi.first + (valid ? li : 0);
+            q[k].i = valid ? i : -1;
+            // padding lanes sit far away: every term stays finite and is discarded
+            q[k].x = valid ? (R)(x[i] - gcx) : R(1e18);
+            q[k].y = valid ? (R)(y[i] - gcy) : R(1e18);
+            q[k].z = valid ? (R)(z[i] - gcz) : R(1e18);
+            q[k].ax = q[k].ay = q[k].az = q[k].ph = R(0);
         }
+
+        // ---- particle-particle terms, tiles staged through LDS; the next tile is
+        //      fetched into registers while the current one is consumed ----
+        auto stream_particles = [&](const int32_t *list, int64_t b, int64_t e, auto &&consume) {
+            PJ<R> pre{};
+            int32_t prej = 0;
+            if (b + tid < e) {
+                prej = list[b + tid];
+                pre = PJ<R>{(R)(x[prej] - gcx), (R)(y[prej] - gcy), (R)(z[prej] - gcz), (R)m[prej]};
+            }
+            for (int64_t t0 = b; t0 < e; t0 += kTile) {
+                const int tl = (int)min<int64_t>(kTile, e - t0);
+                __syncthreads();
+                s_p[tid] = pre;
+                s_jid[tid] = prej;
+                __syncthreads();
+                if (t0 + kTile + tid < e) {
+                    prej = list[t0 + kTile + tid];
+                    pre = PJ<R>{(R)(x[prej] - gcx), (R)(y[prej] - gcy), (R)(z[prej] - gcz),
+                                (R)m[prej]};
+                }
+                consume(tl);
+                if (act0) q[0].flush();
+                if (act1) q[1].flush();
+            }
+        };
+        // far particles: K = W = 1 and j != i, plain softened terms
+        stream_particles(p_idx, pb, pe, [&](int tl) {
+            if (act1) far_tile<R, true>(q, s_p, tl, slice, ns, eps2);
+            else if (act0) far_tile<R, false>(q, s_p, tl, slice, ns, eps2);
+        });
+        // near particles: changeover and self exclusion where s < r_out
+        stream_particles(n_idx, nb, ne, [&](int tl) {
+            if (act1) near_tile<R, true>(q, s_p, s_jid, tl, slice, ns, eps2, rout2, fp);
+            else if (act0) near_tile<R, false>(q, s_p, s_jid, tl, slice, ns, eps2, rout2, fp);
+        });
 
         // ---- particle-cell terms ----
-        for (int64_t t0 = cb; t0 < ce; t0 += kTile) {
-            const int tl = (int)min<int64_t>(kTile, ce - t0);
-            __syncthreads();
-            if (tid < tl) {
-                const NodeMP c = mp[c_idx[t0 + tid]];
-                s_c[0][tid] = (R)(c.cx - gcx);
-                s_c[1][tid] = (R)(c.cy - gcy);
-                s_c[2][tid] = (R)(c.cz - gcz);
-                s_c[3][tid] = (R)c.M;
-                for (int q = 0; q < 6; ++q) s_c[4 + q][tid] = fp.use_quad ? (R)c.q[q] : R(0);
+        {
+            CJ<R> pre{};
+            auto load_cell = [&](int64_t e) {
+                const NodeMP c = mp[c_idx[e]];
+                CJ<R> r;
+                r.x = (R)(c.cx - gcx); r.y = (R)(c.cy - gcy); r.z = (R)(c.cz - gcz); r.M = (R)c.M;
+                r.qxx = (R)c.q[0]; r.qyy = (R)c.q[1]; r.qzz = (R)c.q[2];
+                r.qxy = (R)c.q[3]; r.qxz = (R)c.q[4]; r.qyz = (R)c.q[5];
+                r.pad0 = r.pad1 = R(0);
+                return r;
+            };
+            if (cb + tid < ce) pre = load_cell(cb + tid);
+            for (int64_t t0 = cb; t0 < ce; t0 += kTile) {
+                const int tl = (int)min<int64_t>(kTile, ce - t0);
+                __syncthreads();
+                s_c[tid] = pre;
+                __syncthreads();
+                if (t0 + kTile + tid < ce) pre = load_cell(t0 + kTile + tid);
+                if (act1) cell_tile<R, QUAD, CHECK_K, true>(q, s_c, tl, slice, ns, eps2, rout2, fp);
+                else if (act0) cell_tile<R, QUAD, CHECK_K, false>(q, s_c, tl, slice, ns, eps2, rout2, fp);
+                if (act0) q[0].flush();
+                if (act1) q[1].flush();
             }
-            __syncthreads();
-            Acc4<R> a;
-            for (int k = slice; k < tl; k += nslice) {
-                const R rx = xi - s_c[0][k], ry = yi - s_c[1][k], rz = zi - s_c[2][k];
-                const R M = s_c[3][k];
-                const R r2 = fmaR(rx, rx, fmaR(ry, ry, fmaR(rz, rz, eps2)));
-                const R rinv = rsq(r2);
-                const R rinv2 = rinv * rinv;
-                const R rinv3 = rinv * rinv2;
-                const R qxx = s_c[4][k], qyy = s_c[5][k], qzz = s_c[6][k];
-                const R qxy = s_c[7][k], qxz = s_c[8][k], qyz = s_c[9][k];
-                const R Qx = fmaR(qxx, rx, fmaR(qxy, ry, qxz * rz));
-                const R Qy = fmaR(qxy, rx, fmaR(qyy, ry, qyz * rz));
-                const R Qz = fmaR(qxz, rx, fmaR(qyz, ry, qzz * rz));
-                const R rQr = fmaR(rx, Qx, fmaR(ry, Qy, rz * Qz));
-                const R rinv5 = rinv3 * rinv2;
-                const R rinv7 = rinv5 * rinv2;
-                R fa = fmaR(R(-2.5) * rQr, rinv7, -M * rinv3);   // coefficient of r
-                R fq = rinv5;                                     // coefficient of Q r
-                R pp = fmaR(R(-0.5) * rQr, rinv5, -M * rinv);
-                if (ballot(r2 < rout2)) {
-                    R K, Ws;
-                    changeover<R>(r2, rinv, fp, K, Ws);
-                    const R W = Ws * r2 * rinv;            // W(y) = (W/s) s
-                    fa *= K;
-                    fq *= K;
-                    pp *= W;
-                }
-                a.ax = fmaR(fa, rx, fmaR(fq, Qx, a.ax));
-                a.ay = fmaR(fa, ry, fmaR(fq, Qy, a.ay));
-                a.az = fmaR(fa, rz, fmaR(fq, Qz, a.az));
-                a.ph += pp;
-            }
-            sx.add(a.ax); sy.add(a.ay); sz.add(a.az); sp.add(a.ph);
         }
 
-        // ---- reduce the slices of each particle in FP64, fixed order ----
-        __syncthreads();
-        s_red[0][tid] = sx.value();
-        s_red[1][tid] = sy.value();
-        s_red[2][tid] = sz.value();
-        s_red[3][tid] = sp.value();
-        __syncthreads();
-        if (slice == 0 && ivalid) {
-            double r[4] = {0, 0, 0, 0};
-            for (int s = 0; s < nslice; ++s)
-                for (int q = 0; q < 4; ++q) r[q] += s_red[q][s * pad + li];
-            const int64_t o = perm[i];
-            acc[3 * o] = r[0];
-            acc[3 * o + 1] = r[1];
-            acc[3 * o + 2] = r[2];
-            if (pot) pot[o] = r[3];
+        // ---- reduce the slices of each particle in FP64 (fixed order), write ----
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            if (!(k == 0 ? act0 : act1)) continue;
+            double r0 = q[k].sx.value(), r1 = q[k].sy.value(), r2 = q[k].sz.value(),
+                   r3 = q[k].sp.value();
+            for (int d = nw; d < kWave; d <<= 1) {
+                r0 += __shfl_xor(r0, d, kWave);
+                r1 += __shfl_xor(r1, d, kWave);
+                r2 += __shfl_xor(r2, d, kWave);
+                r3 += __shfl_xor(r3, d, kWave);
+            }
+            if (slice == 0 && q[k].i >= 0) {
+                const int64_t o = perm[q[k].i];
+                acc[3 * o] = r0;
+                acc[3 * o + 1] = r1;
+                acc[3 * o + 2] = r2;
+                if (pot) pot[o] = r3;
+            }
         }
     }
 }
@@ -251,23 +405,34 @@ static ForceParams force_params(const p3t_ctx *ctx) {
     return fp;
 }
 
+template <class R, bool QUAD, bool CHECK_K>
+static void launch_force_t(p3t_ctx *ctx, const ForceParams &fp, double *acc, double *pot) {
+    const int64_t stride = ctx->n_nodes + 1;
+    const int64_t *off = ptr<int64_t>(ctx->off);
+    k_force<R, QUAD, CHECK_K><<<(unsigned)ctx->n_groups, kForceThreads, 0, ctx->stream>>>(
+        ptr<GroupInfo>(ctx->grp), off + stride, ptr<int32_t>(ctx->p_idx), off + 2 * stride,
+        ptr<int32_t>(ctx->n_idx), off,
+        ptr<int32_t>(ctx->c_idx), ptr<double>(ctx->x), ptr<double>(ctx->y), ptr<double>(ctx->z),
+        ptr<double>(ctx->m), ptr<NodeMP>(ctx->node_mp), ptr<int32_t>(ctx->vals[0]), fp, acc, pot);
+}
+
+template <class R>
+static void launch_force_r(p3t_ctx *ctx, const ForceParams &fp, double *acc, double *pot) {
+    // accepted cells lie at least h away from every group member, so K = W = 1
+    // on every cell term whenever h >= r_out
+    const bool check_k = ctx->prm.r_search < ctx->prm.r_out;
+    const bool quad = ctx->prm.use_quadrupole != 0;
+    if (quad && !check_k) launch_force_t<R, true, false>(ctx, fp, acc, pot);
+    else if (quad) launch_force_t<R, true, true>(ctx, fp, acc, pot);
+    else if (!check_k) launch_force_t<R, false, false>(ctx, fp, acc, pot);
+    else launch_force_t<R, false, true>(ctx, fp, acc, pot);
+}
+
 int launch_force(p3t_ctx *ctx, double *acc, double *pot) {
     const ForceParams fp = force_params(ctx);
     if (ctx->n_groups <= 0) return P3T_OK;
-    const unsigned grid = (unsigned)ctx->n_groups;
-    const int64_t stride = ctx->n_nodes + 1;
-    const int64_t *off = ptr<int64_t>(ctx->off);
-    if (ctx->prm.precision == P3T_PREC_MIXED) {
-        k_force<float><<<grid, kForceThreads, 0, ctx->stream>>>(
-            ptr<GroupInfo>(ctx->grp), off + stride, ptr<int32_t>(ctx->p_idx), off,
-            ptr<int32_t>(ctx->c_idx), ptr<double>(ctx->x), ptr<double>(ctx->y), ptr<double>(ctx->z),
-            ptr<double>(ctx->m), ptr<NodeMP>(ctx->node_mp), ptr<int32_t>(ctx->vals[0]), fp, acc, pot);
-    } else {
-        k_force<double><<<grid, kForceThreads, 0, ctx->stream>>>(
-            ptr<GroupInfo>(ctx->grp), off + stride, ptr<int32_t>(ctx->p_idx), off,
-            ptr<int32_t>(ctx->c_idx), ptr<double>(ctx->x), ptr<double>(ctx->y), ptr<double>(ctx->z),
-            ptr<double>(ctx->m), ptr<NodeMP>(ctx->node_mp), ptr<int32_t>(ctx->vals[0]), fp, acc, pot);
-    }
+    if (ctx->prm.precision == P3T_PREC_MIXED) launch_force_r<float>(ctx, fp, acc, pot);
+    else launch_force_r<double>(ctx, fp, acc, pot);
     return check_hip(ctx, hipGetLastError(), "force");
 }
 

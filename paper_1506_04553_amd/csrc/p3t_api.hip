@@ -318,6 +318,8 @@ extern "C" int p3t_copy_array(p3t_ctx *ctx, int which, void *dst, int64_t bytes)
     case P3T_ARR_PART_OFF: src = (const int64_t *)ctx->off.p + stride; size = (G + 1) * 8; break;
     case P3T_ARR_PART_IDX: src = ctx->p_idx.p; size = ctx->n_part_entries * 4; break;
     case P3T_ARR_ROOT: src = ctx->root.p; size = 32; break;
+    case P3T_ARR_NEAR_OFF: src = (const int64_t *)ctx->off.p + 2 * stride; size = (G + 1) * 8; break;
+    case P3T_ARR_NEAR_IDX: src = ctx->n_idx.p; size = ctx->n_near_entries * 4; break;
     default: return set_error(ctx, P3T_EINVAL, "unknown array id %d", which);
     }
     if (rows) size = rows * pitch;

@@ -78,13 +78,30 @@ __global__ __launch_bounds__(kRedThreads) void k_bbox_partial(const double *__re
     }
 }
 
-__global__ void k_bbox_final(const double *partial, int nb, const int32_t *bad, RootInfo *root) {
-    if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(kRedThreads) void k_bbox_final(const double *partial, int nb,
+                                                            const int32_t *bad, RootInfo *root) {
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int b = 0; b < nb; ++b)
+    for (int b = threadIdx.x; b < nb; b += blockDim.x)
         for (int a = 0; a < 3; ++a) {
             lo[a] = fmin(lo[a], partial[6 * b + a]);
             hi[a] = fmax(hi[a], partial[6 * b + 3 + a]);
+        }
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fmin(lo[a], __shfl_xor(lo[a], d, kWave));
+            hi[a] = fmax(hi[a], __shfl_xor(hi[a], d, kWave));
+        }
+    __shared__ double s[kRedThreads / kWave][6];
+    const int w = threadIdx.x / kWave;
+    if (threadIdx.x % kWave == 0)
+        for (int a = 0; a < 3; ++a) { s[w][a] = lo[a]; s[w][3 + a] = hi[a]; }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int k = 1; k < kRedThreads / kWave; ++k)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fmin(lo[a], s[k][a]);
+            hi[a] = fmax(hi[a], s[k][3 + a]);
         }
     double ext = 0.0;
     for (int a = 0; a < 3; ++a) {
@@ -147,7 +164,7 @@ int build_root_keys(p3t_ctx *ctx, const double *pos, const double *mass, int64_t
         return rc;
     double *partial = ptr<double>(ctx->bbox);
     k_bbox_partial<<<nb, kRedThreads, 0, ctx->stream>>>(pos, mass, n, partial, flags);
-    k_bbox_final<<<1, 64, 0, ctx->stream>>>(partial, nb, flags, ptr<RootInfo>(ctx->root));
+    k_bbox_final<<<1, kRedThreads, 0, ctx->stream>>>(partial, nb, flags, ptr<RootInfo>(ctx->root));
     k_keys<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(pos, n, ptr<RootInfo>(ctx->root),
                                                          ptr<uint64_t>(ctx->keys[0]),
                                                          ptr<int32_t>(ctx->vals[0]));

@@ -2,9 +2,11 @@
 // theta, walked once per group).  One wavefront walks the tree for one group
 // and emits three lists:
 //   C_g  accepted cells (multipole interactions),
-//   P_g  particles of opened leaves (direct interactions),
-//   N_g  opened leaves whose box lies closer than h to the group box (the only
-//        leaves that can hold neighbours of the group's particles).
+//   F_g  particles of opened leaves whose box is at least h* = max(h, r_out)
+//        away from the group box: for them K = W = 1 and j != i,
+//   N_g  particles of the other opened leaves: the only candidates for
+//        neighbours of the group's particles and for K, W < 1.
+// The particle list P_g of the method is F_g + N_g.
 // A cell c is accepted iff theta^2 * D^2(com_c, box_g) > side_c^2 and
 // B^2(box_c, box_g) >= h^2, with D the point-to-box and B the box-to-box gap
 // distance, each summed as (tx*tx + ty*ty) + tz*tz over per-axis gaps
@@ -27,7 +29,7 @@ constexpr int kLdsStack = 2048;
 constexpr int kGlobalStack = kLevels * 8 * kWave + kWave;
 
 struct WalkParams {
-    double th2, h2;
+    double th2, h2, hn2;   // theta^2, h^2, max(h, r_out)^2
 };
 
 __device__ __forceinline__ double gap(double u, double v) {
@@ -76,33 +78,38 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(
                 const double B2 = b0 * b0 + b1 * b1 + b2 * b2;
                 acc = (wp.th2 * D2 > nd.l2) && (B2 >= wp.h2);
                 leaf = nd.n_child == 0;
-                near = B2 < wp.h2;
+                near = B2 < wp.hn2;
                 first = nd.first;
                 count = nd.count;
                 cf = nd.child_first;
                 ncld = nd.n_child;
             }
             const bool isC = node >= 0 && acc;
-            const bool isP = node >= 0 && !acc && leaf;
             const bool isO = node >= 0 && !acc && !leaf;
-            const bool isN = isP && near;
+            const bool isF = node >= 0 && !acc && leaf && !near;
+            const bool isN = node >= 0 && !acc && leaf && near;
             // accepted cells
             const uint64_t mC = ballot(isC);
             if (EMIT && isC) c_idx[oc + nc + count_below(mC)] = node;
             nc += __popcll(mC);
-            // particles of opened leaves
-            const int pcnt = isP ? count : 0;
+            // particles of far opened leaves
+            const int pcnt = isF ? count : 0;
             const int pincl = wave_incl_scan(pcnt);
             const int ptot = __shfl(pincl, kWave - 1, kWave);
-            if (EMIT && isP) {
+            if (EMIT && isF) {
                 int32_t *dst = p_idx + op + np + (pincl - pcnt);
                 for (int t = 0; t < pcnt; ++t) dst[t] = first + t;
             }
             np += ptot;
-            // near leaves
-            const uint64_t mN = ballot(isN);
-            if (EMIT && isN) n_idx[on + nn + count_below(mN)] = node;
-            nn += __popcll(mN);
+            // particles of near opened leaves
+            const int ncnt = isN ? count : 0;
+            const int nincl = wave_incl_scan(ncnt);
+            const int ntot = __shfl(nincl, kWave - 1, kWave);
+            if (EMIT && isN) {
+                int32_t *dst = n_idx + on + nn + (nincl - ncnt);
+                for (int t = 0; t < ncnt; ++t) dst[t] = first + t;
+            }
+            nn += ntot;
             // children of opened internal nodes
             const int ocnt = isO ? ncld : 0;
             const int oincl = wave_incl_scan(ocnt);
@@ -128,7 +135,7 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(
             cnt_p[g] = np;
             cnt_n[g] = nn;
             atomicAdd(&inter[0], (unsigned long long)(gi.count * nc));
-            atomicAdd(&inter[1], (unsigned long long)(gi.count * np));
+            atomicAdd(&inter[1], (unsigned long long)(gi.count * (np + nn)));
         }
     }
 }
@@ -148,7 +155,9 @@ int build_lists(p3t_ctx *ctx) {
     int64_t *rb = ptr<int64_t>(ctx->readback);
     int32_t *flags = ptr<int32_t>(ctx->dflags);
     const int32_t *G_dev = ptr<int32_t>(ctx->gscan) + ctx->n;
-    const WalkParams wp{ctx->prm.theta * ctx->prm.theta, ctx->prm.r_search * ctx->prm.r_search};
+    const double hn = ctx->prm.r_search > ctx->prm.r_out ? ctx->prm.r_search : ctx->prm.r_out;
+    const WalkParams wp{ctx->prm.theta * ctx->prm.theta, ctx->prm.r_search * ctx->prm.r_search,
+                        hn * hn};
     const unsigned grid = walk_grid(ctx);
 
     for (int attempt = 0; attempt < 2; ++attempt) {

@@ -41,6 +41,8 @@ ARRAYS = {  # id, dtype, per-row shape, size key
     "part_off": (16, np.int64, (), "n_groups+1"),
     "part_idx": (17, np.int32, (), "n_part_entries"),
     "root": (18, np.float64, (), "4"),
+    "near_off": (19, np.int64, (), "n_groups+1"),
+    "near_idx": (20, np.int32, (), "n_near_entries"),
 }
 
 
@@ -157,6 +159,7 @@ class P3T:
         self._h = h
         self.n = 0
         self.params = None
+        self.build_id = 0
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -191,6 +194,7 @@ class P3T:
         self._tensor(pos, (n, 3), "pos")
         self._tensor(mass, (n,), "mass")
         p = make_params(**params)
+        self.build_id += 1
         self._check(self._L.p3t_build_tree(self._h, n, _dptr(pos), _dptr(mass), C.byref(p)))
         self.n = n
         self.params = p

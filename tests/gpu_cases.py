@@ -38,7 +38,7 @@ def gpu_run(ctx, pos, mass, params, want_neighbors=True, want_arrays=True):
         for k in ("sorted_keys", "perm", "node_level", "node_first", "node_count", "node_child",
                   "node_nchild", "node_parent", "node_prefix", "node_mass", "node_com",
                   "node_quad", "node_box", "group_node", "cell_off", "cell_idx", "part_off",
-                  "part_idx", "root"):
+                  "part_idx", "near_off", "near_idx", "root"):
             out[k] = ctx.copy_array(k)
     return out
 
@@ -72,14 +72,18 @@ def compare_tree(g, t: oracle.Tree, groups_sample=None):
     G = t.n_groups
     gs = range(G) if groups_sample is None else groups_sample
     st = g["stats"]
-    assert st["n_cell_entries"] == ol["c_off"][-1] and st["n_part_entries"] == ol["p_off"][-1]
+    assert st["n_cell_entries"] == ol["c_off"][-1]
+    assert st["n_part_entries"] + st["n_near_entries"] == ol["p_off"][-1]
     np.testing.assert_array_equal(g["cell_off"], ol["c_off"])
-    np.testing.assert_array_equal(g["part_off"], ol["p_off"])
+    np.testing.assert_array_equal(np.diff(g["part_off"]) + np.diff(g["near_off"]), np.diff(ol["p_off"]))
     for k in gs:
         a, b = ol["c_off"][k], ol["c_off"][k + 1]
         np.testing.assert_array_equal(np.sort(g["cell_idx"][a:b]), ol["c_idx"][a:b])
+        # the walk's particle list P_g is the union of the far and near parts
+        far = g["part_idx"][g["part_off"][k]:g["part_off"][k + 1]]
+        near = g["near_idx"][g["near_off"][k]:g["near_off"][k + 1]]
         a, b = ol["p_off"][k], ol["p_off"][k + 1]
-        np.testing.assert_array_equal(np.sort(g["part_idx"][a:b]), ol["p_idx"][a:b])
+        np.testing.assert_array_equal(np.sort(np.concatenate([far, near])), ol["p_idx"][a:b])
     cnt = t.counts()
     assert st["n_pc"] == cnt["n_pc"] and st["n_pp"] == cnt["n_pp"]
 
