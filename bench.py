@@ -17,6 +17,7 @@ kernel), timed with HIP events on the stream it runs on.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -30,11 +31,54 @@ sys.path.insert(0, ROOT)
 
 METRIC = "long-range interactions/s & ms per leapfrog step at N=1M, FP32 vs FP64, RMS err"
 PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}     # MI355X vector FP32 (packed) / FP64
+# Without packed FP32 instructions (not generated: the library is built without
+# them) one FP32 FMA per lane per cycle is the ceiling: 256 CUs x 4 SIMDs x
+# 16 lanes x 2 flops x 2.4 GHz.
+PEAK_UNPACKED_FP32 = 78.6
 # Algorithmic flops per interaction of the common path (FMA = 2, add/sub/mul = 1,
-# rsqrt = 4); see the design doc for the itemisation.
+# rsqrt = 4):
+#   particle: 3 differences, r^2 (3 FMA), rsqrt, m/s, 1/s^2, m/s^3, 3 FMA into a,
+#             1 into phi                                                 = 23
+#   cell (quadrupole): 3 differences, r^2, rsqrt, 1/s^2, 1/s^3, Q r (3 mul +
+#             6 FMA), r.Q.r (1 mul + 2 FMA), 1/s^4, B, phi factor (FMA + mul),
+#             radial factor (FMA + mul), 1/s^5, 6 FMA into a, 1 into phi = 57
+#   cell (monopole): 3 differences, r^2, rsqrt, 1/s^2, 1/s^3, 2 mul, 3 FMA
+#             into a, 1 into phi                                         = 24
 F_PP = 23
-F_PC_QUAD = 58
-F_PC_MONO = 22
+F_PC_QUAD = 57
+F_PC_MONO = 24
+
+
+# HBM bytes per launch of the interaction kernel come from two rocprofv3 --pmc
+# passes (FETCH_SIZE, WRITE_SIZE) on the headline workload, scaled by what the
+# same counters read for a plain device copy of known size; the summary holds a
+# digest of the kernel sources it was taken on, and the figure is reported only
+# while those sources are unchanged.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_force_king9_1m_hbm_traffic.md")
+KERNEL_SOURCES = ["force.hip", "internal.h", "device_util.h"]
+
+
+def kernel_sources_digest():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1506_04553_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(workload, precision):
+    """HBM bytes per launch recorded for the current kernel sources, else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if line.startswith("traffic: "):
+                    rec = json.loads(line[len("traffic: "):])
+                    if (rec["sources_sha256"] == kernel_sources_digest()
+                            and rec["workload"] == workload and rec["precision"] == precision):
+                        return rec
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
 
 
 def log(msg):
@@ -139,6 +183,99 @@ def cpu_baseline(pos, mass, params, gpu_first, target_s=12.0, seed=3):
     return out, errs
 
 
+def vjp_timing(ctx, workload="plummer256k", seed=1, reps=3):
+    """FP32 forward + FP64 VJP of sum(w.a) + sum(c.phi) on the 2^18 Plummer workload."""
+    import torch
+    from inputs import WORKLOADS, make_cluster
+    w_ = WORKLOADS[workload]
+    c = make_cluster(w_, seed=seed)
+    dev = torch.device("cuda", 0)
+    pos = torch.from_numpy(c.pos).to(dev)
+    mass = torch.from_numpy(c.mass).to(dev)
+    rng = np.random.default_rng(seed + 1)
+    wv = torch.from_numpy(rng.normal(size=(w_.n, 3))).to(dev)
+    cv = torch.from_numpy(rng.normal(size=w_.n)).to(dev)
+    p = w_.params(precision="mixed")
+    ctx.build_tree(pos, mass, **p)
+    ctx.long_force()
+    ctx.long_force_vjp(wv, cv)
+    ms = []
+    for _ in range(reps):
+        ctx.long_force_vjp(wv, cv)
+        ms.append(ctx.stats()["ms_vjp"])
+    st = ctx.stats()
+    return {"workload": workload, "n": w_.n, "vjp_ms": float(np.median(ms)),
+            "forward_ms": st["ms_force"], "interactions": st["n_pp"] + st["n_pc"]}
+
+
+def sweep(args):
+    """theta x n_crit sweep on the 2^22 Plummer/Salpeter workload: FP32-compensated
+    vs FP64 interaction kernels, throughput and RMS / max force error on sampled
+    groups against the oracle.  Prints one JSON line per setting."""
+    import torch
+    import oracle
+    from inputs import WORKLOADS, make_cluster
+    from paper_1506_04553_amd import P3T
+    w = WORKLOADS["plummer4m_salpeter"]
+    c = make_cluster(w, seed=args.seed)
+    dev = torch.device("cuda", 0)
+    pos = torch.from_numpy(c.pos).to(dev)
+    mass = torch.from_numpy(c.mass).to(dev)
+    ctx = P3T(0)
+    rng = np.random.default_rng(7)
+    for theta in w.extra["thetas"]:
+        for n_crit in w.extra["n_crits"]:
+            base = w.params(theta=theta, n_crit=n_crit)
+            t0 = time.perf_counter()
+            stride = 997     # the oracle walks every 997-th group only
+            tree = oracle.Tree(c.pos, c.mass, base, walk_stride=stride)
+            t_or = time.perf_counter() - t0
+            G = tree.n_groups
+            walked = np.arange(0, G, stride)
+            sample = rng.choice(walked, min(len(walked), 128), replace=False)
+            ra, rp = tree.force_groups(sample)
+            rows = np.nonzero(~np.isnan(rp))[0]
+            line = {"workload": w.name, "n": w.n, "theta": theta, "n_crit": n_crit,
+                    "groups": G, "oracle_build_s": t_or, "sample_particles": int(len(rows))}
+            for prec in ("mixed", "fp64"):
+                p = dict(base, precision=prec)
+                ctx.build_tree(pos, mass, **p)
+                acc, pot = ctx.long_force()
+                fms = []
+                for _ in range(3):
+                    ctx.long_force(acc, pot)
+                    fms.append(ctx.stats()["ms_force"])
+                st = ctx.stats()
+                a = acc.cpu().numpy()[rows]
+                e = np.linalg.norm(a - ra[rows], axis=1) / np.linalg.norm(ra[rows], axis=1)
+                inter = st["n_pp"] + st["n_pc"]
+                f_ms = float(np.median(fms))
+                flops = st["n_pp"] * F_PP + st["n_pc"] * F_PC_QUAD
+                line[prec] = {"force_ms": f_ms, "build_ms": st["ms_build"],
+                              "interactions": inter, "interactions_per_s": inter / (f_ms * 1e-3),
+                              "tflops": flops / (f_ms * 1e-3) / 1e12,
+                              "acc_rel_rms": float(np.sqrt(((a - ra[rows]) ** 2).sum()
+                                                           / (ra[rows] ** 2).sum())),
+                              "acc_max_rel": float(e.max())}
+            line["speedup_mixed_vs_fp64"] = line["fp64"]["force_ms"] / line["mixed"]["force_ms"]
+            print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def copy_calibration(mib=512, reps=3):
+    """A plain device-to-device copy of known size, for scaling HBM byte counters
+    (FETCH_SIZE / WRITE_SIZE) read by a profiler in the same way as the kernels."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.arange(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "reps": reps,
+                      "kib_per_copy": n * 8 // 1024}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,11 +286,23 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-vjp", action="store_true", help="skip the VJP timing")
+    ap.add_argument("--sweep", action="store_true",
+                    help="run the theta x n_crit sweep on the 2^22 workload instead")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 512 MiB device copy (profiler counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU design is described in DESIGN.md)", file=sys.stderr)
+              "(one process drives one GPU; there is no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.sweep:
+        sweep(args)
+        return
 
     import torch
     from inputs import WORKLOADS, make_cluster
@@ -182,6 +331,8 @@ def main():
         log(f"bench: {prec}: {json.dumps(results[prec])}")
     head = results[args.precision]
     peak = PEAK_TFLOPS[args.precision]
+    tr = recorded_traffic(w.name, args.precision)
+    traffic = None if tr is None else tr["fetch_bytes"] + tr["write_bytes"]
     out = {
         "metric": METRIC,
         "value": head["interactions_per_s"],
@@ -201,7 +352,13 @@ def main():
                    "eps": w.eps, "dt": dt, "precision": args.precision, "seed": args.seed},
         "roofline": {"bound": "alu", "kernel": f"k_force<{'float' if args.precision == 'mixed' else 'double'}>",
                      "achieved": head["force_tflops"], "peak": peak, "unit": "TFLOP/s",
-                     "frac": head["force_tflops"] / peak, "traffic": None,
+                     "frac": head["force_tflops"] / peak, "traffic": traffic,
+                     "issue_ceiling": PEAK_UNPACKED_FP32 if args.precision == "mixed" else peak,
+                     "frac_of_issue_ceiling": head["force_tflops"] /
+                     (PEAK_UNPACKED_FP32 if args.precision == "mixed" else peak),
+                     "traffic_split": None if tr is None else
+                     {"fetch_bytes": tr["fetch_bytes"], "write_bytes": tr["write_bytes"],
+                      "source": os.path.relpath(TRAFFIC_FILE, ROOT)},
                      "flops_per_launch": head["flops_per_launch"],
                      "avg_launch_ms": head["force_ms"],
                      "flops_per_interaction": {"pp": F_PP, "pc": F_PC_QUAD}},
@@ -223,6 +380,9 @@ def main():
         out["mixed_vs_fp64_gpu"] = {
             "acc_rel_rms": float(np.sqrt(((a32 - a64) ** 2).sum() / (a64 ** 2).sum())),
             "pot_rel_rms": float(np.sqrt(((p32 - p64) ** 2).sum() / (p64 ** 2).sum()))}
+    if not args.no_vjp:
+        log("bench: VJP timing")
+        out["vjp"] = vjp_timing(ctx)
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline on sampled groups")
         cb, errs = cpu_baseline(c.pos, c.mass, w.params(), firsts)

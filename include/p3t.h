@@ -74,7 +74,6 @@ typedef struct {
     int64_t n_pc, n_pp;       /* interactions: sum_g n_g |C_g|, sum_g n_g |P_g| */
     int64_t nnz;              /* neighbour pairs found by the last p3t_neighbors */
     int32_t walk_global_stack;/* 1 if the walk needed its global-memory stack */
-    int32_t pad_;
     double ms_build, ms_force, ms_neighbors, ms_vjp; /* GPU time of the last calls */
 } p3t_stats;
 
@@ -159,13 +158,18 @@ enum {
     P3T_ARR_NODE_QUAD = 11,    /* double [n_nodes][6] xx yy zz xy xz yz */
     P3T_ARR_NODE_BOX = 12,     /* double [n_nodes][6] lo xyz, hi xyz */
     P3T_ARR_GROUP_NODE = 13,   /* int32  [n_groups] node id, ordered by first particle */
-    P3T_ARR_CELL_OFF = 14,     /* int64  [n_groups+1] */
-    P3T_ARR_CELL_IDX = 15,     /* int32  [n_cell_entries] node ids */
-    P3T_ARR_PART_OFF = 16,     /* int64  [n_groups+1] offsets of F_g */
+    /* Lists: group g's entries of a list are IDX[BEG[g] .. END[g]); the segments of
+     * different groups may lie in any order. */
+    P3T_ARR_CELL_BEG = 14,     /* int64  [n_groups] */
+    P3T_ARR_CELL_IDX = 15,     /* int32  [n_cell_entries] node ids of C_g */
+    P3T_ARR_PART_BEG = 16,     /* int64  [n_groups] */
     P3T_ARR_PART_IDX = 17,     /* int32  [n_part_entries] sorted particle indices of F_g */
     P3T_ARR_ROOT = 18,         /* double [4] lo xyz, side L */
-    P3T_ARR_NEAR_OFF = 19,     /* int64  [n_groups+1] offsets of N_g */
-    P3T_ARR_NEAR_IDX = 20      /* int32  [n_near_entries] sorted particle indices of N_g */
+    P3T_ARR_NEAR_BEG = 19,     /* int64  [n_groups] */
+    P3T_ARR_NEAR_IDX = 20,     /* int32  [n_near_entries] sorted particle indices of N_g */
+    P3T_ARR_CELL_END = 21,     /* int64  [n_groups] */
+    P3T_ARR_PART_END = 22,     /* int64  [n_groups] */
+    P3T_ARR_NEAR_END = 23      /* int64  [n_groups] */
 };
 int p3t_copy_array(p3t_ctx *ctx, int which, void *dst, int64_t bytes);
 

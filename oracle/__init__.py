@@ -49,6 +49,8 @@ def lib():
         P = C.c_void_p
         L.or_build.argtypes = [C.c_int64, P, P, C.POINTER(_Params), C.POINTER(C.c_void_p)]
         L.or_build.restype = C.c_int
+        L.or_build_ex.argtypes = [C.c_int64, P, P, C.POINTER(_Params), C.c_int64, C.POINTER(C.c_void_p)]
+        L.or_build_ex.restype = C.c_int
         L.or_free.argtypes = [P]
         L.or_force.argtypes = [P, P, P]
         L.or_neighbors.argtypes = [P, P, P]
@@ -134,7 +136,7 @@ class Params:
 class Tree:
     """Oracle tree for one particle set: every step of the method, inspectable."""
 
-    def __init__(self, pos, mass, params: Params | dict):
+    def __init__(self, pos, mass, params: Params | dict, walk_stride: int = 1):
         if isinstance(params, dict):
             params = Params(**{k: v for k, v in params.items() if k in Params.__annotations__})
         self.params = params
@@ -145,7 +147,9 @@ class Tree:
         L = lib()
         h = C.c_void_p()
         cp = params.c()
-        rc = L.or_build(self.n, _ptr(self.pos), _ptr(self.mass), C.byref(cp), C.byref(h))
+        self.walk_stride = int(walk_stride)
+        rc = L.or_build_ex(self.n, _ptr(self.pos), _ptr(self.mass), C.byref(cp), self.walk_stride,
+                           C.byref(h))
         if rc != 0:
             raise ValueError("oracle build failed")
         self._h = h

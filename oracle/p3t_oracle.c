@@ -331,8 +331,21 @@ static void compute_moments(or_tree *t)
 /* Build: root, keys, sort, tree, moments, groups, walk.                      */
 /* ------------------------------------------------------------------------ */
 
+/* Build with the walk restricted to every walk_stride-th group (walk_stride = 1:
+ * all groups); the lists of the other groups are left empty.  Used to sample
+ * very large problems. */
+int or_build_ex(int64_t n, const double *pos, const double *mass, const or_params *p,
+                int64_t walk_stride, or_tree **out);
+
 int or_build(int64_t n, const double *pos, const double *mass, const or_params *p, or_tree **out)
 {
+    return or_build_ex(n, pos, mass, p, 1, out);
+}
+
+int or_build_ex(int64_t n, const double *pos, const double *mass, const or_params *p,
+                int64_t walk_stride, or_tree **out)
+{
+    if (walk_stride < 1) return -1;
     if (n < 1 || !pos || !mass || !p || !out) return -1;
     or_tree *t = calloc(1, sizeof(or_tree));
     t->n = n;
@@ -428,6 +441,11 @@ int or_build(int64_t n, const double *pos, const double *mass, const or_params *
     int64_t *cn = calloc(ng, sizeof(int64_t)), *pn = calloc(ng, sizeof(int64_t));
     #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t gi = 0; gi < ng; gi++) {
+        if (gi % walk_stride != 0) {
+            cl[gi] = malloc(sizeof(int64_t));
+            pl[gi] = malloc(sizeof(int64_t));
+            continue;
+        }
         int64_t g = t->grp[gi];
         int64_t ccap = 64, pcap = 256, scap = 256, sp = 0;
         int64_t *cc = malloc(ccap * sizeof(int64_t)), *pp = malloc(pcap * sizeof(int64_t));

@@ -32,11 +32,54 @@ __device__ __forceinline__ T wave_incl_scan(T v) {
     return v;
 }
 
+// Exclusive wave prefix sum and total of small non-negative counts (< 2^BITS),
+// bit-sliced through ballots: no cross-lane data movement.
+template <int BITS>
+__device__ __forceinline__ int wave_excl_small(int v, int &total) {
+    int excl = 0, tot = 0;
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+        const uint64_t m = ballot((v >> b) & 1);
+        excl += count_below(m) << b;
+        tot += __popcll(m) << b;
+    }
+    total = tot;
+    return excl;
+}
+
+// Exclusive wave prefix sum of any non-negative counts: bit-sliced when every
+// count is below 32, shuffle scan otherwise.
+__device__ __forceinline__ int wave_excl_count(int v, int &total) {
+    if (!ballot(v >= 32)) return wave_excl_small<5>(v, total);
+    const int incl = wave_incl_scan(v);
+    total = __shfl(incl, kWave - 1, kWave);
+    return incl - v;
+}
+
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
     return v;
+}
+
+// Slices per wavefront for a group of n members: s slices of 64/s i-particles,
+// V = ceil(n s / 64) virtual wavefronts, `per_round` per round;
+// minimise issued lane work V * 64 / s, with a small charge per extra round.
+__device__ __forceinline__ int choose_log2_slices(int n, int per_round) {
+    int best = 0;
+    float best_cost = 1e30f;
+    for (int ls = 0; ls <= 6; ++ls) {
+        const int nw = kWave >> ls;
+        const int V = (n + nw - 1) / nw;
+        const int rounds = (V + per_round - 1) / per_round;
+        const float cost = (float)V * (float)nw * (1.0f + 0.05f * (float)(rounds - 1));
+        if (cost < best_cost - 1e-3f) {
+            best_cost = cost;
+            best = ls;
+        }
+    }
+    return best;
 }
 
 // Common leading octal digits (tree levels) of two 63-bit Morton keys: 21 if equal.

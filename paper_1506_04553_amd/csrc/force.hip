@@ -7,17 +7,20 @@
 // with s the softened distance, y = s / r_out, K and W the changeover functions
 // of Section 2.1 (denominator of G read as (gamma - 1)^7).
 //
-// Kernel design (one 256-thread block = 4 wavefronts per group):
-//  * a wavefront lane is (i, slice): 64/s group members times s slices, each
-//    slice taking every s-th entry of a list tile; s (a power of two) is chosen
-//    per group to minimise padded lane work, so groups of any size keep the
-//    lanes busy.  Each lane carries two i-particles (two "virtual wavefronts")
-//    that share every LDS read; slice partial sums are reduced in FP64 with
+// Kernel design (one block of four wavefronts per group):
+//  * a lane is (i, slice): 64/s group members times s slices, each slice
+//    taking every s-th entry of a list tile; s (a power of two) is chosen per
+//    group to minimise padded lane work, so groups of any size keep the lanes
+//    busy.  Each lane carries two i-particles (two "virtual wavefronts") that
+//    share every LDS read; a group of V virtual wavefronts takes ceil(V/8)
+//    rounds over its lists.  Slice partial sums are reduced in FP64 with
 //    cross-lane shuffles in a fixed order;
-//  * list entries are staged through LDS in tiles of 256, the next tile being
-//    fetched into registers while the current one is consumed; positions are
-//    shifted to the group's box centre in FP64 while staging (the mixed path
-//    then rounds the offsets to FP32);
+//  * list entries are staged through LDS tiles of 256 loaded by the whole
+//    block, the next tile being fetched into registers while the current one
+//    is consumed; loop trip counts are wave-uniform (lanes past the end of a
+//    tile read zero-mass padding entries);
+//    positions are shifted to the group's box centre in FP64 while staging (the
+//    mixed path then rounds the offsets to FP32);
 //  * K and W differ from 1 only when s < r_out.  The walk splits the particle
 //    list into far particles (leaf box at least max(h, r_out) from the group
 //    box: K = W = 1, never i itself), evaluated as plain softened terms with no
@@ -35,8 +38,9 @@
 
 namespace p3t {
 
-constexpr int kForceThreads = 256;
-constexpr int kTile = 256;
+constexpr int kForceWaves = 4;      // wavefronts per group (block)
+constexpr int kForceThreads = kForceWaves * kWave;
+constexpr int kTile = kForceThreads;
 
 struct ForceParams {
     double eps2, rout2, inv_rout, gamma, inv_1mg, C_over_rout;
@@ -198,21 +202,23 @@ __device__ __forceinline__ void pc_term(Slot<R> &q, const CJ<R> &c, R eps2, R ro
 // Per-tile loops of one wavefront over its slice of the staged entries, for
 // one or two active i-slots (TWO), so that the loop bodies carry no branch on
 // the slot count.
+// Trip counts are wave-uniform: lanes past the end of a tile read the padding
+// entries (zero mass, far away), whose terms are exactly zero.
 template <class R, bool TWO>
-__device__ __forceinline__ void far_tile(Slot<R> *q, const PJ<R> *sp, int tl, int slice, int ns,
-                                         R eps2) {
-    for (int k = slice; k < tl; k += ns) {
-        const PJ<R> pj = sp[k];
+__device__ __forceinline__ void far_tile(Slot<R> *q, const PJ<R> *sp, int iters, int ns, R eps2) {
+#pragma unroll 2
+    for (int it = 0; it < iters; ++it) {
+        const PJ<R> pj = sp[it * ns];
         pp_fast<R>(q[0], pj, eps2);
         if (TWO) pp_fast<R>(q[1], pj, eps2);
     }
 }
 
 template <class R, bool TWO>
-__device__ __forceinline__ void near_tile(Slot<R> *q, const PJ<R> *sp, const int32_t *sj, int tl,
-                                          int slice, int ns, R eps2, R rout2,
-                                          const ForceParams &fp) {
-    for (int k = slice; k < tl; k += ns) {
+__device__ __forceinline__ void near_tile(Slot<R> *q, const PJ<R> *sp, const int32_t *sj, int iters,
+                                          int ns, R eps2, R rout2, const ForceParams &fp) {
+    for (int it = 0; it < iters; ++it) {
+        const int k = it * ns;
         const PJ<R> pj = sp[k];
         const R dx0 = pj.x - q[0].x, dy0 = pj.y - q[0].y, dz0 = pj.z - q[0].z;
         bool nr = fmaR(dx0, dx0, fmaR(dy0, dy0, fmaR(dz0, dz0, eps2))) < rout2;
@@ -232,69 +238,61 @@ __device__ __forceinline__ void near_tile(Slot<R> *q, const PJ<R> *sp, const int
 }
 
 template <class R, bool QUAD, bool CHECK_K, bool TWO>
-__device__ __forceinline__ void cell_tile(Slot<R> *q, const CJ<R> *sc, int tl, int slice, int ns,
-                                          R eps2, R rout2, const ForceParams &fp) {
-    for (int k = slice; k < tl; k += ns) {
-        const CJ<R> cj = sc[k];
+__device__ __forceinline__ void cell_tile(Slot<R> *q, const CJ<R> *sc, int iters, int ns, R eps2,
+                                          R rout2, const ForceParams &fp) {
+#pragma unroll 2
+    for (int it = 0; it < iters; ++it) {
+        const CJ<R> cj = sc[it * ns];
         pc_term<R, QUAD, CHECK_K>(q[0], cj, eps2, rout2, fp);
         if (TWO) pc_term<R, QUAD, CHECK_K>(q[1], cj, eps2, rout2, fp);
     }
 }
 
-// Slices per wavefront for a group of n members: s slices of 64/s i-particles,
-// V = ceil(n s / 64) virtual wavefronts, 8 per round (4 wavefronts x 2 slots);
-// minimise issued lane work V * 64 / s, with a small charge per extra round.
-__device__ __forceinline__ int choose_log2_slices(int n) {
-    int best = 0;
-    float best_cost = 1e30f;
-    for (int ls = 0; ls <= 6; ++ls) {
-        const int nw = kWave >> ls;
-        const int V = (n + nw - 1) / nw;
-        const int rounds = (V + 7) / 8;
-        const float cost = (float)V * (float)nw * (1.0f + 0.05f * (float)(rounds - 1));
-        if (cost < best_cost - 1e-3f) {
-            best_cost = cost;
-            best = ls;
-        }
-    }
-    return best;
-}
-
 template <class R, bool QUAD, bool CHECK_K>
 __global__ __launch_bounds__(kForceThreads) void k_force(
-    const GroupInfo *__restrict__ grp, const int64_t *__restrict__ p_off,
-    const int32_t *__restrict__ p_idx, const int64_t *__restrict__ n_off,
-    const int32_t *__restrict__ n_idx, const int64_t *__restrict__ c_off,
-    const int32_t *__restrict__ c_idx, const double *__restrict__ x, const double *__restrict__ y,
-    const double *__restrict__ z, const double *__restrict__ m, const NodeMP *__restrict__ mp,
-    const int32_t *__restrict__ perm, ForceParams fp, double *__restrict__ acc,
-    double *__restrict__ pot) {
-    __shared__ PJ<R> s_p[kTile];
-    __shared__ int32_t s_jid[kTile];
-    __shared__ CJ<R> s_c[kTile];
+    const GroupInfo *__restrict__ grp, ListsDev L, const double *__restrict__ x,
+    const double *__restrict__ y, const double *__restrict__ z, const double *__restrict__ m,
+    const NodeMP *__restrict__ mp, const int32_t *__restrict__ perm, ForceParams fp,
+    double *__restrict__ acc, double *__restrict__ pot) {
+    // tile + padding read by lanes past the tile end (zero mass, far away)
+    __shared__ PJ<R> s_p[kTile + kWave];
+    __shared__ int32_t s_jid[kTile + kWave];
+    __shared__ CJ<R> s_c[kTile + kWave];
+    const PJ<R> zero_p{R(-1e18), R(-1e18), R(-1e18), R(0)};
+    CJ<R> zero_c;
+    zero_c.x = zero_c.y = zero_c.z = R(-1e18);
+    zero_c.M = zero_c.qxx = zero_c.qyy = zero_c.qzz = zero_c.qxy = zero_c.qxz = zero_c.qyz = R(0);
+    zero_c.pad0 = zero_c.pad1 = R(0);
 
     const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
     const GroupInfo gi = grp[blockIdx.x];
     const double gcx = gi.c[0], gcy = gi.c[1], gcz = gi.c[2];
-    const int64_t pb = p_off[blockIdx.x], pe = p_off[blockIdx.x + 1];
-    const int64_t nb = n_off[blockIdx.x], ne = n_off[blockIdx.x + 1];
-    const int64_t cb = c_off[blockIdx.x], ce = c_off[blockIdx.x + 1];
+    const int64_t cb = L.beg[0][blockIdx.x], ce = L.end[0][blockIdx.x];
+    const int64_t pb = L.beg[1][blockIdx.x], pe = L.end[1][blockIdx.x];
+    const int64_t nb = L.beg[2][blockIdx.x], ne = L.end[2][blockIdx.x];
+    const int32_t *__restrict__ c_idx = L.idx[0];
+    const int32_t *__restrict__ p_idx = L.idx[1];
+    const int32_t *__restrict__ n_idx = L.idx[2];
     const R eps2 = (R)fp.eps2, rout2 = (R)fp.rout2;
 
-    const int ls = choose_log2_slices(gi.count);
+    if (w == 0) {
+        s_p[kTile + lane] = zero_p;
+        s_jid[kTile + lane] = -2;
+        s_c[kTile + lane] = zero_c;
+    }
+    const int ls = choose_log2_slices(gi.count, 2 * kForceWaves);
     const int ns = 1 << ls;
     const int nw = kWave >> ls;                 // i-particles per virtual wavefront
     const int il = lane & (nw - 1), slice = lane >> (6 - ls);
     const int V = (gi.count + nw - 1) / nw;
 
-    for (int v0 = 0; v0 < V; v0 += 8) {
-        // this wavefront's two virtual wavefronts in this round
-        const bool act0 = v0 + w < V, act1 = v0 + 4 + w < V;
+    for (int v0 = 0; v0 < V; v0 += 2 * kForceWaves) {
+        // this wavefront's two virtual wavefronts (i-slots) in this round
+        const bool act0 = v0 + w < V, act1 = v0 + kForceWaves + w < V;
         Slot<R> q[2];
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-            const int v = v0 + 4 * k + w;
-            const int li = v * nw + il;
+            const int li = (v0 + kForceWaves * k + w) * nw + il;
             const bool valid = (k == 0 ? act0 : act1) && li < gi.count;
             const int32_t i = gi.first + (valid ? li : 0);
             q[k].i = valid ? i : -1;
@@ -304,12 +302,23 @@ __global__ __launch_bounds__(kForceThreads) void k_force(
             q[k].z = valid ? (R)(z[i] - gcz) : R(1e18);
             q[k].ax = q[k].ay = q[k].az = q[k].ph = R(0);
         }
+        // FP32 partials are folded into the compensated sums every >= 64 iterations
+        int since = 0;
+        auto fold = [&](int iters, bool last) {
+            since += iters;
+            if (since >= 64 || last) {
+                if (act0) q[0].flush();
+                if (act1) q[1].flush();
+                since = 0;
+            }
+        };
 
-        // ---- particle-particle terms, tiles staged through LDS; the next tile is
-        //      fetched into registers while the current one is consumed ----
+        // ---- particle-particle terms: tiles staged through LDS by the whole
+        //      block, the next tile fetched into registers while the current one
+        //      is consumed ----
         auto stream_particles = [&](const int32_t *list, int64_t b, int64_t e, auto &&consume) {
-            PJ<R> pre{};
-            int32_t prej = 0;
+            PJ<R> pre = zero_p;
+            int32_t prej = -2;
             if (b + tid < e) {
                 prej = list[b + tid];
                 pre = PJ<R>{(R)(x[prej] - gcx), (R)(y[prej] - gcy), (R)(z[prej] - gcz), (R)m[prej]};
@@ -324,26 +333,29 @@ __global__ __launch_bounds__(kForceThreads) void k_force(
                     prej = list[t0 + kTile + tid];
                     pre = PJ<R>{(R)(x[prej] - gcx), (R)(y[prej] - gcy), (R)(z[prej] - gcz),
                                 (R)m[prej]};
+                } else {
+                    pre = zero_p;
+                    prej = -2;
                 }
-                consume(tl);
-                if (act0) q[0].flush();
-                if (act1) q[1].flush();
+                const int iters = (tl + ns - 1) >> ls;
+                consume(iters);
+                fold(iters, t0 + kTile >= e);
             }
         };
         // far particles: K = W = 1 and j != i, plain softened terms
-        stream_particles(p_idx, pb, pe, [&](int tl) {
-            if (act1) far_tile<R, true>(q, s_p, tl, slice, ns, eps2);
-            else if (act0) far_tile<R, false>(q, s_p, tl, slice, ns, eps2);
+        stream_particles(p_idx, pb, pe, [&](int iters) {
+            if (act1) far_tile<R, true>(q, s_p + slice, iters, ns, eps2);
+            else if (act0) far_tile<R, false>(q, s_p + slice, iters, ns, eps2);
         });
         // near particles: changeover and self exclusion where s < r_out
-        stream_particles(n_idx, nb, ne, [&](int tl) {
-            if (act1) near_tile<R, true>(q, s_p, s_jid, tl, slice, ns, eps2, rout2, fp);
-            else if (act0) near_tile<R, false>(q, s_p, s_jid, tl, slice, ns, eps2, rout2, fp);
+        stream_particles(n_idx, nb, ne, [&](int iters) {
+            if (act1) near_tile<R, true>(q, s_p + slice, s_jid + slice, iters, ns, eps2, rout2, fp);
+            else if (act0)
+                near_tile<R, false>(q, s_p + slice, s_jid + slice, iters, ns, eps2, rout2, fp);
         });
 
         // ---- particle-cell terms ----
         {
-            CJ<R> pre{};
             auto load_cell = [&](int64_t e) {
                 const NodeMP c = mp[c_idx[e]];
                 CJ<R> r;
@@ -353,17 +365,19 @@ __global__ __launch_bounds__(kForceThreads) void k_force(
                 r.pad0 = r.pad1 = R(0);
                 return r;
             };
-            if (cb + tid < ce) pre = load_cell(cb + tid);
+            CJ<R> pre = (cb + tid < ce) ? load_cell(cb + tid) : zero_c;
             for (int64_t t0 = cb; t0 < ce; t0 += kTile) {
                 const int tl = (int)min<int64_t>(kTile, ce - t0);
                 __syncthreads();
                 s_c[tid] = pre;
                 __syncthreads();
-                if (t0 + kTile + tid < ce) pre = load_cell(t0 + kTile + tid);
-                if (act1) cell_tile<R, QUAD, CHECK_K, true>(q, s_c, tl, slice, ns, eps2, rout2, fp);
-                else if (act0) cell_tile<R, QUAD, CHECK_K, false>(q, s_c, tl, slice, ns, eps2, rout2, fp);
-                if (act0) q[0].flush();
-                if (act1) q[1].flush();
+                pre = (t0 + kTile + tid < ce) ? load_cell(t0 + kTile + tid) : zero_c;
+                const int iters = (tl + ns - 1) >> ls;
+                if (act1)
+                    cell_tile<R, QUAD, CHECK_K, true>(q, s_c + slice, iters, ns, eps2, rout2, fp);
+                else if (act0)
+                    cell_tile<R, QUAD, CHECK_K, false>(q, s_c + slice, iters, ns, eps2, rout2, fp);
+                fold(iters, t0 + kTile >= ce);
             }
         }
 
@@ -407,12 +421,9 @@ static ForceParams force_params(const p3t_ctx *ctx) {
 
 template <class R, bool QUAD, bool CHECK_K>
 static void launch_force_t(p3t_ctx *ctx, const ForceParams &fp, double *acc, double *pot) {
-    const int64_t stride = ctx->n_nodes + 1;
-    const int64_t *off = ptr<int64_t>(ctx->off);
     k_force<R, QUAD, CHECK_K><<<(unsigned)ctx->n_groups, kForceThreads, 0, ctx->stream>>>(
-        ptr<GroupInfo>(ctx->grp), off + stride, ptr<int32_t>(ctx->p_idx), off + 2 * stride,
-        ptr<int32_t>(ctx->n_idx), off,
-        ptr<int32_t>(ctx->c_idx), ptr<double>(ctx->x), ptr<double>(ctx->y), ptr<double>(ctx->z),
+        ptr<GroupInfo>(ctx->grp), lists_dev(ctx), ptr<double>(ctx->x), ptr<double>(ctx->y),
+        ptr<double>(ctx->z),
         ptr<double>(ctx->m), ptr<NodeMP>(ctx->node_mp), ptr<int32_t>(ctx->vals[0]), fp, acc, pot);
 }
 

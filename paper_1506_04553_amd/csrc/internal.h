@@ -56,6 +56,15 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// The walk's per-group lists: 0 = accepted cells (node ids), 1 = far particles,
+// 2 = near particles (sorted particle indices); group g's entries of list k are
+// idx[k][beg[k][g] .. end[k][g]).
+struct ListsDev {
+    const int64_t *beg[3];
+    const int64_t *end[3];
+    const int32_t *idx[3];
+};
+
 }  // namespace p3t
 
 struct p3t_ctx {
@@ -88,6 +97,7 @@ struct p3t_ctx {
     p3t::DevBuf cnt, off, c_idx, p_idx, n_idx;
     p3t::DevBuf wstack, dflags, readback, scan_tmp, nbr_cnt;
     p3t::DevBuf vjp_gx, vjp_gm, vjp_cell, bbox;
+    p3t::DevBuf seg_end;
 };
 
 namespace p3t {
@@ -129,6 +139,9 @@ int launch_kick_drift(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const d
 
 template <class T>
 inline T *ptr(const DevBuf &b) { return static_cast<T *>(b.p); }
+
+// Device view of the lists of the last build.
+ListsDev lists_dev(const p3t_ctx *ctx);
 
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 

@@ -152,7 +152,8 @@ extern "C" void p3t_destroy(p3t_ctx *ctx) {
                       &ctx->node_prefix, &ctx->node_S, &ctx->node_walk, &ctx->node_mp, &ctx->gflag,
                       &ctx->gscan, &ctx->grp, &ctx->cnt, &ctx->off, &ctx->c_idx, &ctx->p_idx,
                       &ctx->n_idx, &ctx->wstack, &ctx->dflags, &ctx->readback, &ctx->scan_tmp,
-                      &ctx->nbr_cnt, &ctx->vjp_gx, &ctx->vjp_gm, &ctx->vjp_cell, &ctx->bbox};
+                      &ctx->nbr_cnt, &ctx->vjp_gx, &ctx->vjp_gm, &ctx->vjp_cell, &ctx->bbox,
+                      &ctx->seg_end};
     for (DevBuf *b : bufs) release(ctx, *b);
     if (ctx->hpin) (void)hipHostFree(ctx->hpin);
     for (int k = 0; k < 8; ++k)
@@ -313,12 +314,15 @@ extern "C" int p3t_copy_array(p3t_ctx *ctx, int which, void *dst, int64_t bytes)
     case P3T_ARR_GROUP_NODE:
         src = (const char *)ctx->grp.p + offsetof(GroupInfo, node); pitch = 4;
         spitch = sizeof(GroupInfo); rows = G; break;
-    case P3T_ARR_CELL_OFF: src = ctx->off.p; size = (G + 1) * 8; break;
+    case P3T_ARR_CELL_BEG: src = ctx->off.p; size = G * 8; break;
+    case P3T_ARR_CELL_END: src = ctx->seg_end.p; size = G * 8; break;
+    case P3T_ARR_PART_END: src = (const int64_t *)ctx->seg_end.p + stride; size = G * 8; break;
+    case P3T_ARR_NEAR_END: src = (const int64_t *)ctx->seg_end.p + 2 * stride; size = G * 8; break;
     case P3T_ARR_CELL_IDX: src = ctx->c_idx.p; size = ctx->n_cell_entries * 4; break;
-    case P3T_ARR_PART_OFF: src = (const int64_t *)ctx->off.p + stride; size = (G + 1) * 8; break;
+    case P3T_ARR_PART_BEG: src = (const int64_t *)ctx->off.p + stride; size = G * 8; break;
     case P3T_ARR_PART_IDX: src = ctx->p_idx.p; size = ctx->n_part_entries * 4; break;
     case P3T_ARR_ROOT: src = ctx->root.p; size = 32; break;
-    case P3T_ARR_NEAR_OFF: src = (const int64_t *)ctx->off.p + 2 * stride; size = (G + 1) * 8; break;
+    case P3T_ARR_NEAR_BEG: src = (const int64_t *)ctx->off.p + 2 * stride; size = G * 8; break;
     case P3T_ARR_NEAR_IDX: src = ctx->n_idx.p; size = ctx->n_near_entries * 4; break;
     default: return set_error(ctx, P3T_EINVAL, "unknown array id %d", which);
     }

@@ -497,7 +497,10 @@ int build_topology(p3t_ctx *ctx, int64_t n) {
 // ---------------------------------------------------------------------------
 // Moments, one launch per level from the deepest up.
 // ---------------------------------------------------------------------------
-__global__ void k_moments_level(int64_t begin, int64_t end, int lev, const RootInfo *__restrict__ root,
+// mode 1: every leaf of the tree (leaves depend on particles only);
+// mode 2: the internal nodes of one level (their children are complete).
+__global__ void k_moments_level(int64_t begin, int64_t end, int lev, int mode,
+                                const int32_t *__restrict__ level, const RootInfo *__restrict__ root,
                                 const double *__restrict__ x, const double *__restrict__ y,
                                 const double *__restrict__ z, const double *__restrict__ m,
                                 const int32_t *__restrict__ first, const int32_t *__restrict__ count,
@@ -507,6 +510,8 @@ __global__ void k_moments_level(int64_t begin, int64_t end, int lev, const RootI
     const int64_t id = begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= end) return;
     const int nc = nchild[id];
+    if ((mode == 1) != (nc == 0)) return;
+    if (mode == 1) lev = level[id];
     const int32_t f = first[id], cnt = count[id];
     double M = 0.0, Sx = 0.0, Sy = 0.0, Sz = 0.0;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -585,11 +590,15 @@ int build_moments(p3t_ctx *ctx) {
     if ((rc = ensure(ctx, ctx->node_S, 3 * nn * sizeof(double)))) return rc;
     if ((rc = ensure(ctx, ctx->node_walk, nn * sizeof(NodeWalk)))) return rc;
     if ((rc = ensure(ctx, ctx->node_mp, nn * sizeof(NodeMP)))) return rc;
-    for (int l = kMaxLevel; l >= 0; --l) {
-        const int64_t b = ctx->level_start[l], e = ctx->level_start[l + 1];
-        if (e <= b) continue;
+    for (int l = kLevels; l >= 0; --l) {
+        // l == kLevels: one launch over all leaves; then internal nodes level by level
+        const bool leaves = l == kLevels;
+        const int64_t b = leaves ? 0 : ctx->level_start[l];
+        const int64_t e = leaves ? nn : ctx->level_start[l + 1];
+        if (e <= b || l == kMaxLevel) continue;   // level 21 holds leaves only
         k_moments_level<<<blocks_for(e - b, 128), 128, 0, ctx->stream>>>(
-            b, e, l, ptr<RootInfo>(ctx->root), ptr<double>(ctx->x), ptr<double>(ctx->y),
+            b, e, l, leaves ? 1 : 2, ptr<int32_t>(ctx->node_level), ptr<RootInfo>(ctx->root),
+            ptr<double>(ctx->x), ptr<double>(ctx->y),
             ptr<double>(ctx->z), ptr<double>(ctx->m), ptr<int32_t>(ctx->node_first),
             ptr<int32_t>(ctx->node_count), ptr<int32_t>(ctx->node_child),
             ptr<int32_t>(ctx->node_nchild), ptr<double>(ctx->node_S), ptr<NodeWalk>(ctx->node_walk),
@@ -607,8 +616,9 @@ __global__ void k_group_mark(int64_t n_nodes, const int32_t *__restrict__ count,
                              const int32_t *__restrict__ first, int n_crit, int32_t *__restrict__ flag,
                              int32_t *__restrict__ node_at, unsigned long long *__restrict__ n_leaves) {
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t leaves = ballot(id < n_nodes && nchild[id] == 0);   // one atomic per wavefront
+    if (lane_id() == 0 && leaves) atomicAdd(n_leaves, (unsigned long long)__popcll(leaves));
     if (id >= n_nodes) return;
-    if (nchild[id] == 0) atomicAdd(n_leaves, 1ull);
     const bool cand = count[id] <= n_crit || nchild[id] == 0;
     const bool top = (id == 0) || count[parent[id]] > n_crit;
     if (cand && top) {

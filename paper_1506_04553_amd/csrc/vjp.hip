@@ -147,10 +147,8 @@ __device__ __forceinline__ void cell_grad(double rx, double ry, double rz, doubl
 // Pass 1: per particle i (one group per block), the i-side terms.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
-    const GroupInfo *__restrict__ grp, const int64_t *__restrict__ p_off,
-    const int32_t *__restrict__ p_idx, const int64_t *__restrict__ n_off,
-    const int32_t *__restrict__ n_idx, const int64_t *__restrict__ c_off,
-    const int32_t *__restrict__ c_idx, const double *__restrict__ x, const double *__restrict__ y,
+    const GroupInfo *__restrict__ grp, ListsDev L, const double *__restrict__ x,
+    const double *__restrict__ y,
     const double *__restrict__ z, const double *__restrict__ m, const NodeMP *__restrict__ mp,
     const int32_t *__restrict__ perm, const double *__restrict__ wv, const double *__restrict__ cv,
     VjpParams vp, double *__restrict__ gx, double *__restrict__ gm, int64_t n) {
@@ -160,7 +158,8 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
     __shared__ double s_red[3][kVjpThreads];
     const int tid = threadIdx.x;
     const GroupInfo gi = grp[blockIdx.x];
-    const int64_t cb = c_off[blockIdx.x], ce = c_off[blockIdx.x + 1];
+    const int64_t cb = L.beg[0][blockIdx.x], ce = L.end[0][blockIdx.x];
+    const int32_t *__restrict__ c_idx = L.idx[0];
     for (int chunk = 0; chunk < gi.count; chunk += kVjpThreads) {
         const int nc = min(kVjpThreads, gi.count - chunk);
         int lg = 0;
@@ -175,9 +174,9 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
         const double ci = vp.has_c ? cv[o] : 0.0;
         double g0 = 0, g1 = 0, g2 = 0;
         for (int list = 0; list < 2; ++list) {        // far and near particles
-            const int32_t *idxs = list ? n_idx : p_idx;
-            const int64_t pb = list ? n_off[blockIdx.x] : p_off[blockIdx.x];
-            const int64_t pe = list ? n_off[blockIdx.x + 1] : p_off[blockIdx.x + 1];
+            const int32_t *idxs = L.idx[1 + list];
+            const int64_t pb = L.beg[1 + list][blockIdx.x];
+            const int64_t pe = L.end[1 + list][blockIdx.x];
             for (int64_t t0 = pb; t0 < pe; t0 += kVjpTile) {
                 const int tl = (int)min<int64_t>(kVjpTile, pe - t0);
                 __syncthreads();
@@ -228,10 +227,8 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
 // members, scattered with one atomic add per component.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
-    const GroupInfo *__restrict__ grp, const int64_t *__restrict__ p_off,
-    const int32_t *__restrict__ p_idx, const int64_t *__restrict__ n_off,
-    const int32_t *__restrict__ n_idx, const int64_t *__restrict__ c_off,
-    const int32_t *__restrict__ c_idx, const double *__restrict__ x, const double *__restrict__ y,
+    const GroupInfo *__restrict__ grp, ListsDev L, const double *__restrict__ x,
+    const double *__restrict__ y,
     const double *__restrict__ z, const double *__restrict__ m, const NodeMP *__restrict__ mp,
     const int32_t *__restrict__ perm, const double *__restrict__ wv, const double *__restrict__ cv,
     VjpParams vp, double *__restrict__ gx, double *__restrict__ gm, double *__restrict__ cadj,
@@ -240,9 +237,12 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
     __shared__ int32_t s_id[kVjpThreads];
     const int tid = threadIdx.x;
     const GroupInfo gi = grp[blockIdx.x];
-    const int64_t cb = c_off[blockIdx.x], ce = c_off[blockIdx.x + 1];
-    const int64_t fb = p_off[blockIdx.x], fe = p_off[blockIdx.x + 1];
-    const int64_t nb = n_off[blockIdx.x], ne = n_off[blockIdx.x + 1];
+    const int64_t cb = L.beg[0][blockIdx.x], ce = L.end[0][blockIdx.x];
+    const int64_t fb = L.beg[1][blockIdx.x], fe = L.end[1][blockIdx.x];
+    const int64_t nb = L.beg[2][blockIdx.x], ne = L.end[2][blockIdx.x];
+    const int32_t *__restrict__ c_idx = L.idx[0];
+    const int32_t *__restrict__ p_idx = L.idx[1];
+    const int32_t *__restrict__ n_idx = L.idx[2];
     const int64_t nf = fe - fb, np = nf + (ne - nb);   // far entries first, then near
     for (int chunk = 0; chunk < gi.count; chunk += kVjpThreads) {
         const int nc = min(kVjpThreads, gi.count - chunk);
@@ -397,22 +397,17 @@ int launch_vjp(p3t_ctx *ctx, const double *w, const double *c, double *gpos, dou
     vp.has_c = c != nullptr;
     double *gx = ptr<double>(ctx->vjp_gx), *gm = ptr<double>(ctx->vjp_gm);
     double *cadj = ptr<double>(ctx->vjp_cell);
-    const int64_t stride = nn + 1;
-    const int64_t *off = ptr<int64_t>(ctx->off);
+    const ListsDev L = lists_dev(ctx);
     if ((rc = check_hip(ctx, hipMemsetAsync(cadj, 0, 10 * nn * sizeof(double), ctx->stream), "memset")))
         return rc;
     const unsigned G = (unsigned)ctx->n_groups;
     k_vjp_i<<<G, kVjpThreads, 0, ctx->stream>>>(
-        ptr<GroupInfo>(ctx->grp), off + stride, ptr<int32_t>(ctx->p_idx), off + 2 * stride,
-        ptr<int32_t>(ctx->n_idx), off,
-        ptr<int32_t>(ctx->c_idx), ptr<double>(ctx->x), ptr<double>(ctx->y), ptr<double>(ctx->z),
+        ptr<GroupInfo>(ctx->grp), L, ptr<double>(ctx->x), ptr<double>(ctx->y), ptr<double>(ctx->z),
         ptr<double>(ctx->m), ptr<NodeMP>(ctx->node_mp), ptr<int32_t>(ctx->vals[0]), w, c, vp, gx, gm,
         n);
     if ((rc = check_hip(ctx, hipGetLastError(), "vjp i-side"))) return rc;
     k_vjp_scatter<<<G, kVjpThreads, 0, ctx->stream>>>(
-        ptr<GroupInfo>(ctx->grp), off + stride, ptr<int32_t>(ctx->p_idx), off + 2 * stride,
-        ptr<int32_t>(ctx->n_idx), off,
-        ptr<int32_t>(ctx->c_idx), ptr<double>(ctx->x), ptr<double>(ctx->y), ptr<double>(ctx->z),
+        ptr<GroupInfo>(ctx->grp), L, ptr<double>(ctx->x), ptr<double>(ctx->y), ptr<double>(ctx->z),
         ptr<double>(ctx->m), ptr<NodeMP>(ctx->node_mp), ptr<int32_t>(ctx->vals[0]), w, c, vp, gx, gm,
         cadj, n);
     if ((rc = check_hip(ctx, hipGetLastError(), "vjp scatter"))) return rc;

@@ -17,8 +17,13 @@
 // stack, classified in parallel, and the children of opened internal nodes are
 // pushed back.  Node levels never decrease towards the top of the stack and at
 // most 8*64 entries of one level are pending at once, so 22*512 entries bound
-// the stack; the walk first runs with a small stack in LDS and falls back to a
+// the stack; the walk runs with a small stack in LDS and falls back to a
 // per-block stack of that bound in global memory if a group overflows it.
+//
+// The lists are produced in two passes: count, prefix-sum, then walk again
+// writing at the exact offsets; the statistics (interaction counts, longest
+// lists) are reductions over the per-group counts, so no two groups ever
+// update the same memory word.
 #include "device_util.h"
 #include "internal.h"
 
@@ -28,8 +33,19 @@ constexpr int kWalkThreads = 64;        // one wavefront per block
 constexpr int kLdsStack = 2048;
 constexpr int kGlobalStack = kLevels * 8 * kWave + kWave;
 
+enum WalkMode { kCount = 0, kEmit = 1 };
+
 struct WalkParams {
     double th2, h2, hn2;   // theta^2, h^2, max(h, r_out)^2
+};
+
+// Device outputs of one walk launch.
+struct WalkOut {
+    int64_t *cnt;            // [3][stride] per-group counts (count pass)
+    int64_t *beg, *end;      // [3][stride] segments (emit pass)
+    int32_t *idx[3];         // final lists
+    int32_t *stack_ovf;
+    int64_t stride;
 };
 
 __device__ __forceinline__ double gap(double u, double v) {
@@ -37,23 +53,24 @@ __device__ __forceinline__ double gap(double u, double v) {
     return v > w ? v : w;
 }
 
-template <bool EMIT>
-__global__ __launch_bounds__(kWalkThreads) void k_walk(
-    const GroupInfo *__restrict__ grp, const int32_t *__restrict__ n_groups_dev,
-    const NodeWalk *__restrict__ nodes, WalkParams wp, int64_t *__restrict__ cnt_c,
-    int64_t *__restrict__ cnt_p, int64_t *__restrict__ cnt_n, const int64_t *__restrict__ off_c,
-    const int64_t *__restrict__ off_p, const int64_t *__restrict__ off_n, int32_t *__restrict__ c_idx,
-    int32_t *__restrict__ p_idx, int32_t *__restrict__ n_idx, int32_t *__restrict__ gstack,
-    int use_global, int32_t *__restrict__ overflow, unsigned long long *__restrict__ inter) {
+template <int MODE>
+__global__ __launch_bounds__(kWalkThreads) void k_walk(const GroupInfo *__restrict__ grp,
+                                                        const int32_t *__restrict__ n_groups_dev,
+                                                        const NodeWalk *__restrict__ nodes,
+                                                        WalkParams wp, WalkOut wo,
+                                                        int32_t *__restrict__ gstack, int use_global) {
     __shared__ int32_t lstack[kLdsStack];
     int32_t *stk = use_global ? gstack + (int64_t)blockIdx.x * kGlobalStack : lstack;
     const int cap = use_global ? kGlobalStack : kLdsStack;
     const int lane = threadIdx.x;
     const int G = *n_groups_dev;
+    const int64_t S = wo.stride;
     for (int g = blockIdx.x; g < G; g += gridDim.x) {
         const GroupInfo gi = grp[g];
-        int64_t nc = 0, np = 0, nn = 0;
-        const int64_t oc = EMIT ? off_c[g] : 0, op = EMIT ? off_p[g] : 0, on = EMIT ? off_n[g] : 0;
+        int64_t run[3] = {0, 0, 0};
+        int32_t *dst[3] = {nullptr, nullptr, nullptr};
+        if (MODE == kEmit)
+            for (int k = 0; k < 3; ++k) dst[k] = wo.idx[k] + wo.beg[k * S + g];
         int sp = 1;
         if (lane == 0) stk[0] = 0;
         __syncthreads();
@@ -89,54 +106,81 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(
             const bool isF = node >= 0 && !acc && leaf && !near;
             const bool isN = node >= 0 && !acc && leaf && near;
             // accepted cells
-            const uint64_t mC = ballot(isC);
-            if (EMIT && isC) c_idx[oc + nc + count_below(mC)] = node;
-            nc += __popcll(mC);
-            // particles of far opened leaves
-            const int pcnt = isF ? count : 0;
-            const int pincl = wave_incl_scan(pcnt);
-            const int ptot = __shfl(pincl, kWave - 1, kWave);
-            if (EMIT && isF) {
-                int32_t *dst = p_idx + op + np + (pincl - pcnt);
-                for (int t = 0; t < pcnt; ++t) dst[t] = first + t;
+            {
+                const uint64_t mC = ballot(isC);
+                if (MODE == kEmit && isC) dst[0][run[0] + count_below(mC)] = node;
+                run[0] += __popcll(mC);
             }
-            np += ptot;
-            // particles of near opened leaves
-            const int ncnt = isN ? count : 0;
-            const int nincl = wave_incl_scan(ncnt);
-            const int ntot = __shfl(nincl, kWave - 1, kWave);
-            if (EMIT && isN) {
-                int32_t *dst = n_idx + on + nn + (nincl - ncnt);
-                for (int t = 0; t < ncnt; ++t) dst[t] = first + t;
+            // particles of far, then near, opened leaves
+#pragma unroll
+            for (int kk = 1; kk < 3; ++kk) {
+                const bool mine = kk == 1 ? isF : isN;
+                const int c = mine ? count : 0;
+                int tot;
+                const int excl = wave_excl_count(c, tot);
+                if (MODE == kEmit && mine) {
+                    int32_t *d = dst[kk] + run[kk] + excl;
+                    for (int t = 0; t < c; ++t) d[t] = first + t;
+                }
+                run[kk] += tot;
             }
-            nn += ntot;
-            // children of opened internal nodes
+            // children of opened internal nodes (at most 8 each)
             const int ocnt = isO ? ncld : 0;
-            const int oincl = wave_incl_scan(ocnt);
-            const int otot = __shfl(oincl, kWave - 1, kWave);
+            int otot;
+            const int oexcl = wave_excl_small<4>(ocnt, otot);
             if (sp + otot > cap) {
                 ovf = true;
                 break;
             }
             if (isO) {
-                int32_t *dst = stk + sp + (oincl - ocnt);
-                for (int t = 0; t < ocnt; ++t) dst[t] = cf + t;
+                int32_t *d = stk + sp + oexcl;
+                for (int t = 0; t < ocnt; ++t) d[t] = cf + t;
             }
             sp += otot;
             __syncthreads();
         }
         __syncthreads();
         if (ovf) {
-            if (lane == 0) atomicOr(overflow, 1);
+            if (lane == 0) atomicOr(wo.stack_ovf, 1);
             continue;
         }
-        if (!EMIT && lane == 0) {
-            cnt_c[g] = nc;
-            cnt_p[g] = np;
-            cnt_n[g] = nn;
-            atomicAdd(&inter[0], (unsigned long long)(gi.count * nc));
-            atomicAdd(&inter[1], (unsigned long long)(gi.count * (np + nn)));
+        if (lane == 0) {
+            for (int k = 0; k < 3; ++k) {
+                if (MODE == kCount) wo.cnt[k * S + g] = run[k];
+                else wo.end[k * S + g] = wo.beg[k * S + g] + run[k];
+            }
         }
+    }
+}
+
+// Statistics from the per-group counts: interactions sum_g n_g |C_g| and
+// sum_g n_g (|F_g| + |N_g|), and the longest list of each kind.
+__global__ __launch_bounds__(256) void k_walk_stats(const GroupInfo *__restrict__ grp,
+                                                    const int32_t *__restrict__ n_groups_dev,
+                                                    const int64_t *__restrict__ cnt, int64_t S,
+                                                    unsigned long long *__restrict__ out) {
+    const int G = *n_groups_dev;
+    unsigned long long pc = 0, pp = 0, mx[3] = {0, 0, 0};
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x) {
+        const unsigned long long n = (unsigned long long)grp[g].count;
+        const unsigned long long c0 = cnt[g], c1 = cnt[S + g], c2 = cnt[2 * S + g];
+        pc += n * c0;
+        pp += n * (c1 + c2);
+        mx[0] = c0 > mx[0] ? c0 : mx[0];
+        mx[1] = c1 > mx[1] ? c1 : mx[1];
+        mx[2] = c2 > mx[2] ? c2 : mx[2];
+    }
+    pc = wave_sum(pc);
+    pp = wave_sum(pp);
+    for (int k = 0; k < 3; ++k)
+        for (int d = kWave / 2; d > 0; d >>= 1) {
+            const unsigned long long o = __shfl_xor(mx[k], d, kWave);
+            mx[k] = o > mx[k] ? o : mx[k];
+        }
+    if (lane_id() == 0) {   // one update per wavefront
+        atomicAdd(&out[0], pc);
+        atomicAdd(&out[1], pp);
+        for (int k = 0; k < 3; ++k) atomicMax(&out[3 + k], mx[k]);
     }
 }
 
@@ -145,13 +189,32 @@ static unsigned walk_grid(p3t_ctx *ctx) {
     return (unsigned)(g > 0 ? g : 1);
 }
 
+ListsDev lists_dev(const p3t_ctx *ctx) {
+    ListsDev L;
+    const int64_t stride = ctx->n_nodes + 1;
+    const int64_t *beg = ptr<int64_t>(ctx->off), *end = ptr<int64_t>(ctx->seg_end);
+    const DevBuf *bufs[3] = {&ctx->c_idx, &ctx->p_idx, &ctx->n_idx};
+    for (int k = 0; k < 3; ++k) {
+        L.beg[k] = beg + k * stride;
+        L.end[k] = end + k * stride;
+        L.idx[k] = ptr<int32_t>(*bufs[k]);
+    }
+    return L;
+}
+
+// read-back slots of the walk (int64 units of the readback area); slot 32 holds
+// the leaf count written while marking groups
+enum { RB_TOT = 24, RB_G = 28, RB_STACK = 29, RB_INTER = 30, RB_LEAVES = 32, RB_MAX = 33 };
+
 int build_lists(p3t_ctx *ctx) {
     int rc;
     const int64_t nn = ctx->n_nodes;   // bound on the number of groups
     const int64_t stride = nn + 1;
     if ((rc = ensure(ctx, ctx->cnt, 3 * stride * sizeof(int64_t)))) return rc;
     if ((rc = ensure(ctx, ctx->off, 3 * stride * sizeof(int64_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->seg_end, 3 * stride * sizeof(int64_t)))) return rc;
     int64_t *cnt = ptr<int64_t>(ctx->cnt), *off = ptr<int64_t>(ctx->off);
+    int64_t *end = ptr<int64_t>(ctx->seg_end);
     int64_t *rb = ptr<int64_t>(ctx->readback);
     int32_t *flags = ptr<int32_t>(ctx->dflags);
     const int32_t *G_dev = ptr<int32_t>(ctx->gscan) + ctx->n;
@@ -159,60 +222,73 @@ int build_lists(p3t_ctx *ctx) {
     const WalkParams wp{ctx->prm.theta * ctx->prm.theta, ctx->prm.r_search * ctx->prm.r_search,
                         hn * hn};
     const unsigned grid = walk_grid(ctx);
+    hipStream_t st = ctx->stream;
+    DevBuf *lbuf[3] = {&ctx->c_idx, &ctx->p_idx, &ctx->n_idx};
+    WalkOut wo{};
+    wo.cnt = cnt;
+    wo.beg = off;
+    wo.end = end;
+    wo.stack_ovf = flags + 1;
+    wo.stride = stride;
 
     for (int attempt = 0; attempt < 2; ++attempt) {
         const int use_global = attempt;
         if (use_global) {
-            if ((rc = ensure(ctx, ctx->wstack, (size_t)grid * kGlobalStack * sizeof(int32_t)))) return rc;
-        }
-        if ((rc = check_hip(ctx, hipMemsetAsync(cnt, 0, 3 * stride * sizeof(int64_t), ctx->stream),
-                            "memset")))
-            return rc;
-        if ((rc = check_hip(ctx, hipMemsetAsync(flags + 1, 0, sizeof(int32_t), ctx->stream), "memset")))
-            return rc;
-        if ((rc = check_hip(ctx, hipMemsetAsync(rb + 30, 0, 2 * sizeof(int64_t), ctx->stream), "memset")))
-            return rc;
-        k_walk<false><<<grid, kWalkThreads, 0, ctx->stream>>>(
-            ptr<GroupInfo>(ctx->grp), G_dev, ptr<NodeWalk>(ctx->node_walk), wp, cnt, cnt + stride,
-            cnt + 2 * stride, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-            ptr<int32_t>(ctx->wstack), use_global, flags + 1, (unsigned long long *)(rb + 30));
-        if ((rc = check_hip(ctx, hipGetLastError(), "walk count"))) return rc;
-        for (int k = 0; k < 3; ++k)
-            if ((rc = scan_exclusive_i64(ctx, cnt + k * stride, off + k * stride, stride, rb + 24 + k)))
+            if ((rc = ensure(ctx, ctx->wstack, (size_t)grid * kGlobalStack * sizeof(int32_t))))
                 return rc;
-        // read back: groups, list totals, overflow flag
-        if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + 24, rb + 24, 9 * sizeof(int64_t),
-                                                hipMemcpyDeviceToHost, ctx->stream), "readback")))
+        }
+        if ((rc = check_hip(ctx, hipMemsetAsync(flags + 1, 0, sizeof(int32_t), st), "memset")))
             return rc;
-        if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + 28, G_dev, sizeof(int32_t),
-                                                hipMemcpyDeviceToHost, ctx->stream), "readback")))
+        // entries past the last group take part in the scans as zeros
+        if ((rc = check_hip(ctx, hipMemsetAsync(cnt, 0, 3 * stride * sizeof(int64_t), st), "memset")))
             return rc;
-        if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + 29, flags + 1, sizeof(int32_t),
-                                                hipMemcpyDeviceToHost, ctx->stream), "readback")))
+        if ((rc = check_hip(ctx, hipMemsetAsync(rb + RB_INTER, 0, 2 * sizeof(int64_t), st), "memset")))
             return rc;
-        if ((rc = check_hip(ctx, hipStreamSynchronize(ctx->stream), "sync"))) return rc;
-        const int32_t ovf = *(int32_t *)(ctx->hpin + 29);
-        if (!ovf) {
+        if ((rc = check_hip(ctx, hipMemsetAsync(rb + RB_MAX, 0, 3 * sizeof(int64_t), st), "memset")))
+            return rc;
+        k_walk<kCount><<<grid, kWalkThreads, 0, st>>>(ptr<GroupInfo>(ctx->grp), G_dev,
+                                                       ptr<NodeWalk>(ctx->node_walk), wp, wo,
+                                                       ptr<int32_t>(ctx->wstack), use_global);
+        if ((rc = check_hip(ctx, hipGetLastError(), "walk count"))) return rc;
+        k_walk_stats<<<64, 256, 0, st>>>(ptr<GroupInfo>(ctx->grp), G_dev, cnt, stride,
+                                         (unsigned long long *)(rb + RB_INTER));
+        if ((rc = check_hip(ctx, hipGetLastError(), "walk stats"))) return rc;
+        for (int k = 0; k < 3; ++k)
+            if ((rc = scan_exclusive_i64(ctx, cnt + k * stride, off + k * stride, stride,
+                                         rb + RB_TOT + k)))
+                return rc;
+        // read back: list totals, statistics, group count, stack overflow flag
+        if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + RB_TOT, rb + RB_TOT,
+                                                (RB_MAX + 3 - RB_TOT) * sizeof(int64_t),
+                                                hipMemcpyDeviceToHost, st), "readback")))
+            return rc;
+        if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + RB_G, G_dev, sizeof(int32_t),
+                                                hipMemcpyDeviceToHost, st), "readback")))
+            return rc;
+        if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + RB_STACK, flags + 1, sizeof(int32_t),
+                                                hipMemcpyDeviceToHost, st), "readback")))
+            return rc;
+        if ((rc = check_hip(ctx, hipStreamSynchronize(st), "sync"))) return rc;
+        if (!*(int32_t *)(ctx->hpin + RB_STACK)) {
             ctx->walk_global = use_global;
             break;
         }
         if (use_global) return set_error(ctx, P3T_EINVAL, "tree walk stack overflow");
     }
-    ctx->n_groups = *(int32_t *)(ctx->hpin + 28);
-    ctx->n_cell_entries = ctx->hpin[24];
-    ctx->n_part_entries = ctx->hpin[25];
-    ctx->n_near_entries = ctx->hpin[26];
-    ctx->n_pc = ctx->hpin[30];
-    ctx->n_pp = ctx->hpin[31];
-    ctx->n_leaves = ctx->hpin[32];
-    if ((rc = ensure(ctx, ctx->c_idx, (ctx->n_cell_entries + 1) * sizeof(int32_t)))) return rc;
-    if ((rc = ensure(ctx, ctx->p_idx, (ctx->n_part_entries + 1) * sizeof(int32_t)))) return rc;
-    if ((rc = ensure(ctx, ctx->n_idx, (ctx->n_near_entries + 1) * sizeof(int32_t)))) return rc;
-    k_walk<true><<<grid, kWalkThreads, 0, ctx->stream>>>(
-        ptr<GroupInfo>(ctx->grp), G_dev, ptr<NodeWalk>(ctx->node_walk), wp, nullptr, nullptr,
-        nullptr, off, off + stride, off + 2 * stride, ptr<int32_t>(ctx->c_idx),
-        ptr<int32_t>(ctx->p_idx), ptr<int32_t>(ctx->n_idx), ptr<int32_t>(ctx->wstack),
-        ctx->walk_global, flags + 1, nullptr);
+    ctx->n_groups = *(int32_t *)(ctx->hpin + RB_G);
+    ctx->n_cell_entries = ctx->hpin[RB_TOT];
+    ctx->n_part_entries = ctx->hpin[RB_TOT + 1];
+    ctx->n_near_entries = ctx->hpin[RB_TOT + 2];
+    ctx->n_pc = ctx->hpin[RB_INTER];
+    ctx->n_pp = ctx->hpin[RB_INTER + 1];
+    ctx->n_leaves = ctx->hpin[RB_LEAVES];
+    for (int k = 0; k < 3; ++k) {
+        if ((rc = ensure(ctx, *lbuf[k], (ctx->hpin[RB_TOT + k] + 1) * sizeof(int32_t)))) return rc;
+        wo.idx[k] = ptr<int32_t>(*lbuf[k]);
+    }
+    k_walk<kEmit><<<grid, kWalkThreads, 0, st>>>(ptr<GroupInfo>(ctx->grp), G_dev,
+                                                  ptr<NodeWalk>(ctx->node_walk), wp, wo,
+                                                  ptr<int32_t>(ctx->wstack), ctx->walk_global);
     return check_hip(ctx, hipGetLastError(), "walk emit");
 }
 

@@ -36,13 +36,16 @@ ARRAYS = {  # id, dtype, per-row shape, size key
     "node_quad": (11, np.float64, (6,), "n_nodes"),
     "node_box": (12, np.float64, (6,), "n_nodes"),
     "group_node": (13, np.int32, (), "n_groups"),
-    "cell_off": (14, np.int64, (), "n_groups+1"),
+    "cell_beg": (14, np.int64, (), "n_groups"),
     "cell_idx": (15, np.int32, (), "n_cell_entries"),
-    "part_off": (16, np.int64, (), "n_groups+1"),
+    "part_beg": (16, np.int64, (), "n_groups"),
     "part_idx": (17, np.int32, (), "n_part_entries"),
     "root": (18, np.float64, (), "4"),
-    "near_off": (19, np.int64, (), "n_groups+1"),
+    "near_beg": (19, np.int64, (), "n_groups"),
     "near_idx": (20, np.int32, (), "n_near_entries"),
+    "cell_end": (21, np.int64, (), "n_groups"),
+    "part_end": (22, np.int64, (), "n_groups"),
+    "near_end": (23, np.int64, (), "n_groups"),
 }
 
 
@@ -62,7 +65,7 @@ class Stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("n", "n_nodes", "n_leaves", "n_groups", "depth",
                                          "n_cell_entries", "n_part_entries", "n_near_entries",
                                          "n_pc", "n_pp", "nnz")] + \
-               [("walk_global_stack", C.c_int32), ("pad_", C.c_int32)] + \
+               [("walk_global_stack", C.c_int32)] + \
                [(k, C.c_double) for k in ("ms_build", "ms_force", "ms_neighbors", "ms_vjp")]
 
 
@@ -249,17 +252,12 @@ class P3T:
     def stats(self) -> dict:
         s = Stats()
         self._check(self._L.p3t_get_stats(self._h, C.byref(s)))
-        return {k: getattr(s, k) for k, _ in Stats._fields_ if k != "pad_"}
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
 
     def copy_array(self, name: str) -> np.ndarray:
         aid, dt, row, key = ARRAYS[name]
         st = self.stats()
-        if key == "4":
-            count = 4
-        elif key.endswith("+1"):
-            count = st[key[:-2]] + 1
-        else:
-            count = st[key]
+        count = 4 if key == "4" else st[key]
         out = np.empty((count, *row), dtype=dt)
         self._check(self._L.p3t_copy_array(self._h, aid, out.ctypes.data_as(C.c_void_p),
                                            out.nbytes))

@@ -37,14 +37,15 @@ def gpu_run(ctx, pos, mass, params, want_neighbors=True, want_arrays=True):
     if want_arrays:
         for k in ("sorted_keys", "perm", "node_level", "node_first", "node_count", "node_child",
                   "node_nchild", "node_parent", "node_prefix", "node_mass", "node_com",
-                  "node_quad", "node_box", "group_node", "cell_off", "cell_idx", "part_off",
-                  "part_idx", "near_off", "near_idx", "root"):
+                  "node_quad", "node_box", "group_node", "cell_beg", "cell_end", "cell_idx",
+                  "part_beg", "part_end", "part_idx", "near_beg", "near_end", "near_idx", "root"):
             out[k] = ctx.copy_array(k)
     return out
 
 
 def compare_tree(g, t: oracle.Tree, groups_sample=None):
-    """Keys, order, topology, moments, groups and lists must match bit for bit."""
+    """Keys, order, topology, moments, groups and lists must match bit for bit.
+    With an oracle that walked only every k-th group, lists are compared for those."""
     key, perm = t.keys()
     lo, L = t.root()
     assert np.array_equal(g["root"][:3], lo) and g["root"][3] == L
@@ -72,20 +73,37 @@ def compare_tree(g, t: oracle.Tree, groups_sample=None):
     G = t.n_groups
     gs = range(G) if groups_sample is None else groups_sample
     st = g["stats"]
-    assert st["n_cell_entries"] == ol["c_off"][-1]
-    assert st["n_part_entries"] + st["n_near_entries"] == ol["p_off"][-1]
-    np.testing.assert_array_equal(g["cell_off"], ol["c_off"])
-    np.testing.assert_array_equal(np.diff(g["part_off"]) + np.diff(g["near_off"]), np.diff(ol["p_off"]))
+    stride = getattr(t, "walk_stride", 1)
+    # segments: every list's segments tile its array exactly (no gap, no overlap)
+    for lst, tot in (("cell", st["n_cell_entries"]), ("part", st["n_part_entries"]),
+                     ("near", st["n_near_entries"])):
+        b, e = g[lst + "_beg"], g[lst + "_end"]
+        assert np.all(e >= b)
+        o = np.argsort(b, kind="stable")
+        nz = (e - b)[o] > 0
+        bb, ee = b[o][nz], e[o][nz]
+        assert (len(bb) == 0 and tot == 0) or (bb[0] == 0 and ee[-1] == tot
+                                               and np.all(bb[1:] == ee[:-1]))
+    if stride == 1:
+        assert st["n_cell_entries"] == ol["c_off"][-1]
+        assert st["n_part_entries"] + st["n_near_entries"] == ol["p_off"][-1]
+        np.testing.assert_array_equal(g["cell_end"] - g["cell_beg"], np.diff(ol["c_off"]))
+        np.testing.assert_array_equal(g["part_end"] - g["part_beg"] + g["near_end"] - g["near_beg"],
+                                      np.diff(ol["p_off"]))
+    else:
+        gs = [k for k in gs if k % stride == 0]
     for k in gs:
         a, b = ol["c_off"][k], ol["c_off"][k + 1]
-        np.testing.assert_array_equal(np.sort(g["cell_idx"][a:b]), ol["c_idx"][a:b])
+        np.testing.assert_array_equal(np.sort(g["cell_idx"][g["cell_beg"][k]:g["cell_end"][k]]),
+                                      ol["c_idx"][a:b])
         # the walk's particle list P_g is the union of the far and near parts
-        far = g["part_idx"][g["part_off"][k]:g["part_off"][k + 1]]
-        near = g["near_idx"][g["near_off"][k]:g["near_off"][k + 1]]
+        far = g["part_idx"][g["part_beg"][k]:g["part_end"][k]]
+        near = g["near_idx"][g["near_beg"][k]:g["near_end"][k]]
         a, b = ol["p_off"][k], ol["p_off"][k + 1]
         np.testing.assert_array_equal(np.sort(np.concatenate([far, near])), ol["p_idx"][a:b])
-    cnt = t.counts()
-    assert st["n_pc"] == cnt["n_pc"] and st["n_pp"] == cnt["n_pp"]
+    if stride == 1:
+        cnt = t.counts()
+        assert st["n_pc"] == cnt["n_pc"] and st["n_pp"] == cnt["n_pp"]
 
 
 def compare_neighbors(g, t: oracle.Tree):

@@ -114,6 +114,28 @@ def test_large_sampled(ctx, name, prec):
     np.testing.assert_array_equal(a, b)
 
 
+@pytest.mark.parametrize("theta,n_crit", [(0.5, 128), (0.3, 64)])
+def test_plummer4m_sampled(ctx, theta, n_crit):
+    """The 2^22-particle Salpeter workload: whole tree bit-exact, lists of every
+    997th group (the oracle walks only those), forces of 96 of them."""
+    w = WORKLOADS["plummer4m_salpeter"]
+    c = make_cluster(w, seed=1)
+    log(f"case plummer4m theta={theta} n_crit={n_crit}")
+    for prec in ("mixed", "fp64"):
+        p = _params(w, theta=theta, n_crit=n_crit, precision=prec)
+        g = gpu_run(ctx, c.pos, c.mass, p, want_neighbors=(prec == "mixed"))
+        if prec == "mixed":
+            t = oracle.Tree(c.pos, c.mass, p, walk_stride=997)
+            compare_tree(g, t)
+            rng = np.random.default_rng(9)
+            walked = np.arange(0, t.n_groups, 997)
+            sample = rng.choice(walked, min(96, len(walked)), replace=False)
+            acc, pot = t.force_groups(sample)
+            rows = np.nonzero(~np.isnan(pot))[0]
+        _check_forces(g, acc, pot, FP64_TOL if prec == "fp64" else MIXED_TOL,
+                      f"plummer4m theta={theta} n_crit={n_crit} {prec}", rows)
+
+
 def _edge_cases():
     rng = np.random.default_rng(11)
     base = dict(eps=1e-3, r_in=0.002, r_out=0.02, theta=0.5, r_search=0.022, n_crit=64, n_leaf=16)
@@ -171,6 +193,32 @@ def test_forward_is_deterministic(ctx):
         b = gpu_run(ctx, c.pos, c.mass, p, want_arrays=False)
         assert np.array_equal(a["acc"], b["acc"]) and np.array_equal(a["pot"], b["pot"])
         assert np.array_equal(a["nbr_idx"], b["nbr_idx"])
+
+
+def test_reused_context_matches_fresh_context(ctx):
+    """Workspaces left by a larger problem must not leak into a smaller one: a
+    context that has just built a bigger tree gives the same lists (as per-group
+    sequences), forces and neighbours as a fresh context."""
+    from paper_1506_04553_amd import P3T
+    w = WORKLOADS["plummer64k_salpeter"]
+    c = make_cluster(w, seed=3)
+    big = make_cluster(WORKLOADS["plummer256k"], seed=4)
+    used = P3T(0)
+    gpu_run(used, big.pos, big.mass, _params(WORKLOADS["plummer256k"]), want_arrays=False)
+    for prec in ("mixed", "fp64"):
+        p = _params(w, precision=prec)
+        fresh = P3T(0)
+        a = gpu_run(fresh, c.pos, c.mass, p)
+        fresh.close()
+        b = gpu_run(used, c.pos, c.mass, p)
+        for lst in ("cell", "part", "near"):
+            for k in range(len(a["group_node"])):
+                np.testing.assert_array_equal(
+                    a[lst + "_idx"][a[lst + "_beg"][k]:a[lst + "_end"][k]],
+                    b[lst + "_idx"][b[lst + "_beg"][k]:b[lst + "_end"][k]])
+        assert np.array_equal(a["acc"], b["acc"]) and np.array_equal(a["pot"], b["pot"])
+        assert np.array_equal(a["nbr_idx"], b["nbr_idx"])
+    used.close()
 
 
 def test_errors_and_capacity(ctx):

@@ -68,7 +68,14 @@ def test_vjp_theta0_direct(ctx):
 
 
 def _lists_signature(ctx):
-    return [ctx.copy_array(k) for k in ("group_node", "cell_off", "cell_idx", "part_off", "part_idx")]
+    """Groups and every group's lists, concatenated in group order (segment
+    placement in the list arrays may differ between builds)."""
+    out = [ctx.copy_array("group_node")]
+    for lst in ("cell", "part", "near"):
+        b, e, idx = (ctx.copy_array(lst + s) for s in ("_beg", "_end", "_idx"))
+        out.append(np.concatenate([idx[x:y] for x, y in zip(b, e)]) if len(b) else idx)
+        out.append(e - b)
+    return out
 
 
 def _direct_grad_coords(pos, mass, p, w, cw, coords):
