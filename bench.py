@@ -47,6 +47,25 @@ PEAK_UNPACKED_FP32 = 78.6
 F_PP = 23
 F_PC_QUAD = 57
 F_PC_MONO = 24
+HBM_PEAK_GBPS = 8000.0
+
+# Algorithmic HBM bytes of the tree build before the walk (bounding cube to
+# groups): every array read or written once per pass that needs it.
+BUILD_BYTES_PER_PARTICLE = {
+    "bbox": 24,                      # read positions
+    "keys": 24 + 12,                 # read positions; write key + index
+    "sort": 8 * (8 + 12 + 12),       # 8 passes: histogram reads the key, scatter
+                                     # reads and writes key + index
+    "gather": 4 + 32 + 32,           # read index, position + mass; write x y z m
+    "topology": 16,                  # sorted keys read by the neighbour comparisons
+    "moments": 64,                   # leaves read x y z m twice
+    "groups": 12,                    # flag, scan, compaction
+}
+BUILD_BYTES_PER_NODE = {
+    "topology": 32,                  # level first count child n_child parent prefix
+    "moments": 400,                  # write S, walk and multipole records (200 B);
+                                     # the parent reads them back once
+}
 
 
 # HBM bytes per launch of the interaction kernel come from two rocprofv3 --pmc
@@ -129,14 +148,34 @@ def summarize(rec, seconds, steps, quad):
         interactions_per_s=inter / seconds,
         force_ms=avg_force_ms,
         build_ms=float(np.mean([s["ms_build"] for s in rec])),
+        walk_ms=float(np.mean([s["ms_walk"] for s in rec])),
+        n_nodes=float(np.mean([s["n_nodes"] for s in rec])),
         neighbors_ms=float(np.mean([s["ms_neighbors"] for s in rec])),
         force_tflops=avg_flops / (avg_force_ms * 1e-3) / 1e12,
         flops_per_launch=avg_flops,
         n_pp=float(np.mean([s["n_pp"] for s in rec])),
+        n_pp_near=float(np.mean([s["n_pp_near"] for s in rec])),
+        list_entries={k: float(np.mean([s[f"n_{k}_entries"] for s in rec]))
+                      for k in ("cell", "part", "near")},
+        walk_fixed_stride=float(np.mean([s["walk_fixed_stride"] for s in rec])),
         n_pc=float(np.mean([s["n_pc"] for s in rec])),
         n_groups=float(np.mean([s["n_groups"] for s in rec])),
         nnz=float(np.mean([s["nnz"] for s in rec])),
     )
+
+
+def build_roofline(head, n):
+    """Algorithmic HBM rate of the tree build before the walk (the walk itself is
+    bound by dependent node reads, not bandwidth)."""
+    tree_ms = head["build_ms"] - head["walk_ms"]
+    byts = n * sum(BUILD_BYTES_PER_PARTICLE.values()) + \
+        head["n_nodes"] * sum(BUILD_BYTES_PER_NODE.values())
+    gbps = byts / (tree_ms * 1e-3) / 1e9
+    return {"ms": head["build_ms"], "walk_ms": head["walk_ms"], "tree_ms": tree_ms,
+            "algorithmic_bytes": byts, "achieved_GBps": gbps, "peak_GBps": HBM_PEAK_GBPS,
+            "frac": gbps / HBM_PEAK_GBPS,
+            "bytes_per_particle": BUILD_BYTES_PER_PARTICLE,
+            "bytes_per_node": BUILD_BYTES_PER_NODE}
 
 
 def cpu_baseline(pos, mass, params, gpu_first, target_s=12.0, seed=3):
@@ -364,7 +403,11 @@ def main():
                      "flops_per_interaction": {"pp": F_PP, "pc": F_PC_QUAD}},
         "phase_ms": {"build": head["build_ms"], "force": head["force_ms"],
                      "neighbors": head["neighbors_ms"]},
+        "build": build_roofline(head, w.n),
         "interactions_per_step": head["interactions_per_step"],
+        "interactions_split": {"particle_cell": head["n_pc"], "particle_particle": head["n_pp"],
+                               "of_which_near": head["n_pp_near"]},
+        "list_entries": head["list_entries"],
         "n_groups": head["n_groups"],
         "neighbour_pairs": head["nnz"],
     }

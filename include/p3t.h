@@ -71,10 +71,16 @@ typedef struct {
                                  is at least max(h, r_out) from the group box */
     int64_t n_near_entries;   /* sum over groups of |N_g|: particles of the other opened leaves;
                                  the walk's particle list is P_g = F_g + N_g */
+    int64_t cell_extent, part_extent, near_extent; /* entries spanned by the CELL/PART/NEAR
+                                 index arrays: segments may leave unused gaps between them */
     int64_t n_pc, n_pp;       /* interactions: sum_g n_g |C_g|, sum_g n_g |P_g| */
+    int64_t n_pp_near;        /* the part of n_pp over near particles: sum_g n_g |N_g| */
     int64_t nnz;              /* neighbour pairs found by the last p3t_neighbors */
     int32_t walk_global_stack;/* 1 if the walk needed its global-memory stack */
+    int32_t walk_fixed_stride;/* 1 if the lists were written in one walk into segments
+                                 reserved from the previous build's sizes */
     double ms_build, ms_force, ms_neighbors, ms_vjp; /* GPU time of the last calls */
+    double ms_walk;           /* the part of ms_build spent in the group walk (lists) */
 } p3t_stats;
 
 /* Optional device allocator (e.g. a framework's caching allocator). */
@@ -159,14 +165,14 @@ enum {
     P3T_ARR_NODE_BOX = 12,     /* double [n_nodes][6] lo xyz, hi xyz */
     P3T_ARR_GROUP_NODE = 13,   /* int32  [n_groups] node id, ordered by first particle */
     /* Lists: group g's entries of a list are IDX[BEG[g] .. END[g]); the segments of
-     * different groups may lie in any order. */
+     * different groups may lie in any order, with unused gaps between them. */
     P3T_ARR_CELL_BEG = 14,     /* int64  [n_groups] */
-    P3T_ARR_CELL_IDX = 15,     /* int32  [n_cell_entries] node ids of C_g */
+    P3T_ARR_CELL_IDX = 15,     /* int32  [cell_extent] node ids of C_g */
     P3T_ARR_PART_BEG = 16,     /* int64  [n_groups] */
-    P3T_ARR_PART_IDX = 17,     /* int32  [n_part_entries] sorted particle indices of F_g */
+    P3T_ARR_PART_IDX = 17,     /* int32  [part_extent] sorted particle indices of F_g */
     P3T_ARR_ROOT = 18,         /* double [4] lo xyz, side L */
     P3T_ARR_NEAR_BEG = 19,     /* int64  [n_groups] */
-    P3T_ARR_NEAR_IDX = 20,     /* int32  [n_near_entries] sorted particle indices of N_g */
+    P3T_ARR_NEAR_IDX = 20,     /* int32  [near_extent] sorted particle indices of N_g */
     P3T_ARR_CELL_END = 21,     /* int64  [n_groups] */
     P3T_ARR_PART_END = 22,     /* int64  [n_groups] */
     P3T_ARR_NEAR_END = 23      /* int64  [n_groups] */

@@ -154,6 +154,9 @@ __device__ __forceinline__ void pp_full(Slot<R> &q, const PJ<R> &j, int32_t jid,
 
 // cell term; with B = (r.Q.r)/s^4:
 //   phi += -(M + B/2)/s,  a += -(M + 5B/2) r/s^3 + Q r/s^5
+// Where K = W = 1 for every cell (CHECK_K false) the potential is accumulated
+// as two FMAs and the radial factor as -M/s^3 - 5/2 (r.Q.r)/s^7, one operation
+// fewer than scaling a combined factor.
 template <class R, bool QUAD, bool CHECK_K>
 __device__ __forceinline__ void pc_term(Slot<R> &q, const CJ<R> &c, R eps2, R rout2,
                                         const ForceParams &fp) {
@@ -162,6 +165,21 @@ __device__ __forceinline__ void pc_term(Slot<R> &q, const CJ<R> &c, R eps2, R ro
     const R rinv = rsq(r2);
     const R u = rinv * rinv;
     const R rinv3 = rinv * u;
+    if (QUAD && !CHECK_K) {
+        const R Qx = fmaR(c.qxx, rx, fmaR(c.qxy, ry, c.qxz * rz));
+        const R Qy = fmaR(c.qxy, rx, fmaR(c.qyy, ry, c.qyz * rz));
+        const R Qz = fmaR(c.qxz, rx, fmaR(c.qyz, ry, c.qzz * rz));
+        const R rQr = fmaR(rx, Qx, fmaR(ry, Qy, rz * Qz));
+        const R rinv5 = rinv3 * u;
+        const R Bs = rQr * rinv5;   // (r.Q.r)/s^5
+        q.ph = fmaR(-c.M, rinv, q.ph);
+        q.ph = fmaR(Bs, R(-0.5), q.ph);
+        const R cr = fmaR(Bs * u, R(-2.5), -c.M * rinv3);
+        q.ax = fmaR(cr, rx, fmaR(rinv5, Qx, q.ax));
+        q.ay = fmaR(cr, ry, fmaR(rinv5, Qy, q.ay));
+        q.az = fmaR(cr, rz, fmaR(rinv5, Qz, q.az));
+        return;
+    }
     R cr, cq = R(0), pot;
     R Qx = R(0), Qy = R(0), Qz = R(0);
     if (QUAD) {
@@ -207,8 +225,8 @@ __device__ __forceinline__ void pc_term(Slot<R> &q, const CJ<R> &c, R eps2, R ro
 template <class R, bool TWO>
 __device__ __forceinline__ void far_tile(Slot<R> *q, const PJ<R> *sp, int iters, int ns, R eps2) {
 #pragma unroll 2
-    for (int it = 0; it < iters; ++it) {
-        const PJ<R> pj = sp[it * ns];
+    for (int it = 0; it < iters; ++it, sp += ns) {
+        const PJ<R> pj = *sp;
         pp_fast<R>(q[0], pj, eps2);
         if (TWO) pp_fast<R>(q[1], pj, eps2);
     }
@@ -217,9 +235,8 @@ __device__ __forceinline__ void far_tile(Slot<R> *q, const PJ<R> *sp, int iters,
 template <class R, bool TWO>
 __device__ __forceinline__ void near_tile(Slot<R> *q, const PJ<R> *sp, const int32_t *sj, int iters,
                                           int ns, R eps2, R rout2, const ForceParams &fp) {
-    for (int it = 0; it < iters; ++it) {
-        const int k = it * ns;
-        const PJ<R> pj = sp[k];
+    for (int it = 0; it < iters; ++it, sp += ns, sj += ns) {
+        const PJ<R> pj = *sp;
         const R dx0 = pj.x - q[0].x, dy0 = pj.y - q[0].y, dz0 = pj.z - q[0].z;
         bool nr = fmaR(dx0, dx0, fmaR(dy0, dy0, fmaR(dz0, dz0, eps2))) < rout2;
         if (TWO) {
@@ -227,7 +244,7 @@ __device__ __forceinline__ void near_tile(Slot<R> *q, const PJ<R> *sp, const int
             nr = nr | (fmaR(dx1, dx1, fmaR(dy1, dy1, fmaR(dz1, dz1, eps2))) < rout2);
         }
         if (ballot(nr)) {
-            const int32_t jid = sj[k];
+            const int32_t jid = *sj;
             pp_full<R>(q[0], pj, jid, eps2, fp);
             if (TWO) pp_full<R>(q[1], pj, jid, eps2, fp);
         } else {
@@ -241,8 +258,8 @@ template <class R, bool QUAD, bool CHECK_K, bool TWO>
 __device__ __forceinline__ void cell_tile(Slot<R> *q, const CJ<R> *sc, int iters, int ns, R eps2,
                                           R rout2, const ForceParams &fp) {
 #pragma unroll 2
-    for (int it = 0; it < iters; ++it) {
-        const CJ<R> cj = sc[it * ns];
+    for (int it = 0; it < iters; ++it, sc += ns) {
+        const CJ<R> cj = *sc;
         pc_term<R, QUAD, CHECK_K>(q[0], cj, eps2, rout2, fp);
         if (TWO) pc_term<R, QUAD, CHECK_K>(q[1], cj, eps2, rout2, fp);
     }

@@ -81,12 +81,18 @@ struct p3t_ctx {
     p3t::Changeover chg{};
 
     int64_t n_nodes = 0, n_groups = 0, n_leaves = 0, depth = 0;
-    int64_t n_cell_entries = 0, n_part_entries = 0, n_near_entries = 0;
-    int64_t n_pc = 0, n_pp = 0, nnz = 0;
+    int64_t list_total[3] = {0, 0, 0};    // entries of C, F, N over all groups
+    int64_t list_extent[3] = {0, 0, 0};   // entries the list arrays span (segments may leave gaps)
+    int64_t n_pc = 0, n_pp = 0, n_pp_near = 0, nnz = 0;
     int64_t level_start[p3t::kLevels + 2] = {0};
-    int walk_global = 0;
-    double ms_build = 0, ms_force = 0, ms_nbr = 0, ms_vjp = 0;
-    hipEvent_t ev[8] = {nullptr};  // start/end pairs: build, force, neighbours, vjp
+    int walk_global = 0, walk_fixed = 0;
+    // sizes seen by the last two-pass or fixed-stride walk, used to reserve
+    // fixed-stride list segments on the next build
+    int64_t hint_groups = 0, hint_max[3] = {0, 0, 0};
+    int32_t hint_n_crit = -1;
+    int32_t nbr_cap = 0;   // neighbour row slot size for the next p3t_neighbors (0: default)
+    double ms_build = 0, ms_walk = 0, ms_force = 0, ms_nbr = 0, ms_vjp = 0;
+    hipEvent_t ev[10] = {nullptr};  // start/end pairs: build, force, neighbours, vjp, walk
     int64_t *hpin = nullptr;      // pinned host readback area (64 int64)
 
     p3t::DevBuf root, keys[2], vals[2], hist, histc, x, y, z, m;
@@ -95,7 +101,7 @@ struct p3t_ctx {
         node_prefix, node_S, node_walk, node_mp;
     p3t::DevBuf gflag, gscan, grp;
     p3t::DevBuf cnt, off, c_idx, p_idx, n_idx;
-    p3t::DevBuf wstack, dflags, readback, scan_tmp, nbr_cnt;
+    p3t::DevBuf wstack, dflags, readback, scan_tmp, nbr_cnt, nbr_slots;
     p3t::DevBuf vjp_gx, vjp_gm, vjp_cell, bbox;
     p3t::DevBuf seg_end;
 };
@@ -121,7 +127,7 @@ int build_topology(p3t_ctx *ctx, int64_t n);    // sets ctx->n_nodes, level_star
 int build_moments(p3t_ctx *ctx);
 int build_groups(p3t_ctx *ctx);                 // sets ctx->n_groups
 
-// Walk (walk.hip): counts, offsets, list emission; sets list sizes.
+// Walk (walk.hip): lists and their statistics; sets n_groups and list sizes.
 int build_lists(p3t_ctx *ctx);
 
 // Interactions (force.hip).

@@ -2,92 +2,166 @@
 // particle i the particles j != i with |x_j - x_i| < h.  Only the near
 // particles N_g of i's group can be neighbours (every other particle of the
 // walk lies in a leaf whose box is at least h from the group's box, and
-// rounding is monotone, so the FP64 test below fails for it); N_g is staged
-// through LDS in tiles.  The test is dx*dx + dy*dy + dz*dz < h*h in FP64
-// with dx = x_j - x_i, without fused multiply-adds (this file is compiled with
-// -ffp-contract=off), which makes the lists exactly reproducible.
-// Output: CSR in original particle order, each row ascending.
+// rounding is monotone, so the FP64 test below fails for it).  The test is
+// dx*dx + dy*dy + dz*dz < h*h in FP64 with dx = x_j - x_i, without fused
+// multiply-adds (this file is compiled with -ffp-contract=off), which makes
+// the lists exactly reproducible.
+//
+// One block per group.  N_g is staged through LDS in tiles; each staged
+// particle is first tested against the group's bounding box, with the same
+// FP64 expression on the per-axis gaps t = max(lo - x_j, 0, x_j - hi).  Since
+// |dx| >= t for every member and rounding is monotone, a particle whose gap
+// test fails cannot pass the pair test for any member, so only the survivors
+// (usually a handful) are compacted and tested against every member.
+//
+// Rows are written in one pass into fixed-size slots (row o at o * cap, the
+// slot size taken from the longest row of the previous call), then packed into
+// the caller's CSR (original particle order, each row ascending).  A row
+// longer than its slot raises a flag; the pass then runs again writing straight
+// into the CSR at the offsets the first pass counted, and the rows are sorted
+// in place.  Each row is written by the one thread that owns its particle.
 #include "device_util.h"
 #include "internal.h"
 
 namespace p3t {
 
 constexpr int kNbrThreads = 256;
+constexpr int kNbrWaves = kNbrThreads / kWave;
+constexpr int kNbrTile = kNbrThreads;
+constexpr int32_t kNbrFirstCap = 32;
 
-constexpr int kNbrTile = 256;
+__device__ __forceinline__ double axis_gap(double v, double lo, double hi) {
+    const double a = lo - v, b = v - hi;
+    const double t = a > 0.0 ? a : 0.0;
+    return b > t ? b : t;
+}
 
-// One block per group; a lane is (i, slice) as in the interaction kernel: 64/s
-// members times s slices of every staged tile of N_g.  The count pass reduces
-// the slice counts per particle; the fill pass claims row slots with an atomic
-// cursor per particle; a last kernel sorts each row.
-template <bool FILL>
+// CSR = false: rows into slots of `cap` entries, counts into cnt, flag on overflow.
+// CSR = true: rows straight into out at the offsets off (cnt, cap unused).
+template <bool CSR>
 __global__ __launch_bounds__(kNbrThreads) void k_neighbors(
     const GroupInfo *__restrict__ grp, ListsDev L, const double *__restrict__ x,
-    const double *__restrict__ y,
-    const double *__restrict__ z, const int32_t *__restrict__ perm, double h2,
-    int64_t *__restrict__ cnt, const int64_t *__restrict__ offsets, int32_t *__restrict__ cursor,
-    int32_t *__restrict__ idx) {
-    __shared__ double s_x[kNbrTile + kWave], s_y[kNbrTile + kWave], s_z[kNbrTile + kWave];
-    __shared__ int32_t s_j[kNbrTile + kWave];
+    const double *__restrict__ y, const double *__restrict__ z, const int32_t *__restrict__ perm,
+    double h2, int32_t cap, int32_t *__restrict__ out, const int64_t *__restrict__ off,
+    int64_t *__restrict__ cnt, int32_t *__restrict__ overflow) {
+    __shared__ double s_x[kNbrTile], s_y[kNbrTile], s_z[kNbrTile];
+    __shared__ int32_t s_j[kNbrTile];
+    __shared__ int32_t s_wn[kNbrWaves];
     const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
     const GroupInfo gi = grp[blockIdx.x];
     const int64_t nb = L.beg[2][blockIdx.x], ne = L.end[2][blockIdx.x];   // near particles
     const int32_t *__restrict__ n_idx = L.idx[2];
-    if (tid < kWave) {   // padding entries: never within h
-        s_x[kNbrTile + tid] = s_y[kNbrTile + tid] = s_z[kNbrTile + tid] = INFINITY;
-        s_j[kNbrTile + tid] = -2;
-    }
-    const int ls = choose_log2_slices(gi.count, 4);
-    const int ns = 1 << ls, nw = kWave >> ls;
-    const int il = lane & (nw - 1), slice = lane >> (6 - ls);
-    const int V = (gi.count + nw - 1) / nw;
-    for (int v0 = 0; v0 < V; v0 += 4) {
-        const bool act = v0 + w < V;
-        const int li = (v0 + w) * nw + il;
-        const bool valid = act && li < gi.count;
-        const int32_t i = gi.first + (valid ? li : 0);
+
+    for (int m0 = 0; m0 < gi.count; m0 += kNbrThreads) {
+        const bool valid = m0 + tid < gi.count;
+        const int32_t i = gi.first + (valid ? m0 + tid : 0);
         const double xi = x[i], yi = y[i], zi = z[i];
         const int64_t o = perm[i];
-        const int64_t base = (FILL && valid) ? offsets[o] : 0;
+        int32_t *row = CSR ? out + (valid ? off[o] : 0) : out + o * (int64_t)cap;
         int k = 0;
         for (int64_t t0 = nb; t0 < ne; t0 += kNbrTile) {
-            const int tl = (int)min<int64_t>(kNbrTile, ne - t0);
+            // stage: box prefilter, compacted survivors
+            bool cand = false;
+            int32_t j = 0;
+            double xj = 0.0, yj = 0.0, zj = 0.0;
+            if (t0 + tid < ne) {
+                j = n_idx[t0 + tid];
+                xj = x[j];
+                yj = y[j];
+                zj = z[j];
+                const double tx = axis_gap(xj, gi.lo[0], gi.hi[0]);
+                const double ty = axis_gap(yj, gi.lo[1], gi.hi[1]);
+                const double tz = axis_gap(zj, gi.lo[2], gi.hi[2]);
+                cand = tx * tx + ty * ty + tz * tz < h2;
+            }
+            const uint64_t mc = ballot(cand);
+            __syncthreads();   // previous tile consumed
+            if (lane == 0) s_wn[w] = __popcll(mc);
             __syncthreads();
-            if (tid < tl) {
-                const int32_t j = n_idx[t0 + tid];
-                s_x[tid] = x[j];
-                s_y[tid] = y[j];
-                s_z[tid] = z[j];
-                s_j[tid] = j;
-            } else {
-                s_x[tid] = s_y[tid] = s_z[tid] = INFINITY;
-                s_j[tid] = -2;
+            int base = 0, nc = 0;
+            for (int q = 0; q < kNbrWaves; ++q) {
+                base += q < w ? s_wn[q] : 0;
+                nc += s_wn[q];
+            }
+            if (cand) {
+                const int p = base + count_below(mc);
+                s_x[p] = xj;
+                s_y[p] = yj;
+                s_z[p] = zj;
+                s_j[p] = j;
             }
             __syncthreads();
             if (!valid) continue;
-            const int iters = (tl + ns - 1) >> ls;
-            for (int it = 0; it < iters; ++it) {
-                const int e = slice + it * ns;
-                const double dx = s_x[e] - xi, dy = s_y[e] - yi, dz = s_z[e] - zi;
+            for (int c = 0; c < nc; ++c) {
+                const double dx = s_x[c] - xi, dy = s_y[c] - yi, dz = s_z[c] - zi;
                 const double r2 = dx * dx + dy * dy + dz * dz;
-                const int32_t j = s_j[e];
-                if (r2 < h2 && j != i) {
-                    if (FILL) idx[base + atomicAdd(&cursor[o], 1)] = perm[j];
+                const int32_t jj = s_j[c];
+                if (r2 < h2 && jj != i) {
+                    if (CSR || k < cap) row[k] = perm[jj];
                     ++k;
                 }
             }
         }
-        if (!act || FILL) continue;
-        for (int d = nw; d < kWave; d <<= 1) k += __shfl_xor(k, d, kWave);
-        if (valid && slice == 0) cnt[o] = k;
+        if (!CSR && valid) {
+            cnt[o] = k;
+            if (k > cap) atomicOr(overflow, 1);
+        }
     }
 }
 
-// Rows are short: insertion sort of each row into ascending original index.
-__global__ void k_sort_rows(int64_t n, const int64_t *__restrict__ offsets, int32_t *__restrict__ idx) {
+// Longest row (one update per block of 256).
+__global__ __launch_bounds__(256) void k_row_max(int64_t n, const int64_t *__restrict__ cnt,
+                                                  unsigned long long *__restrict__ out) {
+    unsigned long long mx = 0;
+    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n;
+         o += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long c = (unsigned long long)cnt[o];
+        mx = c > mx ? c : mx;
+    }
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        const unsigned long long v = __shfl_xor(mx, d, kWave);
+        mx = v > mx ? v : mx;
+    }
+    __shared__ unsigned long long s_mx[4];
+    if (lane_id() == 0) s_mx[threadIdx.x / kWave] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {   // one update per block
+        for (int q = 1; q < 4; ++q) mx = s_mx[q] > mx ? s_mx[q] : mx;
+        atomicMax(out, mx);
+    }
+}
+
+// Pack row o from its slot into the CSR, ascending (rows are short: insertion
+// sort), and write the caller's offsets.
+__global__ void k_pack_rows(int64_t n, int32_t cap, const int32_t *__restrict__ slots,
+                            const int64_t *__restrict__ off, int64_t *__restrict__ offsets,
+                            int32_t *__restrict__ idx) {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= n) return;
-    const int64_t b0 = offsets[o], len = offsets[o + 1] - b0;
+    if (o > n) return;
+    offsets[o] = off[o];
+    if (o == n) return;
+    const int64_t b0 = off[o], len = off[o + 1] - b0;
+    const int32_t *src = slots + o * (int64_t)cap;
+    int32_t *row = idx + b0;
+    for (int64_t a = 0; a < len; ++a) {
+        const int32_t v = src[a];
+        int64_t b = a - 1;
+        while (b >= 0 && row[b] > v) {
+            row[b + 1] = row[b];
+            --b;
+        }
+        row[b + 1] = v;
+    }
+}
+
+// Sort each CSR row in place and copy the offsets to the caller.
+__global__ void k_sort_rows(int64_t n, const int64_t *__restrict__ off, int64_t *__restrict__ offsets,
+                            int32_t *__restrict__ idx) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o > n) return;
+    offsets[o] = off[o];
+    if (o == n) return;
+    const int64_t b0 = off[o], len = off[o + 1] - b0;
     int32_t *row = idx + b0;
     for (int64_t a = 1; a < len; ++a) {
         const int32_t v = row[a];
@@ -100,52 +174,69 @@ __global__ void k_sort_rows(int64_t n, const int64_t *__restrict__ offsets, int3
     }
 }
 
+// readback slots (int64 units) used here: neighbour total, overflow flag, longest row
+enum { RB_NNZ = 40, RB_NOVF = 41, RB_NMAX = 42 };
+
 int launch_neighbors(p3t_ctx *ctx, int64_t *offsets, int32_t *idx, int64_t cap, int64_t *nnz) {
     int rc;
     const int64_t n = ctx->n;
+    hipStream_t st = ctx->stream;
     if ((rc = ensure(ctx, ctx->nbr_cnt, (n + 1) * sizeof(int64_t)))) return rc;
     int64_t *cnt = ptr<int64_t>(ctx->nbr_cnt);
     int64_t *rb = ptr<int64_t>(ctx->readback);
     const ListsDev L = lists_dev(ctx);
     const double h2 = ctx->prm.r_search * ctx->prm.r_search;
-    if ((rc = check_hip(ctx, hipMemsetAsync(cnt, 0, (n + 1) * sizeof(int64_t), ctx->stream), "memset")))
-        return rc;
     const unsigned grid = (unsigned)ctx->n_groups;
-    if (grid) {
-        k_neighbors<false><<<grid, kNbrThreads, 0, ctx->stream>>>(
-            ptr<GroupInfo>(ctx->grp), L, ptr<double>(ctx->x),
-            ptr<double>(ctx->y), ptr<double>(ctx->z), ptr<int32_t>(ctx->vals[0]), h2, cnt, nullptr,
-            nullptr, nullptr);
-        if ((rc = check_hip(ctx, hipGetLastError(), "neighbour count"))) return rc;
-    }
-    if ((rc = scan_exclusive_i64(ctx, cnt, cnt, n + 1, rb + 40))) return rc;
-    if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + 40, rb + 40, sizeof(int64_t),
-                                            hipMemcpyDeviceToHost, ctx->stream), "readback")))
+    const int32_t row_cap = ctx->nbr_cap > 0 ? ctx->nbr_cap : kNbrFirstCap;
+    if ((rc = ensure(ctx, ctx->nbr_slots, (size_t)n * row_cap * sizeof(int32_t) + 4))) return rc;
+    // the entry past the last particle takes part in the scan as zero
+    if ((rc = check_hip(ctx, hipMemsetAsync(cnt, 0, (n + 1) * sizeof(int64_t), st), "memset")))
         return rc;
-    if ((rc = check_hip(ctx, hipStreamSynchronize(ctx->stream), "sync"))) return rc;
-    const int64_t total = ctx->hpin[40];
+    if ((rc = check_hip(ctx, hipMemsetAsync(rb + RB_NNZ, 0, 3 * sizeof(int64_t), st), "memset")))
+        return rc;
+    if (grid) {
+        k_neighbors<false><<<grid, kNbrThreads, 0, st>>>(
+            ptr<GroupInfo>(ctx->grp), L, ptr<double>(ctx->x), ptr<double>(ctx->y),
+            ptr<double>(ctx->z), ptr<int32_t>(ctx->vals[0]), h2, row_cap,
+            ptr<int32_t>(ctx->nbr_slots), nullptr, cnt, reinterpret_cast<int32_t *>(rb + RB_NOVF));
+        if ((rc = check_hip(ctx, hipGetLastError(), "neighbours"))) return rc;
+    }
+    k_row_max<<<256, 256, 0, st>>>(n, cnt, reinterpret_cast<unsigned long long *>(rb + RB_NMAX));
+    if ((rc = check_hip(ctx, hipGetLastError(), "neighbour row max"))) return rc;
+    if ((rc = scan_exclusive_i64(ctx, cnt, cnt, n + 1, rb + RB_NNZ))) return rc;
+    if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + RB_NNZ, rb + RB_NNZ, 3 * sizeof(int64_t),
+                                            hipMemcpyDeviceToHost, st), "readback")))
+        return rc;
+    if ((rc = check_hip(ctx, hipStreamSynchronize(st), "sync"))) return rc;
+    const int64_t total = ctx->hpin[RB_NNZ];
+    const bool over = *reinterpret_cast<int32_t *>(ctx->hpin + RB_NOVF) != 0;
+    const int64_t longest = ctx->hpin[RB_NMAX];
+    // next call: room for rows a little longer than the longest seen, within
+    // a workspace of at most 1 GiB
+    int64_t want = longest + longest / 4 + 8;
+    const int64_t limit = n > 0 ? ((int64_t)1 << 28) / n : kNbrFirstCap;
+    want = want < kNbrFirstCap ? kNbrFirstCap : want;
+    want = want > limit ? limit : want;
+    ctx->nbr_cap = (int32_t)(want > 1 ? want : 1);
     *nnz = total;
     ctx->nnz = total;
     if (total > cap)
         return set_error(ctx, P3T_ECAPACITY, "neighbour buffer holds %lld entries, %lld needed",
                          (long long)cap, (long long)total);
-    if ((rc = check_hip(ctx, hipMemcpyAsync(offsets, cnt, (n + 1) * sizeof(int64_t),
-                                            hipMemcpyDeviceToDevice, ctx->stream), "copy offsets")))
-        return rc;
-    if (grid && total > 0) {
-        int32_t *cursor = ptr<int32_t>(ctx->gflag);   // free after the build: row cursors
-        if ((rc = check_hip(ctx, hipMemsetAsync(cursor, 0, n * sizeof(int32_t), ctx->stream),
-                            "memset")))
-            return rc;
-        k_neighbors<true><<<grid, kNbrThreads, 0, ctx->stream>>>(
-            ptr<GroupInfo>(ctx->grp), L, ptr<double>(ctx->x),
-            ptr<double>(ctx->y), ptr<double>(ctx->z), ptr<int32_t>(ctx->vals[0]), h2, nullptr, cnt,
-            cursor, idx);
-        if ((rc = check_hip(ctx, hipGetLastError(), "neighbour fill"))) return rc;
-        k_sort_rows<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, cnt, idx);
-        if ((rc = check_hip(ctx, hipGetLastError(), "neighbour sort"))) return rc;
+    if (!over) {
+        k_pack_rows<<<blocks_for(n + 1, 256), 256, 0, st>>>(n, row_cap, ptr<int32_t>(ctx->nbr_slots),
+                                                            cnt, offsets, idx);
+        return check_hip(ctx, hipGetLastError(), "neighbour pack");
     }
-    return P3T_OK;
+    // some row did not fit its slot: write the rows straight into the CSR
+    if (grid) {
+        k_neighbors<true><<<grid, kNbrThreads, 0, st>>>(
+            ptr<GroupInfo>(ctx->grp), L, ptr<double>(ctx->x), ptr<double>(ctx->y),
+            ptr<double>(ctx->z), ptr<int32_t>(ctx->vals[0]), h2, 0, idx, cnt, nullptr, nullptr);
+        if ((rc = check_hip(ctx, hipGetLastError(), "neighbours (CSR)"))) return rc;
+    }
+    k_sort_rows<<<blocks_for(n + 1, 256), 256, 0, st>>>(n, cnt, offsets, idx);
+    return check_hip(ctx, hipGetLastError(), "neighbour sort");
 }
 
 }  // namespace p3t

@@ -131,7 +131,7 @@ extern "C" int p3t_create(p3t_ctx **out, int device, void *hip_stream, p3t_alloc
     ctx->free_ = free_;
     ctx->user = alloc_user;
     hipError_t e = hipHostMalloc((void **)&ctx->hpin, 64 * sizeof(int64_t), hipHostMallocDefault);
-    for (int k = 0; k < 8 && e == hipSuccess; ++k) e = hipEventCreate(&ctx->ev[k]);
+    for (int k = 0; k < 10 && e == hipSuccess; ++k) e = hipEventCreate(&ctx->ev[k]);
     if (e != hipSuccess) {
         p3t_destroy(ctx);
         return P3T_EHIP;
@@ -152,16 +152,16 @@ extern "C" void p3t_destroy(p3t_ctx *ctx) {
                       &ctx->node_prefix, &ctx->node_S, &ctx->node_walk, &ctx->node_mp, &ctx->gflag,
                       &ctx->gscan, &ctx->grp, &ctx->cnt, &ctx->off, &ctx->c_idx, &ctx->p_idx,
                       &ctx->n_idx, &ctx->wstack, &ctx->dflags, &ctx->readback, &ctx->scan_tmp,
-                      &ctx->nbr_cnt, &ctx->vjp_gx, &ctx->vjp_gm, &ctx->vjp_cell, &ctx->bbox,
+                      &ctx->nbr_cnt, &ctx->nbr_slots, &ctx->vjp_gx, &ctx->vjp_gm, &ctx->vjp_cell, &ctx->bbox,
                       &ctx->seg_end};
     for (DevBuf *b : bufs) release(ctx, *b);
     if (ctx->hpin) (void)hipHostFree(ctx->hpin);
-    for (int k = 0; k < 8; ++k)
+    for (int k = 0; k < 10; ++k)
         if (ctx->ev[k]) (void)hipEventDestroy(ctx->ev[k]);
     delete ctx;
 }
 
-enum { EV_BUILD = 0, EV_FORCE = 2, EV_NBR = 4, EV_VJP = 6 };
+enum { EV_BUILD = 0, EV_FORCE = 2, EV_NBR = 4, EV_VJP = 6, EV_WALK = 8 };
 
 static int mark(p3t_ctx *ctx, int ev) {
     return check_hip(ctx, hipEventRecord(ctx->ev[ev], ctx->stream), "event record");
@@ -197,9 +197,11 @@ extern "C" int p3t_build_tree(p3t_ctx *ctx, int64_t n, const double *pos, const 
     if ((rc = build_topology(ctx, n))) return rc;
     if ((rc = build_moments(ctx))) return rc;
     if ((rc = build_groups(ctx))) return rc;
+    if ((rc = mark(ctx, EV_WALK))) return rc;
     if ((rc = build_lists(ctx))) return rc;
+    if ((rc = mark(ctx, EV_WALK + 1))) return rc;
     if ((rc = mark(ctx, EV_BUILD + 1))) return rc;
-    ctx->ms_build = -1.0;   // resolved lazily by p3t_get_stats
+    ctx->ms_build = ctx->ms_walk = -1.0;   // resolved lazily by p3t_get_stats
     ctx->ms_force = ctx->ms_nbr = ctx->ms_vjp = 0.0;
     ctx->built = 1;
     return P3T_OK;
@@ -258,6 +260,7 @@ extern "C" int p3t_kick_drift(p3t_ctx *ctx, int64_t n, double *pos, double *vel,
 extern "C" int p3t_get_stats(p3t_ctx *ctx, p3t_stats *out) {
     if (!ctx || !out) return P3T_EINVAL;
     if (ctx->ms_build < 0.0 && elapsed_ms(ctx, EV_BUILD, &ctx->ms_build)) ctx->ms_build = 0.0;
+    if (ctx->ms_walk < 0.0 && elapsed_ms(ctx, EV_WALK, &ctx->ms_walk)) ctx->ms_walk = 0.0;
     if (ctx->ms_force < 0.0 && elapsed_ms(ctx, EV_FORCE, &ctx->ms_force)) ctx->ms_force = 0.0;
     if (ctx->ms_nbr < 0.0 && elapsed_ms(ctx, EV_NBR, &ctx->ms_nbr)) ctx->ms_nbr = 0.0;
     if (ctx->ms_vjp < 0.0 && elapsed_ms(ctx, EV_VJP, &ctx->ms_vjp)) ctx->ms_vjp = 0.0;
@@ -267,14 +270,20 @@ extern "C" int p3t_get_stats(p3t_ctx *ctx, p3t_stats *out) {
     out->n_leaves = ctx->n_leaves;
     out->n_groups = ctx->n_groups;
     out->depth = ctx->depth;
-    out->n_cell_entries = ctx->n_cell_entries;
-    out->n_part_entries = ctx->n_part_entries;
-    out->n_near_entries = ctx->n_near_entries;
+    out->n_cell_entries = ctx->list_total[0];
+    out->n_part_entries = ctx->list_total[1];
+    out->n_near_entries = ctx->list_total[2];
+    out->cell_extent = ctx->list_extent[0];
+    out->part_extent = ctx->list_extent[1];
+    out->near_extent = ctx->list_extent[2];
+    out->n_pp_near = ctx->n_pp_near;
+    out->walk_fixed_stride = ctx->walk_fixed;
     out->n_pc = ctx->n_pc;
     out->n_pp = ctx->n_pp;
     out->nnz = ctx->nnz;
     out->walk_global_stack = ctx->walk_global;
     out->ms_build = ctx->ms_build;
+    out->ms_walk = ctx->ms_walk;
     out->ms_force = ctx->ms_force;
     out->ms_neighbors = ctx->ms_nbr;
     out->ms_vjp = ctx->ms_vjp;
@@ -318,12 +327,12 @@ extern "C" int p3t_copy_array(p3t_ctx *ctx, int which, void *dst, int64_t bytes)
     case P3T_ARR_CELL_END: src = ctx->seg_end.p; size = G * 8; break;
     case P3T_ARR_PART_END: src = (const int64_t *)ctx->seg_end.p + stride; size = G * 8; break;
     case P3T_ARR_NEAR_END: src = (const int64_t *)ctx->seg_end.p + 2 * stride; size = G * 8; break;
-    case P3T_ARR_CELL_IDX: src = ctx->c_idx.p; size = ctx->n_cell_entries * 4; break;
+    case P3T_ARR_CELL_IDX: src = ctx->c_idx.p; size = ctx->list_extent[0] * 4; break;
     case P3T_ARR_PART_BEG: src = (const int64_t *)ctx->off.p + stride; size = G * 8; break;
-    case P3T_ARR_PART_IDX: src = ctx->p_idx.p; size = ctx->n_part_entries * 4; break;
+    case P3T_ARR_PART_IDX: src = ctx->p_idx.p; size = ctx->list_extent[1] * 4; break;
     case P3T_ARR_ROOT: src = ctx->root.p; size = 32; break;
     case P3T_ARR_NEAR_BEG: src = (const int64_t *)ctx->off.p + 2 * stride; size = G * 8; break;
-    case P3T_ARR_NEAR_IDX: src = ctx->n_idx.p; size = ctx->n_near_entries * 4; break;
+    case P3T_ARR_NEAR_IDX: src = ctx->n_idx.p; size = ctx->list_extent[2] * 4; break;
     default: return set_error(ctx, P3T_EINVAL, "unknown array id %d", which);
     }
     if (rows) size = rows * pitch;

@@ -497,9 +497,10 @@ int build_topology(p3t_ctx *ctx, int64_t n) {
 // ---------------------------------------------------------------------------
 // Moments, one launch per level from the deepest up.
 // ---------------------------------------------------------------------------
-// mode 1: every leaf of the tree (leaves depend on particles only);
-// mode 2: the internal nodes of one level (their children are complete).
-__global__ void k_moments_level(int64_t begin, int64_t end, int lev, int mode,
+// MODE 1: every leaf of the tree (leaves depend on particles only);
+// MODE 2: the internal nodes of one level (their children are complete).
+template <int MODE>
+__global__ __launch_bounds__(128) void k_moments_level(int64_t begin, int64_t end, int lev,
                                 const int32_t *__restrict__ level, const RootInfo *__restrict__ root,
                                 const double *__restrict__ x, const double *__restrict__ y,
                                 const double *__restrict__ z, const double *__restrict__ m,
@@ -510,50 +511,97 @@ __global__ void k_moments_level(int64_t begin, int64_t end, int lev, int mode,
     const int64_t id = begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= end) return;
     const int nc = nchild[id];
-    if ((mode == 1) != (nc == 0)) return;
-    if (mode == 1) lev = level[id];
+    if ((MODE == 1) != (nc == 0)) return;
+    if (MODE == 1) lev = level[id];
     const int32_t f = first[id], cnt = count[id];
     double M = 0.0, Sx = 0.0, Sy = 0.0, Sz = 0.0;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     double q[6] = {0, 0, 0, 0, 0, 0};
-    if (nc == 0) {
-        for (int32_t k = f; k < f + cnt; ++k) {
-            const double mk = m[k], xk = x[k], yk = y[k], zk = z[k];
-            M = M + mk;
-            Sx = Sx + mk * xk;
-            Sy = Sy + mk * yk;
-            Sz = Sz + mk * zk;
-            lo[0] = fmin(lo[0], xk); lo[1] = fmin(lo[1], yk); lo[2] = fmin(lo[2], zk);
-            hi[0] = fmax(hi[0], xk); hi[1] = fmax(hi[1], yk); hi[2] = fmax(hi[2], zk);
+    if (MODE == 1) {
+        // particles in chunks of 8, loaded together (clamped to the last
+        // member), folded in order
+        const int32_t e = f + cnt;
+        for (int32_t k0 = f; k0 < e; k0 += 8) {
+            double cm[8], cx8[8], cy8[8], cz8[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int32_t k = k0 + c < e ? k0 + c : e - 1;
+                cm[c] = m[k]; cx8[c] = x[k]; cy8[c] = y[k]; cz8[c] = z[k];
+            }
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                if (k0 + c >= e) continue;
+                const double mk = cm[c], xk = cx8[c], yk = cy8[c], zk = cz8[c];
+                M = M + mk;
+                Sx = Sx + mk * xk;
+                Sy = Sy + mk * yk;
+                Sz = Sz + mk * zk;
+                lo[0] = fmin(lo[0], xk); lo[1] = fmin(lo[1], yk); lo[2] = fmin(lo[2], zk);
+                hi[0] = fmax(hi[0], xk); hi[1] = fmax(hi[1], yk); hi[2] = fmax(hi[2], zk);
+            }
         }
         const double cx = Sx / M, cy = Sy / M, cz = Sz / M;
-        for (int32_t k = f; k < f + cnt; ++k) {
-            const double mk = m[k];
-            const double dx = x[k] - cx, dy = y[k] - cy, dz = z[k] - cz;
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            q[0] += mk * (3.0 * dx * dx - r2);
-            q[1] += mk * (3.0 * dy * dy - r2);
-            q[2] += mk * (3.0 * dz * dz - r2);
-            q[3] += mk * 3.0 * dx * dy;
-            q[4] += mk * 3.0 * dx * dz;
-            q[5] += mk * 3.0 * dy * dz;
+        for (int32_t k0 = f; k0 < e; k0 += 8) {
+            double cm[8], cx8[8], cy8[8], cz8[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int32_t k = k0 + c < e ? k0 + c : e - 1;
+                cm[c] = m[k]; cx8[c] = x[k]; cy8[c] = y[k]; cz8[c] = z[k];
+            }
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                if (k0 + c >= e) continue;
+                const double mk = cm[c];
+                const double dx = cx8[c] - cx, dy = cy8[c] - cy, dz = cz8[c] - cz;
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                q[0] += mk * (3.0 * dx * dx - r2);
+                q[1] += mk * (3.0 * dy * dy - r2);
+                q[2] += mk * (3.0 * dz * dz - r2);
+                q[3] += mk * 3.0 * dx * dy;
+                q[4] += mk * 3.0 * dx * dz;
+                q[5] += mk * 3.0 * dy * dz;
+            }
         }
     } else {
         const int32_t cf = child[id];
-        for (int k = cf; k < cf + nc; ++k) {
-            M = M + mp[k].M;
-            Sx = Sx + S[k];
-            Sy = Sy + S[n_nodes + k];
-            Sz = Sz + S[2 * n_nodes + k];
+        // at most 8 children: every child slot is loaded (clamped to the last
+        // child) so that the loads issue together; the folds keep child order
+        // and skip the slots past nc
+        double cM[8], cS[8][3], clo[8][3], chi[8][3];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int k = cf + (c < nc ? c : nc - 1);
+            cM[c] = mp[k].M;
+            cS[c][0] = S[k];
+            cS[c][1] = S[n_nodes + k];
+            cS[c][2] = S[2 * n_nodes + k];
             for (int a = 0; a < 3; ++a) {
-                lo[a] = fmin(lo[a], nw[k].lo[a]);
-                hi[a] = fmax(hi[a], nw[k].hi[a]);
+                clo[c][a] = nw[k].lo[a];
+                chi[c][a] = nw[k].hi[a];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            if (c < nc) {
+                M = M + cM[c];
+                Sx = Sx + cS[c][0];
+                Sy = Sy + cS[c][1];
+                Sz = Sz + cS[c][2];
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = fmin(lo[a], clo[c][a]);
+                    hi[a] = fmax(hi[a], chi[c][a]);
+                }
             }
         }
         const double cx = Sx / M, cy = Sy / M, cz = Sz / M;
         // parallel-axis shift of the children's quadrupoles to this centre
-        for (int k = cf; k < cf + nc; ++k) {
-            const NodeMP c = mp[k];
+        NodeMP cm[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) cm[c] = mp[cf + (c < nc ? c : nc - 1)];
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+            if (cc >= nc) continue;
+            const NodeMP c = cm[cc];
             const double dx = c.cx - cx, dy = c.cy - cy, dz = c.cz - cz;
             const double r2 = dx * dx + dy * dy + dz * dz;
             q[0] += c.q[0] + c.M * (3.0 * dx * dx - r2);
@@ -596,8 +644,9 @@ int build_moments(p3t_ctx *ctx) {
         const int64_t b = leaves ? 0 : ctx->level_start[l];
         const int64_t e = leaves ? nn : ctx->level_start[l + 1];
         if (e <= b || l == kMaxLevel) continue;   // level 21 holds leaves only
-        k_moments_level<<<blocks_for(e - b, 128), 128, 0, ctx->stream>>>(
-            b, e, l, leaves ? 1 : 2, ptr<int32_t>(ctx->node_level), ptr<RootInfo>(ctx->root),
+        auto kern = leaves ? k_moments_level<1> : k_moments_level<2>;
+        kern<<<blocks_for(e - b, 128), 128, 0, ctx->stream>>>(
+            b, e, l, ptr<int32_t>(ctx->node_level), ptr<RootInfo>(ctx->root),
             ptr<double>(ctx->x), ptr<double>(ctx->y),
             ptr<double>(ctx->z), ptr<double>(ctx->m), ptr<int32_t>(ctx->node_first),
             ptr<int32_t>(ctx->node_count), ptr<int32_t>(ctx->node_child),
@@ -614,10 +663,8 @@ int build_moments(p3t_ctx *ctx) {
 __global__ void k_group_mark(int64_t n_nodes, const int32_t *__restrict__ count,
                              const int32_t *__restrict__ nchild, const int32_t *__restrict__ parent,
                              const int32_t *__restrict__ first, int n_crit, int32_t *__restrict__ flag,
-                             int32_t *__restrict__ node_at, unsigned long long *__restrict__ n_leaves) {
+                             int32_t *__restrict__ node_at) {
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t leaves = ballot(id < n_nodes && nchild[id] == 0);   // one atomic per wavefront
-    if (lane_id() == 0 && leaves) atomicAdd(n_leaves, (unsigned long long)__popcll(leaves));
     if (id >= n_nodes) return;
     const bool cand = count[id] <= n_crit || nchild[id] == 0;
     const bool top = (id == 0) || count[parent[id]] > n_crit;
@@ -658,13 +705,9 @@ int build_groups(p3t_ctx *ctx) {
     int32_t *node_at = ptr<int32_t>(ctx->lvlrange);
     if ((rc = check_hip(ctx, hipMemsetAsync(flag, 0, (n + 1) * sizeof(int32_t), ctx->stream), "memset")))
         return rc;
-    if ((rc = check_hip(ctx, hipMemsetAsync(ptr<int64_t>(ctx->readback) + 32, 0, sizeof(int64_t),
-                                            ctx->stream), "memset")))
-        return rc;
     k_group_mark<<<blocks_for(nn, 256), 256, 0, ctx->stream>>>(
         nn, ptr<int32_t>(ctx->node_count), ptr<int32_t>(ctx->node_nchild),
-        ptr<int32_t>(ctx->node_parent), ptr<int32_t>(ctx->node_first), ctx->prm.n_crit, flag, node_at,
-        (unsigned long long *)(ptr<int64_t>(ctx->readback) + 32));
+        ptr<int32_t>(ctx->node_parent), ptr<int32_t>(ctx->node_first), ctx->prm.n_crit, flag, node_at);
     if ((rc = check_hip(ctx, hipGetLastError(), "group mark"))) return rc;
     // slot[n] = number of groups (device), read back together with the list sizes
     if ((rc = scan_exclusive_i32(ctx, flag, slot, n + 1, nullptr))) return rc;

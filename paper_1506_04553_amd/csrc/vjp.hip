@@ -74,8 +74,8 @@ __device__ __forceinline__ void pair_grad(double dx, double dy, double dz, doubl
                                           double wy, double wz, double ci, const VjpParams &vp,
                                           double gd[3], double &gm) {
     const double s2 = dx * dx + dy * dy + dz * dz + vp.eps2;
-    const double s = sqrt(s2);
-    const double inv = 1.0 / s;
+    const double inv = rsqrt(s2);
+    const double s = s2 * inv;
     const double inv2 = inv * inv, inv3 = inv2 * inv;
     const Chg c = changeover_ds(s, vp);
     const double g = c.K * inv3;
@@ -98,8 +98,8 @@ __device__ __forceinline__ void cell_grad(double rx, double ry, double rz, doubl
                                           double wx, double wy, double wz, double ci,
                                           const VjpParams &vp, CellGrad &o) {
     const double s2 = rx * rx + ry * ry + rz * rz + vp.eps2;
-    const double s = sqrt(s2);
-    const double inv = 1.0 / s;
+    const double inv = rsqrt(s2);
+    const double s = s2 * inv;
     const double inv2 = inv * inv, inv3 = inv2 * inv, inv5 = inv3 * inv2, inv7 = inv5 * inv2,
                  inv9 = inv7 * inv2;
     const Chg c = changeover_ds(s, vp);
@@ -160,11 +160,14 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
     const GroupInfo gi = grp[blockIdx.x];
     const int64_t cb = L.beg[0][blockIdx.x], ce = L.end[0][blockIdx.x];
     const int32_t *__restrict__ c_idx = L.idx[0];
-    for (int chunk = 0; chunk < gi.count; chunk += kVjpThreads) {
-        const int nc = min(kVjpThreads, gi.count - chunk);
+    // members in chunks of the largest power of two that fits (at most 256),
+    // so that a chunk fills its lanes: 74 members run as 64 + 8 + 2
+    for (int chunk = 0, nc = 0; chunk < gi.count; chunk += nc) {
+        const int rem = gi.count - chunk;
         int lg = 0;
-        while ((1 << lg) < nc) ++lg;
-        const int pad = 1 << lg, nslice = kVjpThreads >> lg;
+        while (lg < 8 && (2 << lg) <= rem) ++lg;
+        nc = 1 << lg;
+        const int pad = nc, nslice = kVjpThreads >> lg;
         const int li = tid & (pad - 1), slice = tid >> lg;
         const bool valid = li < nc;
         const int32_t i = gi.first + chunk + (valid ? li : 0);

@@ -20,20 +20,26 @@
 // the stack; the walk runs with a small stack in LDS and falls back to a
 // per-block stack of that bound in global memory if a group overflows it.
 //
-// The lists are produced in two passes: count, prefix-sum, then walk again
-// writing at the exact offsets; the statistics (interaction counts, longest
-// lists) are reductions over the per-group counts, so no two groups ever
-// update the same memory word.
+// Two ways to lay out the lists, both as one (begin, end) segment per group and
+// list, with no two groups ever updating the same memory word:
+//   fixed stride (when an earlier build gives the group count and the longest
+//     lists): group g writes list k at g * cap_k in a single walk; a group
+//     beyond the estimated count or a list longer than cap_k raises a flag and
+//     the build falls back to
+//   two passes: count, prefix-sum, then walk again writing at the exact
+//     offsets (segments tile the arrays).
+// The statistics (list totals, interaction counts, longest lists) are
+// reductions over the per-group counts.
 #include "device_util.h"
 #include "internal.h"
 
 namespace p3t {
 
 constexpr int kWalkThreads = 64;        // one wavefront per block
-constexpr int kLdsStack = 2048;
+constexpr int kLdsStack = 1536;
 constexpr int kGlobalStack = kLevels * 8 * kWave + kWave;
 
-enum WalkMode { kCount = 0, kEmit = 1 };
+enum WalkMode { kCount = 0, kEmit = 1, kFixed = 2 };
 
 struct WalkParams {
     double th2, h2, hn2;   // theta^2, h^2, max(h, r_out)^2
@@ -41,10 +47,13 @@ struct WalkParams {
 
 // Device outputs of one walk launch.
 struct WalkOut {
-    int64_t *cnt;            // [3][stride] per-group counts (count pass)
-    int64_t *beg, *end;      // [3][stride] segments (emit pass)
-    int32_t *idx[3];         // final lists
-    int32_t *stack_ovf;
+    int64_t *cnt;            // [3][stride] per-group counts (count and fixed passes)
+    int64_t *beg, *end;      // [3][stride] segments (emit and fixed passes)
+    int32_t *idx[3];         // lists
+    int64_t cap[3];          // fixed: entries reserved per group and list
+    int64_t gcap;            // fixed: groups the lists have room for
+    int32_t *stack_ovf;      // set if a group overflowed the stack
+    int32_t *cap_ovf;        // fixed: set if some group did not fit
     int64_t stride;
 };
 
@@ -69,8 +78,14 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(const GroupInfo *__restri
         const GroupInfo gi = grp[g];
         int64_t run[3] = {0, 0, 0};
         int32_t *dst[3] = {nullptr, nullptr, nullptr};
+        if (MODE == kFixed && g >= wo.gcap) {
+            if (lane == 0) atomicOr(wo.cap_ovf, 1);
+            continue;
+        }
         if (MODE == kEmit)
             for (int k = 0; k < 3; ++k) dst[k] = wo.idx[k] + wo.beg[k * S + g];
+        if (MODE == kFixed)
+            for (int k = 0; k < 3; ++k) dst[k] = wo.idx[k] + (int64_t)g * wo.cap[k];
         int sp = 1;
         if (lane == 0) stk[0] = 0;
         __syncthreads();
@@ -108,7 +123,10 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(const GroupInfo *__restri
             // accepted cells
             {
                 const uint64_t mC = ballot(isC);
-                if (MODE == kEmit && isC) dst[0][run[0] + count_below(mC)] = node;
+                if (MODE != kCount && isC) {
+                    const int64_t pos = run[0] + count_below(mC);
+                    if (MODE == kEmit || pos < wo.cap[0]) dst[0][pos] = node;
+                }
                 run[0] += __popcll(mC);
             }
             // particles of far, then near, opened leaves
@@ -121,6 +139,12 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(const GroupInfo *__restri
                 if (MODE == kEmit && mine) {
                     int32_t *d = dst[kk] + run[kk] + excl;
                     for (int t = 0; t < c; ++t) d[t] = first + t;
+                }
+                if (MODE == kFixed && mine) {
+                    const int64_t pos = run[kk] + excl;
+                    const int64_t lim = wo.cap[kk] - pos;
+                    const int cc = lim < c ? (lim > 0 ? (int)lim : 0) : c;
+                    for (int t = 0; t < cc; ++t) dst[kk][pos + t] = first + t;
                 }
                 run[kk] += tot;
             }
@@ -145,43 +169,84 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(const GroupInfo *__restri
             continue;
         }
         if (lane == 0) {
+            bool over = false;
             for (int k = 0; k < 3; ++k) {
                 if (MODE == kCount) wo.cnt[k * S + g] = run[k];
-                else wo.end[k * S + g] = wo.beg[k * S + g] + run[k];
+                if (MODE == kEmit) wo.end[k * S + g] = wo.beg[k * S + g] + run[k];
+                if (MODE == kFixed) {
+                    const int64_t b = (int64_t)g * wo.cap[k];
+                    over = over || run[k] > wo.cap[k];
+                    wo.cnt[k * S + g] = run[k];
+                    wo.beg[k * S + g] = b;
+                    wo.end[k * S + g] = b + (run[k] < wo.cap[k] ? run[k] : wo.cap[k]);
+                }
             }
+            if (over) atomicOr(wo.cap_ovf, 1);
         }
     }
 }
 
-// Statistics from the per-group counts: interactions sum_g n_g |C_g| and
-// sum_g n_g (|F_g| + |N_g|), and the longest list of each kind.
+// Walk results read back by the host (int64 slots).
+struct WalkStats {
+    unsigned long long total[3];   // sum over groups of |C_g|, |F_g|, |N_g|
+    unsigned long long n_groups;
+    unsigned long long pc, pp;     // sum_g n_g |C_g|, sum_g n_g (|F_g| + |N_g|)
+    unsigned long long pp_near;    // sum_g n_g |N_g|
+    unsigned long long n_leaves;
+    unsigned long long maxlen[3];  // longest list of each kind
+    int32_t stack_ovf, cap_ovf;    // flags written by the walk
+};
+
+// Statistics from the per-group counts, and the leaf count of the tree.
 __global__ __launch_bounds__(256) void k_walk_stats(const GroupInfo *__restrict__ grp,
                                                     const int32_t *__restrict__ n_groups_dev,
                                                     const int64_t *__restrict__ cnt, int64_t S,
-                                                    unsigned long long *__restrict__ out) {
+                                                    const int32_t *__restrict__ nchild,
+                                                    int64_t n_nodes, WalkStats *__restrict__ out) {
     const int G = *n_groups_dev;
-    unsigned long long pc = 0, pp = 0, mx[3] = {0, 0, 0};
-    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x) {
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+    unsigned long long tot[3] = {0, 0, 0}, mx[3] = {0, 0, 0}, pc = 0, pp = 0, ppn = 0, lv = 0;
+    for (int64_t g = t0; g < G; g += nt) {
         const unsigned long long n = (unsigned long long)grp[g].count;
-        const unsigned long long c0 = cnt[g], c1 = cnt[S + g], c2 = cnt[2 * S + g];
-        pc += n * c0;
-        pp += n * (c1 + c2);
-        mx[0] = c0 > mx[0] ? c0 : mx[0];
-        mx[1] = c1 > mx[1] ? c1 : mx[1];
-        mx[2] = c2 > mx[2] ? c2 : mx[2];
-    }
-    pc = wave_sum(pc);
-    pp = wave_sum(pp);
-    for (int k = 0; k < 3; ++k)
-        for (int d = kWave / 2; d > 0; d >>= 1) {
-            const unsigned long long o = __shfl_xor(mx[k], d, kWave);
-            mx[k] = o > mx[k] ? o : mx[k];
+        for (int k = 0; k < 3; ++k) {
+            const unsigned long long c = cnt[k * S + g];
+            tot[k] += c;
+            mx[k] = c > mx[k] ? c : mx[k];
         }
-    if (lane_id() == 0) {   // one update per wavefront
-        atomicAdd(&out[0], pc);
-        atomicAdd(&out[1], pp);
-        for (int k = 0; k < 3; ++k) atomicMax(&out[3 + k], mx[k]);
+        pc += n * cnt[g];
+        pp += n * (cnt[S + g] + cnt[2 * S + g]);
+        ppn += n * cnt[2 * S + g];
     }
+    for (int64_t i = t0; i < n_nodes; i += nt) lv += nchild[i] == 0;
+    // wave reductions, then one set of updates per block
+    __shared__ unsigned long long s_red[4][10];
+    unsigned long long v[10] = {pc, pp, ppn, lv, tot[0], tot[1], tot[2], mx[0], mx[1], mx[2]};
+    for (int k = 0; k < 7; ++k) v[k] = wave_sum(v[k]);
+    for (int k = 7; k < 10; ++k)
+        for (int d = kWave / 2; d > 0; d >>= 1) {
+            const unsigned long long o = __shfl_xor(v[k], d, kWave);
+            v[k] = o > v[k] ? o : v[k];
+        }
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0)
+        for (int k = 0; k < 10; ++k) s_red[w][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < (int)(blockDim.x / kWave); ++q) {
+            for (int k = 0; k < 7; ++k) v[k] += s_red[q][k];
+            for (int k = 7; k < 10; ++k) v[k] = s_red[q][k] > v[k] ? s_red[q][k] : v[k];
+        }
+        atomicAdd(&out->pc, v[0]);
+        atomicAdd(&out->pp, v[1]);
+        atomicAdd(&out->pp_near, v[2]);
+        atomicAdd(&out->n_leaves, v[3]);
+        for (int k = 0; k < 3; ++k) {
+            atomicAdd(&out->total[k], v[4 + k]);
+            atomicMax(&out->maxlen[k], v[7 + k]);
+        }
+    }
+    if (t0 == 0) out->n_groups = (unsigned long long)G;
 }
 
 static unsigned walk_grid(p3t_ctx *ctx) {
@@ -202,11 +267,23 @@ ListsDev lists_dev(const p3t_ctx *ctx) {
     return L;
 }
 
-// read-back slots of the walk (int64 units of the readback area); slot 32 holds
-// the leaf count written while marking groups
-enum { RB_TOT = 24, RB_G = 28, RB_STACK = 29, RB_INTER = 30, RB_LEAVES = 32, RB_MAX = 33 };
+// the walk's results sit in the readback area from this int64 slot on
+constexpr int kRbWalk = 24;
+
+static int run_walk_stats(p3t_ctx *ctx, const int32_t *G_dev, int64_t stride, WalkStats *ws) {
+    k_walk_stats<<<256, 256, 0, ctx->stream>>>(ptr<GroupInfo>(ctx->grp), G_dev,
+                                              ptr<int64_t>(ctx->cnt), stride,
+                                              ptr<int32_t>(ctx->node_nchild), ctx->n_nodes, ws);
+    int rc = check_hip(ctx, hipGetLastError(), "walk stats");
+    if (rc) return rc;
+    if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + kRbWalk, ws, sizeof(WalkStats),
+                                            hipMemcpyDeviceToHost, ctx->stream), "readback")))
+        return rc;
+    return check_hip(ctx, hipStreamSynchronize(ctx->stream), "sync");
+}
 
 int build_lists(p3t_ctx *ctx) {
+    static_assert(kRbWalk * 8 + sizeof(WalkStats) <= 40 * 8, "walk readback overlaps other slots");
     int rc;
     const int64_t nn = ctx->n_nodes;   // bound on the number of groups
     const int64_t stride = nn + 1;
@@ -215,8 +292,8 @@ int build_lists(p3t_ctx *ctx) {
     if ((rc = ensure(ctx, ctx->seg_end, 3 * stride * sizeof(int64_t)))) return rc;
     int64_t *cnt = ptr<int64_t>(ctx->cnt), *off = ptr<int64_t>(ctx->off);
     int64_t *end = ptr<int64_t>(ctx->seg_end);
-    int64_t *rb = ptr<int64_t>(ctx->readback);
-    int32_t *flags = ptr<int32_t>(ctx->dflags);
+    WalkStats *ws = reinterpret_cast<WalkStats *>(ptr<int64_t>(ctx->readback) + kRbWalk);
+    const WalkStats *hs = reinterpret_cast<const WalkStats *>(ctx->hpin + kRbWalk);
     const int32_t *G_dev = ptr<int32_t>(ctx->gscan) + ctx->n;
     const double hn = ctx->prm.r_search > ctx->prm.r_out ? ctx->prm.r_search : ctx->prm.r_out;
     const WalkParams wp{ctx->prm.theta * ctx->prm.theta, ctx->prm.r_search * ctx->prm.r_search,
@@ -228,67 +305,94 @@ int build_lists(p3t_ctx *ctx) {
     wo.cnt = cnt;
     wo.beg = off;
     wo.end = end;
-    wo.stack_ovf = flags + 1;
+    wo.stack_ovf = &ws->stack_ovf;
+    wo.cap_ovf = &ws->cap_ovf;
     wo.stride = stride;
+    auto reset = [&]() {
+        return check_hip(ctx, hipMemsetAsync(ws, 0, sizeof(WalkStats), st), "memset");
+    };
+    auto finish = [&](bool fixed) {
+        ctx->n_groups = (int64_t)hs->n_groups;
+        for (int k = 0; k < 3; ++k) {
+            ctx->list_total[k] = (int64_t)hs->total[k];
+            ctx->list_extent[k] = fixed ? ctx->n_groups * wo.cap[k] : ctx->list_total[k];
+            ctx->hint_max[k] = (int64_t)hs->maxlen[k];
+        }
+        ctx->hint_groups = ctx->n_groups;
+        ctx->n_pc = (int64_t)hs->pc;
+        ctx->n_pp = (int64_t)hs->pp;
+        ctx->n_pp_near = (int64_t)hs->pp_near;
+        ctx->n_leaves = (int64_t)hs->n_leaves;
+        ctx->walk_fixed = fixed ? 1 : 0;
+    };
 
-    for (int attempt = 0; attempt < 2; ++attempt) {
-        const int use_global = attempt;
+    // ---- single walk into fixed-stride segments, sized from the last build ----
+    int use_global = 0;
+    if (ctx->hint_groups > 0 && ctx->prm.n_crit == ctx->hint_n_crit) {
+        const int64_t gcap = ctx->hint_groups + ctx->hint_groups / 8 + 64;
+        bool ok = gcap <= stride;
+        for (int k = 0; k < 3 && ok; ++k) {
+            const int64_t m = ctx->hint_max[k];
+            wo.cap[k] = (m + m / 4 + 64 + 63) / 64 * 64;
+            // keep the reserved room within a few times the last build's lists
+            ok = gcap * wo.cap[k] <= 8 * ctx->list_total[k] + (1 << 22);
+        }
+        // a tree that needed the global-memory stack last time starts there
+        const int g0 = ctx->walk_global;
+        if (ok && g0)
+            ok = ensure(ctx, ctx->wstack, (size_t)grid * kGlobalStack * sizeof(int32_t)) == P3T_OK;
+        if (ok) {
+            wo.gcap = gcap;
+            for (int k = 0; k < 3; ++k) {
+                if ((rc = ensure(ctx, *lbuf[k], (gcap * wo.cap[k] + 1) * sizeof(int32_t)))) return rc;
+                wo.idx[k] = ptr<int32_t>(*lbuf[k]);
+            }
+            if ((rc = reset())) return rc;
+            k_walk<kFixed><<<grid, kWalkThreads, 0, st>>>(ptr<GroupInfo>(ctx->grp), G_dev,
+                                                           ptr<NodeWalk>(ctx->node_walk), wp, wo,
+                                                           ptr<int32_t>(ctx->wstack), g0);
+            if ((rc = check_hip(ctx, hipGetLastError(), "walk"))) return rc;
+            if ((rc = run_walk_stats(ctx, G_dev, stride, ws))) return rc;
+            if (!hs->stack_ovf && !hs->cap_ovf) {
+                finish(true);
+                return P3T_OK;
+            }
+            use_global = (hs->stack_ovf || g0) ? 1 : 0;
+        }
+    }
+
+    // ---- two passes: count, prefix sums, emit at exact offsets ----
+    for (;; use_global = 1) {
         if (use_global) {
             if ((rc = ensure(ctx, ctx->wstack, (size_t)grid * kGlobalStack * sizeof(int32_t))))
                 return rc;
         }
-        if ((rc = check_hip(ctx, hipMemsetAsync(flags + 1, 0, sizeof(int32_t), st), "memset")))
-            return rc;
+        if ((rc = reset())) return rc;
         // entries past the last group take part in the scans as zeros
         if ((rc = check_hip(ctx, hipMemsetAsync(cnt, 0, 3 * stride * sizeof(int64_t), st), "memset")))
-            return rc;
-        if ((rc = check_hip(ctx, hipMemsetAsync(rb + RB_INTER, 0, 2 * sizeof(int64_t), st), "memset")))
-            return rc;
-        if ((rc = check_hip(ctx, hipMemsetAsync(rb + RB_MAX, 0, 3 * sizeof(int64_t), st), "memset")))
             return rc;
         k_walk<kCount><<<grid, kWalkThreads, 0, st>>>(ptr<GroupInfo>(ctx->grp), G_dev,
                                                        ptr<NodeWalk>(ctx->node_walk), wp, wo,
                                                        ptr<int32_t>(ctx->wstack), use_global);
         if ((rc = check_hip(ctx, hipGetLastError(), "walk count"))) return rc;
-        k_walk_stats<<<64, 256, 0, st>>>(ptr<GroupInfo>(ctx->grp), G_dev, cnt, stride,
-                                         (unsigned long long *)(rb + RB_INTER));
-        if ((rc = check_hip(ctx, hipGetLastError(), "walk stats"))) return rc;
         for (int k = 0; k < 3; ++k)
-            if ((rc = scan_exclusive_i64(ctx, cnt + k * stride, off + k * stride, stride,
-                                         rb + RB_TOT + k)))
+            if ((rc = scan_exclusive_i64(ctx, cnt + k * stride, off + k * stride, stride, nullptr)))
                 return rc;
-        // read back: list totals, statistics, group count, stack overflow flag
-        if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + RB_TOT, rb + RB_TOT,
-                                                (RB_MAX + 3 - RB_TOT) * sizeof(int64_t),
-                                                hipMemcpyDeviceToHost, st), "readback")))
-            return rc;
-        if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + RB_G, G_dev, sizeof(int32_t),
-                                                hipMemcpyDeviceToHost, st), "readback")))
-            return rc;
-        if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + RB_STACK, flags + 1, sizeof(int32_t),
-                                                hipMemcpyDeviceToHost, st), "readback")))
-            return rc;
-        if ((rc = check_hip(ctx, hipStreamSynchronize(st), "sync"))) return rc;
-        if (!*(int32_t *)(ctx->hpin + RB_STACK)) {
-            ctx->walk_global = use_global;
-            break;
-        }
+        if ((rc = run_walk_stats(ctx, G_dev, stride, ws))) return rc;
+        if (!hs->stack_ovf) break;
         if (use_global) return set_error(ctx, P3T_EINVAL, "tree walk stack overflow");
     }
-    ctx->n_groups = *(int32_t *)(ctx->hpin + RB_G);
-    ctx->n_cell_entries = ctx->hpin[RB_TOT];
-    ctx->n_part_entries = ctx->hpin[RB_TOT + 1];
-    ctx->n_near_entries = ctx->hpin[RB_TOT + 2];
-    ctx->n_pc = ctx->hpin[RB_INTER];
-    ctx->n_pp = ctx->hpin[RB_INTER + 1];
-    ctx->n_leaves = ctx->hpin[RB_LEAVES];
+    ctx->walk_global = use_global;
     for (int k = 0; k < 3; ++k) {
-        if ((rc = ensure(ctx, *lbuf[k], (ctx->hpin[RB_TOT + k] + 1) * sizeof(int32_t)))) return rc;
+        if ((rc = ensure(ctx, *lbuf[k], ((int64_t)hs->total[k] + 1) * sizeof(int32_t)))) return rc;
         wo.idx[k] = ptr<int32_t>(*lbuf[k]);
+        wo.cap[k] = 0;
     }
+    finish(false);
+    ctx->hint_n_crit = ctx->prm.n_crit;
     k_walk<kEmit><<<grid, kWalkThreads, 0, st>>>(ptr<GroupInfo>(ctx->grp), G_dev,
                                                   ptr<NodeWalk>(ctx->node_walk), wp, wo,
-                                                  ptr<int32_t>(ctx->wstack), ctx->walk_global);
+                                                  ptr<int32_t>(ctx->wstack), use_global);
     return check_hip(ctx, hipGetLastError(), "walk emit");
 }
 

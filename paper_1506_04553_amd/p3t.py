@@ -37,12 +37,12 @@ ARRAYS = {  # id, dtype, per-row shape, size key
     "node_box": (12, np.float64, (6,), "n_nodes"),
     "group_node": (13, np.int32, (), "n_groups"),
     "cell_beg": (14, np.int64, (), "n_groups"),
-    "cell_idx": (15, np.int32, (), "n_cell_entries"),
+    "cell_idx": (15, np.int32, (), "cell_extent"),
     "part_beg": (16, np.int64, (), "n_groups"),
-    "part_idx": (17, np.int32, (), "n_part_entries"),
+    "part_idx": (17, np.int32, (), "part_extent"),
     "root": (18, np.float64, (), "4"),
     "near_beg": (19, np.int64, (), "n_groups"),
-    "near_idx": (20, np.int32, (), "n_near_entries"),
+    "near_idx": (20, np.int32, (), "near_extent"),
     "cell_end": (21, np.int64, (), "n_groups"),
     "part_end": (22, np.int64, (), "n_groups"),
     "near_end": (23, np.int64, (), "n_groups"),
@@ -64,9 +64,10 @@ class Params(C.Structure):
 class Stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("n", "n_nodes", "n_leaves", "n_groups", "depth",
                                          "n_cell_entries", "n_part_entries", "n_near_entries",
-                                         "n_pc", "n_pp", "nnz")] + \
-               [("walk_global_stack", C.c_int32)] + \
-               [(k, C.c_double) for k in ("ms_build", "ms_force", "ms_neighbors", "ms_vjp")]
+                                         "cell_extent", "part_extent", "near_extent",
+                                         "n_pc", "n_pp", "n_pp_near", "nnz")] + \
+               [("walk_global_stack", C.c_int32), ("walk_fixed_stride", C.c_int32)] + \
+               [(k, C.c_double) for k in ("ms_build", "ms_force", "ms_neighbors", "ms_vjp", "ms_walk")]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)

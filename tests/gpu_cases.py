@@ -74,16 +74,22 @@ def compare_tree(g, t: oracle.Tree, groups_sample=None):
     gs = range(G) if groups_sample is None else groups_sample
     st = g["stats"]
     stride = getattr(t, "walk_stride", 1)
-    # segments: every list's segments tile its array exactly (no gap, no overlap)
-    for lst, tot in (("cell", st["n_cell_entries"]), ("part", st["n_part_entries"]),
-                     ("near", st["n_near_entries"])):
+    # segments: disjoint, inside the index array, summing to the list total; the
+    # two-pass layout tiles the array exactly (no gap, no overlap)
+    for lst in ("cell", "part", "near"):
+        tot = st[f"n_{lst}_entries"]
+        ext = st[f"{lst}_extent"]
         b, e = g[lst + "_beg"], g[lst + "_end"]
-        assert np.all(e >= b)
+        assert np.all(e >= b) and np.all(b >= 0) and np.all(e <= ext)
+        assert int((e - b).sum()) == tot and len(g[lst + "_idx"]) == ext
         o = np.argsort(b, kind="stable")
         nz = (e - b)[o] > 0
         bb, ee = b[o][nz], e[o][nz]
-        assert (len(bb) == 0 and tot == 0) or (bb[0] == 0 and ee[-1] == tot
-                                               and np.all(bb[1:] == ee[:-1]))
+        assert np.all(bb[1:] >= ee[:-1])
+        if not st["walk_fixed_stride"]:
+            assert ext == tot
+            assert (len(bb) == 0 and tot == 0) or (bb[0] == 0 and ee[-1] == tot
+                                                   and np.all(bb[1:] == ee[:-1]))
     if stride == 1:
         assert st["n_cell_entries"] == ol["c_off"][-1]
         assert st["n_part_entries"] + st["n_near_entries"] == ol["p_off"][-1]

@@ -184,6 +184,24 @@ def test_edge_cases(ctx, name, prec):
     compare_neighbors(g, t)
 
 
+def test_neighbor_rows_longer_than_slots(ctx):
+    """A fresh context reserves 32 entries per neighbour row: 80 coincident
+    particles (79 neighbours each) overflow it, so the rows are written straight
+    into the CSR; the next call reserves room for the longest row and packs the
+    rows from their slots.  Both must equal the oracle's lists."""
+    from paper_1506_04553_amd import P3T
+    rng = np.random.default_rng(21)
+    pos = np.concatenate([np.full((80, 3), 0.25), rng.normal(0, 0.3, (3000, 3))])
+    mass = np.full(len(pos), 1.0 / len(pos))
+    p = dict(eps=1e-3, r_in=0.002, r_out=0.02, theta=0.5, r_search=0.022, n_crit=64, n_leaf=16)
+    t = oracle.Tree(pos, mass, p)
+    fresh = P3T(0)
+    for _ in range(2):
+        g = gpu_run(fresh, pos, mass, p, want_arrays=False)
+        compare_neighbors(g, t)
+    fresh.close()
+
+
 def test_forward_is_deterministic(ctx):
     w = WORKLOADS["plummer64k_salpeter"]
     c = make_cluster(w, seed=2)
@@ -193,6 +211,58 @@ def test_forward_is_deterministic(ctx):
         b = gpu_run(ctx, c.pos, c.mass, p, want_arrays=False)
         assert np.array_equal(a["acc"], b["acc"]) and np.array_equal(a["pot"], b["pot"])
         assert np.array_equal(a["nbr_idx"], b["nbr_idx"])
+
+
+def _same_lists(a, b):
+    for lst in ("cell", "part", "near"):
+        assert len(a["group_node"]) == len(b["group_node"])
+        for k in range(len(a["group_node"])):
+            np.testing.assert_array_equal(
+                a[lst + "_idx"][a[lst + "_beg"][k]:a[lst + "_end"][k]],
+                b[lst + "_idx"][b[lst + "_beg"][k]:b[lst + "_end"][k]])
+
+
+def test_fixed_stride_walk_matches_two_pass(ctx):
+    """The first build of a context walks twice (count, then emit at exact offsets);
+    a repeated build writes the lists in one walk into segments reserved from the
+    first build's sizes.  Lists (per group, in order), forces and neighbours must
+    be identical."""
+    from paper_1506_04553_amd import P3T
+    w = WORKLOADS["plummer64k_salpeter"]
+    c = make_cluster(w, seed=3)
+    for prec in ("mixed", "fp64"):
+        fresh = P3T(0)
+        p = _params(w, precision=prec)
+        a = gpu_run(fresh, c.pos, c.mass, p)
+        b = gpu_run(fresh, c.pos, c.mass, p)
+        fresh.close()
+        assert a["stats"]["walk_fixed_stride"] == 0 and b["stats"]["walk_fixed_stride"] == 1
+        _same_lists(a, b)
+        assert np.array_equal(a["acc"], b["acc"]) and np.array_equal(a["pot"], b["pot"])
+        assert np.array_equal(a["nbr_idx"], b["nbr_idx"])
+        for k in ("n_cell_entries", "n_part_entries", "n_near_entries", "n_pc", "n_pp",
+                  "n_pp_near", "n_leaves", "n_groups"):
+            assert a["stats"][k] == b["stats"][k]
+
+
+def test_fixed_stride_overflow_falls_back(ctx):
+    """Lists longer than the reserved segments (a smaller opening angle after a
+    larger one) make the build fall back to the two-pass walk with the same
+    result as a fresh context."""
+    from paper_1506_04553_amd import P3T
+    w = WORKLOADS["plummer64k_salpeter"]
+    c = make_cluster(w, seed=5)
+    used = P3T(0)
+    gpu_run(used, c.pos, c.mass, _params(w, theta=0.8), want_arrays=False)
+    p = _params(w, theta=0.3)
+    b = gpu_run(used, c.pos, c.mass, p)
+    used.close()
+    assert b["stats"]["walk_fixed_stride"] == 0
+    fresh = P3T(0)
+    a = gpu_run(fresh, c.pos, c.mass, p)
+    fresh.close()
+    _same_lists(a, b)
+    assert np.array_equal(a["acc"], b["acc"]) and np.array_equal(a["pot"], b["pot"])
 
 
 def test_reused_context_matches_fresh_context(ctx):
