@@ -110,8 +110,9 @@ __global__ __launch_bounds__(kNbrThreads) void k_neighbors(
 }
 
 // Longest row (one update per block of 256).
-__global__ __launch_bounds__(256) void k_row_max(int64_t n, const int64_t *__restrict__ cnt,
+__global__ __launch_bounds__(256) void k_row_max(int64_t n, int64_t *__restrict__ cnt,
                                                   unsigned long long *__restrict__ out) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) cnt[n] = 0;
     unsigned long long mx = 0;
     for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n;
          o += (int64_t)gridDim.x * blockDim.x) {
@@ -189,9 +190,8 @@ int launch_neighbors(p3t_ctx *ctx, int64_t *offsets, int32_t *idx, int64_t cap, 
     const unsigned grid = (unsigned)ctx->n_groups;
     const int32_t row_cap = ctx->nbr_cap > 0 ? ctx->nbr_cap : kNbrFirstCap;
     if ((rc = ensure(ctx, ctx->nbr_slots, (size_t)n * row_cap * sizeof(int32_t) + 4))) return rc;
-    // the entry past the last particle takes part in the scan as zero
-    if ((rc = check_hip(ctx, hipMemsetAsync(cnt, 0, (n + 1) * sizeof(int64_t), st), "memset")))
-        return rc;
+    // every particle's count is written (groups partition the particles); the
+    // entry past the last one, which takes part in the scan, is zeroed by k_row_max
     if ((rc = check_hip(ctx, hipMemsetAsync(rb + RB_NNZ, 0, 3 * sizeof(int64_t), st), "memset")))
         return rc;
     if (grid) {

@@ -69,7 +69,11 @@ __device__ __forceinline__ Chg changeover_ds(double s, const VjpParams &vp) {
     return c;
 }
 
-// d(l_ij)/dd and d(l_ij)/dm_j for one pair.
+// K = W = 1 and dK/ds = dW/ds = 0 (pairs and cells at least r_out apart)
+__device__ __forceinline__ Chg changeover_unit() { return Chg{1.0, 0.0, 1.0, 0.0}; }
+
+// d(l_ij)/dd and d(l_ij)/dm_j for one pair; CHG false: K = W = 1 known.
+template <bool CHG>
 __device__ __forceinline__ void pair_grad(double dx, double dy, double dz, double mj, double wx,
                                           double wy, double wz, double ci, const VjpParams &vp,
                                           double gd[3], double &gm) {
@@ -77,7 +81,7 @@ __device__ __forceinline__ void pair_grad(double dx, double dy, double dz, doubl
     const double inv = rsqrt(s2);
     const double s = s2 * inv;
     const double inv2 = inv * inv, inv3 = inv2 * inv;
-    const Chg c = changeover_ds(s, vp);
+    const Chg c = CHG ? changeover_ds(s, vp) : changeover_unit();
     const double g = c.K * inv3;
     const double gp = c.Ks * inv3 - 3.0 * c.K * inv2 * inv2;
     const double wd = wx * dx + wy * dy + wz * dz;
@@ -94,6 +98,7 @@ struct CellGrad {
     double S[6];     // symmetric dl/dQ: xx yy zz xy xz yz
 };
 
+template <bool CHG>
 __device__ __forceinline__ void cell_grad(double rx, double ry, double rz, double M, const double q[6],
                                           double wx, double wy, double wz, double ci,
                                           const VjpParams &vp, CellGrad &o) {
@@ -102,7 +107,7 @@ __device__ __forceinline__ void cell_grad(double rx, double ry, double rz, doubl
     const double s = s2 * inv;
     const double inv2 = inv * inv, inv3 = inv2 * inv, inv5 = inv3 * inv2, inv7 = inv5 * inv2,
                  inv9 = inv7 * inv2;
-    const Chg c = changeover_ds(s, vp);
+    const Chg c = CHG ? changeover_ds(s, vp) : changeover_unit();
     double Qr[3] = {0, 0, 0}, Qw[3] = {0, 0, 0}, qq = 0.0;
     if (vp.use_quad) {
         Qr[0] = q[0] * rx + q[3] * ry + q[4] * rz;
@@ -146,6 +151,8 @@ __device__ __forceinline__ void cell_grad(double rx, double ry, double rz, doubl
 // ---------------------------------------------------------------------------
 // Pass 1: per particle i (one group per block), the i-side terms.
 // ---------------------------------------------------------------------------
+// CELL_K: accepted cells may lie within r_out of a member (h < r_out)
+template <bool CELL_K>
 __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
     const GroupInfo *__restrict__ grp, ListsDev L, const double *__restrict__ x,
     const double *__restrict__ y,
@@ -192,8 +199,12 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
                 for (int k = slice; k < tl; k += nslice) {
                     if (s_j[k] == i) continue;
                     double gd[3], gmj;
-                    pair_grad(s_p[0][k] - xi, s_p[1][k] - yi, s_p[2][k] - zi, s_p[3][k], wx, wy, wz,
-                              ci, vp, gd, gmj);
+                    if (list == 0)   // far particles: K = W = 1
+                        pair_grad<false>(s_p[0][k] - xi, s_p[1][k] - yi, s_p[2][k] - zi, s_p[3][k],
+                                         wx, wy, wz, ci, vp, gd, gmj);
+                    else
+                        pair_grad<true>(s_p[0][k] - xi, s_p[1][k] - yi, s_p[2][k] - zi, s_p[3][k],
+                                        wx, wy, wz, ci, vp, gd, gmj);
                     g0 -= gd[0]; g1 -= gd[1]; g2 -= gd[2];
                 }
             }
@@ -206,7 +217,7 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
             for (int k = slice; k < tl; k += nslice) {
                 const NodeMP c = s_c[k];
                 CellGrad cg;
-                cell_grad(xi - c.cx, yi - c.cy, zi - c.cz, c.M, c.q, wx, wy, wz, ci, vp, cg);
+                cell_grad<CELL_K>(xi - c.cx, yi - c.cy, zi - c.cz, c.M, c.q, wx, wy, wz, ci, vp, cg);
                 g0 += cg.gr[0]; g1 += cg.gr[1]; g2 += cg.gr[2];
             }
         }
@@ -229,6 +240,7 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
 // Pass 2: per list entry (particle j or cell c), the sum over the group's
 // members, scattered with one atomic add per component.
 // ---------------------------------------------------------------------------
+template <bool CELL_K>
 __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
     const GroupInfo *__restrict__ grp, ListsDev L, const double *__restrict__ x,
     const double *__restrict__ y,
@@ -260,14 +272,19 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
         }
         __syncthreads();
         for (int64_t e = tid; e < np; e += kVjpThreads) {
-            const int32_t j = e < nf ? p_idx[fb + e] : n_idx[nb + (e - nf)];
+            const bool far = e < nf;
+            const int32_t j = far ? p_idx[fb + e] : n_idx[nb + (e - nf)];
             const double xj = x[j], yj = y[j], zj = z[j], mj = m[j];
             double a0 = 0, a1 = 0, a2 = 0, am = 0;
             for (int k = 0; k < nc; ++k) {
                 if (s_id[k] == j) continue;
                 double gd[3], gmj;
-                pair_grad(xj - s_i[0][k], yj - s_i[1][k], zj - s_i[2][k], mj, s_i[3][k], s_i[4][k],
-                          s_i[5][k], s_i[6][k], vp, gd, gmj);
+                if (far)   // K = W = 1
+                    pair_grad<false>(xj - s_i[0][k], yj - s_i[1][k], zj - s_i[2][k], mj, s_i[3][k],
+                                     s_i[4][k], s_i[5][k], s_i[6][k], vp, gd, gmj);
+                else
+                    pair_grad<true>(xj - s_i[0][k], yj - s_i[1][k], zj - s_i[2][k], mj, s_i[3][k],
+                                    s_i[4][k], s_i[5][k], s_i[6][k], vp, gd, gmj);
                 a0 += gd[0]; a1 += gd[1]; a2 += gd[2]; am += gmj;
             }
             atomicAdd(&gx[j], a0);
@@ -281,7 +298,7 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
             double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
             for (int k = 0; k < nc; ++k) {
                 CellGrad cg;
-                cell_grad(s_i[0][k] - c.cx, s_i[1][k] - c.cy, s_i[2][k] - c.cz, c.M, c.q, s_i[3][k],
+                cell_grad<CELL_K>(s_i[0][k] - c.cx, s_i[1][k] - c.cy, s_i[2][k] - c.cz, c.M, c.q, s_i[3][k],
                           s_i[4][k], s_i[5][k], s_i[6][k], vp, cg);
                 acc[0] -= cg.gr[0]; acc[1] -= cg.gr[1]; acc[2] -= cg.gr[2];
                 acc[3] += cg.gM;
@@ -404,12 +421,16 @@ int launch_vjp(p3t_ctx *ctx, const double *w, const double *c, double *gpos, dou
     if ((rc = check_hip(ctx, hipMemsetAsync(cadj, 0, 10 * nn * sizeof(double), ctx->stream), "memset")))
         return rc;
     const unsigned G = (unsigned)ctx->n_groups;
-    k_vjp_i<<<G, kVjpThreads, 0, ctx->stream>>>(
+    // accepted cells lie at least h from every member: K = W = 1 on them when h >= r_out
+    const bool cell_k = ctx->prm.r_search < ctx->prm.r_out;
+    auto ki = cell_k ? k_vjp_i<true> : k_vjp_i<false>;
+    auto ks = cell_k ? k_vjp_scatter<true> : k_vjp_scatter<false>;
+    ki<<<G, kVjpThreads, 0, ctx->stream>>>(
         ptr<GroupInfo>(ctx->grp), L, ptr<double>(ctx->x), ptr<double>(ctx->y), ptr<double>(ctx->z),
         ptr<double>(ctx->m), ptr<NodeMP>(ctx->node_mp), ptr<int32_t>(ctx->vals[0]), w, c, vp, gx, gm,
         n);
     if ((rc = check_hip(ctx, hipGetLastError(), "vjp i-side"))) return rc;
-    k_vjp_scatter<<<G, kVjpThreads, 0, ctx->stream>>>(
+    ks<<<G, kVjpThreads, 0, ctx->stream>>>(
         ptr<GroupInfo>(ctx->grp), L, ptr<double>(ctx->x), ptr<double>(ctx->y), ptr<double>(ctx->z),
         ptr<double>(ctx->m), ptr<NodeMP>(ctx->node_mp), ptr<int32_t>(ctx->vals[0]), w, c, vp, gx, gm,
         cadj, n);

@@ -198,7 +198,7 @@ struct WalkStats {
 };
 
 // Statistics from the per-group counts, and the leaf count of the tree.
-__global__ __launch_bounds__(256) void k_walk_stats(const GroupInfo *__restrict__ grp,
+__global__ __launch_bounds__(1024) void k_walk_stats(const GroupInfo *__restrict__ grp,
                                                     const int32_t *__restrict__ n_groups_dev,
                                                     const int64_t *__restrict__ cnt, int64_t S,
                                                     const int32_t *__restrict__ nchild,
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(256) void k_walk_stats(const GroupInfo *__restrict_
     }
     for (int64_t i = t0; i < n_nodes; i += nt) lv += nchild[i] == 0;
     // wave reductions, then one set of updates per block
-    __shared__ unsigned long long s_red[4][10];
+    __shared__ unsigned long long s_red[16][10];
     unsigned long long v[10] = {pc, pp, ppn, lv, tot[0], tot[1], tot[2], mx[0], mx[1], mx[2]};
     for (int k = 0; k < 7; ++k) v[k] = wave_sum(v[k]);
     for (int k = 7; k < 10; ++k)
@@ -271,7 +271,8 @@ ListsDev lists_dev(const p3t_ctx *ctx) {
 constexpr int kRbWalk = 24;
 
 static int run_walk_stats(p3t_ctx *ctx, const int32_t *G_dev, int64_t stride, WalkStats *ws) {
-    k_walk_stats<<<256, 256, 0, ctx->stream>>>(ptr<GroupInfo>(ctx->grp), G_dev,
+    // few large blocks: the block results meet in same-address atomics
+    k_walk_stats<<<32, 1024, 0, ctx->stream>>>(ptr<GroupInfo>(ctx->grp), G_dev,
                                               ptr<int64_t>(ctx->cnt), stride,
                                               ptr<int32_t>(ctx->node_nchild), ctx->n_nodes, ws);
     int rc = check_hip(ctx, hipGetLastError(), "walk stats");
