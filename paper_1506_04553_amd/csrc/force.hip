@@ -282,11 +282,12 @@ __global__ __launch_bounds__(kForceThreads) void k_force(
     zero_c.pad0 = zero_c.pad1 = R(0);
 
     const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
-    const GroupInfo gi = grp[blockIdx.x];
+    const int g = L.order[blockIdx.x];
+    const GroupInfo gi = grp[g];
     const double gcx = gi.c[0], gcy = gi.c[1], gcz = gi.c[2];
-    const int64_t cb = L.beg[0][blockIdx.x], ce = L.end[0][blockIdx.x];
-    const int64_t pb = L.beg[1][blockIdx.x], pe = L.end[1][blockIdx.x];
-    const int64_t nb = L.beg[2][blockIdx.x], ne = L.end[2][blockIdx.x];
+    const int64_t cb = L.beg[0][g], ce = L.end[0][g];
+    const int64_t pb = L.beg[1][g], pe = L.end[1][g];
+    const int64_t nb = L.beg[2][g], ne = L.end[2][g];
     const int32_t *__restrict__ c_idx = L.idx[0];
     const int32_t *__restrict__ p_idx = L.idx[1];
     const int32_t *__restrict__ n_idx = L.idx[2];

@@ -58,11 +58,14 @@ struct DevBuf {
 
 // The walk's per-group lists: 0 = accepted cells (node ids), 1 = far particles,
 // 2 = near particles (sorted particle indices); group g's entries of list k are
-// idx[k][beg[k][g] .. end[k][g]).
+// idx[k][beg[k][g] .. end[k][g]).  Kernels with one block per group take group
+// order[blockIdx.x]: groups sorted by decreasing estimated work, so that the
+// longest blocks start first and the launch has no long tail.
 struct ListsDev {
     const int64_t *beg[3];
     const int64_t *end[3];
     const int32_t *idx[3];
+    const int32_t *order;
 };
 
 }  // namespace p3t
@@ -103,7 +106,7 @@ struct p3t_ctx {
     p3t::DevBuf cnt, off, c_idx, p_idx, n_idx;
     p3t::DevBuf wstack, dflags, readback, scan_tmp, nbr_cnt, nbr_slots;
     p3t::DevBuf vjp_gx, vjp_gm, vjp_cell, bbox;
-    p3t::DevBuf seg_end;
+    p3t::DevBuf seg_end, gorder, grank, ghist;
 };
 
 namespace p3t {

@@ -48,8 +48,9 @@ __global__ __launch_bounds__(kNbrThreads) void k_neighbors(
     __shared__ int32_t s_j[kNbrTile];
     __shared__ int32_t s_wn[kNbrWaves];
     const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
-    const GroupInfo gi = grp[blockIdx.x];
-    const int64_t nb = L.beg[2][blockIdx.x], ne = L.end[2][blockIdx.x];   // near particles
+    const int g = L.order[blockIdx.x];
+    const GroupInfo gi = grp[g];
+    const int64_t nb = L.beg[2][g], ne = L.end[2][g];   // near particles
     const int32_t *__restrict__ n_idx = L.idx[2];
 
     for (int m0 = 0; m0 < gi.count; m0 += kNbrThreads) {

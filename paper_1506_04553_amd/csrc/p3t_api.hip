@@ -153,7 +153,7 @@ extern "C" void p3t_destroy(p3t_ctx *ctx) {
                       &ctx->gscan, &ctx->grp, &ctx->cnt, &ctx->off, &ctx->c_idx, &ctx->p_idx,
                       &ctx->n_idx, &ctx->wstack, &ctx->dflags, &ctx->readback, &ctx->scan_tmp,
                       &ctx->nbr_cnt, &ctx->nbr_slots, &ctx->vjp_gx, &ctx->vjp_gm, &ctx->vjp_cell, &ctx->bbox,
-                      &ctx->seg_end};
+                      &ctx->seg_end, &ctx->gorder, &ctx->grank, &ctx->ghist};
     for (DevBuf *b : bufs) release(ctx, *b);
     if (ctx->hpin) (void)hipHostFree(ctx->hpin);
     for (int k = 0; k < 10; ++k)

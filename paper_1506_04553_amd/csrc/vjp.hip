@@ -164,8 +164,9 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
     __shared__ NodeMP s_c[kVjpTile];
     __shared__ double s_red[3][kVjpThreads];
     const int tid = threadIdx.x;
-    const GroupInfo gi = grp[blockIdx.x];
-    const int64_t cb = L.beg[0][blockIdx.x], ce = L.end[0][blockIdx.x];
+    const int g = L.order[blockIdx.x];
+    const GroupInfo gi = grp[g];
+    const int64_t cb = L.beg[0][g], ce = L.end[0][g];
     const int32_t *__restrict__ c_idx = L.idx[0];
     // members in chunks of the largest power of two that fits (at most 256),
     // so that a chunk fills its lanes: 74 members run as 64 + 8 + 2
@@ -185,8 +186,8 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
         double g0 = 0, g1 = 0, g2 = 0;
         for (int list = 0; list < 2; ++list) {        // far and near particles
             const int32_t *idxs = L.idx[1 + list];
-            const int64_t pb = L.beg[1 + list][blockIdx.x];
-            const int64_t pe = L.end[1 + list][blockIdx.x];
+            const int64_t pb = L.beg[1 + list][g];
+            const int64_t pe = L.end[1 + list][g];
             for (int64_t t0 = pb; t0 < pe; t0 += kVjpTile) {
                 const int tl = (int)min<int64_t>(kVjpTile, pe - t0);
                 __syncthreads();
@@ -251,10 +252,11 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
     __shared__ double s_i[7][kVjpThreads];   // x y z w(3) c of the group's members
     __shared__ int32_t s_id[kVjpThreads];
     const int tid = threadIdx.x;
-    const GroupInfo gi = grp[blockIdx.x];
-    const int64_t cb = L.beg[0][blockIdx.x], ce = L.end[0][blockIdx.x];
-    const int64_t fb = L.beg[1][blockIdx.x], fe = L.end[1][blockIdx.x];
-    const int64_t nb = L.beg[2][blockIdx.x], ne = L.end[2][blockIdx.x];
+    const int g = L.order[blockIdx.x];
+    const GroupInfo gi = grp[g];
+    const int64_t cb = L.beg[0][g], ce = L.end[0][g];
+    const int64_t fb = L.beg[1][g], fe = L.end[1][g];
+    const int64_t nb = L.beg[2][g], ne = L.end[2][g];
     const int32_t *__restrict__ c_idx = L.idx[0];
     const int32_t *__restrict__ p_idx = L.idx[1];
     const int32_t *__restrict__ n_idx = L.idx[2];

@@ -256,6 +256,7 @@ static unsigned walk_grid(p3t_ctx *ctx) {
 
 ListsDev lists_dev(const p3t_ctx *ctx) {
     ListsDev L;
+    L.order = ptr<int32_t>(ctx->gorder);
     const int64_t stride = ctx->n_nodes + 1;
     const int64_t *beg = ptr<int64_t>(ctx->off), *end = ptr<int64_t>(ctx->seg_end);
     const DevBuf *bufs[3] = {&ctx->c_idx, &ctx->p_idx, &ctx->n_idx};
@@ -265,6 +266,91 @@ ListsDev lists_dev(const p3t_ctx *ctx) {
         L.idx[k] = ptr<int32_t>(*bufs[k]);
     }
     return L;
+}
+
+// ---------------------------------------------------------------------------
+// Launch order of the per-group kernels: groups in buckets of estimated work
+// (quarter octaves of n_g (35 |C_g| + 15 |P_g|), the interaction kernel's
+// instruction count), largest first; the order inside a bucket is arbitrary
+// (it decides only which block runs which group).
+// ---------------------------------------------------------------------------
+constexpr int kOrderBins = 128;
+
+__device__ __forceinline__ int order_bin(const GroupInfo &gi, const int64_t *cnt, int64_t S, int g) {
+    const float cost = (float)gi.count * (35.0f * (float)cnt[g] +
+                                          15.0f * (float)(cnt[S + g] + cnt[2 * S + g]));
+    int b = (int)(4.0f * log2f(cost + 1.0f));
+    b = b < 0 ? 0 : (b > kOrderBins - 1 ? kOrderBins - 1 : b);
+    return kOrderBins - 1 - b;
+}
+
+// bucket counts (one atomic per bucket and wavefront) and each group's rank in its bucket
+__global__ __launch_bounds__(256) void k_order_count(const GroupInfo *__restrict__ grp, int64_t G,
+                                                     const int64_t *__restrict__ cnt, int64_t S,
+                                                     uint32_t *__restrict__ hist,
+                                                     int32_t *__restrict__ rank) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = g < G;
+    const int b = valid ? order_bin(grp[g], cnt, S, (int)g) : 0;
+    uint64_t same = ballot(valid);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        const bool bit = (b >> k) & 1;
+        const uint64_t bb = ballot(bit);
+        same &= bit ? bb : ~bb;
+    }
+    const int leader = valid ? __ffsll((long long)same) - 1 : 0;
+    uint32_t base = 0;
+    if (valid && lane_id() == leader) base = atomicAdd(&hist[b], (uint32_t)__popcll(same));
+    base = __shfl(base, leader, kWave);
+    if (valid) rank[g] = (b << 24) | (int32_t)(base + count_below(same));
+}
+
+__global__ __launch_bounds__(kOrderBins) void k_order_scan(uint32_t *__restrict__ hist) {
+    __shared__ uint32_t s[kOrderBins];
+    const int t = threadIdx.x;
+    s[t] = hist[t];
+    __syncthreads();
+    uint32_t e = 0;
+    for (int k = 0; k < t; ++k) e += s[k];
+    hist[kOrderBins + t] = e;   // bucket starts
+}
+
+__global__ __launch_bounds__(256) void k_order_place(int64_t G, const int32_t *__restrict__ rank,
+                                                     const uint32_t *__restrict__ hist,
+                                                     int32_t *__restrict__ order) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    const int32_t r = rank[g];
+    order[hist[kOrderBins + (r >> 24)] + (r & 0xffffff)] = (int32_t)g;
+}
+
+__global__ void k_order_identity(int64_t G, int32_t *__restrict__ order) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < G) order[g] = (int32_t)g;
+}
+
+static int build_order(p3t_ctx *ctx, int64_t stride) {
+    int rc;
+    const int64_t G = ctx->n_groups;
+    if ((rc = ensure(ctx, ctx->gorder, (G + 1) * sizeof(int32_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->grank, (G + 1) * sizeof(int32_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->ghist, 2 * kOrderBins * sizeof(uint32_t)))) return rc;
+    if (G <= 0) return P3T_OK;
+    if (G >= (1 << 24)) {   // ranks are packed in 24 bits: keep the group order
+        k_order_identity<<<blocks_for(G, 256), 256, 0, ctx->stream>>>(G, ptr<int32_t>(ctx->gorder));
+        return check_hip(ctx, hipGetLastError(), "group order");
+    }
+    uint32_t *hist = ptr<uint32_t>(ctx->ghist);
+    if ((rc = check_hip(ctx, hipMemsetAsync(hist, 0, kOrderBins * sizeof(uint32_t), ctx->stream),
+                        "memset")))
+        return rc;
+    k_order_count<<<blocks_for(G, 256), 256, 0, ctx->stream>>>(
+        ptr<GroupInfo>(ctx->grp), G, ptr<int64_t>(ctx->cnt), stride, hist, ptr<int32_t>(ctx->grank));
+    k_order_scan<<<1, kOrderBins, 0, ctx->stream>>>(hist);
+    k_order_place<<<blocks_for(G, 256), 256, 0, ctx->stream>>>(G, ptr<int32_t>(ctx->grank), hist,
+                                                              ptr<int32_t>(ctx->gorder));
+    return check_hip(ctx, hipGetLastError(), "group order");
 }
 
 // the walk's results sit in the readback area from this int64 slot on
@@ -356,7 +442,7 @@ int build_lists(p3t_ctx *ctx) {
             if ((rc = run_walk_stats(ctx, G_dev, stride, ws))) return rc;
             if (!hs->stack_ovf && !hs->cap_ovf) {
                 finish(true);
-                return P3T_OK;
+                return build_order(ctx, stride);
             }
             use_global = (hs->stack_ovf || g0) ? 1 : 0;
         }
@@ -394,7 +480,8 @@ int build_lists(p3t_ctx *ctx) {
     k_walk<kEmit><<<grid, kWalkThreads, 0, st>>>(ptr<GroupInfo>(ctx->grp), G_dev,
                                                   ptr<NodeWalk>(ctx->node_walk), wp, wo,
                                                   ptr<int32_t>(ctx->wstack), use_global);
-    return check_hip(ctx, hipGetLastError(), "walk emit");
+    if ((rc = check_hip(ctx, hipGetLastError(), "walk emit"))) return rc;
+    return build_order(ctx, stride);
 }
 
 }  // namespace p3t
