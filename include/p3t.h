@@ -76,7 +76,7 @@ typedef struct {
     int64_t n_pc, n_pp;       /* interactions: sum_g n_g |C_g|, sum_g n_g |P_g| */
     int64_t n_pp_near;        /* the part of n_pp over near particles: sum_g n_g |N_g| */
     int64_t nnz;              /* neighbour pairs found by the last p3t_neighbors */
-    int32_t walk_global_stack;/* 1 if the walk needed its global-memory stack */
+    int32_t walk_global_stack;/* 1 if some group's walk needed the global-memory stack */
     int32_t walk_fixed_stride;/* 1 if the lists were written in one walk into segments
                                  reserved from the previous build's sizes */
     double ms_build, ms_force, ms_neighbors, ms_vjp; /* GPU time of the last calls */
@@ -92,7 +92,11 @@ typedef struct p3t_ctx p3t_ctx;
 /* Create a context on HIP device `device` whose work goes to `hip_stream`
  * (a hipStream_t; NULL = the default stream).  `alloc`/`free_` may both be NULL
  * (hipMalloc/hipFree are used) or both set; the context owns every internal
- * workspace.  *out receives the context.  Errors: EINVAL, EHIP. */
+ * workspace.  *out receives the context.  Errors: EINVAL, EHIP.
+ * The tree walk keeps each group's pending nodes on a stack in LDS and moves a
+ * group whose stack outgrows it to a stack in global memory; the environment
+ * variable P3T_WALK_LDS_STACK=k (64 <= k < 1536) at creation caps the LDS stack
+ * at k entries (results are the same; it exercises the global-memory path). */
 int p3t_create(p3t_ctx **out, int device, void *hip_stream, p3t_alloc_fn alloc,
                p3t_free_fn free_, void *alloc_user);
 

@@ -1,6 +1,7 @@
 // p3t_api.hip -- the C ABI (include/p3t.h): context, workspaces, parameter
 // validation, stage sequencing, statistics and inspection.
 #include <math.h>
+#include <stdlib.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -130,6 +131,8 @@ extern "C" int p3t_create(p3t_ctx **out, int device, void *hip_stream, p3t_alloc
     ctx->alloc = alloc;
     ctx->free_ = free_;
     ctx->user = alloc_user;
+    // P3T_WALK_LDS_STACK=k (k >= 64) caps the walk's on-chip stack at k entries
+    if (const char *ev = getenv("P3T_WALK_LDS_STACK")) ctx->walk_lds_cap = atoi(ev);
     hipError_t e = hipHostMalloc((void **)&ctx->hpin, 64 * sizeof(int64_t), hipHostMallocDefault);
     for (int k = 0; k < 10 && e == hipSuccess; ++k) e = hipEventCreate(&ctx->ev[k]);
     if (e != hipSuccess) {

@@ -329,6 +329,26 @@ __device__ __forceinline__ int64_t lower_bound_key(const uint64_t *keys, int64_t
     return lo;
 }
 
+// first index in [lo, hi) whose key exceeds v, searching outwards from lo
+// (doubling steps, then bisection): cost grows with the distance found, and
+// most nodes are small
+__device__ __forceinline__ int64_t gallop_upper_key(const uint64_t *keys, int64_t lo, int64_t hi,
+                                                    uint64_t v) {
+    int64_t step = 1, prev = lo;
+    int64_t probe = lo;
+    while (probe < hi && keys[probe] <= v) {
+        prev = probe + 1;
+        probe = lo + step;
+        step <<= 1;
+    }
+    int64_t a = prev, b = probe < hi ? probe : hi;
+    while (a < b) {
+        const int64_t mid = a + ((b - a) >> 1);
+        if (keys[mid] <= v) a = mid + 1; else b = mid;
+    }
+    return a;
+}
+
 __device__ __forceinline__ int64_t upper_bound_key(const uint64_t *keys, int64_t lo, int64_t hi,
                                                    uint64_t v) {
     while (lo < hi) {
@@ -416,7 +436,7 @@ __global__ __launch_bounds__(kTopoThreads) void k_topo_emit(
         const int32_t next = (l < kMaxLevel) ? rank_at(l + 1) : 0;
         const int sh = 3 * (kMaxLevel - l);
         const uint64_t kmax = ka | ((sh >= 64) ? ~0ull : ((1ull << sh) - 1ull));
-        const int64_t ub = upper_bound_key(keys, a + 1, n, kmax);
+        const int64_t ub = gallop_upper_key(keys, a + 1, n, kmax);
         level[id] = l;
         first[id] = (int32_t)a;
         count[id] = (int32_t)(ub - a);

@@ -36,6 +36,7 @@
 namespace p3t {
 
 constexpr int kWalkThreads = 64;        // one wavefront per block
+constexpr int kWalkGrid = 8192;         // 32 resident wavefronts on each of 256 CUs
 constexpr int kLdsStack = 1536;
 constexpr int kGlobalStack = kLevels * 8 * kWave + kWave;
 
@@ -52,7 +53,8 @@ struct WalkOut {
     int32_t *idx[3];         // lists
     int64_t cap[3];          // fixed: entries reserved per group and list
     int64_t gcap;            // fixed: groups the lists have room for
-    int32_t *stack_ovf;      // set if a group overflowed the stack
+    int32_t *stack_ovf;      // set if a group overflowed even the global stack
+    int32_t *spilled;        // groups that walked on the global stack
     int32_t *cap_ovf;        // fixed: set if some group did not fit
     int64_t stride;
 };
@@ -67,10 +69,9 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(const GroupInfo *__restri
                                                         const int32_t *__restrict__ n_groups_dev,
                                                         const NodeWalk *__restrict__ nodes,
                                                         WalkParams wp, WalkOut wo,
-                                                        int32_t *__restrict__ gstack, int use_global) {
+                                                        int32_t *__restrict__ gstack, int lds_cap) {
     __shared__ int32_t lstack[kLdsStack];
-    int32_t *stk = use_global ? gstack + (int64_t)blockIdx.x * kGlobalStack : lstack;
-    const int cap = use_global ? kGlobalStack : kLdsStack;
+    int32_t *const gstk = gstack + (int64_t)blockIdx.x * kGlobalStack;
     const int lane = threadIdx.x;
     const int G = *n_groups_dev;
     const int64_t S = wo.stride;
@@ -86,88 +87,95 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(const GroupInfo *__restri
             for (int k = 0; k < 3; ++k) dst[k] = wo.idx[k] + wo.beg[k * S + g];
         if (MODE == kFixed)
             for (int k = 0; k < 3; ++k) dst[k] = wo.idx[k] + (int64_t)g * wo.cap[k];
-        int sp = 1;
-        if (lane == 0) stk[0] = 0;
-        __syncthreads();
+        // the walk runs on the LDS stack; a group whose pending nodes outgrow
+        // it walks again from the root on this block's stack in global memory
         bool ovf = false;
-        while (sp > 0) {
-            const int k = sp < kWave ? sp : kWave;
-            const int base = sp - k;
-            const int32_t node = lane < k ? stk[base + lane] : -1;
-            sp = base;
+        for (int pass = 0; pass < 2; ++pass) {
+            int32_t *const stk = pass ? gstk : lstack;
+            const int cap = pass ? kGlobalStack : lds_cap;
+            run[0] = run[1] = run[2] = 0;
+            int sp = 1;
+            ovf = false;
+            if (lane == 0) stk[0] = 0;
             __syncthreads();
-            bool acc = false, leaf = false, near = false;
-            int32_t first = 0, count = 0, cf = 0, ncld = 0;
-            if (node >= 0) {
-                const NodeWalk nd = nodes[node];
-                const double t0 = gap(gi.lo[0] - nd.cx, nd.cx - gi.hi[0]);
-                const double t1 = gap(gi.lo[1] - nd.cy, nd.cy - gi.hi[1]);
-                const double t2 = gap(gi.lo[2] - nd.cz, nd.cz - gi.hi[2]);
-                const double D2 = t0 * t0 + t1 * t1 + t2 * t2;
-                const double b0 = gap(nd.lo[0] - gi.hi[0], gi.lo[0] - nd.hi[0]);
-                const double b1 = gap(nd.lo[1] - gi.hi[1], gi.lo[1] - nd.hi[1]);
-                const double b2 = gap(nd.lo[2] - gi.hi[2], gi.lo[2] - nd.hi[2]);
-                const double B2 = b0 * b0 + b1 * b1 + b2 * b2;
-                acc = (wp.th2 * D2 > nd.l2) && (B2 >= wp.h2);
-                leaf = nd.n_child == 0;
-                near = B2 < wp.hn2;
-                first = nd.first;
-                count = nd.count;
-                cf = nd.child_first;
-                ncld = nd.n_child;
-            }
-            const bool isC = node >= 0 && acc;
-            const bool isO = node >= 0 && !acc && !leaf;
-            const bool isF = node >= 0 && !acc && leaf && !near;
-            const bool isN = node >= 0 && !acc && leaf && near;
-            // accepted cells
-            {
-                const uint64_t mC = ballot(isC);
-                if (MODE != kCount && isC) {
-                    const int64_t pos = run[0] + count_below(mC);
-                    if (MODE == kEmit || pos < wo.cap[0]) dst[0][pos] = node;
+            while (sp > 0) {
+                const int k = sp < kWave ? sp : kWave;
+                const int base = sp - k;
+                const int32_t node = lane < k ? stk[base + lane] : -1;
+                sp = base;
+                __syncthreads();
+                bool acc = false, leaf = false, near = false;
+                int32_t first = 0, count = 0, cf = 0, ncld = 0;
+                if (node >= 0) {
+                    const NodeWalk nd = nodes[node];
+                    const double t0 = gap(gi.lo[0] - nd.cx, nd.cx - gi.hi[0]);
+                    const double t1 = gap(gi.lo[1] - nd.cy, nd.cy - gi.hi[1]);
+                    const double t2 = gap(gi.lo[2] - nd.cz, nd.cz - gi.hi[2]);
+                    const double D2 = t0 * t0 + t1 * t1 + t2 * t2;
+                    const double b0 = gap(nd.lo[0] - gi.hi[0], gi.lo[0] - nd.hi[0]);
+                    const double b1 = gap(nd.lo[1] - gi.hi[1], gi.lo[1] - nd.hi[1]);
+                    const double b2 = gap(nd.lo[2] - gi.hi[2], gi.lo[2] - nd.hi[2]);
+                    const double B2 = b0 * b0 + b1 * b1 + b2 * b2;
+                    acc = (wp.th2 * D2 > nd.l2) && (B2 >= wp.h2);
+                    leaf = nd.n_child == 0;
+                    near = B2 < wp.hn2;
+                    first = nd.first;
+                    count = nd.count;
+                    cf = nd.child_first;
+                    ncld = nd.n_child;
                 }
-                run[0] += __popcll(mC);
-            }
-            // particles of far, then near, opened leaves
-#pragma unroll
-            for (int kk = 1; kk < 3; ++kk) {
-                const bool mine = kk == 1 ? isF : isN;
-                const int c = mine ? count : 0;
-                int tot;
-                const int excl = wave_excl_count(c, tot);
-                if (MODE == kEmit && mine) {
-                    int32_t *d = dst[kk] + run[kk] + excl;
-                    for (int t = 0; t < c; ++t) d[t] = first + t;
+                const bool isC = node >= 0 && acc;
+                const bool isO = node >= 0 && !acc && !leaf;
+                const bool isF = node >= 0 && !acc && leaf && !near;
+                const bool isN = node >= 0 && !acc && leaf && near;
+                // accepted cells
+                {
+                    const uint64_t mC = ballot(isC);
+                    if (MODE != kCount && isC) {
+                        const int64_t pos = run[0] + count_below(mC);
+                        if (MODE == kEmit || pos < wo.cap[0]) dst[0][pos] = node;
+                    }
+                    run[0] += __popcll(mC);
                 }
-                if (MODE == kFixed && mine) {
-                    const int64_t pos = run[kk] + excl;
-                    const int64_t lim = wo.cap[kk] - pos;
-                    const int cc = lim < c ? (lim > 0 ? (int)lim : 0) : c;
-                    for (int t = 0; t < cc; ++t) dst[kk][pos + t] = first + t;
+                // particles of far, then near, opened leaves
+    #pragma unroll
+                for (int kk = 1; kk < 3; ++kk) {
+                    const bool mine = kk == 1 ? isF : isN;
+                    const int c = mine ? count : 0;
+                    int tot;
+                    const int excl = wave_excl_count(c, tot);
+                    if (MODE == kEmit && mine) {
+                        int32_t *d = dst[kk] + run[kk] + excl;
+                        for (int t = 0; t < c; ++t) d[t] = first + t;
+                    }
+                    if (MODE == kFixed && mine) {
+                        const int64_t pos = run[kk] + excl;
+                        const int64_t lim = wo.cap[kk] - pos;
+                        const int cc = lim < c ? (lim > 0 ? (int)lim : 0) : c;
+                        for (int t = 0; t < cc; ++t) dst[kk][pos + t] = first + t;
+                    }
+                    run[kk] += tot;
                 }
-                run[kk] += tot;
+                // children of opened internal nodes (at most 8 each)
+                const int ocnt = isO ? ncld : 0;
+                int otot;
+                const int oexcl = wave_excl_small<4>(ocnt, otot);
+                if (sp + otot > cap) {
+                    ovf = true;
+                    break;
+                }
+                if (isO) {
+                    int32_t *d = stk + sp + oexcl;
+                    for (int t = 0; t < ocnt; ++t) d[t] = cf + t;
+                }
+                sp += otot;
+                __syncthreads();
             }
-            // children of opened internal nodes (at most 8 each)
-            const int ocnt = isO ? ncld : 0;
-            int otot;
-            const int oexcl = wave_excl_small<4>(ocnt, otot);
-            if (sp + otot > cap) {
-                ovf = true;
-                break;
-            }
-            if (isO) {
-                int32_t *d = stk + sp + oexcl;
-                for (int t = 0; t < ocnt; ++t) d[t] = cf + t;
-            }
-            sp += otot;
             __syncthreads();
+            if (!ovf) break;
+            if (lane == 0) atomicAdd(pass ? wo.stack_ovf : wo.spilled, 1);
         }
-        __syncthreads();
-        if (ovf) {
-            if (lane == 0) atomicOr(wo.stack_ovf, 1);
-            continue;
-        }
+        if (ovf) continue;   // cannot happen: the global stack holds the bound
         if (lane == 0) {
             bool over = false;
             for (int k = 0; k < 3; ++k) {
@@ -195,6 +203,7 @@ struct WalkStats {
     unsigned long long n_leaves;
     unsigned long long maxlen[3];  // longest list of each kind
     int32_t stack_ovf, cap_ovf;    // flags written by the walk
+    int32_t spilled, pad;          // groups that needed the global stack
 };
 
 // Statistics from the per-group counts, and the leaf count of the tree.
@@ -250,7 +259,7 @@ __global__ __launch_bounds__(1024) void k_walk_stats(const GroupInfo *__restrict
 }
 
 static unsigned walk_grid(p3t_ctx *ctx) {
-    int64_t g = ctx->n_nodes < 8192 ? ctx->n_nodes : 8192;
+    int64_t g = ctx->n_nodes < kWalkGrid ? ctx->n_nodes : kWalkGrid;
     return (unsigned)(g > 0 ? g : 1);
 }
 
@@ -394,7 +403,14 @@ int build_lists(p3t_ctx *ctx) {
     wo.end = end;
     wo.stack_ovf = &ws->stack_ovf;
     wo.cap_ovf = &ws->cap_ovf;
+    wo.spilled = &ws->spilled;
     wo.stride = stride;
+    // every block has a global-memory stack for groups that outgrow the LDS one
+    if ((rc = ensure(ctx, ctx->wstack, (size_t)grid * kGlobalStack * sizeof(int32_t)))) return rc;
+    int32_t *gstack = ptr<int32_t>(ctx->wstack);
+    const int lds_cap = (ctx->walk_lds_cap >= 64 && ctx->walk_lds_cap < kLdsStack) ? ctx->walk_lds_cap
+                                                                              : kLdsStack;
+
     auto reset = [&]() {
         return check_hip(ctx, hipMemsetAsync(ws, 0, sizeof(WalkStats), st), "memset");
     };
@@ -411,10 +427,13 @@ int build_lists(p3t_ctx *ctx) {
         ctx->n_pp_near = (int64_t)hs->pp_near;
         ctx->n_leaves = (int64_t)hs->n_leaves;
         ctx->walk_fixed = fixed ? 1 : 0;
+        ctx->walk_global = hs->spilled > 0 ? 1 : 0;
+    };
+    auto stack_error = [&]() {
+        return set_error(ctx, P3T_EINVAL, "tree walk stack overflow");
     };
 
     // ---- single walk into fixed-stride segments, sized from the last build ----
-    int use_global = 0;
     if (ctx->hint_groups > 0 && ctx->prm.n_crit == ctx->hint_n_crit) {
         const int64_t gcap = ctx->hint_groups + ctx->hint_groups / 8 + 64;
         bool ok = gcap <= stride;
@@ -424,10 +443,6 @@ int build_lists(p3t_ctx *ctx) {
             // keep the reserved room within a few times the last build's lists
             ok = gcap * wo.cap[k] <= 8 * ctx->list_total[k] + (1 << 22);
         }
-        // a tree that needed the global-memory stack last time starts there
-        const int g0 = ctx->walk_global;
-        if (ok && g0)
-            ok = ensure(ctx, ctx->wstack, (size_t)grid * kGlobalStack * sizeof(int32_t)) == P3T_OK;
         if (ok) {
             wo.gcap = gcap;
             for (int k = 0; k < 3; ++k) {
@@ -437,39 +452,31 @@ int build_lists(p3t_ctx *ctx) {
             if ((rc = reset())) return rc;
             k_walk<kFixed><<<grid, kWalkThreads, 0, st>>>(ptr<GroupInfo>(ctx->grp), G_dev,
                                                            ptr<NodeWalk>(ctx->node_walk), wp, wo,
-                                                           ptr<int32_t>(ctx->wstack), g0);
+                                                           gstack, lds_cap);
             if ((rc = check_hip(ctx, hipGetLastError(), "walk"))) return rc;
             if ((rc = run_walk_stats(ctx, G_dev, stride, ws))) return rc;
-            if (!hs->stack_ovf && !hs->cap_ovf) {
+            if (hs->stack_ovf) return stack_error();
+            if (!hs->cap_ovf) {
                 finish(true);
                 return build_order(ctx, stride);
             }
-            use_global = (hs->stack_ovf || g0) ? 1 : 0;
         }
     }
 
     // ---- two passes: count, prefix sums, emit at exact offsets ----
-    for (;; use_global = 1) {
-        if (use_global) {
-            if ((rc = ensure(ctx, ctx->wstack, (size_t)grid * kGlobalStack * sizeof(int32_t))))
-                return rc;
-        }
-        if ((rc = reset())) return rc;
-        // entries past the last group take part in the scans as zeros
-        if ((rc = check_hip(ctx, hipMemsetAsync(cnt, 0, 3 * stride * sizeof(int64_t), st), "memset")))
+    if ((rc = reset())) return rc;
+    // entries past the last group take part in the scans as zeros
+    if ((rc = check_hip(ctx, hipMemsetAsync(cnt, 0, 3 * stride * sizeof(int64_t), st), "memset")))
+        return rc;
+    k_walk<kCount><<<grid, kWalkThreads, 0, st>>>(ptr<GroupInfo>(ctx->grp), G_dev,
+                                                   ptr<NodeWalk>(ctx->node_walk), wp, wo, gstack,
+                                                   lds_cap);
+    if ((rc = check_hip(ctx, hipGetLastError(), "walk count"))) return rc;
+    for (int k = 0; k < 3; ++k)
+        if ((rc = scan_exclusive_i64(ctx, cnt + k * stride, off + k * stride, stride, nullptr)))
             return rc;
-        k_walk<kCount><<<grid, kWalkThreads, 0, st>>>(ptr<GroupInfo>(ctx->grp), G_dev,
-                                                       ptr<NodeWalk>(ctx->node_walk), wp, wo,
-                                                       ptr<int32_t>(ctx->wstack), use_global);
-        if ((rc = check_hip(ctx, hipGetLastError(), "walk count"))) return rc;
-        for (int k = 0; k < 3; ++k)
-            if ((rc = scan_exclusive_i64(ctx, cnt + k * stride, off + k * stride, stride, nullptr)))
-                return rc;
-        if ((rc = run_walk_stats(ctx, G_dev, stride, ws))) return rc;
-        if (!hs->stack_ovf) break;
-        if (use_global) return set_error(ctx, P3T_EINVAL, "tree walk stack overflow");
-    }
-    ctx->walk_global = use_global;
+    if ((rc = run_walk_stats(ctx, G_dev, stride, ws))) return rc;
+    if (hs->stack_ovf) return stack_error();
     for (int k = 0; k < 3; ++k) {
         if ((rc = ensure(ctx, *lbuf[k], ((int64_t)hs->total[k] + 1) * sizeof(int32_t)))) return rc;
         wo.idx[k] = ptr<int32_t>(*lbuf[k]);
@@ -478,8 +485,8 @@ int build_lists(p3t_ctx *ctx) {
     finish(false);
     ctx->hint_n_crit = ctx->prm.n_crit;
     k_walk<kEmit><<<grid, kWalkThreads, 0, st>>>(ptr<GroupInfo>(ctx->grp), G_dev,
-                                                  ptr<NodeWalk>(ctx->node_walk), wp, wo,
-                                                  ptr<int32_t>(ctx->wstack), use_global);
+                                                  ptr<NodeWalk>(ctx->node_walk), wp, wo, gstack,
+                                                  lds_cap);
     if ((rc = check_hip(ctx, hipGetLastError(), "walk emit"))) return rc;
     return build_order(ctx, stride);
 }

@@ -202,6 +202,29 @@ def test_neighbor_rows_longer_than_slots(ctx):
     fresh.close()
 
 
+def test_walk_global_stack_path(monkeypatch):
+    """With the walk's LDS stack capped at 64 entries most groups move to the
+    global-memory stack; lists, forces and neighbours must still match the oracle,
+    in both the two-pass and the fixed-stride walk."""
+    from paper_1506_04553_amd import P3T
+    w = WORKLOADS["plummer64k_salpeter"]
+    c = make_cluster(w, seed=6)
+    p = _params(w, precision="fp64")
+    t = oracle.Tree(c.pos, c.mass, p)
+    acc, pot = t.force()
+    monkeypatch.setenv("P3T_WALK_LDS_STACK", "64")
+    small = P3T(0)
+    monkeypatch.delenv("P3T_WALK_LDS_STACK")
+    for k in range(2):
+        g = gpu_run(small, c.pos, c.mass, p)
+        assert g["stats"]["walk_global_stack"] == 1
+        assert g["stats"]["walk_fixed_stride"] == k
+        compare_tree(g, t)
+        compare_neighbors(g, t)
+        _check_forces(g, acc, pot, FP64_TOL, f"global stack walk {k}")
+    small.close()
+
+
 def test_forward_is_deterministic(ctx):
     w = WORKLOADS["plummer64k_salpeter"]
     c = make_cluster(w, seed=2)
