@@ -223,7 +223,9 @@ def cpu_baseline(pos, mass, params, gpu_first, target_s=12.0, seed=3):
 
 
 def vjp_timing(ctx, workload="plummer256k", seed=1, reps=3):
-    """FP32 forward + FP64 VJP of sum(w.a) + sum(c.phi) on the 2^18 Plummer workload."""
+    """Forward + VJP of sum(w.a) + sum(c.phi) on the 2^18 Plummer workload, in
+    each precision mode (the VJP's pair and cell terms follow the forward's
+    precision; its sums are FP64 in both)."""
     import torch
     from inputs import WORKLOADS, make_cluster
     w_ = WORKLOADS[workload]
@@ -234,17 +236,24 @@ def vjp_timing(ctx, workload="plummer256k", seed=1, reps=3):
     rng = np.random.default_rng(seed + 1)
     wv = torch.from_numpy(rng.normal(size=(w_.n, 3))).to(dev)
     cv = torch.from_numpy(rng.normal(size=w_.n)).to(dev)
-    p = w_.params(precision="mixed")
-    ctx.build_tree(pos, mass, **p)
-    ctx.long_force()
-    ctx.long_force_vjp(wv, cv)
-    ms = []
-    for _ in range(reps):
-        ctx.long_force_vjp(wv, cv)
-        ms.append(ctx.stats()["ms_vjp"])
-    st = ctx.stats()
-    return {"workload": workload, "n": w_.n, "vjp_ms": float(np.median(ms)),
-            "forward_ms": st["ms_force"], "interactions": st["n_pp"] + st["n_pc"]}
+    out = {"workload": workload, "n": w_.n}
+    grads = {}
+    for prec in ("mixed", "fp64"):
+        ctx.build_tree(pos, mass, **w_.params(precision=prec))
+        ctx.long_force()
+        grads[prec] = ctx.long_force_vjp(wv, cv)
+        ms = []
+        for _ in range(reps):
+            ctx.long_force_vjp(wv, cv)
+            ms.append(ctx.stats()["ms_vjp"])
+        st = ctx.stats()
+        out[prec] = {"vjp_ms": float(np.median(ms)), "forward_ms": st["ms_force"],
+                     "interactions": st["n_pp"] + st["n_pc"]}
+    (g32, m32), (g64, m64) = grads["mixed"], grads["fp64"]
+    out["mixed_vs_fp64_gpu"] = {
+        "gpos_rel_rms": float(((g32 - g64).norm() / g64.norm()).item()),
+        "gmass_rel_rms": float(((m32 - m64).norm() / m64.norm()).item())}
+    return out
 
 
 def sweep(args):

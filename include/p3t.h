@@ -132,7 +132,10 @@ int p3t_neighbors(p3t_ctx *ctx, int64_t *offsets, int32_t *idx, int64_t cap, int
 
 /* Vector-Jacobian product of L = sum_i w_i . a_i + c_i phi_i with respect to
  * positions and masses, with the tree, groups and lists of the last build held
- * fixed (the derivative ignores changes of list membership).
+ * fixed (the derivative ignores changes of list membership).  The pair and
+ * cell terms are evaluated in the last build's precision (P3T_PREC_MIXED:
+ * FP32 on offsets from the group's centre taken in FP64, changeover factors
+ * in FP64); all sums and the push-down through the tree are FP64.
  *   w  device [n][3] float64; c device [n] float64 or NULL (taken as 0)
  *   gpos device [n][3] float64 out; gmass device [n] float64 out
  * Errors: ESTATE, EINVAL, ENOMEM, EHIP. */

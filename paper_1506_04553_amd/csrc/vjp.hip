@@ -20,9 +20,15 @@
 // The forms of a leaf's ancestors are summed top-down, each re-centred at the
 // child's centre of mass, so every particle needs only its leaf's form.
 //
-// Everything is FP64.  Scatter to list entries uses FP64 atomic adds, one per
+// The pair and cell terms are evaluated in the precision of the forward pass
+// (R = double, or R = float on offsets from the group's centre taken in FP64,
+// as in the interaction kernel; K and W themselves are evaluated in FP64) and
+// summed in FP64.  Scatter to list entries uses FP64 atomic adds, one per
 // (group, entry, component) after reduction over the group's members, so the
-// result is reproducible up to the order of those atomic additions.
+// result is reproducible up to the order of those atomic additions.  The cell
+// adjoints are held component-major ([10][n_nodes]): the ten adds of one entry
+// then fall on ten different cache lines, where in cell-major order they
+// would queue on one line.  The push-down of the cell adjoints is FP64.
 #include <math.h>
 
 #include "device_util.h"
@@ -72,43 +78,53 @@ __device__ __forceinline__ Chg changeover_ds(double s, const VjpParams &vp) {
 // K = W = 1 and dK/ds = dW/ds = 0 (pairs and cells at least r_out apart)
 __device__ __forceinline__ Chg changeover_unit() { return Chg{1.0, 0.0, 1.0, 0.0}; }
 
+__device__ __forceinline__ float vrsq(float v) { return __builtin_amdgcn_rsqf(v); }
+__device__ __forceinline__ double vrsq(double v) { return rsqrt(v); }
+
 // d(l_ij)/dd and d(l_ij)/dm_j for one pair; CHG false: K = W = 1 known.
-template <bool CHG>
-__device__ __forceinline__ void pair_grad(double dx, double dy, double dz, double mj, double wx,
-                                          double wy, double wz, double ci, const VjpParams &vp,
-                                          double gd[3], double &gm) {
-    const double s2 = dx * dx + dy * dy + dz * dz + vp.eps2;
-    const double inv = rsqrt(s2);
-    const double s = s2 * inv;
-    const double inv2 = inv * inv, inv3 = inv2 * inv;
-    const Chg c = CHG ? changeover_ds(s, vp) : changeover_unit();
-    const double g = c.K * inv3;
-    const double gp = c.Ks * inv3 - 3.0 * c.K * inv2 * inv2;
-    const double wd = wx * dx + wy * dy + wz * dz;
-    const double t = gp * wd * inv + ci * c.K * inv3;
+template <class R, bool CHG>
+__device__ __forceinline__ void pair_grad(R dx, R dy, R dz, R mj, R wx, R wy, R wz, R ci,
+                                          const VjpParams &vp, R gd[3], R &gm) {
+    const R s2 = dx * dx + dy * dy + dz * dz + (R)vp.eps2;
+    const R inv = vrsq(s2);
+    const R s = s2 * inv;
+    const R inv2 = inv * inv, inv3 = inv2 * inv;
+    const Chg c = CHG ? changeover_ds((double)s, vp) : changeover_unit();
+    const R K = (R)c.K, Ks = (R)c.Ks, W = (R)c.W;
+    const R g = K * inv3;
+    const R gp = Ks * inv3 - R(3) * K * inv2 * inv2;
+    const R wd = wx * dx + wy * dy + wz * dz;
+    const R t = gp * wd * inv + ci * K * inv3;
     gd[0] = mj * (g * wx + t * dx);
     gd[1] = mj * (g * wy + t * dy);
     gd[2] = mj * (g * wz + t * dz);
-    gm = g * wd - ci * c.W * inv;
+    gm = g * wd - ci * W * inv;
 }
 
+template <class R>
 struct CellGrad {
-    double gr[3];    // dl/dr (r = x_i - com)
-    double gM;       // dl/dM
-    double S[6];     // symmetric dl/dQ: xx yy zz xy xz yz
+    R gr[3];    // dl/dr (r = x_i - com)
+    R gM;       // dl/dM
+    R S[6];     // symmetric dl/dQ: xx yy zz xy xz yz
 };
 
-template <bool CHG>
-__device__ __forceinline__ void cell_grad(double rx, double ry, double rz, double M, const double q[6],
-                                          double wx, double wy, double wz, double ci,
-                                          const VjpParams &vp, CellGrad &o) {
-    const double s2 = rx * rx + ry * ry + rz * rz + vp.eps2;
-    const double inv = rsqrt(s2);
-    const double s = s2 * inv;
-    const double inv2 = inv * inv, inv3 = inv2 * inv, inv5 = inv3 * inv2, inv7 = inv5 * inv2,
-                 inv9 = inv7 * inv2;
-    const Chg c = CHG ? changeover_ds(s, vp) : changeover_unit();
-    double Qr[3] = {0, 0, 0}, Qw[3] = {0, 0, 0}, qq = 0.0;
+// a cell as staged for the adjoint kernels: centre of mass (shifted), M, Q
+template <class R>
+struct VjpCell {
+    R x, y, z, M, q[6];
+};
+
+template <class R, bool CHG>
+__device__ __forceinline__ void cell_grad(R rx, R ry, R rz, R M, const R q[6], R wx, R wy, R wz,
+                                          R ci, const VjpParams &vp, CellGrad<R> &o) {
+    const R s2 = rx * rx + ry * ry + rz * rz + (R)vp.eps2;
+    const R inv = vrsq(s2);
+    const R s = s2 * inv;
+    const R inv2 = inv * inv, inv3 = inv2 * inv, inv5 = inv3 * inv2, inv7 = inv5 * inv2,
+            inv9 = inv7 * inv2;
+    const Chg c = CHG ? changeover_ds((double)s, vp) : changeover_unit();
+    const R K = (R)c.K, Ks = (R)c.Ks, W = (R)c.W, Ws = (R)c.Ws;
+    R Qr[3] = {0, 0, 0}, Qw[3] = {0, 0, 0}, qq = 0;
     if (vp.use_quad) {
         Qr[0] = q[0] * rx + q[3] * ry + q[4] * rz;
         Qr[1] = q[3] * rx + q[1] * ry + q[5] * rz;
@@ -118,54 +134,74 @@ __device__ __forceinline__ void cell_grad(double rx, double ry, double rz, doubl
         Qw[2] = q[4] * wx + q[5] * wy + q[2] * wz;
         qq = rx * Qr[0] + ry * Qr[1] + rz * Qr[2];
     }
-    const double r[3] = {rx, ry, rz}, w[3] = {wx, wy, wz};
-    const double rw = rx * wx + ry * wy + rz * wz;
-    const double Qrw = Qr[0] * wx + Qr[1] * wy + Qr[2] * wz;
-    double A[3], Hw[3];
-    const double cw = M * inv3 + 2.5 * qq * inv7;
-    const double cr = -3.0 * M * rw * inv5 + 5.0 * Qrw * inv7 - 17.5 * qq * rw * inv9;
-    const double cq = 5.0 * rw * inv7;
+    const R r[3] = {rx, ry, rz}, w[3] = {wx, wy, wz};
+    const R rw = rx * wx + ry * wy + rz * wz;
+    const R Qrw = Qr[0] * wx + Qr[1] * wy + Qr[2] * wz;
+    R A[3], Hw[3];
+    const R cw = M * inv3 + R(2.5) * qq * inv7;
+    const R cr = R(-3) * M * rw * inv5 + R(5) * Qrw * inv7 - R(17.5) * qq * rw * inv9;
+    const R cq = R(5) * rw * inv7;
     for (int a = 0; a < 3; ++a) {
-        A[a] = -M * r[a] * inv3 + Qr[a] * inv5 - 2.5 * qq * r[a] * inv7;
+        A[a] = -M * r[a] * inv3 + Qr[a] * inv5 - R(2.5) * qq * r[a] * inv7;
         Hw[a] = w[a] * cw - Qw[a] * inv5 + r[a] * cr + Qr[a] * cq;
     }
-    const double Phi = -M * inv - 0.5 * qq * inv5;
-    const double wA = wx * A[0] + wy * A[1] + wz * A[2];
-    const double radial = (c.Ks * wA + ci * c.Ws * Phi) * inv;
-    for (int a = 0; a < 3; ++a) o.gr[a] = radial * r[a] - c.K * Hw[a] - ci * c.W * A[a];
-    o.gM = -c.K * rw * inv3 - ci * c.W * inv;
+    const R Phi = -M * inv - R(0.5) * qq * inv5;
+    const R wA = wx * A[0] + wy * A[1] + wz * A[2];
+    const R radial = (Ks * wA + ci * Ws * Phi) * inv;
+    for (int a = 0; a < 3; ++a) o.gr[a] = radial * r[a] - K * Hw[a] - ci * W * A[a];
+    o.gM = -K * rw * inv3 - ci * W * inv;
     if (vp.use_quad) {
-        const double k5 = 0.5 * c.K * inv5, k7 = -2.5 * c.K * rw * inv7, cwq = -0.5 * ci * c.W * inv5;
-        const double rr = k7 + cwq;
-        o.S[0] = 2.0 * k5 * wx * rx + rr * rx * rx;
-        o.S[1] = 2.0 * k5 * wy * ry + rr * ry * ry;
-        o.S[2] = 2.0 * k5 * wz * rz + rr * rz * rz;
+        const R k5 = R(0.5) * K * inv5, k7 = R(-2.5) * K * rw * inv7, cwq = R(-0.5) * ci * W * inv5;
+        const R rr = k7 + cwq;
+        o.S[0] = R(2) * k5 * wx * rx + rr * rx * rx;
+        o.S[1] = R(2) * k5 * wy * ry + rr * ry * ry;
+        o.S[2] = R(2) * k5 * wz * rz + rr * rz * rz;
         o.S[3] = k5 * (wx * ry + wy * rx) + rr * rx * ry;
         o.S[4] = k5 * (wx * rz + wz * rx) + rr * rx * rz;
         o.S[5] = k5 * (wy * rz + wz * ry) + rr * ry * rz;
     } else {
-        for (int a = 0; a < 6; ++a) o.S[a] = 0.0;
+        for (int a = 0; a < 6; ++a) o.S[a] = R(0);
     }
+}
+
+// coordinates are taken relative to `shift` in FP64 before rounding to R: the
+// group's centre for R = float, the origin (no change) for R = double
+template <class R>
+__device__ __forceinline__ void group_shift(const GroupInfo &gi, double sh[3]) {
+    for (int a = 0; a < 3; ++a) sh[a] = sizeof(R) == 4 ? gi.c[a] : 0.0;
+}
+
+template <class R>
+__device__ __forceinline__ VjpCell<R> stage_cell(const NodeMP &c, const double sh[3]) {
+    VjpCell<R> v;
+    v.x = (R)(c.cx - sh[0]);
+    v.y = (R)(c.cy - sh[1]);
+    v.z = (R)(c.cz - sh[2]);
+    v.M = (R)c.M;
+    for (int a = 0; a < 6; ++a) v.q[a] = (R)c.q[a];
+    return v;
 }
 
 // ---------------------------------------------------------------------------
 // Pass 1: per particle i (one group per block), the i-side terms.
 // ---------------------------------------------------------------------------
 // CELL_K: accepted cells may lie within r_out of a member (h < r_out)
-template <bool CELL_K>
+template <class R, bool CELL_K>
 __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
     const GroupInfo *__restrict__ grp, ListsDev L, const double *__restrict__ x,
     const double *__restrict__ y,
     const double *__restrict__ z, const double *__restrict__ m, const NodeMP *__restrict__ mp,
     const int32_t *__restrict__ perm, const double *__restrict__ wv, const double *__restrict__ cv,
     VjpParams vp, double *__restrict__ gx, double *__restrict__ gm, int64_t n) {
-    __shared__ double s_p[4][kVjpTile];
+    __shared__ R s_p[4][kVjpTile];
     __shared__ int32_t s_j[kVjpTile];
-    __shared__ NodeMP s_c[kVjpTile];
+    __shared__ VjpCell<R> s_c[kVjpTile];
     __shared__ double s_red[3][kVjpThreads];
     const int tid = threadIdx.x;
     const int g = L.order[blockIdx.x];
     const GroupInfo gi = grp[g];
+    double sh[3];
+    group_shift<R>(gi, sh);
     const int64_t cb = L.beg[0][g], ce = L.end[0][g];
     const int32_t *__restrict__ c_idx = L.idx[0];
     // members in chunks of the largest power of two that fits (at most 256),
@@ -180,9 +216,9 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
         const bool valid = li < nc;
         const int32_t i = gi.first + chunk + (valid ? li : 0);
         const int64_t o = perm[i];
-        const double xi = x[i], yi = y[i], zi = z[i];
-        const double wx = wv[3 * o], wy = wv[3 * o + 1], wz = wv[3 * o + 2];
-        const double ci = vp.has_c ? cv[o] : 0.0;
+        const R xi = (R)(x[i] - sh[0]), yi = (R)(y[i] - sh[1]), zi = (R)(z[i] - sh[2]);
+        const R wx = (R)wv[3 * o], wy = (R)wv[3 * o + 1], wz = (R)wv[3 * o + 2];
+        const R ci = vp.has_c ? (R)cv[o] : R(0);
         double g0 = 0, g1 = 0, g2 = 0;
         for (int list = 0; list < 2; ++list) {        // far and near particles
             const int32_t *idxs = L.idx[1 + list];
@@ -193,19 +229,22 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
                 __syncthreads();
                 if (tid < tl) {
                     const int32_t j = idxs[t0 + tid];
-                    s_p[0][tid] = x[j]; s_p[1][tid] = y[j]; s_p[2][tid] = z[j]; s_p[3][tid] = m[j];
+                    s_p[0][tid] = (R)(x[j] - sh[0]);
+                    s_p[1][tid] = (R)(y[j] - sh[1]);
+                    s_p[2][tid] = (R)(z[j] - sh[2]);
+                    s_p[3][tid] = (R)m[j];
                     s_j[tid] = j;
                 }
                 __syncthreads();
                 for (int k = slice; k < tl; k += nslice) {
                     if (s_j[k] == i) continue;
-                    double gd[3], gmj;
+                    R gd[3], gmj;
                     if (list == 0)   // far particles: K = W = 1
-                        pair_grad<false>(s_p[0][k] - xi, s_p[1][k] - yi, s_p[2][k] - zi, s_p[3][k],
-                                         wx, wy, wz, ci, vp, gd, gmj);
+                        pair_grad<R, false>(s_p[0][k] - xi, s_p[1][k] - yi, s_p[2][k] - zi,
+                                            s_p[3][k], wx, wy, wz, ci, vp, gd, gmj);
                     else
-                        pair_grad<true>(s_p[0][k] - xi, s_p[1][k] - yi, s_p[2][k] - zi, s_p[3][k],
-                                        wx, wy, wz, ci, vp, gd, gmj);
+                        pair_grad<R, true>(s_p[0][k] - xi, s_p[1][k] - yi, s_p[2][k] - zi,
+                                           s_p[3][k], wx, wy, wz, ci, vp, gd, gmj);
                     g0 -= gd[0]; g1 -= gd[1]; g2 -= gd[2];
                 }
             }
@@ -213,12 +252,12 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
         for (int64_t t0 = cb; t0 < ce; t0 += kVjpTile) {
             const int tl = (int)min<int64_t>(kVjpTile, ce - t0);
             __syncthreads();
-            if (tid < tl) s_c[tid] = mp[c_idx[t0 + tid]];
+            if (tid < tl) s_c[tid] = stage_cell<R>(mp[c_idx[t0 + tid]], sh);
             __syncthreads();
             for (int k = slice; k < tl; k += nslice) {
-                const NodeMP c = s_c[k];
-                CellGrad cg;
-                cell_grad<CELL_K>(xi - c.cx, yi - c.cy, zi - c.cz, c.M, c.q, wx, wy, wz, ci, vp, cg);
+                const VjpCell<R> c = s_c[k];
+                CellGrad<R> cg;
+                cell_grad<R, CELL_K>(xi - c.x, yi - c.y, zi - c.z, c.M, c.q, wx, wy, wz, ci, vp, cg);
                 g0 += cg.gr[0]; g1 += cg.gr[1]; g2 += cg.gr[2];
             }
         }
@@ -239,21 +278,24 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
 
 // ---------------------------------------------------------------------------
 // Pass 2: per list entry (particle j or cell c), the sum over the group's
-// members, scattered with one atomic add per component.
+// members, scattered with one atomic add per component.  Cell adjoints are
+// component-major: component a of cell c at cadj[a * n_nodes + c].
 // ---------------------------------------------------------------------------
-template <bool CELL_K>
+template <class R, bool CELL_K>
 __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
     const GroupInfo *__restrict__ grp, ListsDev L, const double *__restrict__ x,
     const double *__restrict__ y,
     const double *__restrict__ z, const double *__restrict__ m, const NodeMP *__restrict__ mp,
     const int32_t *__restrict__ perm, const double *__restrict__ wv, const double *__restrict__ cv,
     VjpParams vp, double *__restrict__ gx, double *__restrict__ gm, double *__restrict__ cadj,
-    int64_t n) {
-    __shared__ double s_i[7][kVjpThreads];   // x y z w(3) c of the group's members
+    int64_t n, int64_t n_nodes) {
+    __shared__ R s_i[7][kVjpThreads];   // x y z w(3) c of the group's members
     __shared__ int32_t s_id[kVjpThreads];
     const int tid = threadIdx.x;
     const int g = L.order[blockIdx.x];
     const GroupInfo gi = grp[g];
+    double sh[3];
+    group_shift<R>(gi, sh);
     const int64_t cb = L.beg[0][g], ce = L.end[0][g];
     const int64_t fb = L.beg[1][g], fe = L.end[1][g];
     const int64_t nb = L.beg[2][g], ne = L.end[2][g];
@@ -267,26 +309,31 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
         if (tid < nc) {
             const int32_t i = gi.first + chunk + tid;
             const int64_t o = perm[i];
-            s_i[0][tid] = x[i]; s_i[1][tid] = y[i]; s_i[2][tid] = z[i];
-            s_i[3][tid] = wv[3 * o]; s_i[4][tid] = wv[3 * o + 1]; s_i[5][tid] = wv[3 * o + 2];
-            s_i[6][tid] = vp.has_c ? cv[o] : 0.0;
+            s_i[0][tid] = (R)(x[i] - sh[0]);
+            s_i[1][tid] = (R)(y[i] - sh[1]);
+            s_i[2][tid] = (R)(z[i] - sh[2]);
+            s_i[3][tid] = (R)wv[3 * o];
+            s_i[4][tid] = (R)wv[3 * o + 1];
+            s_i[5][tid] = (R)wv[3 * o + 2];
+            s_i[6][tid] = vp.has_c ? (R)cv[o] : R(0);
             s_id[tid] = i;
         }
         __syncthreads();
         for (int64_t e = tid; e < np; e += kVjpThreads) {
             const bool far = e < nf;
             const int32_t j = far ? p_idx[fb + e] : n_idx[nb + (e - nf)];
-            const double xj = x[j], yj = y[j], zj = z[j], mj = m[j];
+            const R xj = (R)(x[j] - sh[0]), yj = (R)(y[j] - sh[1]), zj = (R)(z[j] - sh[2]);
+            const R mj = (R)m[j];
             double a0 = 0, a1 = 0, a2 = 0, am = 0;
             for (int k = 0; k < nc; ++k) {
                 if (s_id[k] == j) continue;
-                double gd[3], gmj;
+                R gd[3], gmj;
                 if (far)   // K = W = 1
-                    pair_grad<false>(xj - s_i[0][k], yj - s_i[1][k], zj - s_i[2][k], mj, s_i[3][k],
-                                     s_i[4][k], s_i[5][k], s_i[6][k], vp, gd, gmj);
+                    pair_grad<R, false>(xj - s_i[0][k], yj - s_i[1][k], zj - s_i[2][k], mj,
+                                        s_i[3][k], s_i[4][k], s_i[5][k], s_i[6][k], vp, gd, gmj);
                 else
-                    pair_grad<true>(xj - s_i[0][k], yj - s_i[1][k], zj - s_i[2][k], mj, s_i[3][k],
-                                    s_i[4][k], s_i[5][k], s_i[6][k], vp, gd, gmj);
+                    pair_grad<R, true>(xj - s_i[0][k], yj - s_i[1][k], zj - s_i[2][k], mj,
+                                       s_i[3][k], s_i[4][k], s_i[5][k], s_i[6][k], vp, gd, gmj);
                 a0 += gd[0]; a1 += gd[1]; a2 += gd[2]; am += gmj;
             }
             atomicAdd(&gx[j], a0);
@@ -296,19 +343,18 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
         }
         for (int64_t e = cb + tid; e < ce; e += kVjpThreads) {
             const int32_t cid = c_idx[e];
-            const NodeMP c = mp[cid];
+            const VjpCell<R> c = stage_cell<R>(mp[cid], sh);
             double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
             for (int k = 0; k < nc; ++k) {
-                CellGrad cg;
-                cell_grad<CELL_K>(s_i[0][k] - c.cx, s_i[1][k] - c.cy, s_i[2][k] - c.cz, c.M, c.q, s_i[3][k],
-                          s_i[4][k], s_i[5][k], s_i[6][k], vp, cg);
+                CellGrad<R> cg;
+                cell_grad<R, CELL_K>(s_i[0][k] - c.x, s_i[1][k] - c.y, s_i[2][k] - c.z, c.M, c.q,
+                                     s_i[3][k], s_i[4][k], s_i[5][k], s_i[6][k], vp, cg);
                 acc[0] -= cg.gr[0]; acc[1] -= cg.gr[1]; acc[2] -= cg.gr[2];
                 acc[3] += cg.gM;
                 for (int a = 0; a < 6; ++a) acc[4 + a] += cg.S[a];
             }
-            double *dst = cadj + 10 * (int64_t)cid;
             for (int a = 0; a < 10; ++a)
-                if (acc[a] != 0.0) atomicAdd(&dst[a], acc[a]);
+                if (acc[a] != 0.0) atomicAdd(&cadj[a * n_nodes + cid], acc[a]);
         }
     }
 }
@@ -323,18 +369,21 @@ struct Form {
     double g;
 };
 
-__device__ __forceinline__ void form_add_own(Form &f, const double *adj, double M) {
-    const double tr = adj[4] + adj[5] + adj[6];
-    f.B[0] += 3.0 * adj[4] - tr;
-    f.B[1] += 3.0 * adj[5] - tr;
-    f.B[2] += 3.0 * adj[6] - tr;
-    f.B[3] += 3.0 * adj[7];
-    f.B[4] += 3.0 * adj[8];
-    f.B[5] += 3.0 * adj[9];
-    f.b[0] += adj[0] / M;
-    f.b[1] += adj[1] / M;
-    f.b[2] += adj[2] / M;
-    f.g += adj[3];
+// adj: component a at adj[a * stride]
+__device__ __forceinline__ void form_add_own(Form &f, const double *adj, int64_t stride, double M) {
+    double v[10];
+    for (int a = 0; a < 10; ++a) v[a] = adj[a * stride];
+    const double tr = v[4] + v[5] + v[6];
+    f.B[0] += 3.0 * v[4] - tr;
+    f.B[1] += 3.0 * v[5] - tr;
+    f.B[2] += 3.0 * v[6] - tr;
+    f.B[3] += 3.0 * v[7];
+    f.B[4] += 3.0 * v[8];
+    f.B[5] += 3.0 * v[9];
+    f.b[0] += v[0] / M;
+    f.b[1] += v[1] / M;
+    f.b[2] += v[2] / M;
+    f.g += v[3];
 }
 
 __device__ __forceinline__ void Bmul(const double B[6], const double v[3], double o[3]) {
@@ -370,7 +419,7 @@ __global__ void k_vjp_down(int64_t n_nodes, const int32_t *__restrict__ nchild,
             const double e[3] = {mp[c].cx - mp[p].cx, mp[c].cy - mp[p].cy, mp[c].cz - mp[p].cz};
             form_shift(f, e);
         }
-        form_add_own(f, cadj + 10 * (int64_t)c, mp[c].M);
+        form_add_own(f, cadj + c, n_nodes, mp[c].M);
     }
     const double cx = mp[leaf].cx, cy = mp[leaf].cy, cz = mp[leaf].cz;
     const int32_t first = nw[leaf].first, cnt = nw[leaf].count;
@@ -425,8 +474,12 @@ int launch_vjp(p3t_ctx *ctx, const double *w, const double *c, double *gpos, dou
     const unsigned G = (unsigned)ctx->n_groups;
     // accepted cells lie at least h from every member: K = W = 1 on them when h >= r_out
     const bool cell_k = ctx->prm.r_search < ctx->prm.r_out;
-    auto ki = cell_k ? k_vjp_i<true> : k_vjp_i<false>;
-    auto ks = cell_k ? k_vjp_scatter<true> : k_vjp_scatter<false>;
+    // the adjoint terms follow the forward pass's precision
+    const bool mixed = ctx->prm.precision == P3T_PREC_MIXED;
+    auto ki = mixed ? (cell_k ? k_vjp_i<float, true> : k_vjp_i<float, false>)
+                    : (cell_k ? k_vjp_i<double, true> : k_vjp_i<double, false>);
+    auto ks = mixed ? (cell_k ? k_vjp_scatter<float, true> : k_vjp_scatter<float, false>)
+                    : (cell_k ? k_vjp_scatter<double, true> : k_vjp_scatter<double, false>);
     ki<<<G, kVjpThreads, 0, ctx->stream>>>(
         ptr<GroupInfo>(ctx->grp), L, ptr<double>(ctx->x), ptr<double>(ctx->y), ptr<double>(ctx->z),
         ptr<double>(ctx->m), ptr<NodeMP>(ctx->node_mp), ptr<int32_t>(ctx->vals[0]), w, c, vp, gx, gm,
@@ -435,7 +488,7 @@ int launch_vjp(p3t_ctx *ctx, const double *w, const double *c, double *gpos, dou
     ks<<<G, kVjpThreads, 0, ctx->stream>>>(
         ptr<GroupInfo>(ctx->grp), L, ptr<double>(ctx->x), ptr<double>(ctx->y), ptr<double>(ctx->z),
         ptr<double>(ctx->m), ptr<NodeMP>(ctx->node_mp), ptr<int32_t>(ctx->vals[0]), w, c, vp, gx, gm,
-        cadj, n);
+        cadj, n, nn);
     if ((rc = check_hip(ctx, hipGetLastError(), "vjp scatter"))) return rc;
     k_vjp_down<<<blocks_for(nn, 128), 128, 0, ctx->stream>>>(
         nn, ptr<int32_t>(ctx->node_nchild), ptr<int32_t>(ctx->node_parent), ptr<NodeMP>(ctx->node_mp),

@@ -1,10 +1,12 @@
 """GPU VJP of the long-range force and potential (lists frozen).
 
-Checked against: the oracle's VJP (same tree, same lists) to 1e-10; at
-theta = 0 the analytic gradient of the direct soft sum; central finite
-differences of the GPU FP64 forward (h = 1e-6) on sampled coordinates whose
-perturbation leaves the lists unchanged; a direct-summation FP64 reference
-gradient at the tree-error level; and torch.autograd.gradcheck on a tiny case.
+Checked against: the oracle's VJP (same tree, same lists) to 1e-10 in FP64
+and 1e-4 relative RMS in mixed precision (FP32 terms on group-centred
+offsets, FP64 sums); at theta = 0 the analytic gradient of the direct soft
+sum; central finite differences of the GPU FP64 forward (h = 1e-6) on sampled
+coordinates whose perturbation leaves the lists unchanged; a direct-summation
+FP64 reference gradient at the tree-error level; and torch.autograd.gradcheck
+on a tiny case.
 """
 import numpy as np
 import pytest
@@ -36,24 +38,28 @@ def _gpu_vjp(ctx, pos, mass, params, w, cw):
     return gp.cpu().numpy(), gm.cpu().numpy()
 
 
+VJP_TOL = {"fp64": 1e-10, "mixed": 1e-4}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("quad,theta,r_out,with_c", [(1, 0.5, 0.05, True), (0, 0.6, 0.05, True),
                                                      (1, 0.4, 0.3, True), (1, 0.7, 0.01, False)])
-def test_vjp_matches_oracle(ctx, quad, theta, r_out, with_c):
+def test_vjp_matches_oracle(ctx, quad, theta, r_out, with_c, precision):
     n = 4096
     c = plummer(n, 41)
     mass = np.random.default_rng(42).uniform(0.5, 2.0, n)
     mass /= mass.sum()
     p = dict(eps=4.0 / n, r_in=0.1 * r_out, r_out=r_out, theta=theta, r_search=1.1 * r_out,
-             n_crit=64, n_leaf=16, use_quadrupole=quad)
+             n_crit=64, n_leaf=16, use_quadrupole=quad, precision=precision)
     rng = np.random.default_rng(43)
     w = rng.normal(size=(n, 3))
     cw = rng.normal(size=n) if with_c else None
-    log(f"vjp vs oracle quad={quad} theta={theta} r_out={r_out}")
+    log(f"vjp vs oracle {precision} quad={quad} theta={theta} r_out={r_out}")
     gp, gm = _gpu_vjp(ctx, c.pos, mass, p, w, cw)
     op, om = oracle.Tree(c.pos, mass, p).vjp(w, cw)
     ep, em = rel_rms(gp, op), rel_rms(gm, om)
     log(f"  gpos rel-RMS {ep:.2e}  gmass rel-RMS {em:.2e}")
-    assert ep < 1e-10 and em < 1e-10
+    assert ep < VJP_TOL[precision] and em < VJP_TOL[precision]
 
 
 def test_vjp_theta0_direct(ctx):
@@ -111,9 +117,11 @@ def _direct_grad_coords(pos, mass, p, w, cw, coords):
 
 
 def test_vjp_plummer256k_fd_and_direct(ctx):
-    """The 2^18-particle workload: FP32 forward, FP64 VJP; FD with h = 1e-6 of the
-    FP64 forward on 64 coordinates whose perturbation leaves the lists unchanged,
-    and the direct-summation reference gradient on the same coordinates."""
+    """The 2^18-particle workload.  FP64 build: the VJP against FD with h = 1e-6
+    of the FP64 forward on 64 coordinates whose perturbation leaves the lists
+    unchanged, and the direct-summation reference gradient on the same
+    coordinates.  Mixed build (same lists): the mixed VJP against the FP64 VJP
+    over every particle, and against the same FD values."""
     import torch
     w_ = WORKLOADS["plummer256k"]
     c = make_cluster(w_, seed=1)
@@ -128,10 +136,16 @@ def test_vjp_plummer256k_fd_and_direct(ctx):
     pos = torch.from_numpy(c.pos).to(dev)
     mass = torch.from_numpy(c.mass).to(dev)
     ctx.build_tree(pos, mass, **p32)
-    a32, _ = ctx.long_force()
-    gp, gm = ctx.long_force_vjp(tw, tc)
-    gp = gp.cpu().numpy()
+    ctx.long_force()
+    g32, m32 = (t.cpu().numpy() for t in ctx.long_force_vjp(tw, tc))
+    sig32 = _lists_signature(ctx)
+    ctx.build_tree(pos, mass, **p64)
+    g64, m64 = (t.cpu().numpy() for t in ctx.long_force_vjp(tw, tc))
     base = _lists_signature(ctx)
+    assert all(np.array_equal(u, v) for u, v in zip(sig32, base))
+    e32p, e32m = rel_rms(g32, g64), rel_rms(m32, m64)
+    log(f"plummer256k mixed VJP vs FP64 VJP: gpos rel-RMS {e32p:.2e}  gmass rel-RMS {e32m:.2e}")
+    assert e32p < 1e-4 and e32m < 1e-4
 
     def loss(pp):
         ctx.build_tree(pp, mass, **p64)
@@ -154,12 +168,15 @@ def test_vjp_plummer256k_fd_and_direct(ctx):
         coords.append((int(k), a))
         fds.append((lp - lm) / (2 * h))
     fds = np.array(fds)
-    got = np.array([gp[k, a] for k, a in coords])
-    err = np.abs(got - fds)
-    scale = np.abs(fds) + 1e-3 * np.abs(fds).max()
-    log(f"plummer256k VJP vs FD: max rel err {np.max(err / scale):.2e} over {len(coords)} coords")
     assert len(coords) >= 48
-    assert np.all(err <= 2e-4 * scale)
+    scale = np.abs(fds) + 1e-3 * np.abs(fds).max()
+    for name, g, tol in (("FP64", g64, 2e-4), ("mixed", g32, 1e-3)):
+        got = np.array([g[k, a] for k, a in coords])
+        err = np.abs(got - fds)
+        log(f"plummer256k {name} VJP vs FD: max rel err {np.max(err / scale):.2e} "
+            f"over {len(coords)} coords")
+        assert np.all(err <= tol * scale)
+    got = np.array([g64[k, a] for k, a in coords])
     ref = _direct_grad_coords(c.pos, c.mass, p64, w, cw, coords)
     e_dir = rel_rms(got, ref)
     log(f"plummer256k VJP vs direct-summation gradient: rel-RMS {e_dir:.2e} (tree error level)")
