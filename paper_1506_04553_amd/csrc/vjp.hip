@@ -20,6 +20,10 @@
 // The forms of a leaf's ancestors are summed top-down, each re-centred at the
 // child's centre of mass, so every particle needs only its leaf's form.
 //
+// The adjoint arithmetic takes no decisions (the lists are frozen), so unlike
+// the rest of the library it lets the compiler fuse multiply-adds.  Runs of at
+// most 32 terms are summed in R before each run's sum joins an FP64 sum.
+//
 // The pair and cell terms are evaluated in the precision of the forward pass
 // (R = double, or R = float on offsets from the group's centre taken in FP64,
 // as in the interaction kernel; K and W themselves are evaluated in FP64) and
@@ -53,6 +57,7 @@ struct Chg {
 };
 
 __device__ __forceinline__ Chg changeover_ds(double s, const VjpParams &vp) {
+#pragma clang fp contract(fast)
     Chg c;
     const double y = s * vp.inv_rout;
     if (y >= 1.0) {
@@ -85,6 +90,7 @@ __device__ __forceinline__ double vrsq(double v) { return rsqrt(v); }
 template <class R, bool CHG>
 __device__ __forceinline__ void pair_grad(R dx, R dy, R dz, R mj, R wx, R wy, R wz, R ci,
                                           const VjpParams &vp, R gd[3], R &gm) {
+#pragma clang fp contract(fast)
     const R s2 = dx * dx + dy * dy + dz * dz + (R)vp.eps2;
     const R inv = vrsq(s2);
     const R s = s2 * inv;
@@ -117,6 +123,7 @@ struct VjpCell {
 template <class R, bool CHG>
 __device__ __forceinline__ void cell_grad(R rx, R ry, R rz, R M, const R q[6], R wx, R wy, R wz,
                                           R ci, const VjpParams &vp, CellGrad<R> &o) {
+#pragma clang fp contract(fast)
     const R s2 = rx * rx + ry * ry + rz * rz + (R)vp.eps2;
     const R inv = vrsq(s2);
     const R s = s2 * inv;
@@ -185,6 +192,37 @@ __device__ __forceinline__ VjpCell<R> stage_cell(const NodeMP &c, const double s
 // ---------------------------------------------------------------------------
 // Pass 1: per particle i (one group per block), the i-side terms.
 // ---------------------------------------------------------------------------
+// Terms are summed in R over runs of at most kFold and each run's sum is added
+// to an FP64 accumulator.
+constexpr int kFold = 32;
+
+// a list particle as staged in LDS: position (shifted) and mass
+template <class R>
+struct alignas(4 * sizeof(R)) VjpPart {
+    R x, y, z, m;
+};
+
+// one tile of particle-list entries against member i (NEAR: the list may hold
+// i itself, which is skipped)
+template <class R, bool NEAR>
+__device__ __forceinline__ void vjp_i_pp_tile(const VjpPart<R> *sp, const int32_t *sj, int tl,
+                                              int slice, int nslice, int32_t i, R xi, R yi, R zi,
+                                              R wx, R wy, R wz, R ci, const VjpParams &vp,
+                                              double &g0, double &g1, double &g2) {
+    for (int k0 = slice; k0 < tl; k0 += kFold * nslice) {
+        const int k1 = min(tl, k0 + kFold * nslice);
+        R p0 = 0, p1 = 0, p2 = 0;
+        for (int k = k0; k < k1; k += nslice) {
+            if (NEAR && sj[k] == i) continue;
+            const VjpPart<R> q = sp[k];
+            R gd[3], gmj;
+            pair_grad<R, NEAR>(q.x - xi, q.y - yi, q.z - zi, q.m, wx, wy, wz, ci, vp, gd, gmj);
+            p0 -= gd[0]; p1 -= gd[1]; p2 -= gd[2];
+        }
+        g0 += (double)p0; g1 += (double)p1; g2 += (double)p2;
+    }
+}
+
 // CELL_K: accepted cells may lie within r_out of a member (h < r_out)
 template <class R, bool CELL_K>
 __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
@@ -193,7 +231,7 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
     const double *__restrict__ z, const double *__restrict__ m, const NodeMP *__restrict__ mp,
     const int32_t *__restrict__ perm, const double *__restrict__ wv, const double *__restrict__ cv,
     VjpParams vp, double *__restrict__ gx, double *__restrict__ gm, int64_t n) {
-    __shared__ R s_p[4][kVjpTile];
+    __shared__ VjpPart<R> s_p[kVjpTile];
     __shared__ int32_t s_j[kVjpTile];
     __shared__ VjpCell<R> s_c[kVjpTile];
     __shared__ double s_red[3][kVjpThreads];
@@ -213,8 +251,7 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
         nc = 1 << lg;
         const int pad = nc, nslice = kVjpThreads >> lg;
         const int li = tid & (pad - 1), slice = tid >> lg;
-        const bool valid = li < nc;
-        const int32_t i = gi.first + chunk + (valid ? li : 0);
+        const int32_t i = gi.first + chunk + li;
         const int64_t o = perm[i];
         const R xi = (R)(x[i] - sh[0]), yi = (R)(y[i] - sh[1]), zi = (R)(z[i] - sh[2]);
         const R wx = (R)wv[3 * o], wy = (R)wv[3 * o + 1], wz = (R)wv[3 * o + 2];
@@ -229,24 +266,17 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
                 __syncthreads();
                 if (tid < tl) {
                     const int32_t j = idxs[t0 + tid];
-                    s_p[0][tid] = (R)(x[j] - sh[0]);
-                    s_p[1][tid] = (R)(y[j] - sh[1]);
-                    s_p[2][tid] = (R)(z[j] - sh[2]);
-                    s_p[3][tid] = (R)m[j];
+                    s_p[tid] = VjpPart<R>{(R)(x[j] - sh[0]), (R)(y[j] - sh[1]), (R)(z[j] - sh[2]),
+                                          (R)m[j]};
                     s_j[tid] = j;
                 }
                 __syncthreads();
-                for (int k = slice; k < tl; k += nslice) {
-                    if (s_j[k] == i) continue;
-                    R gd[3], gmj;
-                    if (list == 0)   // far particles: K = W = 1
-                        pair_grad<R, false>(s_p[0][k] - xi, s_p[1][k] - yi, s_p[2][k] - zi,
-                                            s_p[3][k], wx, wy, wz, ci, vp, gd, gmj);
-                    else
-                        pair_grad<R, true>(s_p[0][k] - xi, s_p[1][k] - yi, s_p[2][k] - zi,
-                                           s_p[3][k], wx, wy, wz, ci, vp, gd, gmj);
-                    g0 -= gd[0]; g1 -= gd[1]; g2 -= gd[2];
-                }
+                if (list == 0)   // far particles: K = W = 1, never a member
+                    vjp_i_pp_tile<R, false>(s_p, s_j, tl, slice, nslice, i, xi, yi, zi, wx, wy,
+                                            wz, ci, vp, g0, g1, g2);
+                else
+                    vjp_i_pp_tile<R, true>(s_p, s_j, tl, slice, nslice, i, xi, yi, zi, wx, wy,
+                                           wz, ci, vp, g0, g1, g2);
             }
         }
         for (int64_t t0 = cb; t0 < ce; t0 += kVjpTile) {
@@ -254,17 +284,23 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
             __syncthreads();
             if (tid < tl) s_c[tid] = stage_cell<R>(mp[c_idx[t0 + tid]], sh);
             __syncthreads();
-            for (int k = slice; k < tl; k += nslice) {
-                const VjpCell<R> c = s_c[k];
-                CellGrad<R> cg;
-                cell_grad<R, CELL_K>(xi - c.x, yi - c.y, zi - c.z, c.M, c.q, wx, wy, wz, ci, vp, cg);
-                g0 += cg.gr[0]; g1 += cg.gr[1]; g2 += cg.gr[2];
+            for (int k0 = slice; k0 < tl; k0 += kFold * nslice) {
+                const int k1 = min(tl, k0 + kFold * nslice);
+                R p0 = 0, p1 = 0, p2 = 0;
+                for (int k = k0; k < k1; k += nslice) {
+                    const VjpCell<R> c = s_c[k];
+                    CellGrad<R> cg;
+                    cell_grad<R, CELL_K>(xi - c.x, yi - c.y, zi - c.z, c.M, c.q, wx, wy, wz, ci,
+                                         vp, cg);
+                    p0 += cg.gr[0]; p1 += cg.gr[1]; p2 += cg.gr[2];
+                }
+                g0 += (double)p0; g1 += (double)p1; g2 += (double)p2;
             }
         }
         __syncthreads();
         s_red[0][tid] = g0; s_red[1][tid] = g1; s_red[2][tid] = g2;
         __syncthreads();
-        if (slice == 0 && valid) {
+        if (slice == 0) {
             double r[3] = {0, 0, 0};
             for (int sidx = 0; sidx < nslice; ++sidx)
                 for (int a = 0; a < 3; ++a) r[a] += s_red[a][sidx * pad + li];
@@ -281,6 +317,32 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
 // members, scattered with one atomic add per component.  Cell adjoints are
 // component-major: component a of cell c at cadj[a * n_nodes + c].
 // ---------------------------------------------------------------------------
+// a group member as staged in LDS: position (shifted), w and c
+template <class R>
+struct alignas(4 * sizeof(R)) VjpMember {
+    R x, y, z, c, wx, wy, wz, pad;
+};
+
+// list particle j against members [0, nc); NEAR: j may be a member, skipped
+template <class R, bool NEAR>
+__device__ __forceinline__ void vjp_scatter_pp(const VjpMember<R> *si, const int32_t *sid, int nc,
+                                               int32_t j, R xj, R yj, R zj, R mj,
+                                               const VjpParams &vp, double acc[4]) {
+    for (int k0 = 0; k0 < nc; k0 += kFold) {
+        const int k1 = min(nc, k0 + kFold);
+        R p0 = 0, p1 = 0, p2 = 0, pm = 0;
+        for (int k = k0; k < k1; ++k) {
+            if (NEAR && sid[k] == j) continue;
+            const VjpMember<R> q = si[k];
+            R gd[3], gmj;
+            pair_grad<R, NEAR>(xj - q.x, yj - q.y, zj - q.z, mj, q.wx, q.wy, q.wz, q.c, vp, gd,
+                               gmj);
+            p0 += gd[0]; p1 += gd[1]; p2 += gd[2]; pm += gmj;
+        }
+        acc[0] += (double)p0; acc[1] += (double)p1; acc[2] += (double)p2; acc[3] += (double)pm;
+    }
+}
+
 template <class R, bool CELL_K>
 __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
     const GroupInfo *__restrict__ grp, ListsDev L, const double *__restrict__ x,
@@ -289,7 +351,7 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
     const int32_t *__restrict__ perm, const double *__restrict__ wv, const double *__restrict__ cv,
     VjpParams vp, double *__restrict__ gx, double *__restrict__ gm, double *__restrict__ cadj,
     int64_t n, int64_t n_nodes) {
-    __shared__ R s_i[7][kVjpThreads];   // x y z w(3) c of the group's members
+    __shared__ VjpMember<R> s_i[kVjpThreads];
     __shared__ int32_t s_id[kVjpThreads];
     const int tid = threadIdx.x;
     const int g = L.order[blockIdx.x];
@@ -309,13 +371,9 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
         if (tid < nc) {
             const int32_t i = gi.first + chunk + tid;
             const int64_t o = perm[i];
-            s_i[0][tid] = (R)(x[i] - sh[0]);
-            s_i[1][tid] = (R)(y[i] - sh[1]);
-            s_i[2][tid] = (R)(z[i] - sh[2]);
-            s_i[3][tid] = (R)wv[3 * o];
-            s_i[4][tid] = (R)wv[3 * o + 1];
-            s_i[5][tid] = (R)wv[3 * o + 2];
-            s_i[6][tid] = vp.has_c ? (R)cv[o] : R(0);
+            s_i[tid] = VjpMember<R>{(R)(x[i] - sh[0]), (R)(y[i] - sh[1]), (R)(z[i] - sh[2]),
+                                    vp.has_c ? (R)cv[o] : R(0), (R)wv[3 * o], (R)wv[3 * o + 1],
+                                    (R)wv[3 * o + 2], R(0)};
             s_id[tid] = i;
         }
         __syncthreads();
@@ -324,34 +382,33 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
             const int32_t j = far ? p_idx[fb + e] : n_idx[nb + (e - nf)];
             const R xj = (R)(x[j] - sh[0]), yj = (R)(y[j] - sh[1]), zj = (R)(z[j] - sh[2]);
             const R mj = (R)m[j];
-            double a0 = 0, a1 = 0, a2 = 0, am = 0;
-            for (int k = 0; k < nc; ++k) {
-                if (s_id[k] == j) continue;
-                R gd[3], gmj;
-                if (far)   // K = W = 1
-                    pair_grad<R, false>(xj - s_i[0][k], yj - s_i[1][k], zj - s_i[2][k], mj,
-                                        s_i[3][k], s_i[4][k], s_i[5][k], s_i[6][k], vp, gd, gmj);
-                else
-                    pair_grad<R, true>(xj - s_i[0][k], yj - s_i[1][k], zj - s_i[2][k], mj,
-                                       s_i[3][k], s_i[4][k], s_i[5][k], s_i[6][k], vp, gd, gmj);
-                a0 += gd[0]; a1 += gd[1]; a2 += gd[2]; am += gmj;
-            }
-            atomicAdd(&gx[j], a0);
-            atomicAdd(&gx[n + j], a1);
-            atomicAdd(&gx[2 * n + j], a2);
-            atomicAdd(&gm[j], am);
+            double acc[4] = {0, 0, 0, 0};
+            if (far)   // K = W = 1, never a member
+                vjp_scatter_pp<R, false>(s_i, s_id, nc, j, xj, yj, zj, mj, vp, acc);
+            else
+                vjp_scatter_pp<R, true>(s_i, s_id, nc, j, xj, yj, zj, mj, vp, acc);
+            atomicAdd(&gx[j], acc[0]);
+            atomicAdd(&gx[n + j], acc[1]);
+            atomicAdd(&gx[2 * n + j], acc[2]);
+            atomicAdd(&gm[j], acc[3]);
         }
         for (int64_t e = cb + tid; e < ce; e += kVjpThreads) {
             const int32_t cid = c_idx[e];
             const VjpCell<R> c = stage_cell<R>(mp[cid], sh);
             double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-            for (int k = 0; k < nc; ++k) {
-                CellGrad<R> cg;
-                cell_grad<R, CELL_K>(s_i[0][k] - c.x, s_i[1][k] - c.y, s_i[2][k] - c.z, c.M, c.q,
-                                     s_i[3][k], s_i[4][k], s_i[5][k], s_i[6][k], vp, cg);
-                acc[0] -= cg.gr[0]; acc[1] -= cg.gr[1]; acc[2] -= cg.gr[2];
-                acc[3] += cg.gM;
-                for (int a = 0; a < 6; ++a) acc[4 + a] += cg.S[a];
+            for (int k0 = 0; k0 < nc; k0 += kFold) {
+                const int k1 = min(nc, k0 + kFold);
+                R p[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+                for (int k = k0; k < k1; ++k) {
+                    const VjpMember<R> q = s_i[k];
+                    CellGrad<R> cg;
+                    cell_grad<R, CELL_K>(q.x - c.x, q.y - c.y, q.z - c.z, c.M, c.q, q.wx, q.wy,
+                                         q.wz, q.c, vp, cg);
+                    p[0] -= cg.gr[0]; p[1] -= cg.gr[1]; p[2] -= cg.gr[2];
+                    p[3] += cg.gM;
+                    for (int a = 0; a < 6; ++a) p[4 + a] += cg.S[a];
+                }
+                for (int a = 0; a < 10; ++a) acc[a] += (double)p[a];
             }
             for (int a = 0; a < 10; ++a)
                 if (acc[a] != 0.0) atomicAdd(&cadj[a * n_nodes + cid], acc[a]);
