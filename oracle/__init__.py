@@ -3,8 +3,10 @@
 Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
 leg may import this package.  The product library never links or calls it; the
 two share no code.  ``p3t_oracle.c`` holds the tree method written out step by
-step (its header lists the conventions); ``direct.py`` holds the plain O(N^2)
-definitions the tree method reduces to.
+step (its header lists the conventions); ``hard_oracle.c`` the hard part (the
+(1 - K) force and jerk over neighbour lists and its block-timestep Hermite
+integration); ``direct.py`` holds the plain O(N^2) definitions the tree method
+reduces to.
 """
 from __future__ import annotations
 
@@ -16,7 +18,7 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "p3t_oracle.c")
+_SRCS = [os.path.join(_HERE, f) for f in ("p3t_oracle.c", "hard_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
@@ -25,9 +27,10 @@ CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or not os.path.exists(_LIB) or \
+            os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc", *CFLAGS, *_SRCS, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -36,6 +39,11 @@ class _Params(C.Structure):
     _fields_ = [("eps", C.c_double), ("r_in", C.c_double), ("r_out", C.c_double),
                 ("theta", C.c_double), ("r_search", C.c_double), ("n_crit", C.c_int32),
                 ("n_leaf", C.c_int32), ("use_quadrupole", C.c_int32), ("precision", C.c_int32)]
+
+
+class _HermiteParams(C.Structure):
+    _fields_ = [("dt_soft", C.c_double), ("dt_max", C.c_double), ("eta", C.c_double),
+                ("eta_s", C.c_double), ("a0", C.c_double)]
 
 
 _lib = None
@@ -75,6 +83,11 @@ def lib():
         L.or_morton.argtypes = [C.c_double, C.c_double, C.c_double, P, C.c_double]
         L.or_morton.restype = C.c_uint64
         L.or_num_threads.restype = C.c_int
+        L.or_hard_force.argtypes = [C.c_int64, P, P, P, P, P, C.c_double, C.c_double,
+                                    C.c_double, P, P, P]
+        L.or_hermite.argtypes = [C.c_int64, P, P, P, P, P, C.c_double, C.c_double, C.c_double,
+                                 C.POINTER(_HermiteParams), P, P]
+        L.or_hermite.restype = C.c_int
         _lib = L
     return _lib
 
@@ -269,3 +282,38 @@ def group_lists(tree: Tree):
         out.append((int(g[k]), L["p_idx"][L["p_off"][k]:L["p_off"][k + 1]],
                     L["c_idx"][L["c_off"][k]:L["c_off"][k + 1]]))
     return out
+
+
+def _csr(off, idx):
+    return (np.ascontiguousarray(off, dtype=np.int64),
+            np.ascontiguousarray(idx, dtype=np.int32))
+
+
+def hard_force(pos, vel, mass, off, idx, eps, r_in, r_out):
+    """(acc [n,3], jerk [n,3], pot [n]) of the hard part over the neighbour CSR."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    vel = np.ascontiguousarray(vel, dtype=np.float64)
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    off, idx = _csr(off, idx)
+    n = len(mass)
+    acc, jerk, pot = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros(n)
+    lib().or_hard_force(n, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(off), _ptr(idx), eps, r_in,
+                        r_out, _ptr(acc), _ptr(jerk), _ptr(pot))
+    return acc, jerk, pot
+
+
+def hermite(pos, vel, mass, off, idx, eps, r_in, r_out, dt_soft, dt_max, eta, eta_s, a0):
+    """Integrate H_hard over dt_soft: returns (pos, vel, steps per particle, block steps)."""
+    pos = np.array(pos, dtype=np.float64, order="C")
+    vel = np.array(vel, dtype=np.float64, order="C")
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    off, idx = _csr(off, idx)
+    n = len(mass)
+    nsteps = np.zeros(n, np.int32)
+    nblk = C.c_int64(0)
+    hp = _HermiteParams(dt_soft, dt_max, eta, eta_s, a0)
+    rc = lib().or_hermite(n, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(off), _ptr(idx), eps, r_in,
+                          r_out, C.byref(hp), _ptr(nsteps), C.byref(nblk))
+    if rc != 0:
+        raise RuntimeError(f"oracle hermite failed ({rc})")
+    return pos, vel, nsteps, int(nblk.value)
