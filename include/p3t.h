@@ -42,6 +42,7 @@ extern "C" {
 #define P3T_ECAPACITY (-3) /* caller buffer too small; required size reported */
 #define P3T_ESTATE (-4)    /* call out of order (e.g. force before build) */
 #define P3T_EHIP (-5)      /* HIP runtime error */
+#define P3T_ELIMIT (-6)    /* a bounded iteration reached its limit */
 
 #define P3T_PREC_FP64 0    /* every interaction in FP64 */
 #define P3T_PREC_MIXED 1   /* FP64 group-relative offsets, FP32 interactions, compensated sums */
@@ -147,6 +148,79 @@ int p3t_long_force_vjp(p3t_ctx *ctx, const double *w, const double *c, double *g
  * [n][3] device arrays.  Errors: EINVAL, EHIP. */
 int p3t_kick_drift(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const double *acc,
                    double dt_kick, double dt_drift);
+
+/* ---- Hard part (Section 2.1: H_hard; Section 2.2: evaluated over the
+ * neighbour lists).  Neighbour lists are CSR in original indices, as
+ * p3t_neighbors writes them: offsets device [n+1] int64, idx device
+ * [offsets[n]] int32; they must be symmetric (j on i's list iff i on j's),
+ * free of self entries and in range, which is checked (EINVAL otherwise). */
+
+/* Hard force, its jerk and the hard potential of every particle from its
+ * list (Section 2.1, F_hard with the cutoff function K; potential of H_hard):
+ *   a_i    = sum_j m_j (1 - K(s)) d / s^3,   d = x_j - x_i, v = v_j - v_i
+ *   jerk_i = sum_j m_j [(1 - K)(v - 3 (d.v) d / s^2) / s^3 - K'(s) ((d.v)/s) d / s^3]
+ *   phi_i  = -sum_j m_j (1 - W(s)) / s
+ * in FP64, summed in list order.  Uses eps, r_in, r_out of *p.
+ *   pos, vel device [n][3]; mass device [n]; acc, jerk device [n][3] out;
+ *   pot device [n] out or NULL.  Isolated particles (empty rows) get zeros.
+ * Synchronises the stream (list check).  Errors: EINVAL, ENOMEM, EHIP. */
+int p3t_hard_force(p3t_ctx *ctx, int64_t n, const double *pos, const double *vel,
+                   const double *mass, const int64_t *offsets, const int32_t *idx,
+                   const p3t_params *p, double *acc, double *jerk, double *pot);
+
+/* Parameters of the Hermite integration of H_hard (Section 2.1).
+ *   dt_soft  the soft step, integrated over (> 0, a whole multiple of dt_max)
+ *   dt_max   the largest Hermite step (0 < dt_max <= dt_soft)
+ *   eta      accuracy parameter of the timestep criterion (> 0)
+ *   eta_s    accuracy parameter of the first-step criterion (> 0; the paper
+ *            uses eta / 10)
+ *   a0       acceleration floor of the criteria, alpha m / r_cut^2 (>= 0)
+ *   max_block_steps  bound on the block steps of one cluster (0: 2^26);
+ *            reaching it ends the call with P3T_ELIMIT */
+typedef struct {
+    double dt_soft, dt_max, eta, eta_s, a0;
+    int64_t max_block_steps;
+} p3t_hermite_params;
+
+typedef struct {
+    int64_t n_hard;          /* particles with a non-empty list */
+    int64_t n_clusters;      /* connected components of the neighbour graph among them */
+    int64_t max_cluster;     /* members of the largest component */
+    int64_t steps;           /* Hermite steps summed over particles */
+    int64_t max_block_steps; /* block steps of the busiest component */
+    double ms;               /* GPU time of the call */
+} p3t_hermite_stats;
+
+/* Advance H_hard over dt_soft (Section 2.1, step 3 of the scheme; Section 2.2,
+ * steps 5-6 of the GPU procedure), in place on pos and vel: particles with an
+ * empty row are isolated and drift, x += dt_soft v; the others are integrated
+ * with the fourth-order Hermite scheme and block timesteps dt_max / 2^k
+ * under the hard force of their list, the list held fixed.  Timestep: first
+ * step eta_s sqrt((|a|^2 + a0^2) / |a'|^2); later
+ * eta sqrt((sqrt(|a|^2 + a0^2) |a''| + |a'|^2) / (|a'| |a'''| + |a''|^2)), with
+ * a'' and a''' from Hermite interpolation; a step doubles only where the
+ * particle's time is a multiple of the doubled step.  Each connected
+ * component of the neighbour graph is integrated by one workgroup.
+ *   nsteps   device [n] int32 out (Hermite steps per particle) or NULL
+ *   stats    host out or NULL
+ * Synchronises the stream.  Errors: EINVAL, ENOMEM, ELIMIT, EHIP. */
+int p3t_hermite_hard(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const double *mass,
+                     const int64_t *offsets, const int32_t *idx, const p3t_params *p,
+                     const p3t_hermite_params *hp, int32_t *nsteps, p3t_hermite_stats *stats);
+
+/* One step of the P3T scheme (Section 2.2's GPU procedure), in place:
+ * v += dt_soft/2 a_soft; neighbour lists of the current build; p3t_hermite_hard
+ * over dt_soft; rebuild at the new positions; a_soft (and the soft potential
+ * if pot is not NULL) at the new positions into acc; v += dt_soft/2 a_soft.
+ * On entry the context must hold a build of these n particles at the current
+ * positions and acc their soft acceleration (p3t_build_tree + p3t_long_force);
+ * on return both hold for the new positions, so steps chain.
+ *   pos, vel device [n][3]; mass device [n]; acc device [n][3] in/out;
+ *   pot device [n] out or NULL; stats: the hard part's, host out or NULL.
+ * Errors: ESTATE, EINVAL, ENOMEM, ELIMIT, EHIP. */
+int p3t_step(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const double *mass, double *acc,
+             double *pot, const p3t_params *p, const p3t_hermite_params *hp,
+             p3t_hermite_stats *stats);
 
 /* Statistics of the last calls.  Errors: EINVAL. */
 int p3t_get_stats(p3t_ctx *ctx, p3t_stats *out);

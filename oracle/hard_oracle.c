@@ -164,6 +164,15 @@ int or_hermite(int64_t n, double *pos, double *vel, const double *mass, const in
         hard[i] = off[i + 1] > off[i];
         nsteps[i] = 0;
     }
+    /* the lists must be symmetric: every listed particle is itself non-isolated */
+    for (int64_t i = 0; i < n && rc == 0; ++i)
+        for (int64_t e = off[i]; e < off[i + 1]; ++e)
+            if (idx[e] < 0 || idx[e] >= n || idx[e] == i || !hard[idx[e]]) rc = -1;
+    if (rc) {
+        free(a); free(jk); free(a2); free(a3); free(xp); free(vp); free(a1); free(j1);
+        free(t); free(dt); free(hard);
+        return rc;
+    }
     /* isolated particles drift through the whole soft step */
     for (int64_t i = 0; i < n; ++i)
         if (!hard[i])

@@ -1,0 +1,594 @@
+// hard.hip -- the hard part of the P3T split (Section 2.1) on the GPU: the
+// (1 - K) force, its jerk and the (1 - W) potential over neighbour lists, and
+// the fourth-order Hermite integration of H_hard with block timesteps over one
+// soft step.
+//
+// Pair term, d = x_j - x_i, v = v_j - v_i, s^2 = |d|^2 + eps^2, y = s / r_out:
+//   a_i   += m_j (1 - K) d / s^3
+//   jerk_i += m_j [ (1 - K) (v - 3 (d.v) d / s^2) / s^3 - K'(s) ((d.v)/s) d / s^3 ]
+//   phi_i -= m_j (1 - W) / s
+// summed over i's list in list order, each quantity by the same IEEE operation
+// sequence as the definition (the library builds with contraction off), so the
+// force and jerk of a given list are reproducible bit for bit.
+//
+// Integration.  Particles with an empty list are isolated and drift.  The
+// others form clusters: connected components of the neighbour graph.  No force
+// crosses a component boundary during the soft step, so every component is
+// integrated by one workgroup on its own, with its own block steps, and no
+// grid-wide synchronisation is needed.  Per block step of a component:
+// t_next = min (t_i + dt_i); every member is predicted to t_next; members with
+// t_i + dt_i = t_next are active; their force and jerk are evaluated from the
+// predicted states, then they are corrected (Hermite interpolation of the
+// second and third derivatives from a and jerk at both ends) and given their
+// next timestep:
+//   first step  dt <= eta_s sqrt((|a|^2 + a0^2) / |a'|^2)
+//   later       dt <= eta sqrt((sqrt(|a|^2 + a0^2) |a''| + |a'|^2) / (|a'| |a'''| + |a''|^2))
+// with dt = dt_max / 2^k; the step doubles when twice the step fits, stays
+// within dt_max and the particle's time is a multiple of it, else it halves
+// until it fits.  A particle's trajectory depends only on its own component,
+// so this equals one global block-step loop over all particles.
+//
+// Components come from a lock-free union-find over the list edges (a root is
+// always linked under a smaller root, so every chain decreases and the final
+// root of a component is its smallest index), members are gathered into
+// contiguous slots, and components are launched largest first.
+#include <math.h>
+
+#include "device_util.h"
+#include "internal.h"
+
+namespace p3t {
+
+constexpr int kHardThreads = 256;
+constexpr int kHermThreads = 128;
+constexpr int kMaxDtLevel = 40;
+constexpr int kUnionTries = 1 << 20;
+
+struct HardConsts {
+    double eps, r_in, r_out;
+    double C, G1;          // W/y below r_in, G(1) of the changeover region
+};
+
+struct HermConsts {
+    double t_end, dt_max, dt_min, eta, eta_s, a0;
+    int64_t max_block_steps;
+};
+
+// readback slots (int64 units) used here
+enum { RB_HBAD = 48, RB_HNHARD = 49, RB_HNCL = 50, RB_HMAXCL = 51, RB_HLIMIT = 52,
+       RB_HSTEPS = 53, RB_HMAXBLK = 54 };
+
+// ---------------------------------------------------------------------------
+// Changeover functions, written as the formulas of Section 2.1 (G with the
+// denominator (gamma - 1)^7).
+// ---------------------------------------------------------------------------
+__host__ __device__ inline double hk_K(double y, double gam) {
+    if (y < gam) return 0.0;
+    if (y >= 1.0) return 1.0;
+    const double x = (y - gam) / (1.0 - gam);
+    const double x2 = x * x;
+    return x2 * x2 * (35.0 + x * (-84.0 + x * (70.0 - 20.0 * x)));
+}
+
+__host__ __device__ inline double hk_dK(double y, double gam) {   // dK/dy
+    if (y < gam || y >= 1.0) return 0.0;
+    const double x = (y - gam) / (1.0 - gam);
+    const double u = x * (1.0 - x);
+    return 140.0 * u * u * u / (1.0 - gam);
+}
+
+__host__ __device__ inline double hk_G(double y, double g) {
+    const double g2 = g * g, g3 = g2 * g, g4 = g3 * g, g5 = g4 * g, g6 = g5 * g, g7 = g6 * g;
+    const double y2 = y * y, y3 = y2 * y, y4 = y3 * y, y5 = y4 * y, y6 = y5 * y, y7 = y6 * y;
+    const double gm1 = g - 1.0;
+    const double gm7 = gm1 * gm1 * gm1 * gm1 * gm1 * gm1 * gm1;
+    const double num = -(10.0 / 3.0) * y7 + 14.0 * (g + 1.0) * y6 - 21.0 * (g2 + 3.0 * g + 1.0) * y5 +
+                       (35.0 * (g3 + 9.0 * g2 + 9.0 * g + 1.0) / 3.0) * y4 -
+                       70.0 * (g3 + 3.0 * g2 + g) * y3 + 210.0 * (g3 + g2) * y2 -
+                       140.0 * g3 * y * log(y) + (g7 - 7.0 * g6 + 21.0 * g5 - 35.0 * g4);
+    return num / gm7;
+}
+
+static double hk_C(double g) {
+    const double g2 = g * g, g3 = g2 * g, g4 = g3 * g, g5 = g4 * g, g6 = g5 * g;
+    const double gm1 = g - 1.0;
+    const double gm7 = gm1 * gm1 * gm1 * gm1 * gm1 * gm1 * gm1;
+    return 7.0 * (g6 - 9.0 * g5 + 45.0 * g4 - 60.0 * g3 * log(g) - 45.0 * g2 + 9.0 * g - 1.0) /
+           (3.0 * gm7);
+}
+
+__device__ inline double hk_W(double y, double gam, const HardConsts &hc) {
+    if (y < gam) return hc.C * y;
+    if (y >= 1.0) return 1.0;
+    return hk_G(y, gam) + (1.0 - hc.G1) * y;
+}
+
+// Hard force, jerk (and potential if POT) on i from its list at positions x and
+// velocities v, indexed through `map` (identity for caller arrays, particle ->
+// slot for the integrator's state).
+template <bool POT, bool MAP>
+__device__ inline void hard_sum(int64_t i, int64_t si, const double *__restrict__ x,
+                                const double *__restrict__ v, const double *__restrict__ mass,
+                                const int64_t *__restrict__ off, const int32_t *__restrict__ idx,
+                                const int32_t *__restrict__ map, const HardConsts &hc,
+                                double a[3], double jk[3], double *phi) {
+    const double gam = hc.r_in / hc.r_out;
+    a[0] = a[1] = a[2] = 0.0;
+    jk[0] = jk[1] = jk[2] = 0.0;
+    double p = 0.0;
+    const double xi = x[3 * si], yi = x[3 * si + 1], zi = x[3 * si + 2];
+    const double ui = v[3 * si], vi = v[3 * si + 1], wi = v[3 * si + 2];
+    for (int64_t e = off[i]; e < off[i + 1]; ++e) {
+        const int32_t j = idx[e];
+        const int64_t sj = MAP ? map[j] : j;
+        const double dx = x[3 * sj] - xi;
+        const double dy = x[3 * sj + 1] - yi;
+        const double dz = x[3 * sj + 2] - zi;
+        const double vx = v[3 * sj] - ui;
+        const double vy = v[3 * sj + 1] - vi;
+        const double vz = v[3 * sj + 2] - wi;
+        const double s2 = dx * dx + dy * dy + dz * dz + hc.eps * hc.eps;
+        const double s = sqrt(s2);
+        const double y = s / hc.r_out;
+        const double K = hk_K(y, gam);
+        const double Ks = hk_dK(y, gam) / hc.r_out;
+        const double mj = mass[j];
+        const double inv_s3 = 1.0 / (s2 * s);
+        const double rv = dx * vx + dy * vy + dz * vz;
+        const double f = mj * (1.0 - K) * inv_s3;
+        const double c = 3.0 * rv / s2;
+        const double g = mj * Ks * rv / s * inv_s3;
+        a[0] += f * dx;
+        a[1] += f * dy;
+        a[2] += f * dz;
+        jk[0] += f * (vx - c * dx) - g * dx;
+        jk[1] += f * (vy - c * dy) - g * dy;
+        jk[2] += f * (vz - c * dz) - g * dz;
+        if (POT) p -= mj * (1.0 - hk_W(y, gam, hc)) / s;
+    }
+    if (POT) *phi = p;
+}
+
+// Rows must be well formed before any kernel walks them: offsets non-decreasing
+// from a non-negative start, entries in [0, n), not the row's own particle, and
+// every listed particle's own row non-empty (symmetric lists).
+__global__ void k_hard_validate(int64_t n, const int64_t *__restrict__ off,
+                                const int32_t *__restrict__ idx, int64_t *bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t b = off[i], e = off[i + 1];
+    if (b < 0 || e < b) { atomicOr((unsigned long long *)bad, 1ull); return; }
+    for (int64_t k = b; k < e; ++k) {
+        const int32_t j = idx[k];
+        if (j < 0 || j >= n || j == i) { atomicOr((unsigned long long *)bad, 1ull); return; }
+        if (off[j + 1] <= off[j]) { atomicOr((unsigned long long *)bad, 1ull); return; }
+    }
+}
+
+__global__ __launch_bounds__(kHardThreads) void k_hard_force(
+    int64_t n, const double *__restrict__ pos, const double *__restrict__ vel,
+    const double *__restrict__ mass, const int64_t *__restrict__ off,
+    const int32_t *__restrict__ idx, HardConsts hc, double *__restrict__ acc,
+    double *__restrict__ jerk, double *__restrict__ pot) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double a[3], jk[3], p = 0.0;
+    if (pot)
+        hard_sum<true, false>(i, i, pos, vel, mass, off, idx, nullptr, hc, a, jk, &p);
+    else
+        hard_sum<false, false>(i, i, pos, vel, mass, off, idx, nullptr, hc, a, jk, &p);
+    for (int k = 0; k < 3; ++k) {
+        acc[3 * i + k] = a[k];
+        jerk[3 * i + k] = jk[k];
+    }
+    if (pot) pot[i] = p;
+}
+
+// ---------------------------------------------------------------------------
+// Components of the neighbour graph.
+// ---------------------------------------------------------------------------
+__device__ inline int32_t ld_par(const int32_t *par, int32_t x) {
+    return __hip_atomic_load(&par[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of x.  Parents only ever decrease, so the chain is finite; path halving
+// by compare-and-swap keeps that invariant.
+__device__ int32_t uf_find(int32_t *par, int32_t x) {
+    for (;;) {
+        int32_t p = ld_par(par, x);
+        if (p == x) return x;
+        const int32_t gp = ld_par(par, p);
+        if (gp != p) atomicCAS(&par[x], p, gp);
+        x = gp;
+    }
+}
+
+__global__ void k_cc_init(int64_t n, int32_t *__restrict__ par, int32_t *__restrict__ ccount,
+                          int32_t *__restrict__ cfill) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    par[i] = (int32_t)i;
+    ccount[i] = 0;
+    cfill[i] = 0;
+}
+
+__global__ void k_cc_union(int64_t n, const int64_t *__restrict__ off,
+                           const int32_t *__restrict__ idx, int32_t *par, int64_t *bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int64_t e = off[i]; e < off[i + 1]; ++e) {
+        const int32_t j = idx[e];
+        if (j <= i) continue;            // each edge once
+        int32_t a = (int32_t)i, b = j;
+        int t = 0;
+        for (; t < kUnionTries; ++t) {
+            a = uf_find(par, a);
+            b = uf_find(par, b);
+            if (a == b) break;
+            if (a < b) { const int32_t s = a; a = b; b = s; }
+            if (atomicCAS(&par[a], a, b) == a) break;   // a was still a root
+        }
+        if (t == kUnionTries) atomicOr((unsigned long long *)bad, 2ull);
+    }
+}
+
+// label = root; count members per root
+__global__ void k_cc_count(int64_t n, const int64_t *__restrict__ off, int32_t *par,
+                           int32_t *__restrict__ label, int32_t *__restrict__ ccount) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (off[i + 1] == off[i]) { label[i] = -1; return; }
+    const int32_t r = uf_find(par, (int32_t)i);
+    label[i] = r;
+    atomicAdd(&ccount[r], 1);
+}
+
+__global__ void k_cc_rootflag(int64_t n, const int32_t *__restrict__ ccount,
+                              int32_t *__restrict__ rflag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    rflag[i] = ccount[i] > 0 ? 1 : 0;
+}
+
+// members into slots cstart[root] + k; isolated particles drift
+__global__ void k_cc_place(int64_t n, const int32_t *__restrict__ label,
+                           const int32_t *__restrict__ cstart, int32_t *__restrict__ cfill,
+                           int32_t *__restrict__ mem, int32_t *__restrict__ slot,
+                           double *__restrict__ pos, const double *__restrict__ vel,
+                           double dt_soft) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t r = label[i];
+    if (r < 0) {
+        slot[i] = -1;
+        for (int k = 0; k < 3; ++k) pos[3 * i + k] += dt_soft * vel[3 * i + k];
+        return;
+    }
+    const int32_t s = cstart[r] + atomicAdd(&cfill[r], 1);
+    mem[s] = (int32_t)i;
+    slot[i] = s;
+}
+
+__device__ inline int size_bucket(int32_t size) { return 31 - __clz(size); }
+
+// cluster ranges and a histogram of floor(log2(size))
+__global__ void k_cc_clusters(int64_t n, const int32_t *__restrict__ ccount,
+                              const int32_t *__restrict__ cstart, const int32_t *__restrict__ cid,
+                              int32_t *__restrict__ cl_beg, int32_t *__restrict__ cl_end,
+                              int32_t *__restrict__ bhist, unsigned long long *maxsize) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int32_t c = ccount[r];
+    if (c == 0) return;
+    const int32_t k = cid[r];
+    cl_beg[k] = cstart[r];
+    cl_end[k] = cstart[r] + c;
+    atomicAdd(&bhist[size_bucket(c)], 1);
+    atomicMax(maxsize, (unsigned long long)c);
+}
+
+// exclusive offsets of the size buckets, largest sizes first (one thread)
+__global__ void k_cc_bucket_scan(int32_t *bhist) {
+    int32_t acc = 0;
+    for (int b = 31; b >= 0; --b) {
+        const int32_t c = bhist[b];
+        bhist[b] = acc;
+        acc += c;
+    }
+}
+
+__global__ void k_cc_order(int64_t n_cl, const int32_t *__restrict__ cl_beg,
+                           const int32_t *__restrict__ cl_end, int32_t *__restrict__ bfill,
+                           const int32_t *__restrict__ boff, int32_t *__restrict__ order) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cl) return;
+    const int b = size_bucket(cl_end[c] - cl_beg[c]);
+    order[boff[b] + atomicAdd(&bfill[b], 1)] = (int32_t)c;
+}
+
+// ---------------------------------------------------------------------------
+// Hermite integration, one workgroup per component.
+// ---------------------------------------------------------------------------
+struct HermState {
+    double *x, *v, *a, *j, *a2, *a3, *xp, *vp, *a1, *j1;   // [slots][3]
+    double *t, *dt;                                        // [slots]
+    int32_t *ns;                                           // [slots]
+};
+
+__device__ inline double norm3(const double *v) {
+    return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+}
+
+__device__ inline double crit_first(const double *a, const double *j, const HermConsts &hp) {
+    const double na = norm3(a), nj = norm3(j);
+    if (nj == 0.0) return hp.dt_max;
+    return hp.eta_s * sqrt((na * na + hp.a0 * hp.a0) / (nj * nj));
+}
+
+// the denominator's first term is |a'| |a'''| (the form with matching units)
+__device__ inline double crit_full(const double *a, const double *j, const double *a2,
+                                   const double *a3, const HermConsts &hp) {
+    const double na = norm3(a), nj = norm3(j), n2 = norm3(a2), n3 = norm3(a3);
+    const double num = sqrt(na * na + hp.a0 * hp.a0) * n2 + nj * nj;
+    const double den = nj * n3 + n2 * n2;
+    if (den == 0.0) return hp.dt_max;
+    return hp.eta * sqrt(num / den);
+}
+
+__device__ inline double block_min(double v, double *s_red) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s_red[w] = v;
+    __syncthreads();
+    double r = s_red[0];
+    for (int k = 1; k < kHermThreads / 64; ++k) r = fmin(r, s_red[k]);
+    return r;
+}
+
+__global__ __launch_bounds__(kHermThreads) void k_hermite_cluster(
+    const int32_t *__restrict__ cl_beg, const int32_t *__restrict__ cl_end,
+    const int32_t *__restrict__ order, const int32_t *__restrict__ mem,
+    const int32_t *__restrict__ slot, const int64_t *__restrict__ off,
+    const int32_t *__restrict__ idx, const double *__restrict__ mass, double *__restrict__ pos,
+    double *__restrict__ vel, HardConsts hc, HermConsts hp, HermState S,
+    int32_t *__restrict__ nsteps_out, unsigned long long *rb) {
+    __shared__ double s_red[kHermThreads / 64];
+    const int c = order[blockIdx.x];
+    const int b = cl_beg[c], e = cl_end[c];
+    const int tid = threadIdx.x;
+    for (int s = b + tid; s < e; s += kHermThreads) {
+        const int32_t i = mem[s];
+        for (int k = 0; k < 3; ++k) {
+            S.x[3 * s + k] = pos[3 * i + k];
+            S.v[3 * s + k] = vel[3 * i + k];
+        }
+        S.t[s] = 0.0;
+        S.ns[s] = 0;
+    }
+    __syncthreads();
+    for (int s = b + tid; s < e; s += kHermThreads) {
+        double dummy;
+        hard_sum<false, true>(mem[s], s, S.x, S.v, mass, off, idx, slot, hc, S.a + 3 * s,
+                              S.j + 3 * s, &dummy);
+        const double cr = crit_first(S.a + 3 * s, S.j + 3 * s, hp);
+        double d = hp.dt_max;
+        while (d > cr && d > hp.dt_min) d *= 0.5;
+        S.dt[s] = d;
+    }
+    int64_t steps = 0;
+    for (;;) {
+        double lmin = INFINITY;
+        for (int s = b + tid; s < e; s += kHermThreads) {
+            const double tn = S.t[s] + S.dt[s];
+            if (tn < lmin) lmin = tn;
+        }
+        const double t_next = block_min(lmin, s_red);
+        if (!(t_next <= hp.t_end)) break;          // every member is at the end
+        if (steps == hp.max_block_steps) {
+            if (tid == 0) atomicOr(rb + (RB_HLIMIT - RB_HBAD), 1ull);
+            break;
+        }
+        ++steps;
+        for (int s = b + tid; s < e; s += kHermThreads) {
+            const double h = t_next - S.t[s];
+            for (int k = 0; k < 3; ++k) {
+                const int q = 3 * s + k;
+                S.xp[q] = S.x[q] + S.v[q] * h + S.a[q] * (h * h / 2.0) +
+                          S.j[q] * (h * h * h / 6.0);
+                S.vp[q] = S.v[q] + S.a[q] * h + S.j[q] * (h * h / 2.0);
+            }
+        }
+        __syncthreads();
+        for (int s = b + tid; s < e; s += kHermThreads) {
+            if (S.t[s] + S.dt[s] != t_next) continue;
+            double dummy;
+            hard_sum<false, true>(mem[s], s, S.xp, S.vp, mass, off, idx, slot, hc, S.a1 + 3 * s,
+                                  S.j1 + 3 * s, &dummy);
+        }
+        __syncthreads();
+        for (int s = b + tid; s < e; s += kHermThreads) {
+            if (S.t[s] + S.dt[s] != t_next) continue;
+            const double h = S.dt[s];
+            for (int k = 0; k < 3; ++k) {
+                const int q = 3 * s + k;
+                const double s2 = (-6.0 * (S.a[q] - S.a1[q]) - h * (4.0 * S.j[q] + 2.0 * S.j1[q])) /
+                                  (h * h);
+                const double s3 = (12.0 * (S.a[q] - S.a1[q]) + 6.0 * h * (S.j[q] + S.j1[q])) /
+                                  (h * h * h);
+                S.x[q] = S.xp[q] + s2 * (h * h * h * h / 24.0) + s3 * (h * h * h * h * h / 120.0);
+                S.v[q] = S.vp[q] + s2 * (h * h * h / 6.0) + s3 * (h * h * h * h / 24.0);
+                S.a[q] = S.a1[q];
+                S.j[q] = S.j1[q];
+                S.a2[q] = s2 + s3 * h;
+                S.a3[q] = s3;
+            }
+            S.t[s] = t_next;
+            S.ns[s] += 1;
+            const double cr = crit_full(S.a + 3 * s, S.j + 3 * s, S.a2 + 3 * s, S.a3 + 3 * s, hp);
+            double d = h;
+            if (2.0 * d <= cr && 2.0 * d <= hp.dt_max && fmod(S.t[s], 2.0 * d) == 0.0)
+                d = 2.0 * d;
+            else
+                while (d > cr && d > hp.dt_min) d *= 0.5;
+            S.dt[s] = d;
+        }
+        __syncthreads();
+    }
+    unsigned long long my_steps = 0;
+    for (int s = b + tid; s < e; s += kHermThreads) {
+        const int32_t i = mem[s];
+        for (int k = 0; k < 3; ++k) {
+            pos[3 * i + k] = S.x[3 * s + k];
+            vel[3 * i + k] = S.v[3 * s + k];
+        }
+        if (nsteps_out) nsteps_out[i] = S.ns[s];
+        my_steps += (unsigned long long)S.ns[s];
+    }
+    for (int o = 32; o > 0; o >>= 1) my_steps += __shfl_xor(my_steps, o);
+    if ((tid & 63) == 0 && my_steps) atomicAdd(rb + (RB_HSTEPS - RB_HBAD), my_steps);
+    if (tid == 0) atomicMax(rb + (RB_HMAXBLK - RB_HBAD), (unsigned long long)steps);
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+static HardConsts hard_consts(const p3t_params *p) {
+    HardConsts hc;
+    hc.eps = p->eps;
+    hc.r_in = p->r_in;
+    hc.r_out = p->r_out;
+    const double gam = p->r_in / p->r_out;
+    hc.C = gam > 0.0 ? hk_C(gam) : 7.0 / 3.0;
+    hc.G1 = hk_G(1.0, gam);
+    return hc;
+}
+
+static int validate_lists(p3t_ctx *ctx, int64_t n, const int64_t *off, const int32_t *idx) {
+    int rc;
+    int64_t *rb = ptr<int64_t>(ctx->readback);
+    if ((rc = check_hip(ctx, hipMemsetAsync(rb + RB_HBAD, 0, sizeof(int64_t), ctx->stream), "memset")))
+        return rc;
+    k_hard_validate<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, off, idx, rb + RB_HBAD);
+    if ((rc = check_hip(ctx, hipGetLastError(), "list check"))) return rc;
+    if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + RB_HBAD, rb + RB_HBAD, sizeof(int64_t),
+                                            hipMemcpyDeviceToHost, ctx->stream), "readback")))
+        return rc;
+    if ((rc = check_hip(ctx, hipStreamSynchronize(ctx->stream), "sync"))) return rc;
+    if (ctx->hpin[RB_HBAD])
+        return set_error(ctx, P3T_EINVAL,
+                         "neighbour lists malformed (bad offsets, index out of range, self entry, "
+                         "or not symmetric)");
+    return P3T_OK;
+}
+
+int launch_hard_force(p3t_ctx *ctx, int64_t n, const double *pos, const double *vel,
+                      const double *mass, const int64_t *off, const int32_t *idx,
+                      const p3t_params *p, double *acc, double *jerk, double *pot) {
+    int rc;
+    if ((rc = ensure(ctx, ctx->readback, 64 * sizeof(int64_t)))) return rc;
+    if ((rc = validate_lists(ctx, n, off, idx))) return rc;
+    const HardConsts hc = hard_consts(p);
+    k_hard_force<<<blocks_for(n, kHardThreads), kHardThreads, 0, ctx->stream>>>(
+        n, pos, vel, mass, off, idx, hc, acc, jerk, pot);
+    return check_hip(ctx, hipGetLastError(), "hard force");
+}
+
+int launch_hermite(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const double *mass,
+                   const int64_t *off, const int32_t *idx, const p3t_params *p,
+                   const p3t_hermite_params *hpar, int32_t *nsteps, p3t_hermite_stats *stats) {
+    int rc;
+    hipStream_t st = ctx->stream;
+    if ((rc = ensure(ctx, ctx->readback, 64 * sizeof(int64_t)))) return rc;
+    if ((rc = check_hip(ctx, hipEventRecord(ctx->ev[10], st), "event"))) return rc;
+    if ((rc = validate_lists(ctx, n, off, idx))) return rc;
+    // workspace: 7 per-particle int32 arrays, then per-slot state
+    if ((rc = ensure(ctx, ctx->hard_ix, 7 * (size_t)(n + 1) * sizeof(int32_t)))) return rc;
+    int32_t *par = ptr<int32_t>(ctx->hard_ix), *label = par + (n + 1), *ccount = label + (n + 1),
+            *cfill = ccount + (n + 1), *cstart = cfill + (n + 1), *cid = cstart + (n + 1),
+            *slotv = cid + (n + 1);
+    int64_t *rb = ptr<int64_t>(ctx->readback);
+    if ((rc = check_hip(ctx, hipMemsetAsync(rb + RB_HBAD, 0, 8 * sizeof(int64_t), st), "memset")))
+        return rc;
+    const unsigned nb = blocks_for(n, 256);
+    k_cc_init<<<nb, 256, 0, st>>>(n, par, ccount, cfill);
+    k_cc_union<<<nb, 256, 0, st>>>(n, off, idx, par, rb + RB_HBAD);
+    k_cc_count<<<nb, 256, 0, st>>>(n, off, par, label, ccount);
+    if ((rc = check_hip(ctx, hipGetLastError(), "components"))) return rc;
+    if ((rc = scan_exclusive_i32(ctx, ccount, cstart, n, reinterpret_cast<int32_t *>(rb + RB_HNHARD))))
+        return rc;
+    k_cc_rootflag<<<nb, 256, 0, st>>>(n, ccount, cid);
+    if ((rc = scan_exclusive_i32(ctx, cid, cid, n, reinterpret_cast<int32_t *>(rb + RB_HNCL))))
+        return rc;
+    if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + RB_HBAD, rb + RB_HBAD, 3 * sizeof(int64_t),
+                                            hipMemcpyDeviceToHost, st), "readback")))
+        return rc;
+    if ((rc = check_hip(ctx, hipStreamSynchronize(st), "sync"))) return rc;
+    if (ctx->hpin[RB_HBAD]) return set_error(ctx, P3T_ELIMIT, "component search did not settle");
+    const int64_t n_hard = *reinterpret_cast<const int32_t *>(ctx->hpin + RB_HNHARD);
+    const int64_t n_cl = *reinterpret_cast<const int32_t *>(ctx->hpin + RB_HNCL);
+    // per-slot state: ten [m][3] and two [m] FP64 arrays; then int32 arrays:
+    // steps [m], members [m], cluster begin/end/order [c], size buckets [64]
+    const int64_t m = n_hard > 0 ? n_hard : 1, c = n_cl > 0 ? n_cl : 1;
+    const size_t dbl = (size_t)m * 32;
+    const size_t i32 = 2 * (size_t)m + 3 * (size_t)c + 64;
+    if ((rc = ensure(ctx, ctx->hard_state, dbl * sizeof(double) + i32 * sizeof(int32_t)))) return rc;
+    double *base = ptr<double>(ctx->hard_state);
+    HermState S;
+    double **arr[10] = {&S.x, &S.v, &S.a, &S.j, &S.a2, &S.a3, &S.xp, &S.vp, &S.a1, &S.j1};
+    for (int k = 0; k < 10; ++k) *arr[k] = base + (size_t)k * 3 * m;
+    S.t = base + 30 * (size_t)m;
+    S.dt = S.t + m;
+    S.ns = reinterpret_cast<int32_t *>(base + dbl);
+    int32_t *mem = S.ns + m, *cl_beg = mem + m, *cl_end = cl_beg + c, *order = cl_end + c;
+    int32_t *bhist = order + c, *bfill = bhist + 32;
+    if ((rc = check_hip(ctx, hipMemsetAsync(bhist, 0, 64 * sizeof(int32_t), st), "memset")))
+        return rc;
+    k_cc_place<<<nb, 256, 0, st>>>(n, label, cstart, cfill, mem, slotv, pos, vel, hpar->dt_soft);
+    k_cc_clusters<<<nb, 256, 0, st>>>(n, ccount, cstart, cid, cl_beg, cl_end, bhist,
+                                      reinterpret_cast<unsigned long long *>(rb + RB_HMAXCL));
+    k_cc_bucket_scan<<<1, 1, 0, st>>>(bhist);
+    if (n_cl > 0) {
+        k_cc_order<<<blocks_for(n_cl, 256), 256, 0, st>>>(n_cl, cl_beg, cl_end, bfill, bhist, order);
+        if (nsteps) {
+            // isolated particles take no Hermite step
+            if ((rc = check_hip(ctx, hipMemsetAsync(nsteps, 0, n * sizeof(int32_t), st), "memset")))
+                return rc;
+        }
+        HermConsts hc2;
+        hc2.t_end = hpar->dt_soft;
+        hc2.dt_max = hpar->dt_max;
+        hc2.dt_min = ldexp(hpar->dt_max, -kMaxDtLevel);
+        hc2.eta = hpar->eta;
+        hc2.eta_s = hpar->eta_s;
+        hc2.a0 = hpar->a0;
+        hc2.max_block_steps = hpar->max_block_steps > 0 ? hpar->max_block_steps : (1LL << 26);
+        k_hermite_cluster<<<(unsigned)n_cl, kHermThreads, 0, st>>>(
+            cl_beg, cl_end, order, mem, slotv, off, idx, mass, pos, vel, hard_consts(p), hc2, S,
+            nsteps, reinterpret_cast<unsigned long long *>(rb + RB_HBAD));
+    } else if (nsteps) {
+        if ((rc = check_hip(ctx, hipMemsetAsync(nsteps, 0, n * sizeof(int32_t), st), "memset")))
+            return rc;
+    }
+    if ((rc = check_hip(ctx, hipGetLastError(), "hermite"))) return rc;
+    if ((rc = check_hip(ctx, hipEventRecord(ctx->ev[11], st), "event"))) return rc;
+    if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + RB_HMAXCL, rb + RB_HMAXCL, 4 * sizeof(int64_t),
+                                            hipMemcpyDeviceToHost, st), "readback")))
+        return rc;
+    if ((rc = check_hip(ctx, hipStreamSynchronize(st), "sync"))) return rc;
+    if (stats) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ctx->ev[10], ctx->ev[11]);
+        stats->n_hard = n_hard;
+        stats->n_clusters = n_cl;
+        stats->max_cluster = ctx->hpin[RB_HMAXCL];
+        stats->steps = ctx->hpin[RB_HSTEPS];
+        stats->max_block_steps = ctx->hpin[RB_HMAXBLK];
+        stats->ms = ms;
+    }
+    if (ctx->hpin[RB_HLIMIT])
+        return set_error(ctx, P3T_ELIMIT, "a component reached the block-step limit");
+    return P3T_OK;
+}
+
+}  // namespace p3t

@@ -96,7 +96,7 @@ struct p3t_ctx {
     int32_t hint_n_crit = -1;
     int32_t nbr_cap = 0;   // neighbour row slot size for the next p3t_neighbors (0: default)
     double ms_build = 0, ms_walk = 0, ms_force = 0, ms_nbr = 0, ms_vjp = 0;
-    hipEvent_t ev[10] = {nullptr};  // start/end pairs: build, force, neighbours, vjp, walk
+    hipEvent_t ev[12] = {nullptr};  // start/end pairs: build, force, neighbours, vjp, walk, hermite
     int64_t *hpin = nullptr;      // pinned host readback area (64 int64)
 
     p3t::DevBuf root, keys[2], vals[2], hist, histc, x, y, z, m;
@@ -108,6 +108,8 @@ struct p3t_ctx {
     p3t::DevBuf wstack, dflags, readback, scan_tmp, nbr_cnt, nbr_slots;
     p3t::DevBuf vjp_gx, vjp_gm, vjp_cell, bbox;
     p3t::DevBuf seg_end, gorder, grank, ghist;
+    p3t::DevBuf hard_ix, hard_state;   // hard part: components and integrator state
+    p3t::DevBuf step_off, step_idx;    // neighbour CSR of p3t_step
 };
 
 namespace p3t {
@@ -142,6 +144,15 @@ int launch_neighbors(p3t_ctx *ctx, int64_t *offsets, int32_t *idx, int64_t cap, 
 
 // VJP (vjp.hip).
 int launch_vjp(p3t_ctx *ctx, const double *w, const double *c, double *gpos, double *gmass);
+
+// Hard part (hard.hip): force and jerk over neighbour lists; Hermite block-step
+// integration over one soft step.
+int launch_hard_force(p3t_ctx *ctx, int64_t n, const double *pos, const double *vel,
+                      const double *mass, const int64_t *off, const int32_t *idx,
+                      const p3t_params *p, double *acc, double *jerk, double *pot);
+int launch_hermite(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const double *mass,
+                   const int64_t *off, const int32_t *idx, const p3t_params *p,
+                   const p3t_hermite_params *hp, int32_t *nsteps, p3t_hermite_stats *stats);
 
 // Elementwise leapfrog helper (force.hip).
 int launch_kick_drift(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const double *acc,

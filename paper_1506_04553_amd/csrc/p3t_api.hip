@@ -91,10 +91,11 @@ static Changeover make_changeover(double r_in, double r_out) {
 }  // namespace p3t
 
 static const char *kStatus[] = {"ok", "invalid argument", "out of device memory",
-                                "capacity exceeded", "call out of order", "HIP error"};
+                                "capacity exceeded", "call out of order", "HIP error",
+                                "iteration limit reached"};
 
 extern "C" const char *p3t_status_string(int s) {
-    if (s <= 0 && s >= -5) return kStatus[-s];
+    if (s <= 0 && s >= -6) return kStatus[-s];
     return "unknown status";
 }
 
@@ -134,7 +135,7 @@ extern "C" int p3t_create(p3t_ctx **out, int device, void *hip_stream, p3t_alloc
     // P3T_WALK_LDS_STACK=k (k >= 64) caps the walk's on-chip stack at k entries
     if (const char *ev = getenv("P3T_WALK_LDS_STACK")) ctx->walk_lds_cap = atoi(ev);
     hipError_t e = hipHostMalloc((void **)&ctx->hpin, 64 * sizeof(int64_t), hipHostMallocDefault);
-    for (int k = 0; k < 10 && e == hipSuccess; ++k) e = hipEventCreate(&ctx->ev[k]);
+    for (int k = 0; k < 12 && e == hipSuccess; ++k) e = hipEventCreate(&ctx->ev[k]);
     if (e != hipSuccess) {
         p3t_destroy(ctx);
         return P3T_EHIP;
@@ -156,10 +157,11 @@ extern "C" void p3t_destroy(p3t_ctx *ctx) {
                       &ctx->gscan, &ctx->grp, &ctx->cnt, &ctx->off, &ctx->c_idx, &ctx->p_idx,
                       &ctx->n_idx, &ctx->wstack, &ctx->dflags, &ctx->readback, &ctx->scan_tmp,
                       &ctx->nbr_cnt, &ctx->nbr_slots, &ctx->vjp_gx, &ctx->vjp_gm, &ctx->vjp_cell, &ctx->bbox,
-                      &ctx->seg_end, &ctx->gorder, &ctx->grank, &ctx->ghist};
+                      &ctx->seg_end, &ctx->gorder, &ctx->grank, &ctx->ghist, &ctx->hard_ix,
+                      &ctx->hard_state, &ctx->step_off, &ctx->step_idx};
     for (DevBuf *b : bufs) release(ctx, *b);
     if (ctx->hpin) (void)hipHostFree(ctx->hpin);
-    for (int k = 0; k < 10; ++k)
+    for (int k = 0; k < 12; ++k)
         if (ctx->ev[k]) (void)hipEventDestroy(ctx->ev[k]);
     delete ctx;
 }
@@ -258,6 +260,76 @@ extern "C" int p3t_kick_drift(p3t_ctx *ctx, int64_t n, double *pos, double *vel,
     int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
     if (rc) return rc;
     return launch_kick_drift(ctx, n, pos, vel, acc, dt_kick, dt_drift);
+}
+
+static bool hermite_params_ok(const p3t_hermite_params *hp) {
+    if (!hp) return false;
+    const double v[5] = {hp->dt_soft, hp->dt_max, hp->eta, hp->eta_s, hp->a0};
+    for (double d : v)
+        if (!isfinite(d)) return false;
+    if (!(hp->dt_soft > 0.0) || !(hp->dt_max > 0.0) || hp->dt_max > hp->dt_soft) return false;
+    if (fmod(hp->dt_soft, hp->dt_max) != 0.0) return false;
+    return hp->eta > 0.0 && hp->eta_s > 0.0 && hp->a0 >= 0.0 && hp->max_block_steps >= 0;
+}
+
+extern "C" int p3t_hard_force(p3t_ctx *ctx, int64_t n, const double *pos, const double *vel,
+                              const double *mass, const int64_t *offsets, const int32_t *idx,
+                              const p3t_params *p, double *acc, double *jerk, double *pot) {
+    if (!ctx) return P3T_EINVAL;
+    if (n < 1 || n > INT32_MAX || !pos || !vel || !mass || !offsets || !acc || !jerk ||
+        p3t_check_params(p) != P3T_OK)
+        return set_error(ctx, P3T_EINVAL, "bad hard-force arguments");
+    int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
+    if (rc) return rc;
+    return launch_hard_force(ctx, n, pos, vel, mass, offsets, idx, p, acc, jerk, pot);
+}
+
+extern "C" int p3t_hermite_hard(p3t_ctx *ctx, int64_t n, double *pos, double *vel,
+                                const double *mass, const int64_t *offsets, const int32_t *idx,
+                                const p3t_params *p, const p3t_hermite_params *hp,
+                                int32_t *nsteps, p3t_hermite_stats *stats) {
+    if (!ctx) return P3T_EINVAL;
+    if (n < 1 || n > INT32_MAX || !pos || !vel || !mass || !offsets ||
+        p3t_check_params(p) != P3T_OK || !hermite_params_ok(hp))
+        return set_error(ctx, P3T_EINVAL, "bad Hermite arguments");
+    int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
+    if (rc) return rc;
+    return launch_hermite(ctx, n, pos, vel, mass, offsets, idx, p, hp, nsteps, stats);
+}
+
+extern "C" int p3t_step(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const double *mass,
+                        double *acc, double *pot, const p3t_params *p,
+                        const p3t_hermite_params *hp, p3t_hermite_stats *stats) {
+    if (!ctx) return P3T_EINVAL;
+    if (!ctx->built || ctx->n != n)
+        return set_error(ctx, P3T_ESTATE, "p3t_step needs a build of these n particles");
+    if (!pos || !vel || !mass || !acc || p3t_check_params(p) != P3T_OK || !hermite_params_ok(hp))
+        return set_error(ctx, P3T_EINVAL, "bad step arguments");
+    int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
+    if (rc) return rc;
+    const double half = 0.5 * hp->dt_soft;
+    if ((rc = launch_kick_drift(ctx, n, pos, vel, acc, half, 0.0))) return rc;
+    // neighbour lists of the current build; grow the index buffer if needed
+    if ((rc = ensure(ctx, ctx->step_off, (size_t)(n + 1) * sizeof(int64_t)))) return rc;
+    int64_t cap = (int64_t)(ctx->step_idx.bytes / sizeof(int32_t)), nnz = 0;
+    if (cap < 1) {
+        if ((rc = ensure(ctx, ctx->step_idx, (size_t)n * sizeof(int32_t)))) return rc;
+        cap = n;
+    }
+    rc = launch_neighbors(ctx, ptr<int64_t>(ctx->step_off), ptr<int32_t>(ctx->step_idx), cap, &nnz);
+    if (rc == P3T_ECAPACITY) {
+        if ((rc = ensure(ctx, ctx->step_idx, (size_t)nnz * sizeof(int32_t)))) return rc;
+        rc = launch_neighbors(ctx, ptr<int64_t>(ctx->step_off), ptr<int32_t>(ctx->step_idx), nnz,
+                              &nnz);
+    }
+    if (rc) return rc;
+    ctx->nnz = nnz;
+    if ((rc = launch_hermite(ctx, n, pos, vel, mass, ptr<int64_t>(ctx->step_off),
+                             ptr<int32_t>(ctx->step_idx), p, hp, nullptr, stats)))
+        return rc;
+    if ((rc = p3t_build_tree(ctx, n, pos, mass, p))) return rc;
+    if ((rc = p3t_long_force(ctx, acc, pot))) return rc;
+    return launch_kick_drift(ctx, n, pos, vel, acc, half, 0.0);
 }
 
 extern "C" int p3t_get_stats(p3t_ctx *ctx, p3t_stats *out) {

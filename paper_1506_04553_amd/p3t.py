@@ -18,7 +18,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libp3t.so")
 
-P3T_OK, P3T_EINVAL, P3T_ENOMEM, P3T_ECAPACITY, P3T_ESTATE, P3T_EHIP = 0, -1, -2, -3, -4, -5
+P3T_OK, P3T_EINVAL, P3T_ENOMEM, P3T_ECAPACITY, P3T_ESTATE, P3T_EHIP, P3T_ELIMIT = \
+    0, -1, -2, -3, -4, -5, -6
 PREC_FP64, PREC_MIXED = 0, 1
 
 ARRAYS = {  # id, dtype, per-row shape, size key
@@ -77,7 +78,18 @@ _lib = None
 
 EXPORTS = ("p3t_create", "p3t_destroy", "p3t_check_params", "p3t_build_tree", "p3t_long_force",
            "p3t_neighbors", "p3t_long_force_vjp", "p3t_kick_drift", "p3t_get_stats",
-           "p3t_copy_array", "p3t_status_string", "p3t_last_error")
+           "p3t_copy_array", "p3t_status_string", "p3t_last_error", "p3t_hard_force",
+           "p3t_hermite_hard", "p3t_step")
+
+
+class HermiteParams(C.Structure):
+    _fields_ = [("dt_soft", C.c_double), ("dt_max", C.c_double), ("eta", C.c_double),
+                ("eta_s", C.c_double), ("a0", C.c_double), ("max_block_steps", C.c_int64)]
+
+
+class HermiteStats(C.Structure):
+    _fields_ = [("n_hard", C.c_int64), ("n_clusters", C.c_int64), ("max_cluster", C.c_int64),
+                ("steps", C.c_int64), ("max_block_steps", C.c_int64), ("ms", C.c_double)]
 
 
 def load_library(path: str = LIB_PATH):
@@ -99,6 +111,11 @@ def load_library(path: str = LIB_PATH):
     L.p3t_long_force_vjp.argtypes = [V, V, V, V, V]
     L.p3t_kick_drift.argtypes = [V, C.c_int64, V, V, V, C.c_double, C.c_double]
     L.p3t_get_stats.argtypes = [V, C.POINTER(Stats)]
+    L.p3t_hard_force.argtypes = [V, C.c_int64, V, V, V, V, V, C.POINTER(Params), V, V, V]
+    L.p3t_hermite_hard.argtypes = [V, C.c_int64, V, V, V, V, V, C.POINTER(Params),
+                                   C.POINTER(HermiteParams), V, C.POINTER(HermiteStats)]
+    L.p3t_step.argtypes = [V, C.c_int64, V, V, V, V, V, C.POINTER(Params),
+                           C.POINTER(HermiteParams), C.POINTER(HermiteStats)]
     L.p3t_copy_array.argtypes = [V, C.c_int, V, C.c_int64]
     L.p3t_status_string.argtypes = [C.c_int]
     L.p3t_status_string.restype = C.c_char_p
@@ -181,9 +198,9 @@ class P3T:
             msg = self._L.p3t_last_error(self._h).decode(errors="replace")
             raise P3TError(rc, msg)
 
-    def _tensor(self, t, shape, name):
-        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
-            raise TypeError(f"{name} must be a float64 tensor on the GPU")
+    def _tensor(self, t, shape, name, dtype=torch.float64):
+        if not isinstance(t, torch.Tensor) or t.dtype != dtype or not t.is_cuda:
+            raise TypeError(f"{name} must be a {dtype} tensor on the GPU")
         if t.device.index != self.device:
             raise ValueError(f"{name} is on device {t.device}, context on cuda:{self.device}")
         if tuple(t.shape) != tuple(shape):
@@ -248,6 +265,69 @@ class P3T:
             self._tensor(t, (n, 3), nm)
         self._check(self._L.p3t_kick_drift(self._h, n, _dptr(pos), _dptr(vel), _dptr(acc),
                                            float(dt_kick), float(dt_drift)))
+
+    # -- hard part ----------------------------------------------------------
+    def _csr(self, n, offsets, idx):
+        self._tensor(offsets, (n + 1,), "offsets", torch.int64)
+        if idx.dtype != torch.int32 or not idx.is_cuda or not idx.is_contiguous():
+            raise ValueError("idx must be a contiguous int32 device tensor")
+
+    def hard_force(self, pos, vel, mass, offsets, idx, want_pot: bool = True, **params):
+        """(acc, jerk, pot) of the hard part over the neighbour CSR (FP64)."""
+        n = int(pos.shape[0])
+        for t, nm in ((pos, "pos"), (vel, "vel")):
+            self._tensor(t, (n, 3), nm)
+        self._tensor(mass, (n,), "mass")
+        self._csr(n, offsets, idx)
+        p = make_params(**params)
+        dev = torch.device("cuda", self.device)
+        acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        jerk = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        pot = torch.empty((n,), dtype=torch.float64, device=dev) if want_pot else None
+        self._check(self._L.p3t_hard_force(self._h, n, _dptr(pos), _dptr(vel), _dptr(mass),
+                                           _dptr(offsets), _dptr(idx), C.byref(p), _dptr(acc),
+                                           _dptr(jerk), _dptr(pot)))
+        return acc, jerk, pot
+
+    @staticmethod
+    def hermite_params(dt_soft, dt_max, eta, eta_s=None, a0=0.0, max_block_steps=0):
+        return HermiteParams(float(dt_soft), float(dt_max), float(eta),
+                             float(eta / 10.0 if eta_s is None else eta_s), float(a0),
+                             int(max_block_steps))
+
+    def hermite_hard(self, pos, vel, mass, offsets, idx, hermite: dict, **params):
+        """Advance H_hard over hermite['dt_soft'] in place; returns (steps per particle, stats)."""
+        n = int(pos.shape[0])
+        for t, nm in ((pos, "pos"), (vel, "vel")):
+            self._tensor(t, (n, 3), nm)
+        self._tensor(mass, (n,), "mass")
+        self._csr(n, offsets, idx)
+        p = make_params(**params)
+        hp = self.hermite_params(**hermite)
+        nsteps = torch.empty((n,), dtype=torch.int32, device=torch.device("cuda", self.device))
+        st = HermiteStats()
+        self._check(self._L.p3t_hermite_hard(self._h, n, _dptr(pos), _dptr(vel), _dptr(mass),
+                                             _dptr(offsets), _dptr(idx), C.byref(p), C.byref(hp),
+                                             _dptr(nsteps), C.byref(st)))
+        return nsteps, {k: getattr(st, k) for k, _ in HermiteStats._fields_}
+
+    def step(self, pos, vel, mass, acc, hermite: dict, pot=None, **params):
+        """One P3T step in place (the context must hold a build at pos and acc its
+        soft acceleration); returns the hard part's statistics."""
+        n = int(pos.shape[0])
+        for t, nm in ((pos, "pos"), (vel, "vel"), (acc, "acc")):
+            self._tensor(t, (n, 3), nm)
+        self._tensor(mass, (n,), "mass")
+        if pot is not None:
+            self._tensor(pot, (n,), "pot")
+        p = make_params(**params)
+        hp = self.hermite_params(**hermite)
+        st = HermiteStats()
+        self._check(self._L.p3t_step(self._h, n, _dptr(pos), _dptr(vel), _dptr(mass), _dptr(acc),
+                                     _dptr(pot), C.byref(p), C.byref(hp), C.byref(st)))
+        self.build_id += 1
+        self.params = p
+        return {k: getattr(st, k) for k, _ in HermiteStats._fields_}
 
     # -- inspection ---------------------------------------------------------
     def stats(self) -> dict:

@@ -1,0 +1,235 @@
+"""GPU hard part (Section 2.1 H_hard, Section 2.2 GPU procedure) against the
+oracle: the (1 - K) force and jerk over neighbour lists, the block-timestep
+Hermite integration of one soft step, and the whole P3T step.
+
+The force and jerk of a list are the same IEEE operation sequence on both
+sides (no contraction, correctly rounded division and square root), so they
+must agree bit for bit, and so must the Hermite trajectories and step counts
+built from them.  The potential uses the device logarithm in the changeover
+region and is compared to 1e-14 relative.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from inputs import plummer
+from oracle import direct
+from tests.gpu_cases import log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1506_04553_amd import P3T
+    assert torch.cuda.is_available()
+    c = P3T(0)
+    yield c
+    c.close()
+
+
+def _dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _clumpy(n, seed, scale, vscale):
+    """A Plummer sphere shrunk by `scale` (velocities by `vscale`), so that its
+    neighbour pairs sample the changeover region of K (and, for the densest
+    case, the region inside r_in)."""
+    c = plummer(n, seed)
+    return c.pos * scale, c.vel * vscale, c.mass
+
+
+CASES = [(2048, 61, 0.004, 0.1, 3.0), (5000, 62, 0.01, 0.2, 2.0), (3000, 63, 0.02, 0.1, 3.0)]
+
+
+def _params(r_out, eps=1e-4):
+    return dict(eps=eps, r_in=0.1 * r_out, r_out=r_out, theta=0.5, r_search=1.1 * r_out,
+                n_crit=64, n_leaf=16)
+
+
+def _run_hard(ctx, pos, vel, mass, off, idx, p):
+    import torch
+    a, j, ph = ctx.hard_force(_dev(pos), _dev(vel), _dev(mass), _dev(off, torch.int64),
+                              _dev(idx, torch.int32), **p)
+    return a.cpu().numpy(), j.cpu().numpy(), ph.cpu().numpy()
+
+
+@pytest.mark.parametrize("n,seed,r_out,sc,vs", CASES)
+def test_hard_force_bit_exact(ctx, n, seed, r_out, sc, vs):
+    pos, vel, mass = _clumpy(n, seed, sc, vs)
+    p = _params(r_out)
+    off, idx = direct.brute_neighbors(pos, p["r_search"])
+    log(f"hard force n={n} pairs={len(idx)} isolated={(np.diff(off) == 0).sum()}")
+    assert len(idx) > 300
+    a, j, ph = _run_hard(ctx, pos, vel, mass, off, idx, p)
+    oa, oj, oph = oracle.hard_force(pos, vel, mass, off, idx, p["eps"], p["r_in"], p["r_out"])
+    assert np.array_equal(a, oa) and np.array_equal(j, oj)
+    assert np.max(np.abs(ph - oph)) <= 1e-14 * np.max(np.abs(oph))
+    assert not a[np.diff(off) == 0].any()
+
+
+def _hermite_kw(r_out, mass, dt_soft=2.0 ** -7, eta=0.1):
+    # the block-step bound is far above what these cases need (< 10^4)
+    return dict(dt_soft=dt_soft, dt_max=dt_soft / 4, eta=eta, eta_s=eta / 10,
+                a0=0.1 * float(np.mean(mass)) / r_out ** 2, max_block_steps=200000)
+
+
+def _okw(hk):
+    return {k: hk[k] for k in ("dt_soft", "dt_max", "eta", "eta_s", "a0")}
+
+
+def _run_hermite(ctx, pos, vel, mass, off, idx, p, hk):
+    import torch
+    x, v = _dev(pos), _dev(vel)
+    ns, st = ctx.hermite_hard(x, v, _dev(mass), _dev(off, torch.int64), _dev(idx, torch.int32),
+                              hk, **p)
+    return x.cpu().numpy(), v.cpu().numpy(), ns.cpu().numpy(), st
+
+
+@pytest.mark.parametrize("n,seed,r_out,sc,vs", CASES)
+def test_hermite_matches_oracle(ctx, n, seed, r_out, sc, vs):
+    pos, vel, mass = _clumpy(n, seed, sc, vs)
+    p = _params(r_out)
+    off, idx = direct.brute_neighbors(pos, p["r_search"])
+    hk = _hermite_kw(r_out, mass)
+    x, v, ns, st = _run_hermite(ctx, pos, vel, mass, off, idx, p, hk)
+    ox, ov, ons, _ = oracle.hermite(pos, vel, mass, off, idx, p["eps"], p["r_in"], p["r_out"],
+                                    **_okw(hk))
+    log(f"hermite n={n}: {st}")
+    assert np.array_equal(ns, ons)
+    assert np.array_equal(x, ox) and np.array_equal(v, ov)
+    assert st["n_hard"] == int((np.diff(off) > 0).sum())
+    assert st["steps"] == int(ons.sum())
+
+
+def test_hermite_edge_cases(ctx):
+    import torch
+    from paper_1506_04553_amd.p3t import P3TError
+    rng = np.random.default_rng(70)
+    pos = rng.uniform(-1, 1, (64, 3))
+    vel = rng.normal(size=(64, 3))
+    mass = np.full(64, 1.0 / 64)
+    p = _params(0.01)
+    hk = _hermite_kw(0.01, mass)
+    # every particle isolated: pure drift, no steps
+    off = np.zeros(65, np.int64)
+    idx = np.zeros(1, np.int32)
+    x, v, ns, st = _run_hermite(ctx, pos, vel, mass, off, idx, p, hk)
+    assert np.array_equal(x, pos + hk["dt_soft"] * vel) and np.array_equal(v, vel)
+    assert not ns.any() and st["n_hard"] == 0 and st["n_clusters"] == 0
+    # one pair
+    pos2 = pos.copy()
+    pos2[1] = pos2[0] + np.array([0.003, 0.0, 0.0])
+    off2 = np.zeros(65, np.int64)
+    off2[1:] = 2
+    off2[1] = 1
+    idx2 = np.array([1, 0], np.int32)
+    x, v, ns, st = _run_hermite(ctx, pos2, vel, mass, off2, idx2, p, hk)
+    ox, ov, ons, _ = oracle.hermite(pos2, vel, mass, off2, idx2, p["eps"], p["r_in"], p["r_out"],
+                                    **_okw(hk))
+    assert np.array_equal(x, ox) and np.array_equal(ns, ons) and st["n_clusters"] == 1
+    # malformed lists are rejected before any integration
+    for bad in (np.array([0, 1], np.int32), np.array([1, 64], np.int32)):
+        with pytest.raises(P3TError) as e:
+            _run_hermite(ctx, pos2, vel, mass, off2, bad, p, hk)
+        assert e.value.status == -1
+    asym = np.zeros(65, np.int64)
+    asym[1:] = 1                           # 0 lists 1, 1 lists nothing
+    with pytest.raises(P3TError) as e:
+        _run_hermite(ctx, pos2, vel, mass, asym, np.array([1], np.int32), p, hk)
+    assert e.value.status == -1
+    # a block-step limit set from the host ends the call with ELIMIT
+    with pytest.raises(P3TError) as e:
+        _run_hermite(ctx, pos2, vel, mass, off2, idx2, p, dict(hk, max_block_steps=2))
+    assert e.value.status == -6
+    # dt_soft must be a whole multiple of dt_max
+    with pytest.raises(P3TError) as e:
+        _run_hermite(ctx, pos2, vel, mass, off2, idx2, p, dict(hk, dt_max=hk["dt_soft"] / 3))
+    assert e.value.status == -1
+
+
+def test_hermite_king_1m_sampled_clusters(ctx):
+    """The King W0=9, N=2^20 workload's own neighbour lists (h = 1.1 r_out):
+    the whole GPU integration, checked bit for bit on the particles of sampled
+    clusters (the largest ones and random ones) integrated alone by the oracle
+    -- clusters evolve independently (pinned on the oracle)."""
+    import torch
+    from inputs import WORKLOADS, make_cluster
+    w_ = WORKLOADS["king9_1m"]
+    c = make_cluster(w_, seed=1)
+    p = w_.params(precision="fp64")
+    pos, vel, mass = _dev(c.pos), _dev(c.vel), _dev(c.mass)
+    ctx.build_tree(pos, mass, **p)
+    off, idx = ctx.neighbors()
+    hk = _hermite_kw(p["r_out"], c.mass, dt_soft=w_.extra["dt"])
+    x, v = pos.clone(), vel.clone()
+    ns, st = ctx.hermite_hard(x, v, mass, off, idx, hk, **p)
+    log(f"king9_1m hermite: {st}")
+    off, idx = off.cpu().numpy(), idx.cpu().numpy()
+    x, v, ns = x.cpu().numpy(), v.cpu().numpy(), ns.cpu().numpy()
+    hard = np.diff(off) > 0
+    iso = ~hard
+    assert np.array_equal(x[iso], c.pos[iso] + hk["dt_soft"] * c.vel[iso])
+    # components on the host
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    g = sp.csr_matrix((np.ones(len(idx)), idx, off), shape=(len(off) - 1,) * 2)
+    ncomp, lab = connected_components(g, directed=False)
+    sizes = np.bincount(lab[hard])
+    comps = [k for k in np.argsort(-sizes)[:3] if sizes[k] > 0]
+    rng = np.random.default_rng(5)
+    cand = np.unique(lab[hard])
+    comps += list(rng.choice(cand, size=min(20, len(cand)), replace=False))
+    sel = np.nonzero(np.isin(lab, comps) & hard)[0]
+    remap = -np.ones(len(off) - 1, np.int64)
+    remap[sel] = np.arange(len(sel))
+    rows = [remap[idx[off[i]:off[i + 1]]] for i in sel]
+    soff = np.zeros(len(sel) + 1, np.int64)
+    soff[1:] = np.cumsum([len(r) for r in rows])
+    sidx = np.concatenate(rows).astype(np.int32)
+    assert (sidx >= 0).all()
+    ox, ov, ons, _ = oracle.hermite(c.pos[sel], c.vel[sel], c.mass[sel], soff, sidx, p["eps"],
+                                    p["r_in"], p["r_out"],
+                                    **_okw(hk))
+    log(f"  checked {len(sel)} particles in {len(comps)} clusters (largest {sizes.max()})")
+    assert np.array_equal(ns[sel], ons)
+    assert np.array_equal(x[sel], ox) and np.array_equal(v[sel], ov)
+    assert st["n_hard"] == int(hard.sum()) and st["max_cluster"] == int(sizes.max())
+
+
+def test_p3t_step_matches_oracle_composition(ctx):
+    """One P3T step (kick, hard part over the lists of the build, rebuild,
+    force, kick) against the same sequence composed from oracle pieces, FP64."""
+    import torch
+    n = 4096
+    c = plummer(n, 81)
+    p = dict(eps=4.0 / n, r_in=0.003, r_out=0.03, theta=0.5, r_search=0.04, n_crit=64,
+             n_leaf=16, precision="fp64")
+    hk = _hermite_kw(p["r_out"], c.mass, dt_soft=2.0 ** -6)
+    pos, vel, mass = _dev(c.pos), _dev(c.vel), _dev(c.mass)
+    ctx.build_tree(pos, mass, **p)
+    acc, _ = ctx.long_force()
+    st = ctx.step(pos, vel, mass, acc, hk, **p)
+    log(f"p3t step n={n}: {st}")
+    # oracle composition
+    t0 = oracle.Tree(c.pos, c.mass, p)
+    a0, _ = t0.force()
+    off, idx = t0.neighbors()
+    v1 = c.vel + 0.5 * hk["dt_soft"] * a0
+    x2, v2, ns, _ = oracle.hermite(c.pos, v1, c.mass, off, idx, p["eps"], p["r_in"], p["r_out"],
+                                   **_okw(hk))
+    a2, _ = oracle.Tree(x2, c.mass, p).force()
+    v3 = v2 + 0.5 * hk["dt_soft"] * a2
+    gx, gv, ga = pos.cpu().numpy(), vel.cpu().numpy(), acc.cpu().numpy()
+    ex = np.abs(gx - x2).max() / np.abs(x2).max()
+    ev = np.sqrt(((gv - v3) ** 2).sum() / (v3 ** 2).sum())
+    ea = np.sqrt(((ga - a2) ** 2).sum() / (a2 ** 2).sum())
+    log(f"  pos max rel {ex:.2e}  vel rel-RMS {ev:.2e}  acc rel-RMS {ea:.2e}")
+    assert st["n_hard"] == int((np.diff(off) > 0).sum()) and st["n_hard"] > 0
+    assert ex < 1e-12 and ev < 1e-12 and ea < 1e-12
