@@ -256,6 +256,95 @@ def vjp_timing(ctx, workload="plummer256k", seed=1, reps=3):
     return out
 
 
+HERMITE = dict(eta=0.1, alpha=0.1, dt_max_per_soft=0.25)   # Section 3: eta, alpha, dt_max
+
+
+def p3t_step_timing(ctx, w, c, dt, steps=4, warmup=1, cpu_target_s=6.0, cpu=True):
+    """Whole P3T steps (kick, neighbour lists, Hermite hard part over the soft
+    step, rebuild, soft force, kick) on the workload in FP64 and mixed soft
+    force, with the hard part's statistics; the oracle's Hermite integration
+    timed on sampled clusters of the same lists as its CPU baseline."""
+    import torch
+    dev = torch.device("cuda", 0)
+    mass = torch.from_numpy(c.mass).to(dev)
+    hk = dict(dt_soft=dt, dt_max=dt * HERMITE["dt_max_per_soft"], eta=HERMITE["eta"],
+              eta_s=HERMITE["eta"] / 10, a0=HERMITE["alpha"] * float(c.mass.mean()) / w.r_out ** 2)
+    out = {"workload": w.name, "n": w.n, "hermite": dict(hk, alpha=HERMITE["alpha"]),
+           "steps": steps, "warmup": warmup}
+    for prec in ("mixed", "fp64"):
+        params = w.params(precision=prec)
+        pos = torch.from_numpy(c.pos).to(dev)
+        vel = torch.from_numpy(c.vel).to(dev)
+        ctx.build_tree(pos, mass, **params)
+        acc, _ = ctx.long_force(want_pot=False)
+        for _ in range(warmup):
+            ctx.step(pos, vel, mass, acc, hk, **params)
+        torch.cuda.synchronize()
+        wall, herm, stats = [], [], []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            st = ctx.step(pos, vel, mass, acc, hk, **params)
+            torch.cuda.synchronize()
+            wall.append((time.perf_counter() - t0) * 1e3)
+            herm.append(st["ms"])
+            stats.append(st)
+        last = stats[-1]
+        out[prec] = {"ms_per_step": float(np.median(wall)), "hermite_ms": float(np.median(herm)),
+                     "n_hard": last["n_hard"], "n_clusters": last["n_clusters"],
+                     "max_cluster": last["max_cluster"], "hermite_steps": last["steps"],
+                     "max_block_steps": last["max_block_steps"],
+                     "hermite_steps_per_s": last["steps"] / (last["ms"] * 1e-3)}
+        log(f"bench: p3t step {prec}: {json.dumps(out[prec])}")
+    if cpu:
+        out["cpu_baseline"] = hermite_cpu_baseline(ctx, w, c, hk, cpu_target_s)
+    return out
+
+
+def hermite_cpu_baseline(ctx, w, c, hk, target_s, seed=4):
+    """The oracle's block-step Hermite integration (single-threaded, as it
+    stands) on whole clusters of the step-0 neighbour lists, drawn at random
+    until about target_s seconds of work; in Hermite steps per second."""
+    import oracle
+    import torch
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+    params = w.params(precision="fp64")
+    dev = torch.device("cuda", 0)
+    ctx.build_tree(torch.from_numpy(c.pos).to(dev), torch.from_numpy(c.mass).to(dev), **params)
+    off, idx = (t.cpu().numpy() for t in ctx.neighbors())
+    n = len(off) - 1
+    hard = np.diff(off) > 0
+    _, lab = connected_components(csr_matrix((np.ones(len(idx)), idx, off), shape=(n, n)),
+                                  directed=False)
+    comps = np.unique(lab[hard])
+    rng = np.random.default_rng(seed)
+    rng.shuffle(comps)
+    kw = {k: hk[k] for k in ("dt_soft", "dt_max", "eta", "eta_s", "a0")}
+    done_steps, secs, used, parts, start = 0, 0.0, 0, 0, 0
+    chunk = 64
+    while secs < target_s and start < len(comps):
+        pick = comps[start:start + chunk]
+        start += chunk
+        sel = np.nonzero(np.isin(lab, pick) & hard)[0]
+        remap = -np.ones(n, np.int64)
+        remap[sel] = np.arange(len(sel))
+        rows = [remap[idx[off[i]:off[i + 1]]] for i in sel]
+        soff = np.zeros(len(sel) + 1, np.int64)
+        soff[1:] = np.cumsum([len(r) for r in rows])
+        sidx = np.concatenate(rows).astype(np.int32)
+        t0 = time.perf_counter()
+        _, _, ns, _ = oracle.hermite(c.pos[sel], c.vel[sel], c.mass[sel], soff, sidx, params["eps"],
+                                     params["r_in"], params["r_out"], **kw)
+        secs += time.perf_counter() - t0
+        done_steps += int(ns.sum())
+        used += len(pick)
+        parts += len(sel)
+        chunk = min(4 * chunk, 4096)
+    return {"value": done_steps / secs, "unit": "Hermite steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"block-step Hermite of {used} whole clusters ({parts} particles, "
+                      f"{done_steps} steps) of the step-0 neighbour lists, {secs:.1f} s"}
+
+
 def sweep(args):
     """theta x n_crit sweep on the 2^22 Plummer/Salpeter workload: FP32-compensated
     vs FP64 interaction kernels, throughput and RMS / max force error on sampled
@@ -335,6 +424,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-vjp", action="store_true", help="skip the VJP timing")
+    ap.add_argument("--no-p3t", action="store_true",
+                    help="skip the whole-P3T-step timing (soft step plus Hermite hard part)")
     ap.add_argument("--sweep", action="store_true",
                     help="run the theta x n_crit sweep on the 2^22 workload instead")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -435,6 +526,9 @@ def main():
     if not args.no_vjp:
         log("bench: VJP timing")
         out["vjp"] = vjp_timing(ctx)
+    if not args.no_p3t:
+        log("bench: P3T steps with the Hermite hard part")
+        out["p3t_step"] = p3t_step_timing(ctx, w, c, dt, cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline on sampled groups")
         cb, errs = cpu_baseline(c.pos, c.mass, w.params(), firsts)

@@ -31,8 +31,16 @@
 // Components come from a lock-free union-find over the list edges (a root is
 // always linked under a smaller root, so every chain decreases and the final
 // root of a component is its smallest index), members are gathered into
-// contiguous slots, and components are launched largest first.
+// contiguous slots, and components are launched largest first.  A component of
+// fewer than 1024 members runs from LDS: each thread keeps its members' state
+// in registers, the predicted positions and velocities that neighbours read
+// live in LDS, and so do the component's list entries as local indices (they
+// fall back to a global copy when they outgrow their LDS area).  Three size
+// classes (< 64, < 256, < 1024 members) have their own block shapes and run
+// concurrently on forked streams beside the global-memory kernel that takes
+// larger components.
 #include <math.h>
+#include <string.h>
 
 #include "device_util.h"
 #include "internal.h"
@@ -40,7 +48,7 @@
 namespace p3t {
 
 constexpr int kHardThreads = 256;
-constexpr int kHermThreads = 128;
+constexpr int kHermThreads = 1024;   // the global-memory kernel for components of >= 1024
 constexpr int kMaxDtLevel = 40;
 constexpr int kUnionTries = 1 << 20;
 
@@ -56,7 +64,12 @@ struct HermConsts {
 
 // readback slots (int64 units) used here
 enum { RB_HBAD = 48, RB_HNHARD = 49, RB_HNCL = 50, RB_HMAXCL = 51, RB_HLIMIT = 52,
-       RB_HSTEPS = 53, RB_HMAXBLK = 54 };
+       RB_HSTEPS = 53, RB_HMAXBLK = 54, RB_HNNZ = 55, RB_HCLASS = 56 /* 4 int32 class sizes */ };
+
+// size classes by floor(log2(members)): < 64, < 256, < 1024, the rest
+constexpr int kClassBucket[3] = {5, 7, 9};
+constexpr int kNumClasses = 4;
+constexpr int kAux = 3;         // streams beside the context stream, one per LDS class
 
 // ---------------------------------------------------------------------------
 // Changeover functions, written as the formulas of Section 2.1 (G with the
@@ -271,20 +284,29 @@ __global__ void k_cc_place(int64_t n, const int32_t *__restrict__ label,
 
 __device__ inline int size_bucket(int32_t size) { return 31 - __clz(size); }
 
-// cluster ranges and a histogram of floor(log2(size))
-__global__ void k_cc_clusters(int64_t n, const int32_t *__restrict__ ccount,
-                              const int32_t *__restrict__ cstart, const int32_t *__restrict__ cid,
-                              int32_t *__restrict__ cl_beg, int32_t *__restrict__ cl_end,
-                              int32_t *__restrict__ bhist, unsigned long long *maxsize) {
+// cluster ranges and a histogram of floor(log2(size)); counts gather in LDS
+// first, so that the few global counters see one atomic per block
+__global__ __launch_bounds__(256) void k_cc_clusters(
+    int64_t n, const int32_t *__restrict__ ccount, const int32_t *__restrict__ cstart,
+    const int32_t *__restrict__ cid, int32_t *__restrict__ cl_beg, int32_t *__restrict__ cl_end,
+    int32_t *__restrict__ bhist, unsigned long long *maxsize) {
+    __shared__ int32_t s_h[32];
+    __shared__ unsigned int s_max;
+    if (threadIdx.x < 32) s_h[threadIdx.x] = 0;
+    if (threadIdx.x == 0) s_max = 0;
+    __syncthreads();
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    const int32_t c = ccount[r];
-    if (c == 0) return;
-    const int32_t k = cid[r];
-    cl_beg[k] = cstart[r];
-    cl_end[k] = cstart[r] + c;
-    atomicAdd(&bhist[size_bucket(c)], 1);
-    atomicMax(maxsize, (unsigned long long)c);
+    const int32_t c = r < n ? ccount[r] : 0;
+    if (c > 0) {
+        const int32_t k = cid[r];
+        cl_beg[k] = cstart[r];
+        cl_end[k] = cstart[r] + c;
+        atomicAdd(&s_h[size_bucket(c)], 1);
+        atomicMax(&s_max, (unsigned int)c);
+    }
+    __syncthreads();
+    if (threadIdx.x < 32 && s_h[threadIdx.x]) atomicAdd(&bhist[threadIdx.x], s_h[threadIdx.x]);
+    if (threadIdx.x == 0 && s_max) atomicMax(maxsize, (unsigned long long)s_max);
 }
 
 // exclusive offsets of the size buckets, largest sizes first (one thread)
@@ -297,13 +319,27 @@ __global__ void k_cc_bucket_scan(int32_t *bhist) {
     }
 }
 
-__global__ void k_cc_order(int64_t n_cl, const int32_t *__restrict__ cl_beg,
-                           const int32_t *__restrict__ cl_end, int32_t *__restrict__ bfill,
-                           const int32_t *__restrict__ boff, int32_t *__restrict__ order) {
+// clusters into `order` by bucket, largest buckets first; each block reserves
+// its run of every bucket with one global atomic
+__global__ __launch_bounds__(256) void k_cc_order(int64_t n_cl, const int32_t *__restrict__ cl_beg,
+                                                  const int32_t *__restrict__ cl_end,
+                                                  int32_t *__restrict__ bfill,
+                                                  const int32_t *__restrict__ boff,
+                                                  int32_t *__restrict__ order) {
+    __shared__ int32_t s_cnt[32], s_base[32];
+    if (threadIdx.x < 32) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_cl) return;
-    const int b = size_bucket(cl_end[c] - cl_beg[c]);
-    order[boff[b] + atomicAdd(&bfill[b], 1)] = (int32_t)c;
+    int b = -1, rank = 0;
+    if (c < n_cl) {
+        b = size_bucket(cl_end[c] - cl_beg[c]);
+        rank = atomicAdd(&s_cnt[b], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < 32 && s_cnt[threadIdx.x])
+        s_base[threadIdx.x] = boff[threadIdx.x] + atomicAdd(&bfill[threadIdx.x], s_cnt[threadIdx.x]);
+    __syncthreads();
+    if (b >= 0) order[s_base[b] + rank] = (int32_t)c;
 }
 
 // ---------------------------------------------------------------------------
@@ -348,13 +384,13 @@ __device__ inline double block_min(double v, double *s_red) {
 
 __global__ __launch_bounds__(kHermThreads) void k_hermite_cluster(
     const int32_t *__restrict__ cl_beg, const int32_t *__restrict__ cl_end,
-    const int32_t *__restrict__ order, const int32_t *__restrict__ mem,
+    const int32_t *__restrict__ order, int32_t order_base, const int32_t *__restrict__ mem,
     const int32_t *__restrict__ slot, const int64_t *__restrict__ off,
     const int32_t *__restrict__ idx, const double *__restrict__ mass, double *__restrict__ pos,
     double *__restrict__ vel, HardConsts hc, HermConsts hp, HermState S,
     int32_t *__restrict__ nsteps_out, unsigned long long *rb) {
     __shared__ double s_red[kHermThreads / 64];
-    const int c = order[blockIdx.x];
+    const int c = order[order_base + blockIdx.x];
     const int b = cl_beg[c], e = cl_end[c];
     const int tid = threadIdx.x;
     for (int s = b + tid; s < e; s += kHermThreads) {
@@ -450,6 +486,339 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite_cluster(
     if (tid == 0) atomicMax(rb + (RB_HMAXBLK - RB_HBAD), (unsigned long long)steps);
 }
 
+// cluster counts of the size classes, largest class first: [>= 1024, < 1024,
+// < 256, < 64] members (from the bucket histogram, before it is scanned)
+__global__ void k_cc_classes(const int32_t *bhist, int32_t *cls) {
+    int32_t c[kNumClasses] = {0, 0, 0, 0};
+    for (int b = 0; b < 32; ++b) {
+        int k = 0;
+        for (int q = 0; q < 3; ++q)
+            if (b <= kClassBucket[q]) { k = 3 - q; break; }
+        c[k] += bhist[b];
+    }
+    for (int k = 0; k < kNumClasses; ++k) cls[k] = c[k];
+}
+
+// local index of every list entry: the neighbour's slot minus the first slot of
+// the entry's component
+__global__ void k_hard_local(int64_t n, const int64_t *__restrict__ off,
+                             const int32_t *__restrict__ idx, const int32_t *__restrict__ label,
+                             const int32_t *__restrict__ cid, const int32_t *__restrict__ cl_beg,
+                             const int32_t *__restrict__ slot, int32_t *__restrict__ lidx) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t r = label[i];
+    if (r < 0) return;
+    const int32_t base = cl_beg[cid[r]];
+    for (int64_t e = off[i]; e < off[i + 1]; ++e) lidx[e] = slot[idx[e]] - base;
+}
+
+// The six summands one list entry adds to a and jerk, by the operations of
+// hard_sum: member k's predicted state against neighbour jl, both local.
+__device__ inline void pair_terms(int k, int jl, const double *xs, const double *vs,
+                                  const double *sm, const HardConsts &hc, double gam,
+                                  double o[6]) {
+    const double dx = xs[3 * jl] - xs[3 * k];
+    const double dy = xs[3 * jl + 1] - xs[3 * k + 1];
+    const double dz = xs[3 * jl + 2] - xs[3 * k + 2];
+    const double vx = vs[3 * jl] - vs[3 * k];
+    const double vy = vs[3 * jl + 1] - vs[3 * k + 1];
+    const double vz = vs[3 * jl + 2] - vs[3 * k + 2];
+    const double s2 = dx * dx + dy * dy + dz * dz + hc.eps * hc.eps;
+    const double s = sqrt(s2);
+    const double y = s / hc.r_out;
+    const double K = hk_K(y, gam);
+    const double Ks = hk_dK(y, gam) / hc.r_out;
+    const double mj = sm[jl];
+    const double inv_s3 = 1.0 / (s2 * s);
+    const double rv = dx * vx + dy * vy + dz * vz;
+    const double f = mj * (1.0 - K) * inv_s3;
+    const double c = 3.0 * rv / s2;
+    const double g = mj * Ks * rv / s * inv_s3;
+    o[0] = f * dx;
+    o[1] = f * dy;
+    o[2] = f * dz;
+    o[3] = f * (vx - c * dx) - g * dx;
+    o[4] = f * (vy - c * dy) - g * dy;
+    o[5] = f * (vz - c * dz) - g * dz;
+}
+
+// hard_sum on a component held in LDS: member k's predicted state, neighbours
+// through local indices nb[rb .. re), masses from sm, summed in list order.
+__device__ inline void hard_sum_local(int k, const double *xs, const double *vs, const double *sm,
+                                      const int32_t *nb, int64_t rb, int64_t re,
+                                      const HardConsts &hc, double a[3], double jk[3]) {
+    const double gam = hc.r_in / hc.r_out;
+    a[0] = a[1] = a[2] = 0.0;
+    jk[0] = jk[1] = jk[2] = 0.0;
+    for (int64_t e = rb; e < re; ++e) {
+        double o[6];
+        pair_terms(k, nb[e], xs, vs, sm, hc, gam, o);
+        a[0] += o[0];
+        a[1] += o[1];
+        a[2] += o[2];
+        jk[0] += o[3];
+        jk[1] += o[4];
+        jk[2] += o[5];
+    }
+}
+
+template <int T>
+__device__ inline double block_min_t(double v, double *s_red) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    if (T == 64) return v;
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s_red[w] = v;
+    __syncthreads();
+    double r = s_red[0];
+    for (int k = 1; k < T / 64; ++k) r = fmin(r, s_red[k]);
+    return r;
+}
+
+// Exclusive prefix sum of one int per thread over a block of T threads; the
+// block total in `total`.  Every thread of the block must call it.
+template <int T>
+__device__ inline int block_scan_excl(int v, int *s_ws, int &total) {
+    int incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o);
+        if ((threadIdx.x & 63) >= o) incl += y;
+    }
+    if (T == 64) {
+        total = __shfl(incl, 63);
+        return incl - v;
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 63) s_ws[w] = incl;
+    __syncthreads();
+    int before = 0, tot = 0;
+    for (int q = 0; q < T / 64; ++q) {
+        const int x = s_ws[q];
+        if (q < w) before += x;
+        tot += x;
+    }
+    total = tot;
+    __syncthreads();
+    return before + incl - v;
+}
+
+// One component of fewer than T * R members per block; member k is owned by
+// thread k % T, slot r = k / T of its registers.  With C > 0 and the lists in
+// LDS, a block step gathers the list entries of its active members, evaluates
+// their pair terms across the whole block, C entries at a time, into LDS, and
+// each owner then adds its row's terms in list order -- the same sums as the
+// sequential loop.
+template <int T, int R, int ECAP, int C>
+__global__ __launch_bounds__(T) void k_hermite_lds(
+    const int32_t *__restrict__ cl_beg, const int32_t *__restrict__ cl_end,
+    const int32_t *__restrict__ order, int32_t order_base, const int32_t *__restrict__ mem,
+    const int64_t *__restrict__ off, const int32_t *__restrict__ lidx,
+    const double *__restrict__ mass, double *__restrict__ pos, double *__restrict__ vel,
+    HardConsts hc, HermConsts hp, int32_t *__restrict__ nsteps_out, unsigned long long *rb) {
+    constexpr int M = T * R;
+    __shared__ double s_xp[3 * M], s_vp[3 * M], s_m[M];
+    __shared__ int32_t s_row[M + 1];
+    __shared__ int32_t s_nb[ECAP];
+    __shared__ int16_t s_ae[C > 0 ? ECAP : 1];      // active entries of a step ...
+    __shared__ int16_t s_aown[C > 0 ? ECAP : 1];    // ... and their members
+    __shared__ double s_term[C > 0 ? 6 * C : 1];
+    __shared__ int s_ws[T / 64];
+    __shared__ double s_red[T / 64];
+    const double gam = hc.r_in / hc.r_out;
+    const int c = order[order_base + blockIdx.x];
+    const int b = cl_beg[c], nm = cl_end[c] - b;
+    const int tid = threadIdx.x;
+    for (int k = tid; k < nm; k += T) {
+        const int32_t i = mem[b + k];
+        s_row[k + 1] = (int32_t)(off[i + 1] - off[i]);
+        s_m[k] = mass[i];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        s_row[0] = 0;
+        for (int k = 1; k <= nm; ++k) s_row[k] += s_row[k - 1];
+    }
+    __syncthreads();
+    const int n_edges = s_row[nm];
+    const bool in_lds = n_edges <= ECAP;
+    // list entries as local indices, row by row, in LDS if they fit
+    if (in_lds)
+        for (int k = tid; k < nm; k += T) {
+            const int32_t i = mem[b + k];
+            const int64_t e0 = off[i];
+            for (int q = s_row[k]; q < s_row[k + 1]; ++q) s_nb[q] = lidx[e0 + (q - s_row[k])];
+        }
+    const bool rowpar = C > 0 && in_lds;
+    double x[R][3], v[R][3], a[R][3], jk[R][3], t[R], dt[R];
+    int ns[R];
+    int64_t e0[R];   // first global list entry of the member's row (global fallback)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int k = tid + r * T;
+        t[r] = 0.0;
+        dt[r] = INFINITY;
+        ns[r] = 0;
+        e0[r] = 0;
+        if (k < nm) {
+            const int32_t i = mem[b + k];
+            e0[r] = off[i];
+            for (int q = 0; q < 3; ++q) {
+                x[r][q] = pos[3 * i + q];
+                v[r][q] = vel[3 * i + q];
+                s_xp[3 * k + q] = x[r][q];
+                s_vp[3 * k + q] = v[r][q];
+            }
+        }
+    }
+    __syncthreads();
+    // neighbours of member k: local indices at nbp + rowb
+    const int32_t *nbp = in_lds ? s_nb : lidx;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int k = tid + r * T;
+        if (k >= nm) continue;
+        const int64_t rowb = in_lds ? (int64_t)s_row[k] : e0[r];
+        const int64_t rowe = rowb + (s_row[k + 1] - s_row[k]);
+        hard_sum_local(k, s_xp, s_vp, s_m, nbp, rowb, rowe, hc, a[r], jk[r]);
+        const double cr = crit_first(a[r], jk[r], hp);
+        double d = hp.dt_max;
+        while (d > cr && d > hp.dt_min) d *= 0.5;
+        dt[r] = d;
+    }
+    int64_t steps = 0;
+    for (;;) {
+        double lmin = INFINITY;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double tn = t[r] + dt[r];
+            if (tn < lmin) lmin = tn;
+        }
+        const double t_next = block_min_t<T>(lmin, s_red);
+        if (!(t_next <= hp.t_end)) break;
+        if (steps == hp.max_block_steps) {
+            if (tid == 0) atomicOr(rb + (RB_HLIMIT - RB_HBAD), 1ull);
+            break;
+        }
+        ++steps;
+        if (T == 64) __syncthreads();   // the previous step's reads of s_xp are done
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int k = tid + r * T;
+            if (k >= nm) continue;
+            const double h = t_next - t[r];
+            for (int q = 0; q < 3; ++q) {
+                s_xp[3 * k + q] = x[r][q] + v[r][q] * h + a[r][q] * (h * h / 2.0) +
+                                  jk[r][q] * (h * h * h / 6.0);
+                s_vp[3 * k + q] = v[r][q] + a[r][q] * h + jk[r][q] * (h * h / 2.0);
+            }
+        }
+        __syncthreads();
+        double a1[R][3], j1[R][3];
+        if (rowpar) {
+            // the active members' list entries, gathered in row order
+            int lens[R], abase[R], L = 0, n_act = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int k = tid + r * T;
+                lens[r] = (k < nm && t[r] + dt[r] == t_next) ? s_row[k + 1] - s_row[k] : 0;
+                L += lens[r];
+                for (int q = 0; q < 3; ++q) a1[r][q] = j1[r][q] = 0.0;
+            }
+            int o0 = block_scan_excl<T>(L, s_ws, n_act);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                abase[r] = o0;
+                const int k = tid + r * T;
+                for (int q = 0; q < lens[r]; ++q) {
+                    s_ae[o0 + q] = (int16_t)(s_row[k] + q);
+                    s_aown[o0 + q] = (int16_t)k;
+                }
+                o0 += lens[r];
+            }
+            __syncthreads();
+            for (int c0 = 0; c0 < n_act; c0 += (C > 0 ? C : 1)) {
+                const int c1 = min(c0 + C, n_act);
+                for (int e = c0 + tid; e < c1; e += T) {
+                    double o[6];
+                    pair_terms(s_aown[e], s_nb[s_ae[e]], s_xp, s_vp, s_m, hc, gam, o);
+                    for (int q = 0; q < 6; ++q) s_term[6 * (e - c0) + q] = o[q];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (!lens[r]) continue;
+                    const int rb = max(abase[r], c0), re = min(abase[r] + lens[r], c1);
+                    for (int e = rb; e < re; ++e) {
+                        const double *o = s_term + 6 * (e - c0);
+                        a1[r][0] += o[0];
+                        a1[r][1] += o[1];
+                        a1[r][2] += o[2];
+                        j1[r][0] += o[3];
+                        j1[r][1] += o[4];
+                        j1[r][2] += o[5];
+                    }
+                }
+                __syncthreads();
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int k = tid + r * T;
+                if (k >= nm || t[r] + dt[r] != t_next) continue;
+                const int64_t rowb = in_lds ? (int64_t)s_row[k] : e0[r];
+                const int64_t rowe = rowb + (s_row[k + 1] - s_row[k]);
+                hard_sum_local(k, s_xp, s_vp, s_m, nbp, rowb, rowe, hc, a1[r], j1[r]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int k = tid + r * T;
+            if (k >= nm || t[r] + dt[r] != t_next) continue;
+            double a2[3], a3[3];
+            const double h = dt[r];
+            for (int q = 0; q < 3; ++q) {
+                const double s2 =
+                    (-6.0 * (a[r][q] - a1[r][q]) - h * (4.0 * jk[r][q] + 2.0 * j1[r][q])) / (h * h);
+                const double s3 =
+                    (12.0 * (a[r][q] - a1[r][q]) + 6.0 * h * (jk[r][q] + j1[r][q])) / (h * h * h);
+                x[r][q] = s_xp[3 * k + q] + s2 * (h * h * h * h / 24.0) +
+                          s3 * (h * h * h * h * h / 120.0);
+                v[r][q] = s_vp[3 * k + q] + s2 * (h * h * h / 6.0) + s3 * (h * h * h * h / 24.0);
+                a[r][q] = a1[r][q];
+                jk[r][q] = j1[r][q];
+                a2[q] = s2 + s3 * h;
+                a3[q] = s3;
+            }
+            t[r] = t_next;
+            ns[r] += 1;
+            const double cr = crit_full(a[r], jk[r], a2, a3, hp);
+            double d = h;
+            if (2.0 * d <= cr && 2.0 * d <= hp.dt_max && fmod(t[r], 2.0 * d) == 0.0)
+                d = 2.0 * d;
+            else
+                while (d > cr && d > hp.dt_min) d *= 0.5;
+            dt[r] = d;
+        }
+    }
+    unsigned long long my_steps = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int k = tid + r * T;
+        if (k >= nm) continue;
+        const int32_t i = mem[b + k];
+        for (int q = 0; q < 3; ++q) {
+            pos[3 * i + q] = x[r][q];
+            vel[3 * i + q] = v[r][q];
+        }
+        if (nsteps_out) nsteps_out[i] = ns[r];
+        my_steps += (unsigned long long)ns[r];
+    }
+    for (int o = 32; o > 0; o >>= 1) my_steps += __shfl_xor(my_steps, o);
+    if ((tid & 63) == 0 && my_steps) atomicAdd(rb + (RB_HSTEPS - RB_HBAD), my_steps);
+    if (tid == 0) atomicMax(rb + (RB_HMAXBLK - RB_HBAD), (unsigned long long)steps);
+}
+
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
@@ -482,6 +851,25 @@ static int validate_lists(p3t_ctx *ctx, int64_t n, const int64_t *off, const int
     return P3T_OK;
 }
 
+// kAux streams (default priority) and kAux + 1 events for the concurrent
+// classes, made on first use
+static int aux_streams(p3t_ctx *ctx) {
+    if (ctx->aux_ready) return P3T_OK;
+    int rc;
+    for (int k = 0; k < kAux; ++k)
+        if (!ctx->aux[k] &&
+            (rc = check_hip(ctx, hipStreamCreateWithFlags(&ctx->aux[k], hipStreamNonBlocking),
+                            "stream")))
+            return rc;
+    for (int k = 0; k < kAux + 1; ++k)
+        if (!ctx->aev[k] &&
+            (rc = check_hip(ctx, hipEventCreateWithFlags(&ctx->aev[k], hipEventDisableTiming),
+                            "event")))
+            return rc;
+    ctx->aux_ready = 1;
+    return P3T_OK;
+}
+
 int launch_hard_force(p3t_ctx *ctx, int64_t n, const double *pos, const double *vel,
                       const double *mass, const int64_t *off, const int32_t *idx,
                       const p3t_params *p, double *acc, double *jerk, double *pot) {
@@ -500,6 +888,7 @@ int launch_hermite(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const doub
     int rc;
     hipStream_t st = ctx->stream;
     if ((rc = ensure(ctx, ctx->readback, 64 * sizeof(int64_t)))) return rc;
+    if ((rc = aux_streams(ctx))) return rc;
     if ((rc = check_hip(ctx, hipEventRecord(ctx->ev[10], st), "event"))) return rc;
     if ((rc = validate_lists(ctx, n, off, idx))) return rc;
     // workspace: 7 per-particle int32 arrays, then per-slot state
@@ -523,15 +912,20 @@ int launch_hermite(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const doub
     if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + RB_HBAD, rb + RB_HBAD, 3 * sizeof(int64_t),
                                             hipMemcpyDeviceToHost, st), "readback")))
         return rc;
+    if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + RB_HNNZ, off + n, sizeof(int64_t),
+                                            hipMemcpyDeviceToHost, st), "readback")))
+        return rc;
     if ((rc = check_hip(ctx, hipStreamSynchronize(st), "sync"))) return rc;
     if (ctx->hpin[RB_HBAD]) return set_error(ctx, P3T_ELIMIT, "component search did not settle");
     const int64_t n_hard = *reinterpret_cast<const int32_t *>(ctx->hpin + RB_HNHARD);
     const int64_t n_cl = *reinterpret_cast<const int32_t *>(ctx->hpin + RB_HNCL);
+    const int64_t nnz = ctx->hpin[RB_HNNZ];
     // per-slot state: ten [m][3] and two [m] FP64 arrays; then int32 arrays:
-    // steps [m], members [m], cluster begin/end/order [c], size buckets [64]
+    // steps [m], members [m], cluster begin/end/order [c], size buckets [64],
+    // local list indices [nnz]
     const int64_t m = n_hard > 0 ? n_hard : 1, c = n_cl > 0 ? n_cl : 1;
     const size_t dbl = (size_t)m * 32;
-    const size_t i32 = 2 * (size_t)m + 3 * (size_t)c + 64;
+    const size_t i32 = 2 * (size_t)m + 3 * (size_t)c + 64 + (size_t)(nnz > 0 ? nnz : 1);
     if ((rc = ensure(ctx, ctx->hard_state, dbl * sizeof(double) + i32 * sizeof(int32_t)))) return rc;
     double *base = ptr<double>(ctx->hard_state);
     HermState S;
@@ -541,20 +935,29 @@ int launch_hermite(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const doub
     S.dt = S.t + m;
     S.ns = reinterpret_cast<int32_t *>(base + dbl);
     int32_t *mem = S.ns + m, *cl_beg = mem + m, *cl_end = cl_beg + c, *order = cl_end + c;
-    int32_t *bhist = order + c, *bfill = bhist + 32;
+    int32_t *bhist = order + c, *bfill = bhist + 32, *lidx = bfill + 32;
     if ((rc = check_hip(ctx, hipMemsetAsync(bhist, 0, 64 * sizeof(int32_t), st), "memset")))
         return rc;
     k_cc_place<<<nb, 256, 0, st>>>(n, label, cstart, cfill, mem, slotv, pos, vel, hpar->dt_soft);
     k_cc_clusters<<<nb, 256, 0, st>>>(n, ccount, cstart, cid, cl_beg, cl_end, bhist,
                                       reinterpret_cast<unsigned long long *>(rb + RB_HMAXCL));
+    k_cc_classes<<<1, 1, 0, st>>>(bhist, reinterpret_cast<int32_t *>(rb + RB_HCLASS));
     k_cc_bucket_scan<<<1, 1, 0, st>>>(bhist);
+    if (nsteps) {
+        // isolated particles take no Hermite step
+        if ((rc = check_hip(ctx, hipMemsetAsync(nsteps, 0, n * sizeof(int32_t), st), "memset")))
+            return rc;
+    }
     if (n_cl > 0) {
         k_cc_order<<<blocks_for(n_cl, 256), 256, 0, st>>>(n_cl, cl_beg, cl_end, bfill, bhist, order);
-        if (nsteps) {
-            // isolated particles take no Hermite step
-            if ((rc = check_hip(ctx, hipMemsetAsync(nsteps, 0, n * sizeof(int32_t), st), "memset")))
-                return rc;
-        }
+        k_hard_local<<<nb, 256, 0, st>>>(n, off, idx, label, cid, cl_beg, slotv, lidx);
+        if ((rc = check_hip(ctx, hipGetLastError(), "components"))) return rc;
+        if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + RB_HCLASS, rb + RB_HCLASS, 2 * sizeof(int64_t),
+                                                hipMemcpyDeviceToHost, st), "readback")))
+            return rc;
+        if ((rc = check_hip(ctx, hipStreamSynchronize(st), "sync"))) return rc;
+        int32_t cls[kNumClasses];
+        memcpy(cls, ctx->hpin + RB_HCLASS, sizeof(cls));
         HermConsts hc2;
         hc2.t_end = hpar->dt_soft;
         hc2.dt_max = hpar->dt_max;
@@ -563,12 +966,37 @@ int launch_hermite(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const doub
         hc2.eta_s = hpar->eta_s;
         hc2.a0 = hpar->a0;
         hc2.max_block_steps = hpar->max_block_steps > 0 ? hpar->max_block_steps : (1LL << 26);
-        k_hermite_cluster<<<(unsigned)n_cl, kHermThreads, 0, st>>>(
-            cl_beg, cl_end, order, mem, slotv, off, idx, mass, pos, vel, hard_consts(p), hc2, S,
-            nsteps, reinterpret_cast<unsigned long long *>(rb + RB_HBAD));
-    } else if (nsteps) {
-        if ((rc = check_hip(ctx, hipMemsetAsync(nsteps, 0, n * sizeof(int32_t), st), "memset")))
-            return rc;
+        const HardConsts hk = hard_consts(p);
+        unsigned long long *rbh = reinterpret_cast<unsigned long long *>(rb + RB_HBAD);
+        // fork: the three LDS classes on their own streams, the largest
+        // components on the context stream
+        if ((rc = check_hip(ctx, hipEventRecord(ctx->aev[0], st), "event"))) return rc;
+        for (int k = 0; k < kAux; ++k)
+            if ((rc = check_hip(ctx, hipStreamWaitEvent(ctx->aux[k], ctx->aev[0], 0), "wait")))
+                return rc;
+        int32_t base_k = 0;
+        if (cls[0] > 0)
+            k_hermite_cluster<<<(unsigned)cls[0], kHermThreads, 0, st>>>(
+                cl_beg, cl_end, order, base_k, mem, slotv, off, idx, mass, pos, vel, hk, hc2, S,
+                nsteps, rbh);
+        base_k += cls[0];
+        if (cls[1] > 0)
+            k_hermite_lds<256, 4, 8192, 512><<<(unsigned)cls[1], 256, 0, ctx->aux[0]>>>(
+                cl_beg, cl_end, order, base_k, mem, off, lidx, mass, pos, vel, hk, hc2, nsteps, rbh);
+        base_k += cls[1];
+        if (cls[2] > 0)
+            k_hermite_lds<256, 1, 4096, 512><<<(unsigned)cls[2], 256, 0, ctx->aux[1]>>>(
+                cl_beg, cl_end, order, base_k, mem, off, lidx, mass, pos, vel, hk, hc2, nsteps, rbh);
+        base_k += cls[2];
+        if (cls[3] > 0)
+            k_hermite_lds<64, 1, 2048, 0><<<(unsigned)cls[3], 64, 0, ctx->aux[2]>>>(
+                cl_beg, cl_end, order, base_k, mem, off, lidx, mass, pos, vel, hk, hc2, nsteps, rbh);
+
+        if ((rc = check_hip(ctx, hipGetLastError(), "hermite"))) return rc;
+        for (int k = 0; k < kAux; ++k) {
+            if ((rc = check_hip(ctx, hipEventRecord(ctx->aev[1 + k], ctx->aux[k]), "event"))) return rc;
+            if ((rc = check_hip(ctx, hipStreamWaitEvent(st, ctx->aev[1 + k], 0), "wait"))) return rc;
+        }
     }
     if ((rc = check_hip(ctx, hipGetLastError(), "hermite"))) return rc;
     if ((rc = check_hip(ctx, hipEventRecord(ctx->ev[11], st), "event"))) return rc;

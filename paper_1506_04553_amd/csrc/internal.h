@@ -109,6 +109,9 @@ struct p3t_ctx {
     p3t::DevBuf vjp_gx, vjp_gm, vjp_cell, bbox;
     p3t::DevBuf seg_end, gorder, grank, ghist;
     p3t::DevBuf hard_ix, hard_state;   // hard part: components and integrator state
+    hipStream_t aux[4] = {nullptr, nullptr, nullptr, nullptr};   // hard part's concurrent classes
+    hipEvent_t aev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    int aux_ready = 0;
     p3t::DevBuf step_off, step_idx;    // neighbour CSR of p3t_step
 };
 

@@ -163,6 +163,13 @@ extern "C" void p3t_destroy(p3t_ctx *ctx) {
     if (ctx->hpin) (void)hipHostFree(ctx->hpin);
     for (int k = 0; k < 12; ++k)
         if (ctx->ev[k]) (void)hipEventDestroy(ctx->ev[k]);
+    for (int k = 0; k < 4; ++k)
+        if (ctx->aux[k]) {
+            (void)hipStreamSynchronize(ctx->aux[k]);
+            (void)hipStreamDestroy(ctx->aux[k]);
+        }
+    for (int k = 0; k < 5; ++k)
+        if (ctx->aev[k]) (void)hipEventDestroy(ctx->aev[k]);
     delete ctx;
 }
 

@@ -154,6 +154,35 @@ def test_hermite_edge_cases(ctx):
     assert e.value.status == -1
 
 
+def test_hermite_dense_clusters_global_index_path(ctx):
+    """Components whose lists outgrow the LDS index areas of their size class
+    (every pair within h: 60 members, 3540 entries; 200 members, 39800
+    entries) read their indices from the global copy; a 7-member component
+    fills its packed lane group.  All bit for bit against the oracle."""
+    rng = np.random.default_rng(90)
+    parts = []
+    for k, (m, rad) in enumerate(((60, 0.004), (200, 0.004), (7, 0.004))):
+        centre = np.array([k * 1.0, 0.0, 0.0])
+        d = rng.normal(size=(m, 3))
+        d *= (rad * rng.uniform(0, 1, m) ** (1 / 3) / np.linalg.norm(d, axis=1))[:, None]
+        parts.append(centre + d)
+    pos = np.concatenate(parts)
+    n = len(pos)
+    vel = rng.normal(scale=0.05, size=(n, 3))
+    mass = np.full(n, 1e-6)
+    p = dict(eps=1e-4, r_in=0.001, r_out=0.01, theta=0.5, r_search=0.011, n_crit=64, n_leaf=16)
+    off, idx = direct.brute_neighbors(pos, p["r_search"])
+    assert len(idx) == 60 * 59 + 200 * 199 + 7 * 6
+    hk = _hermite_kw(p["r_out"], mass, dt_soft=2.0 ** -10)
+    x, v, ns, st = _run_hermite(ctx, pos, vel, mass, off, idx, p, hk)
+    ox, ov, ons, _ = oracle.hermite(pos, vel, mass, off, idx, p["eps"], p["r_in"], p["r_out"],
+                                    **_okw(hk))
+    log(f"dense clusters: {st}")
+    assert st["n_clusters"] == 3 and st["max_cluster"] == 200
+    assert np.array_equal(ns, ons)
+    assert np.array_equal(x, ox) and np.array_equal(v, ov)
+
+
 def test_hermite_king_1m_sampled_clusters(ctx):
     """The King W0=9, N=2^20 workload's own neighbour lists (h = 1.1 r_out):
     the whole GPU integration, checked bit for bit on the particles of sampled
