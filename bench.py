@@ -257,6 +257,53 @@ def vjp_timing(ctx, workload="plummer256k", seed=1, reps=3):
 
 
 HERMITE = dict(eta=0.1, alpha=0.1, dt_max_per_soft=0.25)   # Section 3: eta, alpha, dt_max
+F_DIRECT = 23   # flops per pair of the direct Newton sum, counted like the tree's pp term
+
+
+def direct_timing(ctx, workload="plummer256k", seed=1, reps=3, cpu=True, cpu_rows=48):
+    """O(N^2) FP64 direct sums on the 2^18 Plummer workload (Newton and soft):
+    median HIP-event time, pairs/s and FP64 TFLOP/s at F_DIRECT per pair; the
+    numpy definition on sampled rows as the CPU baseline."""
+    import torch
+    from inputs import WORKLOADS, make_cluster
+    from oracle import direct as odirect
+    w_ = WORKLOADS[workload]
+    c = make_cluster(w_, seed=seed)
+    dev = torch.device("cuda", 0)
+    pos = torch.from_numpy(c.pos).to(dev)
+    mass = torch.from_numpy(c.mass).to(dev)
+    p = w_.params(precision="fp64")
+    pairs = w_.n * (w_.n - 1)
+    out = {"workload": workload, "n": w_.n, "pairs": pairs, "flops_per_pair": F_DIRECT}
+    for mode in ("newton", "soft"):
+        ctx.direct(pos, mass, mode, **p)
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ctx.direct(pos, mass, mode, **p)
+            e1.record()
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        t = float(np.median(ms))
+        tf = pairs * F_DIRECT / (t * 1e-3) / 1e12
+        out[mode] = {"ms": t, "pairs_per_s": pairs / (t * 1e-3), "tflops": tf,
+                     "frac_of_fp64_peak": tf / PEAK_TFLOPS["fp64"]}
+    if cpu:
+        rows = np.random.default_rng(seed + 2).choice(w_.n, cpu_rows, replace=False)
+        t0 = time.perf_counter()
+        for i in rows:
+            d = c.pos - c.pos[i]
+            s2 = (d * d).sum(1) + p["eps"] ** 2
+            f = c.mass / (s2 * np.sqrt(s2))
+            f[i] = 0.0
+            _ = (f[:, None] * d).sum(0)
+        secs = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": cpu_rows * (w_.n - 1) / secs, "unit": "pairs/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"Newton rows of {cpu_rows} random particles by the "
+                                         f"numpy definition, {secs:.2f} s"}
+    return out
 
 
 def p3t_step_timing(ctx, w, c, dt, steps=4, warmup=1, cpu_target_s=6.0, cpu=True):
@@ -424,6 +471,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-vjp", action="store_true", help="skip the VJP timing")
+    ap.add_argument("--no-direct", action="store_true", help="skip the O(N^2) direct-sum timing")
     ap.add_argument("--no-p3t", action="store_true",
                     help="skip the whole-P3T-step timing (soft step plus Hermite hard part)")
     ap.add_argument("--sweep", action="store_true",
@@ -526,6 +574,9 @@ def main():
     if not args.no_vjp:
         log("bench: VJP timing")
         out["vjp"] = vjp_timing(ctx)
+    if not args.no_direct:
+        log("bench: O(N^2) direct sums")
+        out["direct"] = direct_timing(ctx, cpu=not args.no_cpu_baseline)
     if not args.no_p3t:
         log("bench: P3T steps with the Hermite hard part")
         out["p3t_step"] = p3t_step_timing(ctx, w, c, dt, cpu=not args.no_cpu_baseline)

@@ -222,6 +222,21 @@ int p3t_step(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const double *ma
              double *pot, const p3t_params *p, const p3t_hermite_params *hp,
              p3t_hermite_stats *stats);
 
+/* ---- Direct summation (the exact sums the tree approximates; for energies
+ * and diagnostics).  For every particle i, over all j != i, in FP64:
+ *   P3T_DIRECT_NEWTON  a_i = sum m_j d / s^3,          phi_i = -sum m_j / s
+ *   P3T_DIRECT_SOFT    a_i = sum m_j K(s) d / s^3,     phi_i = -sum m_j W(s) / s
+ *   P3T_DIRECT_HARD    a_i = sum m_j (1-K(s)) d / s^3, phi_i = -sum m_j (1-W(s)) / s
+ * (Section 2.1: F_soft and F_hard, H_soft and H_hard; d = x_j - x_i, s the
+ * softened distance).  O(n^2) work; uses eps, r_in, r_out of *p.
+ *   pos device [n][3]; mass device [n]; acc device [n][3] out; pot device [n]
+ *   out or NULL.  Errors: EINVAL, EHIP. */
+#define P3T_DIRECT_NEWTON 0
+#define P3T_DIRECT_SOFT 1
+#define P3T_DIRECT_HARD 2
+int p3t_direct(p3t_ctx *ctx, int64_t n, const double *pos, const double *mass,
+               const p3t_params *p, int mode, double *acc, double *pot);
+
 /* Statistics of the last calls.  Errors: EINVAL. */
 int p3t_get_stats(p3t_ctx *ctx, p3t_stats *out);
 

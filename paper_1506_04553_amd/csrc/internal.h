@@ -157,6 +157,13 @@ int launch_hermite(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const doub
                    const int64_t *off, const int32_t *idx, const p3t_params *p,
                    const p3t_hermite_params *hp, int32_t *nsteps, p3t_hermite_stats *stats);
 
+// Constants of K and W for gamma = r_in / r_out (p3t_api.hip).
+Changeover make_changeover(double r_in, double r_out);
+
+// O(N^2) direct sums (direct.hip).
+int launch_direct(p3t_ctx *ctx, int64_t n, const double *pos, const double *mass,
+                  const p3t_params *p, int mode, double *acc, double *pot);
+
 // Elementwise leapfrog helper (force.hip).
 int launch_kick_drift(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const double *acc,
                       double dt_kick, double dt_drift);

@@ -59,7 +59,7 @@ void release(p3t_ctx *ctx, DevBuf &b) {
 
 // Constants of K and W for gamma = r_in / r_out (Section 2.1, G with
 // denominator (gamma - 1)^7).
-static Changeover make_changeover(double r_in, double r_out) {
+Changeover make_changeover(double r_in, double r_out) {
     Changeover c{};
     const double g = r_in / r_out;
     c.r_out = r_out;
@@ -337,6 +337,17 @@ extern "C" int p3t_step(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const
     if ((rc = p3t_build_tree(ctx, n, pos, mass, p))) return rc;
     if ((rc = p3t_long_force(ctx, acc, pot))) return rc;
     return launch_kick_drift(ctx, n, pos, vel, acc, half, 0.0);
+}
+
+extern "C" int p3t_direct(p3t_ctx *ctx, int64_t n, const double *pos, const double *mass,
+                          const p3t_params *p, int mode, double *acc, double *pot) {
+    if (!ctx) return P3T_EINVAL;
+    if (n < 1 || !pos || !mass || !acc || p3t_check_params(p) != P3T_OK ||
+        (mode != P3T_DIRECT_NEWTON && mode != P3T_DIRECT_SOFT && mode != P3T_DIRECT_HARD))
+        return set_error(ctx, P3T_EINVAL, "bad direct-sum arguments");
+    int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
+    if (rc) return rc;
+    return launch_direct(ctx, n, pos, mass, p, mode, acc, pot);
 }
 
 extern "C" int p3t_get_stats(p3t_ctx *ctx, p3t_stats *out) {

@@ -79,7 +79,9 @@ _lib = None
 EXPORTS = ("p3t_create", "p3t_destroy", "p3t_check_params", "p3t_build_tree", "p3t_long_force",
            "p3t_neighbors", "p3t_long_force_vjp", "p3t_kick_drift", "p3t_get_stats",
            "p3t_copy_array", "p3t_status_string", "p3t_last_error", "p3t_hard_force",
-           "p3t_hermite_hard", "p3t_step")
+           "p3t_hermite_hard", "p3t_step", "p3t_direct")
+
+DIRECT_MODES = {"newton": 0, "soft": 1, "hard": 2}
 
 
 class HermiteParams(C.Structure):
@@ -116,6 +118,7 @@ def load_library(path: str = LIB_PATH):
                                    C.POINTER(HermiteParams), V, C.POINTER(HermiteStats)]
     L.p3t_step.argtypes = [V, C.c_int64, V, V, V, V, V, C.POINTER(Params),
                            C.POINTER(HermiteParams), C.POINTER(HermiteStats)]
+    L.p3t_direct.argtypes = [V, C.c_int64, V, V, C.POINTER(Params), C.c_int, V, V]
     L.p3t_copy_array.argtypes = [V, C.c_int, V, C.c_int64]
     L.p3t_status_string.argtypes = [C.c_int]
     L.p3t_status_string.restype = C.c_char_p
@@ -265,6 +268,21 @@ class P3T:
             self._tensor(t, (n, 3), nm)
         self._check(self._L.p3t_kick_drift(self._h, n, _dptr(pos), _dptr(vel), _dptr(acc),
                                            float(dt_kick), float(dt_drift)))
+
+    # -- direct sums ----------------------------------------------------------
+    def direct(self, pos, mass, mode: str = "newton", want_pot: bool = True, **params):
+        """(acc, pot) of the O(N^2) direct sum over all pairs: 'newton', 'soft'
+        (K, W) or 'hard' (1 - K, 1 - W), FP64."""
+        n = int(pos.shape[0])
+        self._tensor(pos, (n, 3), "pos")
+        self._tensor(mass, (n,), "mass")
+        p = make_params(**params)
+        dev = torch.device("cuda", self.device)
+        acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        pot = torch.empty((n,), dtype=torch.float64, device=dev) if want_pot else None
+        self._check(self._L.p3t_direct(self._h, n, _dptr(pos), _dptr(mass), C.byref(p),
+                                       DIRECT_MODES[mode], _dptr(acc), _dptr(pot)))
+        return acc, pot
 
     # -- hard part ----------------------------------------------------------
     def _csr(self, n, offsets, idx):
