@@ -46,6 +46,21 @@ class _HermiteParams(C.Structure):
                 ("eta_s", C.c_double), ("a0", C.c_double)]
 
 
+class _Kinds(C.Structure):
+    _fields_ = [("n_special", C.c_int64), ("r_in_ns", C.c_double), ("r_out_ns", C.c_double),
+                ("eps_ns", C.c_double), ("split_ss", C.c_int32), ("r_in_ss", C.c_double),
+                ("r_out_ss", C.c_double), ("eps_ss", C.c_double), ("eta_sp", C.c_double),
+                ("eta_s_sp", C.c_double)]
+
+
+def _kinds(kinds):
+    """kinds: None or a dict with n_special, r_in_ns, r_out_ns, eps_ns, split_ss,
+    r_in_ss, r_out_ss, eps_ss, eta_sp, eta_s_sp."""
+    if kinds is None:
+        return None
+    return C.byref(_Kinds(**kinds))
+
+
 _lib = None
 
 
@@ -84,9 +99,9 @@ def lib():
         L.or_morton.restype = C.c_uint64
         L.or_num_threads.restype = C.c_int
         L.or_hard_force.argtypes = [C.c_int64, P, P, P, P, P, C.c_double, C.c_double,
-                                    C.c_double, P, P, P]
+                                    C.c_double, C.POINTER(_Kinds), P, P, P]
         L.or_hermite.argtypes = [C.c_int64, P, P, P, P, P, C.c_double, C.c_double, C.c_double,
-                                 C.POINTER(_HermiteParams), P, P]
+                                 C.POINTER(_HermiteParams), C.POINTER(_Kinds), P, P]
         L.or_hermite.restype = C.c_int
         _lib = L
     return _lib
@@ -289,7 +304,7 @@ def _csr(off, idx):
             np.ascontiguousarray(idx, dtype=np.int32))
 
 
-def hard_force(pos, vel, mass, off, idx, eps, r_in, r_out):
+def hard_force(pos, vel, mass, off, idx, eps, r_in, r_out, kinds=None):
     """(acc [n,3], jerk [n,3], pot [n]) of the hard part over the neighbour CSR."""
     pos = np.ascontiguousarray(pos, dtype=np.float64)
     vel = np.ascontiguousarray(vel, dtype=np.float64)
@@ -298,11 +313,12 @@ def hard_force(pos, vel, mass, off, idx, eps, r_in, r_out):
     n = len(mass)
     acc, jerk, pot = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros(n)
     lib().or_hard_force(n, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(off), _ptr(idx), eps, r_in,
-                        r_out, _ptr(acc), _ptr(jerk), _ptr(pot))
+                        r_out, _kinds(kinds), _ptr(acc), _ptr(jerk), _ptr(pot))
     return acc, jerk, pot
 
 
-def hermite(pos, vel, mass, off, idx, eps, r_in, r_out, dt_soft, dt_max, eta, eta_s, a0):
+def hermite(pos, vel, mass, off, idx, eps, r_in, r_out, dt_soft, dt_max, eta, eta_s, a0,
+            kinds=None):
     """Integrate H_hard over dt_soft: returns (pos, vel, steps per particle, block steps)."""
     pos = np.array(pos, dtype=np.float64, order="C")
     vel = np.array(vel, dtype=np.float64, order="C")
@@ -313,7 +329,7 @@ def hermite(pos, vel, mass, off, idx, eps, r_in, r_out, dt_soft, dt_max, eta, et
     nblk = C.c_int64(0)
     hp = _HermiteParams(dt_soft, dt_max, eta, eta_s, a0)
     rc = lib().or_hermite(n, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(off), _ptr(idx), eps, r_in,
-                          r_out, C.byref(hp), _ptr(nsteps), C.byref(nblk))
+                          r_out, C.byref(hp), _kinds(kinds), _ptr(nsteps), C.byref(nblk))
     if rc != 0:
         raise RuntimeError(f"oracle hermite failed ({rc})")
     return pos, vel, nsteps, int(nblk.value)

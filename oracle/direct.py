@@ -11,7 +11,10 @@ Everything here is written directly from the definitions, in numpy FP64:
   quadrature -- independent of the closed form the tree oracle uses;
 * neighbour sets "within distance h" (Section 2.2) by testing every pair with
   dx*dx + dy*dy + dz*dz < h*h;
-* the gradient of L = sum w.a + sum c.phi of the direct soft sum.
+* the gradient of L = sum w.a + sum c.phi of the direct soft sum;
+* particle kinds (Section 3.3, the SMBH runs): the soft sum of the pairs that
+  involve a special particle, each pair with its own parameters, and the
+  neighbour sets with a radius per kind of pair.
 """
 from __future__ import annotations
 
@@ -192,3 +195,75 @@ def plummer_potential(r, a=3.0 * math.pi / 16.0):
 def plummer_accel(r, a=3.0 * math.pi / 16.0):
     """Magnitude of the inward acceleration of a unit-mass Plummer sphere."""
     return r / (r * r + a * a) ** 1.5
+
+
+def _kind_pair(n_total, n_special, i, j, eps, r_in, r_out, kinds):
+    """(eps, r_in, r_out, split) of the pair (i, j) by kinds: the last
+    n_special particles are special (Section 3.3)."""
+    first = n_total - n_special
+    si, sj = i >= first, j >= first
+    if si and sj:
+        return kinds["eps_ss"], kinds["r_in_ss"], kinds["r_out_ss"], bool(kinds["split_ss"])
+    if si or sj:
+        return kinds["eps_ns"], kinds["r_in_ns"], kinds["r_out_ns"], True
+    return eps, r_in, r_out, True
+
+
+def kinds_soft(pos, mass, eps, r_in, r_out, kinds):
+    """Soft acceleration and potential of every pair that involves a special
+    particle, with that pair's own parameters (a special-special pair that is
+    not split has no soft part).  Pairs of two normal particles are left out:
+    the tree sums them."""
+    n = len(mass)
+    ns = int(kinds["n_special"])
+    acc = np.zeros((n, 3))
+    pot = np.zeros(n)
+    for b in range(n - ns, n):
+        for i in range(n):
+            if i == b:
+                continue
+            e, ri, ro, split = _kind_pair(n, ns, i, b, eps, r_in, r_out, kinds)
+            if not split:
+                continue
+            d = pos[b] - pos[i]
+            s = math.sqrt(float(d @ d) + e * e)
+            y = np.array([s / ro])
+            g = ri / ro
+            K = float(K_np(y, g)[0])
+            W = float(W_over_y_np(y, g)[0] * y[0])
+            if i < n - ns or i > b:
+                # i gets b's pull; for two special particles each pair is visited once
+                acc[i] += mass[b] * K * d / s ** 3
+                pot[i] -= mass[b] * W / s
+                acc[b] -= mass[i] * K * d / s ** 3
+                pot[b] -= mass[i] * W / s
+    return acc, pot
+
+
+def kinds_neighbors(pos, n_special, h_nn, h_ns, split_ss, h_ss):
+    """CSR of j != i within the pair's radius: h_nn for two normal particles,
+    h_ns for a normal and a special one; two special particles are always
+    neighbours when their pair is not split, else within h_ss.  Same FP64 test
+    as brute_neighbors."""
+    n = pos.shape[0]
+    first = n - n_special
+    rows = []
+    for i in range(n):
+        dx = pos[:, 0] - pos[i, 0]
+        dy = pos[:, 1] - pos[i, 1]
+        dz = pos[:, 2] - pos[i, 2]
+        r2 = dx * dx + dy * dy + dz * dz
+        sp = np.arange(n) >= first
+        if i >= first:
+            h = np.where(sp, h_ss, h_ns)
+        else:
+            h = np.where(sp, h_ns, h_nn)
+        hit = r2 < h * h
+        if i >= first and not split_ss:
+            hit |= sp
+        hit[i] = False
+        rows.append(np.nonzero(hit)[0])
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum([len(r) for r in rows])
+    idx = np.concatenate(rows).astype(np.int64) if rows else np.zeros(0, np.int64)
+    return off, idx

@@ -45,7 +45,12 @@
  *               predicted to t_next, then all active forces are evaluated, then
  *               all active particles are corrected;
  *   a0          the softening term of the criteria is passed in (alpha m / r_cut^2
- *               with m chosen by the caller).
+ *               with m chosen by the caller);
+ *   kinds       optionally the last n_special particles are special (the SMBHs of
+ *               Section 3.3): a normal-special pair takes its own r_in, r_cut and
+ *               softening, a special-special pair its own softening and, when it
+ *               is not split, K = W = 0 (the pair is wholly hard: no soft force);
+ *               special particles take their own eta and eta_s.
  *
  * Compiled with -ffp-contract=off and without fast-math, like the tree oracle.
  */
@@ -65,18 +70,53 @@ typedef struct {
     double dt_soft, dt_max, eta, eta_s, a0;
 } or_hermite_params;
 
+typedef struct {
+    int64_t n_special;                 /* the last n_special particles are special */
+    double r_in_ns, r_out_ns, eps_ns;  /* normal-special pairs */
+    int32_t split_ss;                  /* special-special: 0 = wholly hard */
+    double r_in_ss, r_out_ss, eps_ss;
+    double eta_sp, eta_s_sp;           /* timestep accuracy of special particles */
+} or_kinds;
+
+typedef struct {
+    double eps, r_in, r_out;
+    int split;
+} or_pair;
+
+/* parameters of the pair (i, j) by the kinds of i and j */
+static or_pair pair_of(int64_t n, const or_kinds *kd, int64_t i, int64_t j, double eps,
+                       double r_in, double r_out)
+{
+    const int64_t first = kd ? n - kd->n_special : n;
+    const int si = i >= first, sj = j >= first;
+    or_pair q = {eps, r_in, r_out, 1};
+    if (si && sj) {
+        q.eps = kd->eps_ss;
+        q.r_in = kd->r_in_ss;
+        q.r_out = kd->r_out_ss;
+        q.split = kd->split_ss;
+    } else if (si || sj) {
+        q.eps = kd->eps_ns;
+        q.r_in = kd->r_in_ns;
+        q.r_out = kd->r_out_ns;
+    }
+    return q;
+}
+
 /* Hard force, jerk and potential on particle i from its list, at the given
  * positions and velocities ([n][3] row-major). */
-static void hard_one(int64_t i, const double *pos, const double *vel, const double *mass,
-                     const int64_t *off, const int32_t *idx, double eps, double r_in,
-                     double r_out, double a[3], double jk[3], double *phi)
+static void hard_one(int64_t n, const or_kinds *kd, int64_t i, const double *pos,
+                     const double *vel, const double *mass, const int64_t *off,
+                     const int32_t *idx, double eps0, double r_in0, double r_out0, double a[3],
+                     double jk[3], double *phi)
 {
-    const double gam = r_in / r_out;
     a[0] = a[1] = a[2] = 0.0;
     jk[0] = jk[1] = jk[2] = 0.0;
     double p = 0.0;
     for (int64_t e = off[i]; e < off[i + 1]; ++e) {
         const int64_t j = idx[e];
+        const or_pair q = pair_of(n, kd, i, j, eps0, r_in0, r_out0);
+        const double eps = q.eps, r_out = q.r_out, gam = q.r_in / q.r_out;
         const double dx = pos[3 * j] - pos[3 * i];
         const double dy = pos[3 * j + 1] - pos[3 * i + 1];
         const double dz = pos[3 * j + 2] - pos[3 * i + 2];
@@ -86,9 +126,10 @@ static void hard_one(int64_t i, const double *pos, const double *vel, const doub
         const double s2 = dx * dx + dy * dy + dz * dz + eps * eps;
         const double s = sqrt(s2);
         const double y = s / r_out;
-        const double K = or_K(y, gam);
-        const double Ks = or_dK(y, gam) / r_out;          /* dK/ds */
-        const double W = or_W(y, gam);
+        /* a pair that is not split is wholly hard: K = W = 0 */
+        const double K = q.split ? or_K(y, gam) : 0.0;
+        const double Ks = q.split ? or_dK(y, gam) / r_out : 0.0;   /* dK/ds */
+        const double W = q.split ? or_W(y, gam) : 0.0;
         const double mj = mass[j];
         const double inv_s3 = 1.0 / (s2 * s);
         const double rv = dx * vx + dy * vy + dz * vz;
@@ -108,11 +149,11 @@ static void hard_one(int64_t i, const double *pos, const double *vel, const doub
 
 int or_hard_force(int64_t n, const double *pos, const double *vel, const double *mass,
                   const int64_t *off, const int32_t *idx, double eps, double r_in, double r_out,
-                  double *acc, double *jerk, double *pot)
+                  const or_kinds *kd, double *acc, double *jerk, double *pot)
 {
     for (int64_t i = 0; i < n; ++i)
-        hard_one(i, pos, vel, mass, off, idx, eps, r_in, r_out, acc + 3 * i, jerk + 3 * i,
-                 pot ? pot + i : NULL);
+        hard_one(n, kd, i, pos, vel, mass, off, idx, eps, r_in, r_out, acc + 3 * i,
+                 jerk + 3 * i, pot ? pot + i : NULL);
     return 0;
 }
 
@@ -122,21 +163,22 @@ static double norm3(const double *v) { return sqrt(v[0] * v[0] + v[1] * v[1] + v
  * denominator read as |a^(1)| |a^(3)|: as printed, |a^(0)| |a^(3)| would not
  * have the units of the other terms (a^2 / time^4). */
 static double crit_full(const double *a, const double *j, const double *a2, const double *a3,
-                        const or_hermite_params *hp)
+                        const or_hermite_params *hp, double eta)
 {
     const double na = norm3(a), nj = norm3(j), n2 = norm3(a2), n3 = norm3(a3);
     const double num = sqrt(na * na + hp->a0 * hp->a0) * n2 + nj * nj;
     const double den = nj * n3 + n2 * n2;
     if (den == 0.0) return hp->dt_max;
-    return hp->eta * sqrt(num / den);
+    return eta * sqrt(num / den);
 }
 
 /* First-step criterion (Section 2.1, with eta_s). */
-static double crit_first(const double *a, const double *j, const or_hermite_params *hp)
+static double crit_first(const double *a, const double *j, const or_hermite_params *hp,
+                         double eta_s)
 {
     const double na = norm3(a), nj = norm3(j);
     if (nj == 0.0) return hp->dt_max;
-    return hp->eta_s * sqrt((na * na + hp->a0 * hp->a0) / (nj * nj));
+    return eta_s * sqrt((na * na + hp->a0 * hp->a0) / (nj * nj));
 }
 
 /*
@@ -146,8 +188,10 @@ static double crit_first(const double *a, const double *j, const or_hermite_para
  */
 int or_hermite(int64_t n, double *pos, double *vel, const double *mass, const int64_t *off,
                const int32_t *idx, double eps, double r_in, double r_out,
-               const or_hermite_params *hp, int32_t *nsteps, int64_t *n_block_steps)
+               const or_hermite_params *hp, const or_kinds *kd, int32_t *nsteps,
+               int64_t *n_block_steps)
 {
+    const int64_t first_sp = kd ? n - kd->n_special : n;
     if (!(hp->dt_soft > 0.0) || !(hp->dt_max > 0.0) || hp->dt_max > hp->dt_soft ||
         fmod(hp->dt_soft, hp->dt_max) != 0.0)
         return -1;
@@ -180,8 +224,10 @@ int or_hermite(int64_t n, double *pos, double *vel, const double *mass, const in
     /* initial force, jerk and timestep */
     for (int64_t i = 0; i < n; ++i) {
         if (!hard[i]) continue;
-        hard_one(i, pos, vel, mass, off, idx, eps, r_in, r_out, a + 3 * i, jk + 3 * i, NULL);
-        const double c = crit_first(a + 3 * i, jk + 3 * i, hp);
+        hard_one(n, kd, i, pos, vel, mass, off, idx, eps, r_in, r_out, a + 3 * i, jk + 3 * i,
+                 NULL);
+        const double c = crit_first(a + 3 * i, jk + 3 * i, hp,
+                                    i >= first_sp ? kd->eta_s_sp : hp->eta_s);
         double d = hp->dt_max;
         while (d > c && d > dt_min) d *= 0.5;
         dt[i] = d;
@@ -206,8 +252,8 @@ int or_hermite(int64_t n, double *pos, double *vel, const double *mass, const in
         /* forces of the active particles from the predicted states */
         for (int64_t i = 0; i < n; ++i)
             if (hard[i] && t[i] + dt[i] == t_next)
-                hard_one(i, xp, vp, mass, off, idx, eps, r_in, r_out, a1 + 3 * i, j1 + 3 * i,
-                         NULL);
+                hard_one(n, kd, i, xp, vp, mass, off, idx, eps, r_in, r_out, a1 + 3 * i,
+                         j1 + 3 * i, NULL);
         /* correct them and choose their next timesteps */
         for (int64_t i = 0; i < n; ++i) {
             if (!(hard[i] && t[i] + dt[i] == t_next)) continue;
@@ -225,7 +271,8 @@ int or_hermite(int64_t n, double *pos, double *vel, const double *mass, const in
             }
             t[i] = t_next;
             nsteps[i] += 1;
-            const double c = crit_full(a + 3 * i, jk + 3 * i, a2 + 3 * i, a3 + 3 * i, hp);
+            const double c = crit_full(a + 3 * i, jk + 3 * i, a2 + 3 * i, a3 + 3 * i, hp,
+                                       i >= first_sp ? kd->eta_sp : hp->eta);
             double d = h;
             if (2.0 * d <= c && 2.0 * d <= hp->dt_max && fmod(t[i], 2.0 * d) == 0.0)
                 d = 2.0 * d;
