@@ -149,6 +149,45 @@ int p3t_long_force_vjp(p3t_ctx *ctx, const double *w, const double *c, double *g
 int p3t_kick_drift(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const double *acc,
                    double dt_kick, double dt_drift);
 
+/* Particle kinds (Section 3.3, the SMBH runs): the last n_special particles
+ * of the arrays are special.  A normal-special pair takes its own cutoffs,
+ * softening and neighbour radius; a special-special pair its own softening and,
+ * with split_ss = 0, no soft part at all (K = W = 0: the pair is integrated
+ * wholly by Hermite, and two special particles are always neighbours); special
+ * particles take their own Hermite accuracy parameters.  The tree covers the
+ * normal particles only; a NULL p3t_kinds or n_special = 0 means one kind.
+ *   r_in_ns < r_out_ns, r_search_ns > 0, eps_ns >= 0
+ *   split_ss 0 or 1; with 1: r_in_ss < r_out_ss, r_search_ss > 0; eps_ss >= 0
+ *   eta_sp, eta_s_sp > 0 */
+typedef struct {
+    int64_t n_special;
+    double r_in_ns, r_out_ns, r_search_ns, eps_ns;
+    int32_t split_ss;
+    double r_in_ss, r_out_ss, r_search_ss, eps_ss;
+    double eta_sp, eta_s_sp;
+} p3t_kinds;
+
+/* Soft force and potential of every pair that involves a special particle
+ * (each pair with its own parameters), O(n n_special): ADDED to the rows of the
+ * normal particles (which hold the tree's sum over normal pairs) and WRITTEN
+ * to the rows of the special particles.
+ *   pos device [n][3]; mass device [n]; acc device [n][3] in/out; pot device
+ *   [n] in/out or NULL.  Errors: EINVAL, EHIP. */
+int p3t_kinds_soft(p3t_ctx *ctx, int64_t n, const double *pos, const double *mass,
+                   const p3t_params *p, const p3t_kinds *kinds, double *acc, double *pot);
+
+/* Neighbour lists of all n particles with a radius per kind of pair: a normal
+ * particle's row is its row of the normal lists (nn_off, nn_idx over the first
+ * n - n_special particles, as p3t_neighbors writes them) followed by the
+ * special particles within r_search_ns; a special particle's row lists the
+ * normal particles within r_search_ns and the other special particles (all of
+ * them when split_ss = 0, else those within r_search_ss); rows ascending.
+ *   off device [n+1] int64 out; idx device [cap] int32 out; nnz host out (set
+ *   also on ECAPACITY).  Synchronises.  Errors: EINVAL, ECAPACITY, ENOMEM, EHIP. */
+int p3t_kinds_neighbors(p3t_ctx *ctx, int64_t n, const double *pos, const p3t_kinds *kinds,
+                        const int64_t *nn_off, const int32_t *nn_idx, int64_t *off,
+                        int32_t *idx, int64_t cap, int64_t *nnz);
+
 /* ---- Hard part (Section 2.1: H_hard; Section 2.2: evaluated over the
  * neighbour lists).  Neighbour lists are CSR in original indices, as
  * p3t_neighbors writes them: offsets device [n+1] int64, idx device
@@ -160,13 +199,15 @@ int p3t_kick_drift(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const doub
  *   a_i    = sum_j m_j (1 - K(s)) d / s^3,   d = x_j - x_i, v = v_j - v_i
  *   jerk_i = sum_j m_j [(1 - K)(v - 3 (d.v) d / s^2) / s^3 - K'(s) ((d.v)/s) d / s^3]
  *   phi_i  = -sum_j m_j (1 - W(s)) / s
- * in FP64, summed in list order.  Uses eps, r_in, r_out of *p.
+ * in FP64, summed in list order.  Uses eps, r_in, r_out of *p for pairs of
+ * normal particles and *kinds (or NULL) for pairs with a special particle.
  *   pos, vel device [n][3]; mass device [n]; acc, jerk device [n][3] out;
  *   pot device [n] out or NULL.  Isolated particles (empty rows) get zeros.
  * Synchronises the stream (list check).  Errors: EINVAL, ENOMEM, EHIP. */
 int p3t_hard_force(p3t_ctx *ctx, int64_t n, const double *pos, const double *vel,
                    const double *mass, const int64_t *offsets, const int32_t *idx,
-                   const p3t_params *p, double *acc, double *jerk, double *pot);
+                   const p3t_params *p, const p3t_kinds *kinds, double *acc, double *jerk,
+                   double *pot);
 
 /* Parameters of the Hermite integration of H_hard (Section 2.1).
  *   dt_soft  the soft step, integrated over (> 0, a whole multiple of dt_max)
@@ -206,21 +247,25 @@ typedef struct {
  * Synchronises the stream.  Errors: EINVAL, ENOMEM, ELIMIT, EHIP. */
 int p3t_hermite_hard(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const double *mass,
                      const int64_t *offsets, const int32_t *idx, const p3t_params *p,
-                     const p3t_hermite_params *hp, int32_t *nsteps, p3t_hermite_stats *stats);
+                     const p3t_kinds *kinds, const p3t_hermite_params *hp, int32_t *nsteps,
+                     p3t_hermite_stats *stats);
 
 /* One step of the P3T scheme (Section 2.2's GPU procedure), in place:
  * v += dt_soft/2 a_soft; neighbour lists of the current build; p3t_hermite_hard
  * over dt_soft; rebuild at the new positions; a_soft (and the soft potential
  * if pot is not NULL) at the new positions into acc; v += dt_soft/2 a_soft.
- * On entry the context must hold a build of these n particles at the current
- * positions and acc their soft acceleration (p3t_build_tree + p3t_long_force);
- * on return both hold for the new positions, so steps chain.
+ * On entry the context must hold a build of the normal particles (all n, or
+ * the first n - n_special with kinds) at the current positions and acc their
+ * soft acceleration (p3t_build_tree + p3t_long_force, + p3t_kinds_soft with
+ * kinds); on return both hold for the new positions, so steps chain.  With
+ * kinds the neighbour lists are merged by p3t_kinds_neighbors and the hard
+ * part and soft sums take each pair's own parameters.
  *   pos, vel device [n][3]; mass device [n]; acc device [n][3] in/out;
  *   pot device [n] out or NULL; stats: the hard part's, host out or NULL.
  * Errors: ESTATE, EINVAL, ENOMEM, ELIMIT, EHIP. */
 int p3t_step(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const double *mass, double *acc,
-             double *pot, const p3t_params *p, const p3t_hermite_params *hp,
-             p3t_hermite_stats *stats);
+             double *pot, const p3t_params *p, const p3t_kinds *kinds,
+             const p3t_hermite_params *hp, p3t_hermite_stats *stats);
 
 /* ---- Direct summation (the exact sums the tree approximates; for energies
  * and diagnostics).  For every particle i, over all j != i, in FP64:

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libp3t.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["p3t_api.hip", "scan.hip", "tree.hip", "walk.hip", "force.hip", "neighbors.hip", "vjp.hip", "hard.hip", "direct.hip"]
+SOURCES = ["p3t_api.hip", "scan.hip", "tree.hip", "walk.hip", "force.hip", "neighbors.hip", "vjp.hip", "hard.hip", "direct.hip", "kinds.hip"]
 ARCH = os.environ.get("P3T_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",

@@ -52,13 +52,26 @@ constexpr int kHermThreads = 1024;   // the global-memory kernel for components 
 constexpr int kMaxDtLevel = 40;
 constexpr int kUnionTries = 1 << 20;
 
-struct HardConsts {
-    double eps, r_in, r_out;
+// parameters of one kind of pair: 0 normal-normal, 1 normal-special,
+// 2 special-special (the last particles of the arrays may be special)
+struct PairKind {
+    double eps, r_in, r_out, gam;
     double C, G1;          // W/y below r_in, G(1) of the changeover region
+    int split;             // 0: the pair is wholly hard (K = W = 0)
 };
+
+struct HardConsts {
+    PairKind k[3];
+    int64_t first_sp;      // particles from here on are special (n when there are none)
+};
+
+__device__ inline PairKind pair_kind(const HardConsts &hc, bool si, bool sj) {
+    return (si && sj) ? hc.k[2] : (si || sj) ? hc.k[1] : hc.k[0];
+}
 
 struct HermConsts {
     double t_end, dt_max, dt_min, eta, eta_s, a0;
+    double eta_sp, eta_s_sp;   // accuracy parameters of special particles
     int64_t max_block_steps;
 };
 
@@ -110,10 +123,10 @@ static double hk_C(double g) {
            (3.0 * gm7);
 }
 
-__device__ inline double hk_W(double y, double gam, const HardConsts &hc) {
-    if (y < gam) return hc.C * y;
+__device__ inline double hk_W(double y, const PairKind &q) {
+    if (y < q.gam) return q.C * y;
     if (y >= 1.0) return 1.0;
-    return hk_G(y, gam) + (1.0 - hc.G1) * y;
+    return hk_G(y, q.gam) + (1.0 - q.G1) * y;
 }
 
 // Hard force, jerk (and potential if POT) on i from its list at positions x and
@@ -125,14 +138,15 @@ __device__ inline void hard_sum(int64_t i, int64_t si, const double *__restrict_
                                 const int64_t *__restrict__ off, const int32_t *__restrict__ idx,
                                 const int32_t *__restrict__ map, const HardConsts &hc,
                                 double a[3], double jk[3], double *phi) {
-    const double gam = hc.r_in / hc.r_out;
     a[0] = a[1] = a[2] = 0.0;
     jk[0] = jk[1] = jk[2] = 0.0;
     double p = 0.0;
     const double xi = x[3 * si], yi = x[3 * si + 1], zi = x[3 * si + 2];
     const double ui = v[3 * si], vi = v[3 * si + 1], wi = v[3 * si + 2];
+    const bool spi = i >= hc.first_sp;
     for (int64_t e = off[i]; e < off[i + 1]; ++e) {
         const int32_t j = idx[e];
+        const PairKind q = pair_kind(hc, spi, j >= hc.first_sp);
         const int64_t sj = MAP ? map[j] : j;
         const double dx = x[3 * sj] - xi;
         const double dy = x[3 * sj + 1] - yi;
@@ -140,11 +154,11 @@ __device__ inline void hard_sum(int64_t i, int64_t si, const double *__restrict_
         const double vx = v[3 * sj] - ui;
         const double vy = v[3 * sj + 1] - vi;
         const double vz = v[3 * sj + 2] - wi;
-        const double s2 = dx * dx + dy * dy + dz * dz + hc.eps * hc.eps;
+        const double s2 = dx * dx + dy * dy + dz * dz + q.eps * q.eps;
         const double s = sqrt(s2);
-        const double y = s / hc.r_out;
-        const double K = hk_K(y, gam);
-        const double Ks = hk_dK(y, gam) / hc.r_out;
+        const double y = s / q.r_out;
+        const double K = q.split ? hk_K(y, q.gam) : 0.0;
+        const double Ks = q.split ? hk_dK(y, q.gam) / q.r_out : 0.0;
         const double mj = mass[j];
         const double inv_s3 = 1.0 / (s2 * s);
         const double rv = dx * vx + dy * vy + dz * vz;
@@ -157,7 +171,7 @@ __device__ inline void hard_sum(int64_t i, int64_t si, const double *__restrict_
         jk[0] += f * (vx - c * dx) - g * dx;
         jk[1] += f * (vy - c * dy) - g * dy;
         jk[2] += f * (vz - c * dz) - g * dz;
-        if (POT) p -= mj * (1.0 - hk_W(y, gam, hc)) / s;
+        if (POT) p -= mj * (1.0 - (q.split ? hk_W(y, q) : 0.0)) / s;
     }
     if (POT) *phi = p;
 }
@@ -355,20 +369,21 @@ __device__ inline double norm3(const double *v) {
     return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
 }
 
-__device__ inline double crit_first(const double *a, const double *j, const HermConsts &hp) {
+__device__ inline double crit_first(const double *a, const double *j, const HermConsts &hp,
+                                    double eta_s) {
     const double na = norm3(a), nj = norm3(j);
     if (nj == 0.0) return hp.dt_max;
-    return hp.eta_s * sqrt((na * na + hp.a0 * hp.a0) / (nj * nj));
+    return eta_s * sqrt((na * na + hp.a0 * hp.a0) / (nj * nj));
 }
 
 // the denominator's first term is |a'| |a'''| (the form with matching units)
 __device__ inline double crit_full(const double *a, const double *j, const double *a2,
-                                   const double *a3, const HermConsts &hp) {
+                                   const double *a3, const HermConsts &hp, double eta) {
     const double na = norm3(a), nj = norm3(j), n2 = norm3(a2), n3 = norm3(a3);
     const double num = sqrt(na * na + hp.a0 * hp.a0) * n2 + nj * nj;
     const double den = nj * n3 + n2 * n2;
     if (den == 0.0) return hp.dt_max;
-    return hp.eta * sqrt(num / den);
+    return eta * sqrt(num / den);
 }
 
 __device__ inline double block_min(double v, double *s_red) {
@@ -407,7 +422,8 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite_cluster(
         double dummy;
         hard_sum<false, true>(mem[s], s, S.x, S.v, mass, off, idx, slot, hc, S.a + 3 * s,
                               S.j + 3 * s, &dummy);
-        const double cr = crit_first(S.a + 3 * s, S.j + 3 * s, hp);
+        const double cr = crit_first(S.a + 3 * s, S.j + 3 * s, hp,
+                                     mem[s] >= hc.first_sp ? hp.eta_s_sp : hp.eta_s);
         double d = hp.dt_max;
         while (d > cr && d > hp.dt_min) d *= 0.5;
         S.dt[s] = d;
@@ -461,7 +477,8 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite_cluster(
             }
             S.t[s] = t_next;
             S.ns[s] += 1;
-            const double cr = crit_full(S.a + 3 * s, S.j + 3 * s, S.a2 + 3 * s, S.a3 + 3 * s, hp);
+            const double cr = crit_full(S.a + 3 * s, S.j + 3 * s, S.a2 + 3 * s, S.a3 + 3 * s, hp,
+                                        mem[s] >= hc.first_sp ? hp.eta_sp : hp.eta);
             double d = h;
             if (2.0 * d <= cr && 2.0 * d <= hp.dt_max && fmod(S.t[s], 2.0 * d) == 0.0)
                 d = 2.0 * d;
@@ -516,19 +533,20 @@ __global__ void k_hard_local(int64_t n, const int64_t *__restrict__ off,
 // The six summands one list entry adds to a and jerk, by the operations of
 // hard_sum: member k's predicted state against neighbour jl, both local.
 __device__ inline void pair_terms(int k, int jl, const double *xs, const double *vs,
-                                  const double *sm, const HardConsts &hc, double gam,
+                                  const double *sm, const int8_t *ssp, const HardConsts &hc,
                                   double o[6]) {
+    const PairKind q = pair_kind(hc, ssp[k] != 0, ssp[jl] != 0);
     const double dx = xs[3 * jl] - xs[3 * k];
     const double dy = xs[3 * jl + 1] - xs[3 * k + 1];
     const double dz = xs[3 * jl + 2] - xs[3 * k + 2];
     const double vx = vs[3 * jl] - vs[3 * k];
     const double vy = vs[3 * jl + 1] - vs[3 * k + 1];
     const double vz = vs[3 * jl + 2] - vs[3 * k + 2];
-    const double s2 = dx * dx + dy * dy + dz * dz + hc.eps * hc.eps;
+    const double s2 = dx * dx + dy * dy + dz * dz + q.eps * q.eps;
     const double s = sqrt(s2);
-    const double y = s / hc.r_out;
-    const double K = hk_K(y, gam);
-    const double Ks = hk_dK(y, gam) / hc.r_out;
+    const double y = s / q.r_out;
+    const double K = q.split ? hk_K(y, q.gam) : 0.0;
+    const double Ks = q.split ? hk_dK(y, q.gam) / q.r_out : 0.0;
     const double mj = sm[jl];
     const double inv_s3 = 1.0 / (s2 * s);
     const double rv = dx * vx + dy * vy + dz * vz;
@@ -546,14 +564,14 @@ __device__ inline void pair_terms(int k, int jl, const double *xs, const double 
 // hard_sum on a component held in LDS: member k's predicted state, neighbours
 // through local indices nb[rb .. re), masses from sm, summed in list order.
 __device__ inline void hard_sum_local(int k, const double *xs, const double *vs, const double *sm,
-                                      const int32_t *nb, int64_t rb, int64_t re,
-                                      const HardConsts &hc, double a[3], double jk[3]) {
-    const double gam = hc.r_in / hc.r_out;
+                                      const int8_t *ssp, const int32_t *nb, int64_t rb,
+                                      int64_t re, const HardConsts &hc, double a[3],
+                                      double jk[3]) {
     a[0] = a[1] = a[2] = 0.0;
     jk[0] = jk[1] = jk[2] = 0.0;
     for (int64_t e = rb; e < re; ++e) {
         double o[6];
-        pair_terms(k, nb[e], xs, vs, sm, hc, gam, o);
+        pair_terms(k, nb[e], xs, vs, sm, ssp, hc, o);
         a[0] += o[0];
         a[1] += o[1];
         a[2] += o[2];
@@ -625,7 +643,7 @@ __global__ __launch_bounds__(T) void k_hermite_lds(
     __shared__ double s_term[C > 0 ? 6 * C : 1];
     __shared__ int s_ws[T / 64];
     __shared__ double s_red[T / 64];
-    const double gam = hc.r_in / hc.r_out;
+    __shared__ int8_t s_sp[M];   // 1: special particle
     const int c = order[order_base + blockIdx.x];
     const int b = cl_beg[c], nm = cl_end[c] - b;
     const int tid = threadIdx.x;
@@ -633,6 +651,7 @@ __global__ __launch_bounds__(T) void k_hermite_lds(
         const int32_t i = mem[b + k];
         s_row[k + 1] = (int32_t)(off[i + 1] - off[i]);
         s_m[k] = mass[i];
+        s_sp[k] = i >= hc.first_sp;
     }
     __syncthreads();
     if (tid == 0) {
@@ -680,8 +699,8 @@ __global__ __launch_bounds__(T) void k_hermite_lds(
         if (k >= nm) continue;
         const int64_t rowb = in_lds ? (int64_t)s_row[k] : e0[r];
         const int64_t rowe = rowb + (s_row[k + 1] - s_row[k]);
-        hard_sum_local(k, s_xp, s_vp, s_m, nbp, rowb, rowe, hc, a[r], jk[r]);
-        const double cr = crit_first(a[r], jk[r], hp);
+        hard_sum_local(k, s_xp, s_vp, s_m, s_sp, nbp, rowb, rowe, hc, a[r], jk[r]);
+        const double cr = crit_first(a[r], jk[r], hp, s_sp[k] ? hp.eta_s_sp : hp.eta_s);
         double d = hp.dt_max;
         while (d > cr && d > hp.dt_min) d *= 0.5;
         dt[r] = d;
@@ -741,7 +760,7 @@ __global__ __launch_bounds__(T) void k_hermite_lds(
                 const int c1 = min(c0 + C, n_act);
                 for (int e = c0 + tid; e < c1; e += T) {
                     double o[6];
-                    pair_terms(s_aown[e], s_nb[s_ae[e]], s_xp, s_vp, s_m, hc, gam, o);
+                    pair_terms(s_aown[e], s_nb[s_ae[e]], s_xp, s_vp, s_m, s_sp, hc, o);
                     for (int q = 0; q < 6; ++q) s_term[6 * (e - c0) + q] = o[q];
                 }
                 __syncthreads();
@@ -768,7 +787,7 @@ __global__ __launch_bounds__(T) void k_hermite_lds(
                 if (k >= nm || t[r] + dt[r] != t_next) continue;
                 const int64_t rowb = in_lds ? (int64_t)s_row[k] : e0[r];
                 const int64_t rowe = rowb + (s_row[k + 1] - s_row[k]);
-                hard_sum_local(k, s_xp, s_vp, s_m, nbp, rowb, rowe, hc, a1[r], j1[r]);
+                hard_sum_local(k, s_xp, s_vp, s_m, s_sp, nbp, rowb, rowe, hc, a1[r], j1[r]);
             }
         }
 #pragma unroll
@@ -792,7 +811,7 @@ __global__ __launch_bounds__(T) void k_hermite_lds(
             }
             t[r] = t_next;
             ns[r] += 1;
-            const double cr = crit_full(a[r], jk[r], a2, a3, hp);
+            const double cr = crit_full(a[r], jk[r], a2, a3, hp, s_sp[k] ? hp.eta_sp : hp.eta);
             double d = h;
             if (2.0 * d <= cr && 2.0 * d <= hp.dt_max && fmod(t[r], 2.0 * d) == 0.0)
                 d = 2.0 * d;
@@ -822,14 +841,29 @@ __global__ __launch_bounds__(T) void k_hermite_lds(
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
-static HardConsts hard_consts(const p3t_params *p) {
+static PairKind pair_kind_of(double eps, double r_in, double r_out, int split) {
+    PairKind q;
+    q.eps = eps;
+    q.r_in = r_in;
+    q.r_out = r_out;
+    q.gam = r_in / r_out;
+    q.C = q.gam > 0.0 ? hk_C(q.gam) : 7.0 / 3.0;
+    q.G1 = hk_G(1.0, q.gam);
+    q.split = split;
+    return q;
+}
+
+static HardConsts hard_consts(const p3t_params *p, const p3t_kinds *kd, int64_t n) {
     HardConsts hc;
-    hc.eps = p->eps;
-    hc.r_in = p->r_in;
-    hc.r_out = p->r_out;
-    const double gam = p->r_in / p->r_out;
-    hc.C = gam > 0.0 ? hk_C(gam) : 7.0 / 3.0;
-    hc.G1 = hk_G(1.0, gam);
+    hc.k[0] = pair_kind_of(p->eps, p->r_in, p->r_out, 1);
+    if (kd && kd->n_special > 0) {
+        hc.k[1] = pair_kind_of(kd->eps_ns, kd->r_in_ns, kd->r_out_ns, 1);
+        hc.k[2] = pair_kind_of(kd->eps_ss, kd->r_in_ss, kd->r_out_ss, kd->split_ss);
+        hc.first_sp = n - kd->n_special;
+    } else {
+        hc.k[1] = hc.k[2] = hc.k[0];
+        hc.first_sp = n;
+    }
     return hc;
 }
 
@@ -872,11 +906,12 @@ static int aux_streams(p3t_ctx *ctx) {
 
 int launch_hard_force(p3t_ctx *ctx, int64_t n, const double *pos, const double *vel,
                       const double *mass, const int64_t *off, const int32_t *idx,
-                      const p3t_params *p, double *acc, double *jerk, double *pot) {
+                      const p3t_params *p, const p3t_kinds *kd, double *acc, double *jerk,
+                      double *pot) {
     int rc;
     if ((rc = ensure(ctx, ctx->readback, 64 * sizeof(int64_t)))) return rc;
     if ((rc = validate_lists(ctx, n, off, idx))) return rc;
-    const HardConsts hc = hard_consts(p);
+    const HardConsts hc = hard_consts(p, kd, n);
     k_hard_force<<<blocks_for(n, kHardThreads), kHardThreads, 0, ctx->stream>>>(
         n, pos, vel, mass, off, idx, hc, acc, jerk, pot);
     return check_hip(ctx, hipGetLastError(), "hard force");
@@ -884,7 +919,8 @@ int launch_hard_force(p3t_ctx *ctx, int64_t n, const double *pos, const double *
 
 int launch_hermite(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const double *mass,
                    const int64_t *off, const int32_t *idx, const p3t_params *p,
-                   const p3t_hermite_params *hpar, int32_t *nsteps, p3t_hermite_stats *stats) {
+                   const p3t_kinds *kd, const p3t_hermite_params *hpar, int32_t *nsteps,
+                   p3t_hermite_stats *stats) {
     int rc;
     hipStream_t st = ctx->stream;
     if ((rc = ensure(ctx, ctx->readback, 64 * sizeof(int64_t)))) return rc;
@@ -965,8 +1001,11 @@ int launch_hermite(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const doub
         hc2.eta = hpar->eta;
         hc2.eta_s = hpar->eta_s;
         hc2.a0 = hpar->a0;
+        const bool sp = kd && kd->n_special > 0;
+        hc2.eta_sp = sp ? kd->eta_sp : hpar->eta;
+        hc2.eta_s_sp = sp ? kd->eta_s_sp : hpar->eta_s;
         hc2.max_block_steps = hpar->max_block_steps > 0 ? hpar->max_block_steps : (1LL << 26);
-        const HardConsts hk = hard_consts(p);
+        const HardConsts hk = hard_consts(p, kd, n);
         unsigned long long *rbh = reinterpret_cast<unsigned long long *>(rb + RB_HBAD);
         // fork: the three LDS classes on their own streams, the largest
         // components on the context stream

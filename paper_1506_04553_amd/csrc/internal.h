@@ -113,6 +113,8 @@ struct p3t_ctx {
     hipEvent_t aev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     int aux_ready = 0;
     p3t::DevBuf step_off, step_idx;    // neighbour CSR of p3t_step
+    p3t::DevBuf step_off2, step_idx2;  // ... merged with the special particles' pairs
+    p3t::DevBuf kinds_cnt;
 };
 
 namespace p3t {
@@ -152,10 +154,20 @@ int launch_vjp(p3t_ctx *ctx, const double *w, const double *c, double *gpos, dou
 // integration over one soft step.
 int launch_hard_force(p3t_ctx *ctx, int64_t n, const double *pos, const double *vel,
                       const double *mass, const int64_t *off, const int32_t *idx,
-                      const p3t_params *p, double *acc, double *jerk, double *pot);
+                      const p3t_params *p, const p3t_kinds *kd, double *acc, double *jerk,
+                      double *pot);
 int launch_hermite(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const double *mass,
                    const int64_t *off, const int32_t *idx, const p3t_params *p,
-                   const p3t_hermite_params *hp, int32_t *nsteps, p3t_hermite_stats *stats);
+                   const p3t_kinds *kd, const p3t_hermite_params *hp, int32_t *nsteps,
+                   p3t_hermite_stats *stats);
+
+// Particle kinds (kinds.hip): soft sums of the pairs with a special particle,
+// and the neighbour lists of all particles with a radius per kind of pair.
+int launch_kinds_soft(p3t_ctx *ctx, int64_t n, const double *pos, const double *mass,
+                      const p3t_params *p, const p3t_kinds *kd, double *acc, double *pot);
+int launch_kinds_neighbors(p3t_ctx *ctx, int64_t n, const double *pos, const p3t_kinds *kd,
+                           const int64_t *nn_off, const int32_t *nn_idx, int64_t *off,
+                           int32_t *idx, int64_t cap, int64_t *nnz);
 
 // Constants of K and W for gamma = r_in / r_out (p3t_api.hip).
 Changeover make_changeover(double r_in, double r_out);

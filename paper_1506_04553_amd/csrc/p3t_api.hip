@@ -158,7 +158,8 @@ extern "C" void p3t_destroy(p3t_ctx *ctx) {
                       &ctx->n_idx, &ctx->wstack, &ctx->dflags, &ctx->readback, &ctx->scan_tmp,
                       &ctx->nbr_cnt, &ctx->nbr_slots, &ctx->vjp_gx, &ctx->vjp_gm, &ctx->vjp_cell, &ctx->bbox,
                       &ctx->seg_end, &ctx->gorder, &ctx->grank, &ctx->ghist, &ctx->hard_ix,
-                      &ctx->hard_state, &ctx->step_off, &ctx->step_idx};
+                      &ctx->hard_state, &ctx->step_off, &ctx->step_idx, &ctx->step_off2,
+                      &ctx->step_idx2, &ctx->kinds_cnt};
     for (DevBuf *b : bufs) release(ctx, *b);
     if (ctx->hpin) (void)hipHostFree(ctx->hpin);
     for (int k = 0; k < 12; ++k)
@@ -279,63 +280,141 @@ static bool hermite_params_ok(const p3t_hermite_params *hp) {
     return hp->eta > 0.0 && hp->eta_s > 0.0 && hp->a0 >= 0.0 && hp->max_block_steps >= 0;
 }
 
+// particle kinds: NULL or n_special = 0 mean one kind
+static bool kinds_ok(const p3t_kinds *kd, int64_t n) {
+    if (!kd) return true;
+    if (kd->n_special < 0 || kd->n_special > n) return false;
+    if (kd->n_special == 0) return true;
+    const double v[10] = {kd->r_in_ns, kd->r_out_ns, kd->r_search_ns, kd->eps_ns, kd->r_in_ss,
+                          kd->r_out_ss, kd->r_search_ss, kd->eps_ss, kd->eta_sp, kd->eta_s_sp};
+    for (double d : v)
+        if (!isfinite(d)) return false;
+    if (kd->r_in_ns < 0.0 || !(kd->r_in_ns < kd->r_out_ns) || !(kd->r_search_ns > 0.0) ||
+        kd->eps_ns < 0.0 || kd->eps_ss < 0.0)
+        return false;
+    if (kd->split_ss != 0 && kd->split_ss != 1) return false;
+    if (kd->split_ss &&
+        (kd->r_in_ss < 0.0 || !(kd->r_in_ss < kd->r_out_ss) || !(kd->r_search_ss > 0.0)))
+        return false;
+    return kd->eta_sp > 0.0 && kd->eta_s_sp > 0.0;
+}
+
+static bool has_special(const p3t_kinds *kd) { return kd && kd->n_special > 0; }
+
 extern "C" int p3t_hard_force(p3t_ctx *ctx, int64_t n, const double *pos, const double *vel,
                               const double *mass, const int64_t *offsets, const int32_t *idx,
-                              const p3t_params *p, double *acc, double *jerk, double *pot) {
+                              const p3t_params *p, const p3t_kinds *kinds, double *acc,
+                              double *jerk, double *pot) {
     if (!ctx) return P3T_EINVAL;
     if (n < 1 || n > INT32_MAX || !pos || !vel || !mass || !offsets || !acc || !jerk ||
-        p3t_check_params(p) != P3T_OK)
+        p3t_check_params(p) != P3T_OK || !kinds_ok(kinds, n))
         return set_error(ctx, P3T_EINVAL, "bad hard-force arguments");
     int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
     if (rc) return rc;
-    return launch_hard_force(ctx, n, pos, vel, mass, offsets, idx, p, acc, jerk, pot);
+    return launch_hard_force(ctx, n, pos, vel, mass, offsets, idx, p, kinds, acc, jerk, pot);
 }
 
 extern "C" int p3t_hermite_hard(p3t_ctx *ctx, int64_t n, double *pos, double *vel,
                                 const double *mass, const int64_t *offsets, const int32_t *idx,
-                                const p3t_params *p, const p3t_hermite_params *hp,
-                                int32_t *nsteps, p3t_hermite_stats *stats) {
+                                const p3t_params *p, const p3t_kinds *kinds,
+                                const p3t_hermite_params *hp, int32_t *nsteps,
+                                p3t_hermite_stats *stats) {
     if (!ctx) return P3T_EINVAL;
     if (n < 1 || n > INT32_MAX || !pos || !vel || !mass || !offsets ||
-        p3t_check_params(p) != P3T_OK || !hermite_params_ok(hp))
+        p3t_check_params(p) != P3T_OK || !hermite_params_ok(hp) || !kinds_ok(kinds, n))
         return set_error(ctx, P3T_EINVAL, "bad Hermite arguments");
     int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
     if (rc) return rc;
-    return launch_hermite(ctx, n, pos, vel, mass, offsets, idx, p, hp, nsteps, stats);
+    return launch_hermite(ctx, n, pos, vel, mass, offsets, idx, p, kinds, hp, nsteps, stats);
+}
+
+extern "C" int p3t_kinds_soft(p3t_ctx *ctx, int64_t n, const double *pos, const double *mass,
+                              const p3t_params *p, const p3t_kinds *kinds, double *acc,
+                              double *pot) {
+    if (!ctx) return P3T_EINVAL;
+    if (n < 1 || !pos || !mass || !acc || p3t_check_params(p) != P3T_OK || !kinds_ok(kinds, n))
+        return set_error(ctx, P3T_EINVAL, "bad kinds-soft arguments");
+    int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
+    if (rc) return rc;
+    return launch_kinds_soft(ctx, n, pos, mass, p, kinds, acc, pot);
+}
+
+extern "C" int p3t_kinds_neighbors(p3t_ctx *ctx, int64_t n, const double *pos,
+                                   const p3t_kinds *kinds, const int64_t *nn_off,
+                                   const int32_t *nn_idx, int64_t *off, int32_t *idx, int64_t cap,
+                                   int64_t *nnz) {
+    if (!ctx) return P3T_EINVAL;
+    if (n < 1 || n > INT32_MAX || !pos || !kinds || !kinds_ok(kinds, n) || !nn_off || !off ||
+        !nnz || cap < 0 || (cap > 0 && !idx))
+        return set_error(ctx, P3T_EINVAL, "bad kinds-neighbour arguments");
+    int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
+    if (rc) return rc;
+    return launch_kinds_neighbors(ctx, n, pos, kinds, nn_off, nn_idx, off, idx, cap, nnz);
+}
+
+// neighbour lists of the current build into buf_off/buf_idx, grown as needed
+static int step_neighbors(p3t_ctx *ctx, int64_t n_rows, int64_t *nnz) {
+    int rc;
+    if ((rc = ensure(ctx, ctx->step_off, (size_t)(n_rows + 1) * sizeof(int64_t)))) return rc;
+    int64_t cap = (int64_t)(ctx->step_idx.bytes / sizeof(int32_t));
+    if (cap < 1) {
+        if ((rc = ensure(ctx, ctx->step_idx, (size_t)n_rows * sizeof(int32_t)))) return rc;
+        cap = (int64_t)(ctx->step_idx.bytes / sizeof(int32_t));
+    }
+    rc = launch_neighbors(ctx, ptr<int64_t>(ctx->step_off), ptr<int32_t>(ctx->step_idx), cap, nnz);
+    if (rc == P3T_ECAPACITY) {
+        if ((rc = ensure(ctx, ctx->step_idx, (size_t)*nnz * sizeof(int32_t)))) return rc;
+        rc = launch_neighbors(ctx, ptr<int64_t>(ctx->step_off), ptr<int32_t>(ctx->step_idx), *nnz,
+                              nnz);
+    }
+    return rc;
 }
 
 extern "C" int p3t_step(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const double *mass,
-                        double *acc, double *pot, const p3t_params *p,
+                        double *acc, double *pot, const p3t_params *p, const p3t_kinds *kinds,
                         const p3t_hermite_params *hp, p3t_hermite_stats *stats) {
     if (!ctx) return P3T_EINVAL;
-    if (!ctx->built || ctx->n != n)
-        return set_error(ctx, P3T_ESTATE, "p3t_step needs a build of these n particles");
-    if (!pos || !vel || !mass || !acc || p3t_check_params(p) != P3T_OK || !hermite_params_ok(hp))
+    if (!pos || !vel || !mass || !acc || p3t_check_params(p) != P3T_OK || !hermite_params_ok(hp) ||
+        n < 1 || !kinds_ok(kinds, n))
         return set_error(ctx, P3T_EINVAL, "bad step arguments");
+    const int64_t n_sp = has_special(kinds) ? kinds->n_special : 0, n_tree = n - n_sp;
+    if (!ctx->built || ctx->n != n_tree || n_tree < 1)
+        return set_error(ctx, P3T_ESTATE, "p3t_step needs a build of the normal particles");
     int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
     if (rc) return rc;
     const double half = 0.5 * hp->dt_soft;
     if ((rc = launch_kick_drift(ctx, n, pos, vel, acc, half, 0.0))) return rc;
-    // neighbour lists of the current build; grow the index buffer if needed
-    if ((rc = ensure(ctx, ctx->step_off, (size_t)(n + 1) * sizeof(int64_t)))) return rc;
-    int64_t cap = (int64_t)(ctx->step_idx.bytes / sizeof(int32_t)), nnz = 0;
-    if (cap < 1) {
-        if ((rc = ensure(ctx, ctx->step_idx, (size_t)n * sizeof(int32_t)))) return rc;
-        cap = n;
-    }
-    rc = launch_neighbors(ctx, ptr<int64_t>(ctx->step_off), ptr<int32_t>(ctx->step_idx), cap, &nnz);
-    if (rc == P3T_ECAPACITY) {
-        if ((rc = ensure(ctx, ctx->step_idx, (size_t)nnz * sizeof(int32_t)))) return rc;
-        rc = launch_neighbors(ctx, ptr<int64_t>(ctx->step_off), ptr<int32_t>(ctx->step_idx), nnz,
-                              &nnz);
-    }
-    if (rc) return rc;
+    int64_t nnz = 0;
+    if ((rc = step_neighbors(ctx, n_tree, &nnz))) return rc;
     ctx->nnz = nnz;
-    if ((rc = launch_hermite(ctx, n, pos, vel, mass, ptr<int64_t>(ctx->step_off),
-                             ptr<int32_t>(ctx->step_idx), p, hp, nullptr, stats)))
+    const int64_t *hoff = ptr<int64_t>(ctx->step_off);
+    const int32_t *hidx = ptr<int32_t>(ctx->step_idx);
+    if (n_sp > 0) {
+        // merge in the pairs with special particles
+        if ((rc = ensure(ctx, ctx->step_off2, (size_t)(n + 1) * sizeof(int64_t)))) return rc;
+        int64_t cap = (int64_t)(ctx->step_idx2.bytes / sizeof(int32_t));
+        if (cap < nnz + 1) {
+            if ((rc = ensure(ctx, ctx->step_idx2, (size_t)(nnz + 1) * sizeof(int32_t)))) return rc;
+            cap = (int64_t)(ctx->step_idx2.bytes / sizeof(int32_t));
+        }
+        int64_t tot = 0;
+        rc = launch_kinds_neighbors(ctx, n, pos, kinds, hoff, hidx, ptr<int64_t>(ctx->step_off2),
+                                    ptr<int32_t>(ctx->step_idx2), cap, &tot);
+        if (rc == P3T_ECAPACITY) {
+            if ((rc = ensure(ctx, ctx->step_idx2, (size_t)tot * sizeof(int32_t)))) return rc;
+            rc = launch_kinds_neighbors(ctx, n, pos, kinds, hoff, hidx,
+                                        ptr<int64_t>(ctx->step_off2), ptr<int32_t>(ctx->step_idx2),
+                                        tot, &tot);
+        }
+        if (rc) return rc;
+        hoff = ptr<int64_t>(ctx->step_off2);
+        hidx = ptr<int32_t>(ctx->step_idx2);
+    }
+    if ((rc = launch_hermite(ctx, n, pos, vel, mass, hoff, hidx, p, kinds, hp, nullptr, stats)))
         return rc;
-    if ((rc = p3t_build_tree(ctx, n, pos, mass, p))) return rc;
+    if ((rc = p3t_build_tree(ctx, n_tree, pos, mass, p))) return rc;
     if ((rc = p3t_long_force(ctx, acc, pot))) return rc;
+    if (n_sp > 0 && (rc = launch_kinds_soft(ctx, n, pos, mass, p, kinds, acc, pot))) return rc;
     return launch_kick_drift(ctx, n, pos, vel, acc, half, 0.0);
 }
 

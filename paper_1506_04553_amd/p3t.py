@@ -79,7 +79,8 @@ _lib = None
 EXPORTS = ("p3t_create", "p3t_destroy", "p3t_check_params", "p3t_build_tree", "p3t_long_force",
            "p3t_neighbors", "p3t_long_force_vjp", "p3t_kick_drift", "p3t_get_stats",
            "p3t_copy_array", "p3t_status_string", "p3t_last_error", "p3t_hard_force",
-           "p3t_hermite_hard", "p3t_step", "p3t_direct")
+           "p3t_hermite_hard", "p3t_step", "p3t_direct", "p3t_kinds_soft",
+           "p3t_kinds_neighbors")
 
 DIRECT_MODES = {"newton": 0, "soft": 1, "hard": 2}
 
@@ -87,6 +88,18 @@ DIRECT_MODES = {"newton": 0, "soft": 1, "hard": 2}
 class HermiteParams(C.Structure):
     _fields_ = [("dt_soft", C.c_double), ("dt_max", C.c_double), ("eta", C.c_double),
                 ("eta_s", C.c_double), ("a0", C.c_double), ("max_block_steps", C.c_int64)]
+
+
+class Kinds(C.Structure):
+    _fields_ = [("n_special", C.c_int64), ("r_in_ns", C.c_double), ("r_out_ns", C.c_double),
+                ("r_search_ns", C.c_double), ("eps_ns", C.c_double), ("split_ss", C.c_int32),
+                ("r_in_ss", C.c_double), ("r_out_ss", C.c_double), ("r_search_ss", C.c_double),
+                ("eps_ss", C.c_double), ("eta_sp", C.c_double), ("eta_s_sp", C.c_double)]
+
+
+def _kinds(kinds):
+    """None, or a dict of the p3t_kinds fields (missing ones 0)."""
+    return None if kinds is None else C.byref(Kinds(**kinds))
 
 
 class HermiteStats(C.Structure):
@@ -113,11 +126,15 @@ def load_library(path: str = LIB_PATH):
     L.p3t_long_force_vjp.argtypes = [V, V, V, V, V]
     L.p3t_kick_drift.argtypes = [V, C.c_int64, V, V, V, C.c_double, C.c_double]
     L.p3t_get_stats.argtypes = [V, C.POINTER(Stats)]
-    L.p3t_hard_force.argtypes = [V, C.c_int64, V, V, V, V, V, C.POINTER(Params), V, V, V]
-    L.p3t_hermite_hard.argtypes = [V, C.c_int64, V, V, V, V, V, C.POINTER(Params),
+    K = C.POINTER(Kinds)
+    L.p3t_hard_force.argtypes = [V, C.c_int64, V, V, V, V, V, C.POINTER(Params), K, V, V, V]
+    L.p3t_hermite_hard.argtypes = [V, C.c_int64, V, V, V, V, V, C.POINTER(Params), K,
                                    C.POINTER(HermiteParams), V, C.POINTER(HermiteStats)]
-    L.p3t_step.argtypes = [V, C.c_int64, V, V, V, V, V, C.POINTER(Params),
+    L.p3t_step.argtypes = [V, C.c_int64, V, V, V, V, V, C.POINTER(Params), K,
                            C.POINTER(HermiteParams), C.POINTER(HermiteStats)]
+    L.p3t_kinds_soft.argtypes = [V, C.c_int64, V, V, C.POINTER(Params), K, V, V]
+    L.p3t_kinds_neighbors.argtypes = [V, C.c_int64, V, K, V, V, V, V, C.c_int64,
+                                      C.POINTER(C.c_int64)]
     L.p3t_direct.argtypes = [V, C.c_int64, V, V, C.POINTER(Params), C.c_int, V, V]
     L.p3t_copy_array.argtypes = [V, C.c_int, V, C.c_int64]
     L.p3t_status_string.argtypes = [C.c_int]
@@ -284,13 +301,46 @@ class P3T:
                                        DIRECT_MODES[mode], _dptr(acc), _dptr(pot)))
         return acc, pot
 
+    # -- particle kinds -----------------------------------------------------
+    def kinds_soft(self, pos, mass, acc, pot, kinds: dict, **params):
+        """Add the soft pulls of pairs with a special particle (in place)."""
+        n = int(pos.shape[0])
+        self._tensor(pos, (n, 3), "pos")
+        self._tensor(mass, (n,), "mass")
+        self._tensor(acc, (n, 3), "acc")
+        if pot is not None:
+            self._tensor(pot, (n,), "pot")
+        p = make_params(**params)
+        self._check(self._L.p3t_kinds_soft(self._h, n, _dptr(pos), _dptr(mass), C.byref(p),
+                                           _kinds(kinds), _dptr(acc), _dptr(pot)))
+
+    def kinds_neighbors(self, pos, kinds: dict, nn_off, nn_idx, cap: int | None = None):
+        """Neighbour CSR of all particles, radius by kind of pair."""
+        n = int(pos.shape[0])
+        self._tensor(pos, (n, 3), "pos")
+        dev = torch.device("cuda", self.device)
+        off = torch.empty((n + 1,), dtype=torch.int64, device=dev)
+        cap = int(nn_idx.numel()) + 64 if cap is None else int(cap)
+        while True:
+            idx = torch.empty((max(cap, 1),), dtype=torch.int32, device=dev)
+            nnz = C.c_int64(0)
+            rc = self._L.p3t_kinds_neighbors(self._h, n, _dptr(pos), _kinds(kinds),
+                                             _dptr(nn_off), _dptr(nn_idx), _dptr(off), _dptr(idx),
+                                             cap, C.byref(nnz))
+            if rc == P3T_ECAPACITY:
+                cap = int(nnz.value)
+                continue
+            self._check(rc)
+            return off, idx[:nnz.value]
+
     # -- hard part ----------------------------------------------------------
     def _csr(self, n, offsets, idx):
         self._tensor(offsets, (n + 1,), "offsets", torch.int64)
         if idx.dtype != torch.int32 or not idx.is_cuda or not idx.is_contiguous():
             raise ValueError("idx must be a contiguous int32 device tensor")
 
-    def hard_force(self, pos, vel, mass, offsets, idx, want_pot: bool = True, **params):
+    def hard_force(self, pos, vel, mass, offsets, idx, want_pot: bool = True, kinds=None,
+                   **params):
         """(acc, jerk, pot) of the hard part over the neighbour CSR (FP64)."""
         n = int(pos.shape[0])
         for t, nm in ((pos, "pos"), (vel, "vel")):
@@ -303,8 +353,8 @@ class P3T:
         jerk = torch.empty((n, 3), dtype=torch.float64, device=dev)
         pot = torch.empty((n,), dtype=torch.float64, device=dev) if want_pot else None
         self._check(self._L.p3t_hard_force(self._h, n, _dptr(pos), _dptr(vel), _dptr(mass),
-                                           _dptr(offsets), _dptr(idx), C.byref(p), _dptr(acc),
-                                           _dptr(jerk), _dptr(pot)))
+                                           _dptr(offsets), _dptr(idx), C.byref(p), _kinds(kinds),
+                                           _dptr(acc), _dptr(jerk), _dptr(pot)))
         return acc, jerk, pot
 
     @staticmethod
@@ -313,7 +363,7 @@ class P3T:
                              float(eta / 10.0 if eta_s is None else eta_s), float(a0),
                              int(max_block_steps))
 
-    def hermite_hard(self, pos, vel, mass, offsets, idx, hermite: dict, **params):
+    def hermite_hard(self, pos, vel, mass, offsets, idx, hermite: dict, kinds=None, **params):
         """Advance H_hard over hermite['dt_soft'] in place; returns (steps per particle, stats)."""
         n = int(pos.shape[0])
         for t, nm in ((pos, "pos"), (vel, "vel")):
@@ -325,11 +375,12 @@ class P3T:
         nsteps = torch.empty((n,), dtype=torch.int32, device=torch.device("cuda", self.device))
         st = HermiteStats()
         self._check(self._L.p3t_hermite_hard(self._h, n, _dptr(pos), _dptr(vel), _dptr(mass),
-                                             _dptr(offsets), _dptr(idx), C.byref(p), C.byref(hp),
-                                             _dptr(nsteps), C.byref(st)))
+                                             _dptr(offsets), _dptr(idx), C.byref(p),
+                                             _kinds(kinds), C.byref(hp), _dptr(nsteps),
+                                             C.byref(st)))
         return nsteps, {k: getattr(st, k) for k, _ in HermiteStats._fields_}
 
-    def step(self, pos, vel, mass, acc, hermite: dict, pot=None, **params):
+    def step(self, pos, vel, mass, acc, hermite: dict, pot=None, kinds=None, **params):
         """One P3T step in place (the context must hold a build at pos and acc its
         soft acceleration); returns the hard part's statistics."""
         n = int(pos.shape[0])
@@ -342,7 +393,8 @@ class P3T:
         hp = self.hermite_params(**hermite)
         st = HermiteStats()
         self._check(self._L.p3t_step(self._h, n, _dptr(pos), _dptr(vel), _dptr(mass), _dptr(acc),
-                                     _dptr(pot), C.byref(p), C.byref(hp), C.byref(st)))
+                                     _dptr(pot), C.byref(p), _kinds(kinds), C.byref(hp),
+                                     C.byref(st)))
         self.build_id += 1
         self.params = p
         return {k: getattr(st, k) for k, _ in HermiteStats._fields_}

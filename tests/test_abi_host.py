@@ -73,10 +73,13 @@ def test_null_context_and_status_strings(lib):
     assert lib.p3t_get_stats(None, None) == -1
     assert lib.p3t_copy_array(None, 0, None, 0) == -1
     assert lib.p3t_kick_drift(None, 1, None, None, None, 0.0, 0.0) == -1
-    assert lib.p3t_hard_force(None, 1, None, None, None, None, None, None, None, None, None) == -1
-    assert lib.p3t_hermite_hard(None, 1, None, None, None, None, None, None, None, None,
+    assert lib.p3t_hard_force(None, 1, None, None, None, None, None, None, None, None, None,
+                              None) == -1
+    assert lib.p3t_hermite_hard(None, 1, None, None, None, None, None, None, None, None, None,
                                 None) == -1
-    assert lib.p3t_step(None, 1, None, None, None, None, None, None, None, None) == -1
+    assert lib.p3t_step(None, 1, None, None, None, None, None, None, None, None, None) == -1
+    assert lib.p3t_kinds_soft(None, 1, None, None, None, None, None, None) == -1
+    assert lib.p3t_kinds_neighbors(None, 1, None, None, None, None, None, None, 0, None) == -1
     assert lib.p3t_direct(None, 1, None, None, None, 0, None, None) == -1
     lib.p3t_destroy(None)
     assert lib.p3t_status_string(0) == b"ok"

@@ -1,0 +1,155 @@
+"""GPU particle kinds (Section 3.3, the SMBH runs) against the oracle: two
+SMBH particles of 1 % of the galaxy mass each at (+-0.5, 0, 0) with velocities
+(0, +-0.5, 0) in a Plummer galaxy; r_cut between field stars 1/256, between an
+SMBH and a field star 1/32; softening 1e-4 except between the SMBHs (none, and
+their force is not split); eta 0.1 for field stars, 0.03 for SMBHs.
+
+The soft sums with special particles are compared with the numpy definitions
+to 1e-12 of the Newton scale; the merged neighbour lists bit for bit; the hard
+force and the Hermite integration bit for bit against the oracle with kinds;
+a whole P3T step with kinds against the same step composed from oracle pieces.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from inputs import plummer
+from oracle import direct
+from tests.gpu_cases import log, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+R_NN, R_NS = 1.0 / 256, 1.0 / 32
+PARAMS = dict(eps=1e-4, r_in=0.1 * R_NN, r_out=R_NN, theta=0.4, r_search=1.1 * R_NN,
+              n_crit=64, n_leaf=16, precision="fp64")
+KINDS = dict(n_special=2, r_in_ns=0.1 * R_NS, r_out_ns=R_NS, r_search_ns=1.1 * R_NS,
+             eps_ns=1e-4, split_ss=0, r_in_ss=0.0, r_out_ss=1.0, r_search_ss=1.0, eps_ss=0.0,
+             eta_sp=0.03, eta_s_sp=0.003)
+ORACLE_KINDS = {k: v for k, v in KINDS.items() if k not in ("r_search_ns", "r_search_ss")}
+
+
+def _galaxy(n_fs=6000, seed=3):
+    c = plummer(n_fs, seed)
+    mtot = c.mass.sum()
+    pos = np.concatenate([c.pos, [[-0.5, 0.0, 0.0], [0.5, 0.0, 0.0]]])
+    vel = np.concatenate([c.vel, [[0.0, -0.5, 0.0], [0.0, 0.5, 0.0]]])
+    mass = np.concatenate([c.mass, [0.01 * mtot, 0.01 * mtot]])
+    # a few field stars close to each SMBH, so that their pairs reach every region of K
+    rng = np.random.default_rng(seed + 1)
+    for k, b in enumerate((-2, -1)):
+        pos[40 * k:40 * (k + 1)] = pos[b] + rng.normal(scale=0.02, size=(40, 3))
+    return pos, vel, mass
+
+
+def _dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return (t if dtype is None else t.to(dtype)).cuda()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1506_04553_amd import P3T
+    assert torch.cuda.is_available()
+    c = P3T(0)
+    yield c
+    c.close()
+
+
+def _hk(dt_soft=1.0 / 1024):
+    return dict(dt_soft=dt_soft, dt_max=dt_soft / 4, eta=0.1, eta_s=0.01,
+                a0=0.1 * 1.0 / 6000 / R_NN ** 2, max_block_steps=200000)
+
+
+def test_kinds_soft_matches_definition(ctx):
+    import torch
+    pos, _, mass = _galaxy()
+    n = len(mass)
+    acc = torch.zeros((n, 3), dtype=torch.float64, device="cuda")
+    pot = torch.zeros(n, dtype=torch.float64, device="cuda")
+    ctx.kinds_soft(_dev(pos), _dev(mass), acc, pot, KINDS, **PARAMS)
+    oa, op = direct.kinds_soft(pos, mass, PARAMS["eps"], PARAMS["r_in"], PARAMS["r_out"], KINDS)
+    na, npot = direct.newton_direct(pos, mass, 1e-4)
+    ea = np.sqrt(((acc.cpu().numpy() - oa) ** 2).sum() / (na ** 2).sum())
+    ep = np.sqrt(((pot.cpu().numpy() - op) ** 2).sum() / (npot ** 2).sum())
+    log(f"kinds soft: acc {ea:.1e} pot {ep:.1e}")
+    assert ea < 1e-12 and ep < 1e-12
+    # the special rows: their own soft pull from every other particle
+    assert rel_rms(acc.cpu().numpy()[-2:], oa[-2:]) < 1e-12
+
+
+def _merged_lists(ctx, pos, mass):
+    """GPU tree lists of the field stars merged with the SMBH pairs, and the
+    oracle's brute-force lists with a radius per kind of pair."""
+    n = len(pos)
+    ctx.build_tree(_dev(pos[:n - 2]), _dev(mass[:n - 2]), **PARAMS)
+    nn_off, nn_idx = ctx.neighbors()
+    off, idx = ctx.kinds_neighbors(_dev(pos), KINDS, nn_off, nn_idx)
+    ooff, oidx = direct.kinds_neighbors(pos, 2, PARAMS["r_search"], KINDS["r_search_ns"], 0, 0.0)
+    return off.cpu().numpy(), idx.cpu().numpy(), ooff, oidx
+
+
+def test_kinds_neighbors_bit_exact(ctx):
+    pos, _, mass = _galaxy()
+    off, idx, ooff, oidx = _merged_lists(ctx, pos, mass)
+    log(f"kinds lists: {len(idx)} entries; SMBH rows {np.diff(off)[-2:]}")
+    assert np.array_equal(off, ooff) and np.array_equal(idx, oidx)
+    assert np.diff(off)[-1] > 1 and np.diff(off)[-2] > 1
+
+
+def test_kinds_hard_force_and_hermite_bit_exact(ctx):
+    import torch
+    pos, vel, mass = _galaxy()
+    off, idx, _, _ = _merged_lists(ctx, pos, mass)
+    a, j, ph = ctx.hard_force(_dev(pos), _dev(vel), _dev(mass), _dev(off), _dev(idx),
+                              kinds=KINDS, **PARAMS)
+    oa, oj, oph = oracle.hard_force(pos, vel, mass, off, idx, PARAMS["eps"], PARAMS["r_in"],
+                                    PARAMS["r_out"], kinds=ORACLE_KINDS)
+    assert np.array_equal(a.cpu().numpy(), oa) and np.array_equal(j.cpu().numpy(), oj)
+    assert np.max(np.abs(ph.cpu().numpy() - oph)) <= 1e-14 * np.max(np.abs(oph))
+    hk = _hk()
+    x, v = _dev(pos), _dev(vel)
+    ns, st = ctx.hermite_hard(x, v, _dev(mass), _dev(off), _dev(idx), hk, kinds=KINDS, **PARAMS)
+    okw = {k: hk[k] for k in ("dt_soft", "dt_max", "eta", "eta_s", "a0")}
+    ox, ov, ons, _ = oracle.hermite(pos, vel, mass, off, idx, PARAMS["eps"], PARAMS["r_in"],
+                                    PARAMS["r_out"], **okw, kinds=ORACLE_KINDS)
+    log(f"kinds hermite: {st}; SMBH steps {ons[-2:]}")
+    assert np.array_equal(ns.cpu().numpy(), ons)
+    assert np.array_equal(x.cpu().numpy(), ox) and np.array_equal(v.cpu().numpy(), ov)
+
+
+def test_kinds_p3t_step_matches_oracle_composition(ctx):
+    import torch
+    pos0, vel0, mass = _galaxy()
+    n = len(mass)
+    hk = _hk()
+    pos, vel, m = _dev(pos0), _dev(vel0), _dev(mass)
+    ctx.build_tree(pos[:n - 2].contiguous(), m[:n - 2].contiguous(), **PARAMS)
+    acc = torch.zeros((n, 3), dtype=torch.float64, device="cuda")
+    a_tree, _ = ctx.long_force()
+    acc[:n - 2] = a_tree
+    ctx.kinds_soft(pos, m, acc, None, KINDS, **PARAMS)
+    st = ctx.step(pos, vel, m, acc, hk, kinds=KINDS, **PARAMS)
+    log(f"kinds p3t step: {st}")
+
+    def soft(x):
+        a, _ = oracle.Tree(x[:n - 2], mass[:n - 2], PARAMS).force()
+        ak, _ = direct.kinds_soft(x, mass, PARAMS["eps"], PARAMS["r_in"], PARAMS["r_out"], KINDS)
+        ak[:n - 2] += a
+        return ak
+
+    a0 = soft(pos0)
+    v1 = vel0 + 0.5 * hk["dt_soft"] * a0
+    off, idx = direct.kinds_neighbors(pos0, 2, PARAMS["r_search"], KINDS["r_search_ns"], 0, 0.0)
+    okw = {k: hk[k] for k in ("dt_soft", "dt_max", "eta", "eta_s", "a0")}
+    x2, v2, _, _ = oracle.hermite(pos0, v1, mass, off, idx, PARAMS["eps"], PARAMS["r_in"],
+                                  PARAMS["r_out"], **okw, kinds=ORACLE_KINDS)
+    a2 = soft(x2)
+    v3 = v2 + 0.5 * hk["dt_soft"] * a2
+    gx, gv, ga = pos.cpu().numpy(), vel.cpu().numpy(), acc.cpu().numpy()
+    ex = np.abs(gx - x2).max() / np.abs(x2).max()
+    ev = rel_rms(gv, v3)
+    ea = rel_rms(ga, a2)
+    log(f"  pos max rel {ex:.2e}  vel rel-RMS {ev:.2e}  acc rel-RMS {ea:.2e}")
+    assert ex < 1e-12 and ev < 1e-12 and ea < 1e-12
