@@ -411,12 +411,15 @@ def sweep(args):
         for n_crit in w.extra["n_crits"]:
             base = w.params(theta=theta, n_crit=n_crit)
             t0 = time.perf_counter()
-            stride = 997     # the oracle walks every 997-th group only
+            # the oracle walks every stride-th group only (about 640 of them), and
+            # 512 of those are checked
+            G_est = oracle.Tree(c.pos, c.mass, base, walk_stride=1 << 30).n_groups
+            stride = max(1, G_est // 640)
             tree = oracle.Tree(c.pos, c.mass, base, walk_stride=stride)
             t_or = time.perf_counter() - t0
             G = tree.n_groups
             walked = np.arange(0, G, stride)
-            sample = rng.choice(walked, min(len(walked), 128), replace=False)
+            sample = rng.choice(walked, min(len(walked), 512), replace=False)
             ra, rp = tree.force_groups(sample)
             rows = np.nonzero(~np.isnan(rp))[0]
             line = {"workload": w.name, "n": w.n, "theta": theta, "n_crit": n_crit,
