@@ -178,6 +178,16 @@ def build_roofline(head, n):
             "bytes_per_node": BUILD_BYTES_PER_NODE}
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(pos, mass, params, gpu_first, target_s=12.0, seed=3):
     """The oracle on sampled groups of the step-0 tree: force rate on host cores,
     plus the RMS error of the GPU forces on those groups."""
@@ -206,11 +216,20 @@ def cpu_baseline(pos, mass, params, gpu_first, target_s=12.0, seed=3):
     t_force = time.perf_counter() - t0
     rows = np.nonzero(~np.isnan(pot))[0]
     n_int = int(work[take].sum())
-    out = dict(value=n_int / t_force, unit="interactions/s", cores=oracle.num_threads(),
+    threads = oracle.num_threads()
+    # one core, on a fortieth of the sample (the paper quotes one CPU core)
+    one = take[:max(1, len(take) // 40)]
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    tree.force_groups(one)
+    t_one = time.perf_counter() - t0
+    oracle.set_threads(threads)
+    out = dict(value=n_int / t_force, unit="interactions/s", cores=threads,
                kind="oracle",
                sample=(f"force+potential of {len(take)} random groups of {G} "
                        f"({n_int} interactions, {len(rows)} particles) of the step-0 tree; "
-                       f"oracle tree build (single-threaded, excluded) took {t_build:.1f} s"))
+                       f"oracle tree build (single-threaded, excluded) took {t_build:.1f} s"),
+               one_core_value=int(work[one].sum()) / t_one, cpu_model=cpu_model())
     errs = {}
     for name, (ga, gp) in gpu_first.items():
         ga, gp = ga[rows], gp[rows]

@@ -98,6 +98,8 @@ def lib():
         L.or_morton.argtypes = [C.c_double, C.c_double, C.c_double, P, C.c_double]
         L.or_morton.restype = C.c_uint64
         L.or_num_threads.restype = C.c_int
+        L.or_set_threads.argtypes = [C.c_int]
+        L.or_set_threads.restype = None
         L.or_hard_force.argtypes = [C.c_int64, P, P, P, P, P, C.c_double, C.c_double,
                                     C.c_double, C.POINTER(_Kinds), P, P, P]
         L.or_hermite.argtypes = [C.c_int64, P, P, P, P, P, C.c_double, C.c_double, C.c_double,
@@ -143,6 +145,11 @@ def morton(p, lo, L):
 
 def num_threads() -> int:
     return int(lib().or_num_threads())
+
+
+def set_threads(k: int) -> None:
+    """Threads of the oracle's parallel loops from now on."""
+    lib().or_set_threads(int(k))
 
 
 @dataclass

@@ -844,3 +844,13 @@ int or_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads for the following parallel regions (k < 1: leave as is). */
+void or_set_threads(int k)
+{
+#ifdef _OPENMP
+    if (k >= 1) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}
