@@ -601,7 +601,7 @@ __device__ inline int block_scan_excl(int v, int *s_ws, int &total) {
     int incl = v;
     for (int o = 1; o < 64; o <<= 1) {
         const int y = __shfl_up(incl, o);
-        if ((threadIdx.x & 63) >= o) incl += y;
+        if ((int)(threadIdx.x & 63) >= o) incl += y;
     }
     if (T == 64) {
         total = __shfl(incl, 63);

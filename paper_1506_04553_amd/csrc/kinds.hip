@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kKindThreads) void k_kinds_soft_special(
     s_r[3][threadIdx.x] = ph;
     __syncthreads();
     for (int w = kKindThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
+        if ((int)threadIdx.x < w)
             for (int q = 0; q < 4; ++q) s_r[q][threadIdx.x] += s_r[q][threadIdx.x + w];
         __syncthreads();
     }
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kKindThreads) void k_kn_count_special(const double 
     s_c[threadIdx.x] = c;
     __syncthreads();
     for (int w = kKindThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) s_c[threadIdx.x] += s_c[threadIdx.x + w];
+        if ((int)threadIdx.x < w) s_c[threadIdx.x] += s_c[threadIdx.x + w];
         __syncthreads();
     }
     if (threadIdx.x == 0) cnt[b] = s_c[0];
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(kKindThreads) void k_kn_fill_special(const double *
         s_scan[threadIdx.x] = hit;
         __syncthreads();
         for (int w = 1; w < kKindThreads; w <<= 1) {   // inclusive scan
-            const int v = threadIdx.x >= w ? s_scan[threadIdx.x - w] : 0;
+            const int v = (int)threadIdx.x >= w ? s_scan[threadIdx.x - w] : 0;
             __syncthreads();
             s_scan[threadIdx.x] += v;
             __syncthreads();
