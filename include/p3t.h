@@ -216,7 +216,7 @@ int p3t_hard_force(p3t_ctx *ctx, int64_t n, const double *pos, const double *vel
  *   eta_s    accuracy parameter of the first-step criterion (> 0; the paper
  *            uses eta / 10)
  *   a0       acceleration floor of the criteria, alpha m / r_cut^2 (>= 0)
- *   max_block_steps  bound on the block steps of one cluster (0: 2^26);
+ *   max_block_steps  bound on the block steps of one cluster (0: 2^22);
  *            reaching it ends the call with P3T_ELIMIT */
 typedef struct {
     double dt_soft, dt_max, eta, eta_s, a0;

@@ -37,10 +37,13 @@
 // live in LDS, and so do the component's list entries as local indices (they
 // fall back to a global copy when they outgrow their LDS area).  Three size
 // classes (< 64, < 256, < 1024 members) have their own block shapes and run
-// concurrently on forked streams beside the global-memory kernel that takes
-// larger components.
+// concurrently on forked streams; components of 1024 members or more advance
+// together on the context stream, one grid-wide launch per phase of a block
+// step, so that a large component is spread over the whole device.
 #include <math.h>
 #include <string.h>
+
+#include <vector>
 
 #include "device_util.h"
 #include "internal.h"
@@ -48,7 +51,8 @@
 namespace p3t {
 
 constexpr int kHardThreads = 256;
-constexpr int kHermThreads = 1024;   // the global-memory kernel for components of >= 1024
+constexpr int kGiantThreads = 256;   // grid-wide step kernels for components of >= 1024
+constexpr int kGiantBatch = 32;     // block steps launched between host checks
 constexpr int kMaxDtLevel = 40;
 constexpr int kUnionTries = 1 << 20;
 
@@ -77,7 +81,8 @@ struct HermConsts {
 
 // readback slots (int64 units) used here
 enum { RB_HBAD = 48, RB_HNHARD = 49, RB_HNCL = 50, RB_HMAXCL = 51, RB_HLIMIT = 52,
-       RB_HSTEPS = 53, RB_HMAXBLK = 54, RB_HNNZ = 55, RB_HCLASS = 56 /* 4 int32 class sizes */ };
+       RB_HSTEPS = 53, RB_HMAXBLK = 54, RB_HNNZ = 55, RB_HCLASS = 56 /* 4 int32 class sizes */,
+       RB_HGIANT = 58 };
 
 // size classes by floor(log2(members)): < 64, < 256, < 1024, the rest
 constexpr int kClassBucket[3] = {5, 7, 9};
@@ -386,121 +391,226 @@ __device__ inline double crit_full(const double *a, const double *j, const doubl
     return eta * sqrt(num / den);
 }
 
-__device__ inline double block_min(double v, double *s_red) {
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-    const int w = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) s_red[w] = v;
-    __syncthreads();
-    double r = s_red[0];
-    for (int k = 1; k < kHermThreads / 64; ++k) r = fmin(r, s_red[k]);
-    return r;
+// Components of kGiant members or more run as a sequence of grid-wide launches
+// per block step over all of their members (flattened: member k belongs to
+// component g with gpre[g] <= k < gpre[g + 1], slot gbeg[g] + k - gpre[g]):
+// the minimum of t + dt per component, the prediction, then force and
+// correction of the active members.  Two buffers of per-component minima
+// alternate between steps; the step that reads one resets the other.  A
+// component past t_end does nothing, so the host can run steps in batches
+// and stop when every component is done.
+struct GiantView {
+    const int32_t *gbeg, *gpre;   // [n_giant], [n_giant + 1]
+    int32_t n_giant, n_members;
+};
+
+__device__ inline void giant_member(const GiantView &gv, int32_t k, int32_t &g, int32_t &s) {
+    int lo = 0, hi = gv.n_giant - 1;
+    while (lo < hi) {            // last g with gpre[g] <= k
+        const int mid = (lo + hi + 1) >> 1;
+        if (gv.gpre[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    g = lo;
+    s = gv.gbeg[lo] + (k - gv.gpre[lo]);
 }
 
-__global__ __launch_bounds__(kHermThreads) void k_hermite_cluster(
-    const int32_t *__restrict__ cl_beg, const int32_t *__restrict__ cl_end,
-    const int32_t *__restrict__ order, int32_t order_base, const int32_t *__restrict__ mem,
-    const int32_t *__restrict__ slot, const int64_t *__restrict__ off,
-    const int32_t *__restrict__ idx, const double *__restrict__ mass, double *__restrict__ pos,
-    double *__restrict__ vel, HardConsts hc, HermConsts hp, HermState S,
-    int32_t *__restrict__ nsteps_out, unsigned long long *rb) {
-    __shared__ double s_red[kHermThreads / 64];
-    const int c = order[order_base + blockIdx.x];
-    const int b = cl_beg[c], e = cl_end[c];
-    const int tid = threadIdx.x;
-    for (int s = b + tid; s < e; s += kHermThreads) {
-        const int32_t i = mem[s];
-        for (int k = 0; k < 3; ++k) {
-            S.x[3 * s + k] = pos[3 * i + k];
-            S.v[3 * s + k] = vel[3 * i + k];
-        }
-        S.t[s] = 0.0;
-        S.ns[s] = 0;
+__global__ void k_giant_load(GiantView gv, const int32_t *__restrict__ mem,
+                             const double *__restrict__ pos, const double *__restrict__ vel,
+                             HermState S, unsigned long long *tmin) {
+    const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < gv.n_giant) {
+        tmin[k] = __double_as_longlong(INFINITY);
+        tmin[gv.n_giant + k] = __double_as_longlong(INFINITY);
     }
-    __syncthreads();
-    for (int s = b + tid; s < e; s += kHermThreads) {
-        double dummy;
-        hard_sum<false, true>(mem[s], s, S.x, S.v, mass, off, idx, slot, hc, S.a + 3 * s,
-                              S.j + 3 * s, &dummy);
-        const double cr = crit_first(S.a + 3 * s, S.j + 3 * s, hp,
-                                     mem[s] >= hc.first_sp ? hp.eta_s_sp : hp.eta_s);
-        double d = hp.dt_max;
+    if (k >= gv.n_members) return;
+    int32_t g, s;
+    giant_member(gv, k, g, s);
+    const int32_t i = mem[s];
+    for (int q = 0; q < 3; ++q) {
+        S.x[3 * s + q] = pos[3 * i + q];
+        S.v[3 * s + q] = vel[3 * i + q];
+    }
+    S.t[s] = 0.0;
+    S.ns[s] = 0;
+}
+
+__global__ void k_giant_first(GiantView gv, const int32_t *__restrict__ mem,
+                              const int32_t *__restrict__ slot, const int64_t *__restrict__ off,
+                              const int32_t *__restrict__ idx, const double *__restrict__ mass,
+                              HardConsts hc, HermConsts hp, HermState S) {
+    const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= gv.n_members) return;
+    int32_t g, s;
+    giant_member(gv, k, g, s);
+    double dummy;
+    hard_sum<false, true>(mem[s], s, S.x, S.v, mass, off, idx, slot, hc, S.a + 3 * s, S.j + 3 * s,
+                          &dummy);
+    const double cr = crit_first(S.a + 3 * s, S.j + 3 * s, hp,
+                                 mem[s] >= hc.first_sp ? hp.eta_s_sp : hp.eta_s);
+    double d = hp.dt_max;
+    while (d > cr && d > hp.dt_min) d *= 0.5;
+    S.dt[s] = d;
+}
+
+// step parity b: minima go to tmin[b * n_giant + g]
+__global__ void k_giant_min(GiantView gv, HermState S, unsigned long long *tmin, int b) {
+    const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= gv.n_members) return;
+    int32_t g, s;
+    giant_member(gv, k, g, s);
+    atomicMin(&tmin[b * gv.n_giant + g],
+              (unsigned long long)__double_as_longlong(S.t[s] + S.dt[s]));
+}
+
+__global__ void k_giant_predict(GiantView gv, HermConsts hp, HermState S,
+                                unsigned long long *tmin, int b, int32_t *gsteps) {
+    const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < gv.n_giant) tmin[(1 - b) * gv.n_giant + k] = __double_as_longlong(INFINITY);
+    if (k >= gv.n_members) return;
+    int32_t g, s;
+    giant_member(gv, k, g, s);
+    const double t_next = __longlong_as_double((long long)tmin[b * gv.n_giant + g]);
+    if (!(t_next <= hp.t_end)) return;
+    if (k == gv.gpre[g]) gsteps[g] += 1;   // block steps of component g
+    const double h = t_next - S.t[s];
+    for (int q = 0; q < 3; ++q) {
+        const int i3 = 3 * s + q;
+        S.xp[i3] = S.x[i3] + S.v[i3] * h + S.a[i3] * (h * h / 2.0) + S.j[i3] * (h * h * h / 6.0);
+        S.vp[i3] = S.v[i3] + S.a[i3] * h + S.j[i3] * (h * h / 2.0);
+    }
+}
+
+// The summands one list entry adds to a and jerk (the operations of hard_sum),
+// for particle i at slot si and neighbour j at slot sj of the predicted state.
+__device__ inline void pair_terms_g(int64_t i, int64_t si, int32_t j, int64_t sj,
+                                    const double *__restrict__ x, const double *__restrict__ v,
+                                    const double *__restrict__ mass, const HardConsts &hc,
+                                    double o[6]) {
+    const PairKind q = pair_kind(hc, i >= hc.first_sp, j >= hc.first_sp);
+    const double dx = x[3 * sj] - x[3 * si];
+    const double dy = x[3 * sj + 1] - x[3 * si + 1];
+    const double dz = x[3 * sj + 2] - x[3 * si + 2];
+    const double vx = v[3 * sj] - v[3 * si];
+    const double vy = v[3 * sj + 1] - v[3 * si + 1];
+    const double vz = v[3 * sj + 2] - v[3 * si + 2];
+    const double s2 = dx * dx + dy * dy + dz * dz + q.eps * q.eps;
+    const double s = sqrt(s2);
+    const double y = s / q.r_out;
+    const double K = q.split ? hk_K(y, q.gam) : 0.0;
+    const double Ks = q.split ? hk_dK(y, q.gam) / q.r_out : 0.0;
+    const double mj = mass[j];
+    const double inv_s3 = 1.0 / (s2 * s);
+    const double rv = dx * vx + dy * vy + dz * vz;
+    const double f = mj * (1.0 - K) * inv_s3;
+    const double c = 3.0 * rv / s2;
+    const double g = mj * Ks * rv / s * inv_s3;
+    o[0] = f * dx;
+    o[1] = f * dy;
+    o[2] = f * dz;
+    o[3] = f * (vx - c * dx) - g * dx;
+    o[4] = f * (vy - c * dy) - g * dy;
+    o[5] = f * (vz - c * dz) - g * dz;
+}
+
+// one wavefront per member: the lanes evaluate the row's summands 64 at a time
+// and lane 0 adds them in list order, then corrects the member
+__global__ __launch_bounds__(kGiantThreads) void k_giant_correct(
+    GiantView gv, const int32_t *__restrict__ mem, const int32_t *__restrict__ slot,
+    const int64_t *__restrict__ off, const int32_t *__restrict__ idx,
+    const double *__restrict__ mass, HardConsts hc, HermConsts hp, HermState S,
+    const unsigned long long *tmin, int b) {
+    const int lane = threadIdx.x & 63;
+    const int32_t k = blockIdx.x * (kGiantThreads / 64) + (threadIdx.x >> 6);
+    if (k >= gv.n_members) return;                   // whole wavefront
+    int32_t g, s;
+    giant_member(gv, k, g, s);
+    const double t_next = __longlong_as_double((long long)tmin[b * gv.n_giant + g]);
+    if (!(t_next <= hp.t_end) || S.t[s] + S.dt[s] != t_next) return;   // whole wavefront
+    const int32_t i = mem[s];
+    const int64_t rb = off[i], re = off[i + 1];
+    double sum[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t e0 = rb; e0 < re; e0 += 64) {
+        double o[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        const int64_t e = e0 + lane;
+        if (e < re) {
+            const int32_t j = idx[e];
+            pair_terms_g(i, s, j, slot[j], S.xp, S.vp, mass, hc, o);
+        }
+        const int cnt = (int)min<int64_t>(64, re - e0);
+        for (int src = 0; src < cnt; ++src)
+            for (int q = 0; q < 6; ++q) {
+                const double w = __shfl(o[q], src);
+                if (lane == 0) sum[q] += w;
+            }
+    }
+    if (lane != 0) return;
+    const double h = S.dt[s];
+    double a2[3], a3[3];
+    for (int q = 0; q < 3; ++q) {
+        const int i3 = 3 * s + q;
+        const double a1 = sum[q], j1 = sum[3 + q];
+        const double s2 = (-6.0 * (S.a[i3] - a1) - h * (4.0 * S.j[i3] + 2.0 * j1)) / (h * h);
+        const double s3 = (12.0 * (S.a[i3] - a1) + 6.0 * h * (S.j[i3] + j1)) / (h * h * h);
+        S.x[i3] = S.xp[i3] + s2 * (h * h * h * h / 24.0) + s3 * (h * h * h * h * h / 120.0);
+        S.v[i3] = S.vp[i3] + s2 * (h * h * h / 6.0) + s3 * (h * h * h * h / 24.0);
+        S.a[i3] = a1;
+        S.j[i3] = j1;
+        a2[q] = s2 + s3 * h;
+        a3[q] = s3;
+    }
+    S.t[s] = t_next;
+    S.ns[s] += 1;
+    const double cr = crit_full(S.a + 3 * s, S.j + 3 * s, a2, a3, hp,
+                                i >= hc.first_sp ? hp.eta_sp : hp.eta);
+    double d = h;
+    if (2.0 * d <= cr && 2.0 * d <= hp.dt_max && fmod(S.t[s], 2.0 * d) == 0.0)
+        d = 2.0 * d;
+    else
         while (d > cr && d > hp.dt_min) d *= 0.5;
-        S.dt[s] = d;
-    }
-    int64_t steps = 0;
-    for (;;) {
-        double lmin = INFINITY;
-        for (int s = b + tid; s < e; s += kHermThreads) {
-            const double tn = S.t[s] + S.dt[s];
-            if (tn < lmin) lmin = tn;
-        }
-        const double t_next = block_min(lmin, s_red);
-        if (!(t_next <= hp.t_end)) break;          // every member is at the end
-        if (steps == hp.max_block_steps) {
-            if (tid == 0) atomicOr(rb + (RB_HLIMIT - RB_HBAD), 1ull);
-            break;
-        }
-        ++steps;
-        for (int s = b + tid; s < e; s += kHermThreads) {
-            const double h = t_next - S.t[s];
-            for (int k = 0; k < 3; ++k) {
-                const int q = 3 * s + k;
-                S.xp[q] = S.x[q] + S.v[q] * h + S.a[q] * (h * h / 2.0) +
-                          S.j[q] * (h * h * h / 6.0);
-                S.vp[q] = S.v[q] + S.a[q] * h + S.j[q] * (h * h / 2.0);
-            }
-        }
-        __syncthreads();
-        for (int s = b + tid; s < e; s += kHermThreads) {
-            if (S.t[s] + S.dt[s] != t_next) continue;
-            double dummy;
-            hard_sum<false, true>(mem[s], s, S.xp, S.vp, mass, off, idx, slot, hc, S.a1 + 3 * s,
-                                  S.j1 + 3 * s, &dummy);
-        }
-        __syncthreads();
-        for (int s = b + tid; s < e; s += kHermThreads) {
-            if (S.t[s] + S.dt[s] != t_next) continue;
-            const double h = S.dt[s];
-            for (int k = 0; k < 3; ++k) {
-                const int q = 3 * s + k;
-                const double s2 = (-6.0 * (S.a[q] - S.a1[q]) - h * (4.0 * S.j[q] + 2.0 * S.j1[q])) /
-                                  (h * h);
-                const double s3 = (12.0 * (S.a[q] - S.a1[q]) + 6.0 * h * (S.j[q] + S.j1[q])) /
-                                  (h * h * h);
-                S.x[q] = S.xp[q] + s2 * (h * h * h * h / 24.0) + s3 * (h * h * h * h * h / 120.0);
-                S.v[q] = S.vp[q] + s2 * (h * h * h / 6.0) + s3 * (h * h * h * h / 24.0);
-                S.a[q] = S.a1[q];
-                S.j[q] = S.j1[q];
-                S.a2[q] = s2 + s3 * h;
-                S.a3[q] = s3;
-            }
-            S.t[s] = t_next;
-            S.ns[s] += 1;
-            const double cr = crit_full(S.a + 3 * s, S.j + 3 * s, S.a2 + 3 * s, S.a3 + 3 * s, hp,
-                                        mem[s] >= hc.first_sp ? hp.eta_sp : hp.eta);
-            double d = h;
-            if (2.0 * d <= cr && 2.0 * d <= hp.dt_max && fmod(S.t[s], 2.0 * d) == 0.0)
-                d = 2.0 * d;
-            else
-                while (d > cr && d > hp.dt_min) d *= 0.5;
-            S.dt[s] = d;
-        }
-        __syncthreads();
-    }
-    unsigned long long my_steps = 0;
-    for (int s = b + tid; s < e; s += kHermThreads) {
+    S.dt[s] = d;
+}
+
+__global__ void k_giant_store(GiantView gv, const int32_t *__restrict__ mem, HermState S,
+                              double *__restrict__ pos, double *__restrict__ vel,
+                              int32_t *__restrict__ nsteps_out, unsigned long long *rb) {
+    const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long my = 0;
+    if (k < gv.n_members) {
+        int32_t g, s;
+        giant_member(gv, k, g, s);
         const int32_t i = mem[s];
-        for (int k = 0; k < 3; ++k) {
-            pos[3 * i + k] = S.x[3 * s + k];
-            vel[3 * i + k] = S.v[3 * s + k];
+        for (int q = 0; q < 3; ++q) {
+            pos[3 * i + q] = S.x[3 * s + q];
+            vel[3 * i + q] = S.v[3 * s + q];
         }
         if (nsteps_out) nsteps_out[i] = S.ns[s];
-        my_steps += (unsigned long long)S.ns[s];
+        my = (unsigned long long)S.ns[s];
     }
-    for (int o = 32; o > 0; o >>= 1) my_steps += __shfl_xor(my_steps, o);
-    if ((tid & 63) == 0 && my_steps) atomicAdd(rb + (RB_HSTEPS - RB_HBAD), my_steps);
-    if (tid == 0) atomicMax(rb + (RB_HMAXBLK - RB_HBAD), (unsigned long long)steps);
+    for (int o = 32; o > 0; o >>= 1) my += __shfl_xor(my, o);
+    if ((threadIdx.x & 63) == 0 && my) atomicAdd(rb + (RB_HSTEPS - RB_HBAD), my);
+}
+
+// giant components' ranges (order[0 .. n_giant) are the largest components);
+// one thread: there are few of them
+__global__ void k_giant_ranges(const int32_t *__restrict__ order, const int32_t *__restrict__ cl_beg,
+                               const int32_t *__restrict__ cl_end, int32_t n_giant,
+                               int32_t *__restrict__ gbeg, int32_t *__restrict__ gpre,
+                               int32_t *__restrict__ gsteps) {
+    int32_t acc = 0;
+    for (int32_t g = 0; g < n_giant; ++g) {
+        const int32_t c = order[g];
+        gbeg[g] = cl_beg[c];
+        gpre[g] = acc;
+        gsteps[g] = 0;
+        acc += cl_end[c] - cl_beg[c];
+    }
+    gpre[n_giant] = acc;
+}
+
+__global__ void k_giant_maxsteps(const int32_t *__restrict__ gsteps, int32_t n_giant,
+                                 unsigned long long *rb) {
+    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < n_giant) atomicMax(rb + (RB_HMAXBLK - RB_HBAD), (unsigned long long)gsteps[g]);
 }
 
 // cluster counts of the size classes, largest class first: [>= 1024, < 1024,
@@ -904,6 +1014,66 @@ static int aux_streams(p3t_ctx *ctx) {
     return P3T_OK;
 }
 
+// The components of >= 1024 members, on the context stream: block steps in
+// batches of grid-wide launches until every component has reached t_end (or
+// the block-step bound is reached, which ends the call with ELIMIT).
+static int run_giant(p3t_ctx *ctx, int32_t n_giant, const int32_t *order, const int32_t *cl_beg,
+                     const int32_t *cl_end, const int32_t *mem, const int32_t *slot,
+                     const int64_t *off, const int32_t *idx, const double *mass, double *pos,
+                     double *vel, const HardConsts &hc, const HermConsts &hp, const HermState &S,
+                     int32_t *nsteps, unsigned long long *rbh) {
+    int rc;
+    hipStream_t st = ctx->stream;
+    const size_t ints = 3 * (size_t)n_giant + 1, words = 2 * (size_t)n_giant;
+    if ((rc = ensure(ctx, ctx->hard_giant, words * 8 + ints * 4 + 64))) return rc;
+    unsigned long long *tmin = ptr<unsigned long long>(ctx->hard_giant);
+    int32_t *gbeg = reinterpret_cast<int32_t *>(tmin + words), *gpre = gbeg + n_giant,
+            *gsteps = gpre + n_giant + 1;
+    k_giant_ranges<<<1, 1, 0, st>>>(order, cl_beg, cl_end, n_giant, gbeg, gpre, gsteps);
+    if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + RB_HGIANT, gpre + n_giant, sizeof(int32_t),
+                                            hipMemcpyDeviceToHost, st), "readback")))
+        return rc;
+    if ((rc = check_hip(ctx, hipStreamSynchronize(st), "sync"))) return rc;
+    GiantView gv{gbeg, gpre, n_giant, *reinterpret_cast<const int32_t *>(ctx->hpin + RB_HGIANT)};
+    const unsigned blocks = blocks_for(gv.n_members > n_giant ? gv.n_members : n_giant, kGiantThreads);
+    const unsigned wave_blocks = blocks_for(gv.n_members, kGiantThreads / 64);   // a wave per member
+    k_giant_load<<<blocks, kGiantThreads, 0, st>>>(gv, mem, pos, vel, S, tmin);
+    k_giant_first<<<blocks, kGiantThreads, 0, st>>>(gv, mem, slot, off, idx, mass, hc, hp, S);
+    if ((rc = check_hip(ctx, hipGetLastError(), "giant components"))) return rc;
+    std::vector<unsigned long long> last((size_t)n_giant);
+    for (int64_t step = 0;;) {
+        for (int q = 0; q < kGiantBatch; ++q, ++step) {
+            const int b = (int)(step & 1);
+            k_giant_min<<<blocks, kGiantThreads, 0, st>>>(gv, S, tmin, b);
+            k_giant_predict<<<blocks, kGiantThreads, 0, st>>>(gv, hp, S, tmin, b, gsteps);
+            k_giant_correct<<<wave_blocks, kGiantThreads, 0, st>>>(gv, mem, slot, off, idx, mass,
+                                                                  hc, hp, S, tmin, b);
+        }
+        if ((rc = check_hip(ctx, hipGetLastError(), "giant step"))) return rc;
+        // the minima of the batch's last step: every component done when all exceed t_end
+        const int b = (int)((step - 1) & 1);
+        if ((rc = check_hip(ctx, hipMemcpyAsync(last.data(), tmin + (size_t)b * n_giant,
+                                                (size_t)n_giant * 8, hipMemcpyDeviceToHost, st),
+                            "readback")))
+            return rc;
+        if ((rc = check_hip(ctx, hipStreamSynchronize(st), "sync"))) return rc;
+        bool done = true;
+        for (unsigned long long w : last) {
+            double t;
+            memcpy(&t, &w, sizeof(t));
+            if (t <= hp.t_end) done = false;
+        }
+        if (done) break;
+        if (step >= hp.max_block_steps) {
+            k_giant_store<<<blocks, kGiantThreads, 0, st>>>(gv, mem, S, pos, vel, nsteps, rbh);
+            return set_error(ctx, P3T_ELIMIT, "a component reached the block-step limit");
+        }
+    }
+    k_giant_store<<<blocks, kGiantThreads, 0, st>>>(gv, mem, S, pos, vel, nsteps, rbh);
+    k_giant_maxsteps<<<blocks_for(n_giant, 256), 256, 0, st>>>(gsteps, n_giant, rbh);
+    return check_hip(ctx, hipGetLastError(), "giant store");
+}
+
 int launch_hard_force(p3t_ctx *ctx, int64_t n, const double *pos, const double *vel,
                       const double *mass, const int64_t *off, const int32_t *idx,
                       const p3t_params *p, const p3t_kinds *kd, double *acc, double *jerk,
@@ -1004,7 +1174,7 @@ int launch_hermite(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const doub
         const bool sp = kd && kd->n_special > 0;
         hc2.eta_sp = sp ? kd->eta_sp : hpar->eta;
         hc2.eta_s_sp = sp ? kd->eta_s_sp : hpar->eta_s;
-        hc2.max_block_steps = hpar->max_block_steps > 0 ? hpar->max_block_steps : (1LL << 26);
+        hc2.max_block_steps = hpar->max_block_steps > 0 ? hpar->max_block_steps : (1LL << 22);
         const HardConsts hk = hard_consts(p, kd, n);
         unsigned long long *rbh = reinterpret_cast<unsigned long long *>(rb + RB_HBAD);
         // fork: the three LDS classes on their own streams, the largest
@@ -1013,12 +1183,7 @@ int launch_hermite(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const doub
         for (int k = 0; k < kAux; ++k)
             if ((rc = check_hip(ctx, hipStreamWaitEvent(ctx->aux[k], ctx->aev[0], 0), "wait")))
                 return rc;
-        int32_t base_k = 0;
-        if (cls[0] > 0)
-            k_hermite_cluster<<<(unsigned)cls[0], kHermThreads, 0, st>>>(
-                cl_beg, cl_end, order, base_k, mem, slotv, off, idx, mass, pos, vel, hk, hc2, S,
-                nsteps, rbh);
-        base_k += cls[0];
+        int32_t base_k = cls[0];
         if (cls[1] > 0)
             k_hermite_lds<256, 4, 8192, 512><<<(unsigned)cls[1], 256, 0, ctx->aux[0]>>>(
                 cl_beg, cl_end, order, base_k, mem, off, lidx, mass, pos, vel, hk, hc2, nsteps, rbh);
@@ -1032,6 +1197,9 @@ int launch_hermite(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const doub
                 cl_beg, cl_end, order, base_k, mem, off, lidx, mass, pos, vel, hk, hc2, nsteps, rbh);
 
         if ((rc = check_hip(ctx, hipGetLastError(), "hermite"))) return rc;
+        if (cls[0] > 0 && (rc = run_giant(ctx, cls[0], order, cl_beg, cl_end, mem, slotv, off, idx,
+                                          mass, pos, vel, hk, hc2, S, nsteps, rbh)))
+            return rc;
         for (int k = 0; k < kAux; ++k) {
             if ((rc = check_hip(ctx, hipEventRecord(ctx->aev[1 + k], ctx->aux[k]), "event"))) return rc;
             if ((rc = check_hip(ctx, hipStreamWaitEvent(st, ctx->aev[1 + k], 0), "wait"))) return rc;

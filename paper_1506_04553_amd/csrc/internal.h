@@ -109,6 +109,7 @@ struct p3t_ctx {
     p3t::DevBuf vjp_gx, vjp_gm, vjp_cell, bbox;
     p3t::DevBuf seg_end, gorder, grank, ghist;
     p3t::DevBuf hard_ix, hard_state;   // hard part: components and integrator state
+    p3t::DevBuf hard_giant;            // ... and the step bookkeeping of the largest components
     hipStream_t aux[4] = {nullptr, nullptr, nullptr, nullptr};   // hard part's concurrent classes
     hipEvent_t aev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     int aux_ready = 0;

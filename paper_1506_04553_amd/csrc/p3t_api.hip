@@ -159,7 +159,7 @@ extern "C" void p3t_destroy(p3t_ctx *ctx) {
                       &ctx->nbr_cnt, &ctx->nbr_slots, &ctx->vjp_gx, &ctx->vjp_gm, &ctx->vjp_cell, &ctx->bbox,
                       &ctx->seg_end, &ctx->gorder, &ctx->grank, &ctx->ghist, &ctx->hard_ix,
                       &ctx->hard_state, &ctx->step_off, &ctx->step_idx, &ctx->step_off2,
-                      &ctx->step_idx2, &ctx->kinds_cnt};
+                      &ctx->step_idx2, &ctx->kinds_cnt, &ctx->hard_giant};
     for (DevBuf *b : bufs) release(ctx, *b);
     if (ctx->hpin) (void)hipHostFree(ctx->hpin);
     for (int k = 0; k < 12; ++k)

@@ -262,3 +262,41 @@ def test_p3t_step_matches_oracle_composition(ctx):
     log(f"  pos max rel {ex:.2e}  vel rel-RMS {ev:.2e}  acc rel-RMS {ea:.2e}")
     assert st["n_hard"] == int((np.diff(off) > 0).sum()) and st["n_hard"] > 0
     assert ex < 1e-12 and ev < 1e-12 and ea < 1e-12
+
+
+def test_p3t_energy_conservation(ctx):
+    """Whole P3T steps of a Plummer cluster (N = 2048): the total energy,
+    kinetic plus the full softened Newton potential from the direct sum, is
+    conserved to the scheme's error, which falls as the soft step falls."""
+    import torch
+    n = 2048
+    c = plummer(n, 91)
+    # theta = 0: the soft force is exact, so only the integration error remains
+    p = dict(eps=1.0 / 256, r_in=0.002, r_out=0.02, theta=0.0, r_search=0.03, n_crit=64,
+             n_leaf=16, precision="fp64")
+    mass = _dev(c.mass)
+
+    def energy(pos, vel):
+        _, ph = ctx.direct(pos, mass, "newton", **p)
+        return float(0.5 * (mass * (vel * vel).sum(1)).sum() + 0.5 * (mass * ph).sum())
+
+    errs = []
+    for dt in (2.0 ** -7, 2.0 ** -8):
+        pos, vel = _dev(c.pos), _dev(c.vel)
+        e0 = energy(pos, vel)
+        ctx.build_tree(pos, mass, **p)
+        acc, _ = ctx.long_force(want_pot=False)
+        hk = dict(dt_soft=dt, dt_max=dt / 4, eta=0.1, eta_s=0.01,
+                  a0=0.1 * float(c.mass.mean()) / p["r_out"] ** 2, max_block_steps=200000)
+        steps = int(round(0.125 / dt))
+        n_hard = 0
+        for _ in range(steps):
+            st = ctx.step(pos, vel, mass, acc, hk, **p)
+            n_hard = max(n_hard, st["n_hard"])
+        errs.append(abs(energy(pos, vel) - e0) / abs(e0))
+        log(f"p3t energy: dt_soft {dt:g}, {steps} steps, up to {n_hard} hard particles, "
+            f"|dE/E| {errs[-1]:.2e}")
+        assert n_hard > 0
+    # at these steps the pairs cross the changeover band in a few soft steps, so the
+    # error falls about linearly with dt_soft, not yet as dt_soft^2
+    assert errs[0] < 1e-5 and errs[1] < 0.75 * errs[0]
