@@ -468,6 +468,52 @@ def sweep(args):
     ctx.close()
 
 
+def small_configs(args, reps=10):
+    """The small workloads (Plummer 4096 FP64; Plummer 65536 Salpeter FP64 and
+    mixed): build and interaction-kernel times (median of reps, HIP events),
+    interactions/s, TFLOP/s, and the force and potential error against the
+    whole oracle force.  One JSON line per (workload, precision)."""
+    import torch
+    import oracle
+    from inputs import WORKLOADS, make_cluster
+    from paper_1506_04553_amd import P3T
+    ctx = P3T(0)
+    dev = torch.device("cuda", 0)
+    for name, precs in (("plummer4k", ("fp64",)), ("plummer64k_salpeter", ("fp64", "mixed"))):
+        w = WORKLOADS[name]
+        c = make_cluster(w, seed=args.seed)
+        pos = torch.from_numpy(c.pos).to(dev)
+        mass = torch.from_numpy(c.mass).to(dev)
+        t0 = time.perf_counter()
+        oa, op = oracle.Tree(c.pos, c.mass, w.params()).force()
+        t_or = time.perf_counter() - t0
+        for prec in precs:
+            p = w.params(precision=prec)
+            bms, fms = [], []
+            for _ in range(reps):
+                ctx.build_tree(pos, mass, **p)
+                acc, pot = ctx.long_force()
+                st = ctx.stats()
+                bms.append(st["ms_build"])
+                fms.append(st["ms_force"])
+            a, ph = acc.cpu().numpy(), pot.cpu().numpy()
+            e = np.linalg.norm(a - oa, axis=1) / np.linalg.norm(oa, axis=1)
+            f_ms = float(np.median(fms))
+            inter = st["n_pp"] + st["n_pc"]
+            flops = st["n_pp"] * F_PP + st["n_pc"] * F_PC_QUAD
+            peak = PEAK_TFLOPS[prec]
+            print(json.dumps({
+                "workload": name, "n": w.n, "precision": prec, "theta": w.theta,
+                "n_crit": w.n_crit, "build_ms": float(np.median(bms)), "force_ms": f_ms,
+                "interactions": inter, "interactions_per_s": inter / (f_ms * 1e-3),
+                "tflops": flops / (f_ms * 1e-3) / 1e12, "peak_tflops": peak,
+                "acc_rel_rms": float(np.sqrt(((a - oa) ** 2).sum() / (oa ** 2).sum())),
+                "pot_rel_rms": float(np.sqrt(((ph - op) ** 2).sum() / (op ** 2).sum())),
+                "acc_max_rel": float(e.max()), "oracle_force_s": t_or,
+                "oracle_cores": oracle.num_threads()}), flush=True)
+    ctx.close()
+
+
 def copy_calibration(mib=512, reps=3):
     """A plain device-to-device copy of known size, for scaling HBM byte counters
     (FETCH_SIZE / WRITE_SIZE) read by a profiler in the same way as the kernels."""
@@ -498,6 +544,8 @@ def main():
                     help="skip the whole-P3T-step timing (soft step plus Hermite hard part)")
     ap.add_argument("--sweep", action="store_true",
                     help="run the theta x n_crit sweep on the 2^22 workload instead")
+    ap.add_argument("--configs", action="store_true",
+                    help="time the small workloads (Plummer 4096, Plummer 65536 Salpeter) instead")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 512 MiB device copy (profiler counter calibration)")
     args = ap.parse_args()
@@ -511,6 +559,9 @@ def main():
         return
     if args.sweep:
         sweep(args)
+        return
+    if args.configs:
+        small_configs(args)
         return
 
     import torch
