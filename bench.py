@@ -178,6 +178,18 @@ def build_roofline(head, n):
             "bytes_per_node": BUILD_BYTES_PER_NODE}
 
 
+def walk_rates(head):
+    """The group walk: groups per second and the bytes of lists it writes (one
+    int32 per list entry plus a (begin, end) int64 segment per group and list);
+    the walk's time goes to dependent node reads, so this is a rate, not a roofline."""
+    ent = sum(head["list_entries"].values())
+    byts = 4 * ent + 3 * 16 * head["n_groups"]
+    s = head["walk_ms"] * 1e-3
+    return {"ms": head["walk_ms"], "groups": head["n_groups"],
+            "groups_per_s": head["n_groups"] / s, "list_entries": ent,
+            "list_bytes": byts, "list_write_GBps": byts / s / 1e9}
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -625,6 +637,7 @@ def main():
         "phase_ms": {"build": head["build_ms"], "force": head["force_ms"],
                      "neighbors": head["neighbors_ms"]},
         "build": build_roofline(head, w.n),
+        "walk": walk_rates(head),
         "interactions_per_step": head["interactions_per_step"],
         "interactions_split": {"particle_cell": head["n_pc"], "particle_particle": head["n_pp"],
                                "of_which_near": head["n_pp_near"]},

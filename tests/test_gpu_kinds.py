@@ -153,3 +153,46 @@ def test_kinds_p3t_step_matches_oracle_composition(ctx):
     ea = rel_rms(ga, a2)
     log(f"  pos max rel {ex:.2e}  vel rel-RMS {ev:.2e}  acc rel-RMS {ea:.2e}")
     assert ex < 1e-12 and ev < 1e-12 and ea < 1e-12
+
+
+def test_kinds_split_special_pair_and_no_special(ctx):
+    """A special pair that is split (its own r_in, r_cut, softening and radius)
+    and, separately, n_special = 0, which must equal no kinds bit for bit."""
+    import torch
+    pos, vel, mass = _galaxy(n_fs=3000, seed=5)
+    pos[-1] = pos[-2] + np.array([0.02, 0.0, 0.0])     # the two specials inside each other's r_cut
+    n = len(mass)
+    kinds = dict(KINDS, split_ss=1, r_in_ss=0.005, r_out_ss=0.05, r_search_ss=0.06, eps_ss=1e-3)
+    okinds = {k: v for k, v in kinds.items() if k not in ("r_search_ns", "r_search_ss")}
+    # soft sums
+    acc = torch.zeros((n, 3), dtype=torch.float64, device="cuda")
+    ctx.kinds_soft(_dev(pos), _dev(mass), acc, None, kinds, **PARAMS)
+    oa, _ = direct.kinds_soft(pos, mass, PARAMS["eps"], PARAMS["r_in"], PARAMS["r_out"], kinds)
+    na, _ = direct.newton_direct(pos, mass, 1e-4)
+    assert np.sqrt(((acc.cpu().numpy() - oa) ** 2).sum() / (na ** 2).sum()) < 1e-12
+    # lists and the hard part
+    ctx.build_tree(_dev(pos[:n - 2]), _dev(mass[:n - 2]), **PARAMS)
+    nn_off, nn_idx = ctx.neighbors()
+    off, idx = ctx.kinds_neighbors(_dev(pos), kinds, nn_off, nn_idx)
+    off, idx = off.cpu().numpy(), idx.cpu().numpy()
+    ooff, oidx = direct.kinds_neighbors(pos, 2, PARAMS["r_search"], kinds["r_search_ns"], 1,
+                                        kinds["r_search_ss"])
+    assert np.array_equal(off, ooff) and np.array_equal(idx, oidx)
+    assert n - 1 in idx[off[n - 2]:off[n - 1]]
+    hk = _hk()
+    okw = {k: hk[k] for k in ("dt_soft", "dt_max", "eta", "eta_s", "a0")}
+    x, v = _dev(pos), _dev(vel)
+    ns, _ = ctx.hermite_hard(x, v, _dev(mass), _dev(off), _dev(idx), hk, kinds=kinds, **PARAMS)
+    ox, ov, ons, _ = oracle.hermite(pos, vel, mass, off, idx, PARAMS["eps"], PARAMS["r_in"],
+                                    PARAMS["r_out"], **okw, kinds=okinds)
+    assert np.array_equal(ns.cpu().numpy(), ons)
+    assert np.array_equal(x.cpu().numpy(), ox) and np.array_equal(v.cpu().numpy(), ov)
+    # no special particle: the same as no kinds, and as the oracle without kinds,
+    # over the same lists (pairs beyond r_out add no force but join components)
+    ox, ov, ons, _ = oracle.hermite(pos, vel, mass, off, idx, PARAMS["eps"], PARAMS["r_in"],
+                                    PARAMS["r_out"], **okw)
+    for kd in (None, dict(KINDS, n_special=0)):
+        x, v = _dev(pos), _dev(vel)
+        ns, _ = ctx.hermite_hard(x, v, _dev(mass), _dev(off), _dev(idx), hk, kinds=kd, **PARAMS)
+        assert np.array_equal(ns.cpu().numpy(), ons)
+        assert np.array_equal(x.cpu().numpy(), ox) and np.array_equal(v.cpu().numpy(), ov)
