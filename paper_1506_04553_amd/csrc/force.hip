@@ -50,7 +50,16 @@ struct ForceParams {
 };
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
+// FP64: the hardware estimate y, then one step of the series
+// (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 with e = 1 - x y^2.  The arguments are
+// softened squared distances, finite and positive, so no special values are
+// screened (a zero argument only arises for a particle with itself at zero
+// softening, and that pair is discarded by index).
+__device__ __forceinline__ double rsq(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = __builtin_fma(-x * y, y, 1.0);
+    return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
+}
 __device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -100,14 +109,15 @@ struct Sum<double> {
 };
 
 // LDS records: one 128-bit (float) or 2x128-bit (double) read per particle,
-// three / five per cell.
+// three / five per cell (16-byte aligned: a cell is 48 bytes in float, 80 in
+// double, which keeps the double kernel's LDS within four blocks per CU).
 template <class R>
 struct alignas(4 * sizeof(R)) PJ {
     R x, y, z, m;
 };
 template <class R>
-struct alignas(4 * sizeof(R)) CJ {
-    R x, y, z, M, qxx, qyy, qzz, qxy, qxz, qyz, pad0, pad1;
+struct alignas(16) CJ {
+    R x, y, z, M, qxx, qyy, qzz, qxy, qxz, qyz;
 };
 
 // i-particle slot: position offset, tile partials and compensated sums
@@ -144,12 +154,14 @@ __device__ __forceinline__ void pp_full(Slot<R> &q, const PJ<R> &j, int32_t jid,
     const R rinv = rsq(r2);
     R K, Ws;
     changeover<R>(r2, rinv, fp, K, Ws);
-    if (jid == q.i) { K = R(0); Ws = R(0); }
-    const R f = j.m * K * (rinv * rinv * rinv);
+    // the pair of a particle with itself is discarded by selection, not by a
+    // zero factor: at zero softening its 1/s is infinite
+    const bool self = jid == q.i;
+    const R f = self ? R(0) : j.m * K * (rinv * rinv * rinv);
     q.ax = fmaR(f, dx, q.ax);
     q.ay = fmaR(f, dy, q.ay);
     q.az = fmaR(f, dz, q.az);
-    q.ph = fmaR(-j.m, Ws, q.ph);
+    q.ph = fmaR(-j.m, self ? R(0) : Ws, q.ph);
 }
 
 // cell term; with B = (r.Q.r)/s^4:
@@ -266,7 +278,8 @@ __device__ __forceinline__ void cell_tile(Slot<R> *q, const CJ<R> *sc, int iters
 }
 
 template <class R, bool QUAD, bool CHECK_K>
-__global__ __launch_bounds__(kForceThreads) void k_force(
+__global__ __launch_bounds__(kForceThreads)
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 4 : 1))) void k_force(
     const GroupInfo *__restrict__ grp, ListsDev L, const double *__restrict__ x,
     const double *__restrict__ y, const double *__restrict__ z, const double *__restrict__ m,
     const NodeMP *__restrict__ mp, const int32_t *__restrict__ perm, ForceParams fp,
@@ -279,7 +292,6 @@ __global__ __launch_bounds__(kForceThreads) void k_force(
     CJ<R> zero_c;
     zero_c.x = zero_c.y = zero_c.z = R(-1e18);
     zero_c.M = zero_c.qxx = zero_c.qyy = zero_c.qzz = zero_c.qxy = zero_c.qxz = zero_c.qyz = R(0);
-    zero_c.pad0 = zero_c.pad1 = R(0);
 
     const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
     const int g = L.order[blockIdx.x];
@@ -380,7 +392,6 @@ __global__ __launch_bounds__(kForceThreads) void k_force(
                 r.x = (R)(c.cx - gcx); r.y = (R)(c.cy - gcy); r.z = (R)(c.cz - gcz); r.M = (R)c.M;
                 r.qxx = (R)c.q[0]; r.qyy = (R)c.q[1]; r.qzz = (R)c.q[2];
                 r.qxy = (R)c.q[3]; r.qxz = (R)c.q[4]; r.qyz = (R)c.q[5];
-                r.pad0 = r.pad1 = R(0);
                 return r;
             };
             CJ<R> pre = (cb + tid < ce) ? load_cell(cb + tid) : zero_c;

@@ -84,7 +84,14 @@ __device__ __forceinline__ Chg changeover_ds(double s, const VjpParams &vp) {
 __device__ __forceinline__ Chg changeover_unit() { return Chg{1.0, 0.0, 1.0, 0.0}; }
 
 __device__ __forceinline__ float vrsq(float v) { return __builtin_amdgcn_rsqf(v); }
-__device__ __forceinline__ double vrsq(double v) { return rsqrt(v); }
+// FP64: hardware estimate y and one step of (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8,
+// e = 1 - v y^2; v is a softened squared distance of two different particles,
+// finite and positive, so no special values are screened
+__device__ __forceinline__ double vrsq(double v) {
+    const double y = __builtin_amdgcn_rsq(v);
+    const double e = __builtin_fma(-v * y, y, 1.0);
+    return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
+}
 
 // d(l_ij)/dd and d(l_ij)/dm_j for one pair; CHG false: K = W = 1 known.
 template <class R, bool CHG>

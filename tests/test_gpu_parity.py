@@ -160,6 +160,8 @@ def _edge_cases():
     cases["big_h"] = (plummer(2000, 17).pos, np.full(2000, 1 / 2000),
                       dict(base, r_out=0.2, r_in=0.02, r_search=0.3, theta=0.7))
     cases["large_theta"] = (plummer(3000, 18).pos, np.full(3000, 1 / 3000), dict(base, theta=1.5))
+    # zero softening: every pair distance is positive except a particle's own
+    cases["eps0"] = (plummer(2000, 19).pos, np.full(2000, 1 / 2000), dict(base, eps=0.0))
     return cases
 
 
