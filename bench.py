@@ -526,6 +526,56 @@ def small_configs(args, reps=10):
     ctx.close()
 
 
+def hermite_probe(reps=3, seed=0):
+    """Block-step latency of the Hermite hard part: isolated groups of k equal
+    stars (mass 1e-6, scatter a, 0.05 apart, lists within h inside each group),
+    integrated over one soft step of the King 2^20 workload's parameters; alone
+    (latency) and replicated (load).  One JSON line per case, best of reps."""
+    import torch
+    from paper_1506_04553_amd import P3T
+    prm = dict(eps=3.8e-6, r_in=2e-4, r_out=2e-3, theta=0.5, r_search=2.2e-3, n_crit=256,
+               n_leaf=16, precision="fp64")
+    dt = 1.0 / 256
+    hk = dict(dt_soft=dt, dt_max=dt * HERMITE["dt_max_per_soft"], eta=HERMITE["eta"],
+              eta_s=HERMITE["eta"] / 10, a0=HERMITE["alpha"] * 1e-6 / prm["r_out"] ** 2)
+    h2 = prm["r_search"] ** 2
+    ctx = P3T(0)
+    dev = torch.device("cuda", 0)
+    for copies, k, a in [(1, 2, 3e-5), (1, 4, 5e-5), (1, 16, 1e-4), (1, 48, 2e-4),
+                         (1024, 2, 3e-5), (16384, 2, 3e-5), (4096, 8, 6e-5)]:
+        rng = np.random.default_rng(seed)
+        side = int(np.ceil(copies ** (1 / 3)))
+        grid = np.stack(np.meshgrid(*[np.arange(side)] * 3, indexing="ij"), -1).reshape(-1, 3)
+        centres = grid[:copies] * 0.05
+        pos = (centres[:, None, :] + rng.normal(scale=a, size=(copies, k, 3))).reshape(-1, 3)
+        vel = rng.normal(scale=np.sqrt(k * 1e-6 / a), size=(copies * k, 3))
+        mass = np.full(copies * k, 1e-6)
+        rows = []
+        for g in range(copies):
+            p = pos[g * k:(g + 1) * k]
+            d = p[None, :, :] - p[:, None, :]
+            r2 = d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1] + d[..., 2] * d[..., 2]
+            np.fill_diagonal(r2, np.inf)
+            rows += [g * k + np.nonzero(r2[i] < h2)[0] for i in range(k)]
+        off = np.zeros(copies * k + 1, np.int64)
+        off[1:] = np.cumsum([len(r) for r in rows])
+        idx = np.concatenate(rows).astype(np.int32)
+        best, st = None, None
+        for _ in range(reps):
+            x = torch.from_numpy(pos.copy()).to(dev)
+            v = torch.from_numpy(vel.copy()).to(dev)
+            _, st = ctx.hermite_hard(x, v, torch.from_numpy(mass).to(dev),
+                                     torch.from_numpy(off).to(dev), torch.from_numpy(idx).to(dev),
+                                     hk, **prm)
+            best = st["ms"] if best is None else min(best, st["ms"])
+        print(json.dumps({"copies": copies, "members": k, "scatter": a, "list_entries": len(idx),
+                          "max_block_steps": st["max_block_steps"], "hermite_steps": st["steps"],
+                          "ms": best,
+                          "us_per_block_step": 1e3 * best / max(1, st["max_block_steps"])}),
+              flush=True)
+    ctx.close()
+
+
 def copy_calibration(mib=512, reps=3):
     """A plain device-to-device copy of known size, for scaling HBM byte counters
     (FETCH_SIZE / WRITE_SIZE) read by a profiler in the same way as the kernels."""
@@ -558,6 +608,8 @@ def main():
                     help="run the theta x n_crit sweep on the 2^22 workload instead")
     ap.add_argument("--configs", action="store_true",
                     help="time the small workloads (Plummer 4096, Plummer 65536 Salpeter) instead")
+    ap.add_argument("--hermite-probe", action="store_true",
+                    help="time the Hermite hard part on isolated groups (block-step latency)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 512 MiB device copy (profiler counter calibration)")
     args = ap.parse_args()
@@ -568,6 +620,9 @@ def main():
 
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.hermite_probe:
+        hermite_probe()
         return
     if args.sweep:
         sweep(args)

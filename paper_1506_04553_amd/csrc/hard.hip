@@ -82,7 +82,7 @@ struct HermConsts {
 // readback slots (int64 units) used here
 enum { RB_HBAD = 48, RB_HNHARD = 49, RB_HNCL = 50, RB_HMAXCL = 51, RB_HLIMIT = 52,
        RB_HSTEPS = 53, RB_HMAXBLK = 54, RB_HNNZ = 55, RB_HCLASS = 56 /* 4 int32 class sizes */,
-       RB_HGIANT = 58 };
+       RB_HGIANT = 58, RB_HSUB = 61 /* 5 int32 sub-class sizes of the < 64 class */ };
 
 // size classes by floor(log2(members)): < 64, < 256, < 1024, the rest
 constexpr int kClassBucket[3] = {5, 7, 9};
@@ -615,7 +615,10 @@ __global__ void k_giant_maxsteps(const int32_t *__restrict__ gsteps, int32_t n_g
 
 // cluster counts of the size classes, largest class first: [>= 1024, < 1024,
 // < 256, < 64] members (from the bucket histogram, before it is scanned)
-__global__ void k_cc_classes(const int32_t *bhist, int32_t *cls) {
+// and the < 64 class split by lanes per component, in the same (largest first)
+// order: [32, 64) members on 64 lanes, [16, 32) on 32, [8, 16) on 16, [4, 8) on
+// 8, [1, 4) on 4
+__global__ void k_cc_classes(const int32_t *bhist, int32_t *cls, int32_t *sub) {
     int32_t c[kNumClasses] = {0, 0, 0, 0};
     for (int b = 0; b < 32; ++b) {
         int k = 0;
@@ -624,6 +627,11 @@ __global__ void k_cc_classes(const int32_t *bhist, int32_t *cls) {
         c[k] += bhist[b];
     }
     for (int k = 0; k < kNumClasses; ++k) cls[k] = c[k];
+    sub[0] = bhist[5];
+    sub[1] = bhist[4];
+    sub[2] = bhist[3];
+    sub[3] = bhist[2];
+    sub[4] = bhist[0] + bhist[1];
 }
 
 // local index of every list entry: the neighbour's slot minus the first slot of
@@ -948,6 +956,181 @@ __global__ __launch_bounds__(T) void k_hermite_lds(
     if (tid == 0) atomicMax(rb + (RB_HMAXBLK - RB_HBAD), (unsigned long long)steps);
 }
 
+// Components of fewer than 64 members, several to a wavefront: SUB lanes per
+// component (4, 8, 16, 32 or 64), member k on lane k of its sub-group.  Every
+// sub-group runs its own block-step loop with the operations of k_hermite_lds
+// (its minimum of t + dt by shuffles inside the sub-group); the wavefront loops
+// until every sub-group is past t_end.  The list entries of a component with
+// fewer than 32 members always fit its share of the LDS area.
+constexpr int kPackEdges = 2048;
+
+template <int SUB>
+__device__ __forceinline__ void hermite_sub(
+    int slot, int32_t n_slots, const int32_t *__restrict__ cl_beg,
+    const int32_t *__restrict__ cl_end, const int32_t *__restrict__ order, int32_t order_base,
+    const int32_t *__restrict__ mem, const int64_t *__restrict__ off,
+    const int32_t *__restrict__ lidx, const double *__restrict__ mass, double *__restrict__ pos,
+    double *__restrict__ vel, const HardConsts &hc, const HermConsts &hp,
+    int32_t *__restrict__ nsteps_out, unsigned long long *rb, double *s_xp, double *s_vp,
+    double *s_m, int32_t *s_row, int32_t *s_nb, int8_t *s_sp) {
+    constexpr int P = kWave / SUB;           // components per wavefront
+    constexpr int NBCAP = kPackEdges / P;    // list entries in LDS per component
+    static_assert(SUB == kWave || SUB * (SUB - 1) <= NBCAP, "lists must fit");
+    const int tid = threadIdx.x, sub = tid / SUB, lt = tid % SUB;
+    const int cs = slot * P + sub;           // this sub-group's component, in launch order
+    const bool has = cs < n_slots;
+    const int c = has ? order[order_base + cs] : 0;
+    const int b = has ? cl_beg[c] : 0;
+    const int nm = has ? cl_end[c] - b : 0;
+    double *xs = s_xp + 3 * SUB * sub, *vs = s_vp + 3 * SUB * sub, *sm = s_m + SUB * sub;
+    int8_t *ssp = s_sp + SUB * sub;
+    int32_t *row = s_row + (SUB + 1) * sub, *nb = s_nb + NBCAP * sub;
+    const bool mine = lt < nm;               // this lane owns member lt
+    int32_t i = 0;
+    if (mine) {
+        i = mem[b + lt];
+        row[lt + 1] = (int32_t)(off[i + 1] - off[i]);
+        sm[lt] = mass[i];
+        ssp[lt] = i >= hc.first_sp;
+    }
+    __syncthreads();
+    if (lt == 0 && has) {
+        row[0] = 0;
+        for (int k = 1; k <= nm; ++k) row[k] += row[k - 1];
+    }
+    __syncthreads();
+    const int n_edges = has ? row[nm] : 0;
+    const bool in_lds = n_edges <= NBCAP;
+    const int64_t e0 = mine ? off[i] : 0;
+    if (in_lds && mine)
+        for (int q = row[lt]; q < row[lt + 1]; ++q) nb[q] = lidx[e0 + (q - row[lt])];
+    double x[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0}, a[3], jk[3];
+    double t = 0.0, dt = INFINITY;
+    int ns = 0;
+    if (mine)
+        for (int q = 0; q < 3; ++q) {
+            x[q] = pos[3 * i + q];
+            v[q] = vel[3 * i + q];
+            xs[3 * lt + q] = x[q];
+            vs[3 * lt + q] = v[q];
+        }
+    __syncthreads();
+    // neighbours of the member: local indices at nbp + rowb
+    const int32_t *nbp = in_lds ? nb : lidx;
+    const int64_t rowb = mine ? (in_lds ? (int64_t)row[lt] : e0) : 0;
+    const int64_t rowe = mine ? rowb + (row[lt + 1] - row[lt]) : 0;
+    if (mine) {
+        hard_sum_local(lt, xs, vs, sm, ssp, nbp, rowb, rowe, hc, a, jk);
+        const double cr = crit_first(a, jk, hp, ssp[lt] ? hp.eta_s_sp : hp.eta_s);
+        double d = hp.dt_max;
+        while (d > cr && d > hp.dt_min) d *= 0.5;
+        dt = d;
+    }
+    int64_t steps = 0;
+    bool live = has;
+    for (;;) {
+        double tn = mine ? t + dt : INFINITY;
+        for (int o = SUB / 2; o > 0; o >>= 1) tn = fmin(tn, __shfl_xor(tn, o));
+        const double t_next = tn;
+        if (live && !(t_next <= hp.t_end)) live = false;
+        if (live && steps == hp.max_block_steps) {
+            if (lt == 0) atomicOr(rb + (RB_HLIMIT - RB_HBAD), 1ull);
+            live = false;
+        }
+        if (!__any(live)) break;
+        if (live) ++steps;
+        __syncthreads();   // the previous step's reads of xs and vs are done
+        if (live && mine) {
+            const double h = t_next - t;
+            for (int q = 0; q < 3; ++q) {
+                xs[3 * lt + q] = x[q] + v[q] * h + a[q] * (h * h / 2.0) + jk[q] * (h * h * h / 6.0);
+                vs[3 * lt + q] = v[q] + a[q] * h + jk[q] * (h * h / 2.0);
+            }
+        }
+        __syncthreads();
+        if (live && mine && t + dt == t_next) {
+            double a1[3], j1[3], a2[3], a3[3];
+            hard_sum_local(lt, xs, vs, sm, ssp, nbp, rowb, rowe, hc, a1, j1);
+            const double h = dt;
+            for (int q = 0; q < 3; ++q) {
+                const double s2 = (-6.0 * (a[q] - a1[q]) - h * (4.0 * jk[q] + 2.0 * j1[q])) / (h * h);
+                const double s3 = (12.0 * (a[q] - a1[q]) + 6.0 * h * (jk[q] + j1[q])) / (h * h * h);
+                x[q] = xs[3 * lt + q] + s2 * (h * h * h * h / 24.0) + s3 * (h * h * h * h * h / 120.0);
+                v[q] = vs[3 * lt + q] + s2 * (h * h * h / 6.0) + s3 * (h * h * h * h / 24.0);
+                a[q] = a1[q];
+                jk[q] = j1[q];
+                a2[q] = s2 + s3 * h;
+                a3[q] = s3;
+            }
+            t = t_next;
+            ns += 1;
+            const double cr = crit_full(a, jk, a2, a3, hp, ssp[lt] ? hp.eta_sp : hp.eta);
+            double d = h;
+            if (2.0 * d <= cr && 2.0 * d <= hp.dt_max && fmod(t, 2.0 * d) == 0.0)
+                d = 2.0 * d;
+            else
+                while (d > cr && d > hp.dt_min) d *= 0.5;
+            dt = d;
+        }
+    }
+    unsigned long long my = 0;
+    if (mine) {
+        for (int q = 0; q < 3; ++q) {
+            pos[3 * i + q] = x[q];
+            vel[3 * i + q] = v[q];
+        }
+        if (nsteps_out) nsteps_out[i] = ns;
+        my = (unsigned long long)ns;
+    }
+    unsigned long long mx = (unsigned long long)steps;
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        my += __shfl_xor(my, o);
+        const unsigned long long y = __shfl_xor(mx, o);
+        mx = y > mx ? y : mx;
+    }
+    if (tid == 0 && my) atomicAdd(rb + (RB_HSTEPS - RB_HBAD), my);
+    if (tid == 0 && mx) atomicMax(rb + (RB_HMAXBLK - RB_HBAD), mx);
+}
+
+// Counts of the five packings, largest components first, as laid out in
+// `order` from order_base: n[0] components on 64 lanes, n[1] on 32, n[2] on 16,
+// n[3] on 8, n[4] on 4; blocks [0, bs[0]) take the first, [bs[0], bs[1]) the
+// second, ...
+constexpr int kPacks = 5;
+struct PackPlan {
+    int32_t n[kPacks];
+    int32_t bs[kPacks];
+};
+
+__global__ __launch_bounds__(kWave) void k_hermite_pack(
+    PackPlan pp, const int32_t *__restrict__ cl_beg, const int32_t *__restrict__ cl_end,
+    const int32_t *__restrict__ order, int32_t order_base, const int32_t *__restrict__ mem,
+    const int64_t *__restrict__ off, const int32_t *__restrict__ lidx,
+    const double *__restrict__ mass, double *__restrict__ pos, double *__restrict__ vel,
+    HardConsts hc, HermConsts hp, int32_t *__restrict__ nsteps_out, unsigned long long *rb) {
+    __shared__ double s_xp[3 * kWave], s_vp[3 * kWave], s_m[kWave];
+    __shared__ int32_t s_row[kWave + 16];
+    __shared__ int32_t s_nb[kPackEdges];
+    __shared__ int8_t s_sp[kWave];
+    const int bx = blockIdx.x;
+    const int32_t o1 = order_base + pp.n[0], o2 = o1 + pp.n[1], o3 = o2 + pp.n[2], o4 = o3 + pp.n[3];
+    if (bx < pp.bs[0])
+        hermite_sub<64>(bx, pp.n[0], cl_beg, cl_end, order, order_base, mem, off, lidx, mass,
+                        pos, vel, hc, hp, nsteps_out, rb, s_xp, s_vp, s_m, s_row, s_nb, s_sp);
+    else if (bx < pp.bs[1])
+        hermite_sub<32>(bx - pp.bs[0], pp.n[1], cl_beg, cl_end, order, o1, mem, off, lidx, mass,
+                        pos, vel, hc, hp, nsteps_out, rb, s_xp, s_vp, s_m, s_row, s_nb, s_sp);
+    else if (bx < pp.bs[2])
+        hermite_sub<16>(bx - pp.bs[1], pp.n[2], cl_beg, cl_end, order, o2, mem, off, lidx, mass,
+                        pos, vel, hc, hp, nsteps_out, rb, s_xp, s_vp, s_m, s_row, s_nb, s_sp);
+    else if (bx < pp.bs[3])
+        hermite_sub<8>(bx - pp.bs[2], pp.n[3], cl_beg, cl_end, order, o3, mem, off, lidx, mass,
+                       pos, vel, hc, hp, nsteps_out, rb, s_xp, s_vp, s_m, s_row, s_nb, s_sp);
+    else
+        hermite_sub<4>(bx - pp.bs[3], pp.n[4], cl_beg, cl_end, order, o4, mem, off, lidx, mass,
+                       pos, vel, hc, hp, nsteps_out, rb, s_xp, s_vp, s_m, s_row, s_nb, s_sp);
+}
+
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
@@ -1147,7 +1330,8 @@ int launch_hermite(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const doub
     k_cc_place<<<nb, 256, 0, st>>>(n, label, cstart, cfill, mem, slotv, pos, vel, hpar->dt_soft);
     k_cc_clusters<<<nb, 256, 0, st>>>(n, ccount, cstart, cid, cl_beg, cl_end, bhist,
                                       reinterpret_cast<unsigned long long *>(rb + RB_HMAXCL));
-    k_cc_classes<<<1, 1, 0, st>>>(bhist, reinterpret_cast<int32_t *>(rb + RB_HCLASS));
+    k_cc_classes<<<1, 1, 0, st>>>(bhist, reinterpret_cast<int32_t *>(rb + RB_HCLASS),
+                                  reinterpret_cast<int32_t *>(rb + RB_HSUB));
     k_cc_bucket_scan<<<1, 1, 0, st>>>(bhist);
     if (nsteps) {
         // isolated particles take no Hermite step
@@ -1158,12 +1342,16 @@ int launch_hermite(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const doub
         k_cc_order<<<blocks_for(n_cl, 256), 256, 0, st>>>(n_cl, cl_beg, cl_end, bfill, bhist, order);
         k_hard_local<<<nb, 256, 0, st>>>(n, off, idx, label, cid, cl_beg, slotv, lidx);
         if ((rc = check_hip(ctx, hipGetLastError(), "components"))) return rc;
-        if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + RB_HCLASS, rb + RB_HCLASS, 2 * sizeof(int64_t),
+        if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + RB_HCLASS, rb + RB_HCLASS,
+                                                (RB_HSUB + 3 - RB_HCLASS) * sizeof(int64_t),
                                                 hipMemcpyDeviceToHost, st), "readback")))
             return rc;
         if ((rc = check_hip(ctx, hipStreamSynchronize(st), "sync"))) return rc;
-        int32_t cls[kNumClasses];
+        int32_t cls[kNumClasses], sub[kPacks];
         memcpy(cls, ctx->hpin + RB_HCLASS, sizeof(cls));
+        memcpy(sub, ctx->hpin + RB_HSUB, sizeof(sub));
+        if (sub[0] + sub[1] + sub[2] + sub[3] + sub[4] != cls[3])
+            return set_error(ctx, P3T_EHIP, "component classes do not add up");
         HermConsts hc2;
         hc2.t_end = hpar->dt_soft;
         hc2.dt_max = hpar->dt_max;
@@ -1192,9 +1380,18 @@ int launch_hermite(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const doub
             k_hermite_lds<256, 1, 4096, 512><<<(unsigned)cls[2], 256, 0, ctx->aux[1]>>>(
                 cl_beg, cl_end, order, base_k, mem, off, lidx, mass, pos, vel, hk, hc2, nsteps, rbh);
         base_k += cls[2];
-        if (cls[3] > 0)
-            k_hermite_lds<64, 1, 2048, 0><<<(unsigned)cls[3], 64, 0, ctx->aux[2]>>>(
-                cl_beg, cl_end, order, base_k, mem, off, lidx, mass, pos, vel, hk, hc2, nsteps, rbh);
+        if (cls[3] > 0) {
+            PackPlan pp;
+            int32_t nbk = 0;
+            for (int k = 0; k < kPacks; ++k) {
+                const int per = 1 << k;   // components per block: 1, 2, 4, 8, 16
+                pp.n[k] = sub[k];
+                nbk += (sub[k] + per - 1) / per;
+                pp.bs[k] = nbk;
+            }
+            k_hermite_pack<<<(unsigned)nbk, kWave, 0, ctx->aux[2]>>>(
+                pp, cl_beg, cl_end, order, base_k, mem, off, lidx, mass, pos, vel, hk, hc2, nsteps, rbh);
+        }
 
         if ((rc = check_hip(ctx, hipGetLastError(), "hermite"))) return rc;
         if (cls[0] > 0 && (rc = run_giant(ctx, cls[0], order, cl_beg, cl_end, mem, slotv, off, idx,
