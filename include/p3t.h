@@ -182,6 +182,8 @@ int p3t_kinds_soft(p3t_ctx *ctx, int64_t n, const double *pos, const double *mas
  * special particles within r_search_ns; a special particle's row lists the
  * normal particles within r_search_ns and the other special particles (all of
  * them when split_ss = 0, else those within r_search_ss); rows ascending.
+ * The normal lists are checked like the hard part's (symmetric, in range, no
+ * self entry; nn_idx may be NULL only if every row is empty), EINVAL otherwise.
  *   off device [n+1] int64 out; idx device [cap] int32 out; nnz host out (set
  *   also on ECAPACITY).  Synchronises.  Errors: EINVAL, ECAPACITY, ENOMEM, EHIP. */
 int p3t_kinds_neighbors(p3t_ctx *ctx, int64_t n, const double *pos, const p3t_kinds *kinds,
@@ -192,7 +194,8 @@ int p3t_kinds_neighbors(p3t_ctx *ctx, int64_t n, const double *pos, const p3t_ki
  * neighbour lists).  Neighbour lists are CSR in original indices, as
  * p3t_neighbors writes them: offsets device [n+1] int64, idx device
  * [offsets[n]] int32; they must be symmetric (j on i's list iff i on j's),
- * free of self entries and in range, which is checked (EINVAL otherwise). */
+ * free of self entries and in range, which is checked (EINVAL otherwise); idx
+ * may be NULL only if every row is empty. */
 
 /* Hard force, its jerk and the hard potential of every particle from its
  * list (Section 2.1, F_hard with the cutoff function K; potential of H_hard):
@@ -241,7 +244,9 @@ typedef struct {
  * eta sqrt((sqrt(|a|^2 + a0^2) |a''| + |a'|^2) / (|a'| |a'''| + |a''|^2)), with
  * a'' and a''' from Hermite interpolation; a step doubles only where the
  * particle's time is a multiple of the doubled step.  Each connected
- * component of the neighbour graph is integrated by one workgroup.
+ * component of the neighbour graph is integrated on its own: by a group of
+ * lanes of a wavefront (fewer than 64 members), a workgroup (fewer than 1024)
+ * or grid-wide launches per block step.
  *   nsteps   device [n] int32 out (Hermite steps per particle) or NULL
  *   stats    host out or NULL
  * Synchronises the stream.  Errors: EINVAL, ENOMEM, ELIMIT, EHIP. */

@@ -183,13 +183,16 @@ __device__ inline void hard_sum(int64_t i, int64_t si, const double *__restrict_
 
 // Rows must be well formed before any kernel walks them: offsets non-decreasing
 // from a non-negative start, entries in [0, n), not the row's own particle, and
-// every listed particle's own row non-empty (symmetric lists).
+// every listed particle's own row non-empty (symmetric lists).  Without an
+// index array (HAS_IDX false) every row must be empty and nothing else is read.
+template <bool HAS_IDX>
 __global__ void k_hard_validate(int64_t n, const int64_t *__restrict__ off,
                                 const int32_t *__restrict__ idx, int64_t *bad) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t b = off[i], e = off[i + 1];
-    if (b < 0 || e < b) { atomicOr((unsigned long long *)bad, 1ull); return; }
+    if (b < 0 || e < b || (!HAS_IDX && e != b)) { atomicOr((unsigned long long *)bad, 1ull); return; }
+    if (!HAS_IDX) return;
     for (int64_t k = b; k < e; ++k) {
         const int32_t j = idx[k];
         if (j < 0 || j >= n || j == i) { atomicOr((unsigned long long *)bad, 1ull); return; }
@@ -1160,12 +1163,16 @@ static HardConsts hard_consts(const p3t_params *p, const p3t_kinds *kd, int64_t 
     return hc;
 }
 
-static int validate_lists(p3t_ctx *ctx, int64_t n, const int64_t *off, const int32_t *idx) {
+int validate_csr(p3t_ctx *ctx, int64_t n, const int64_t *off, const int32_t *idx) {
     int rc;
+    if ((rc = ensure(ctx, ctx->readback, 64 * sizeof(int64_t)))) return rc;
     int64_t *rb = ptr<int64_t>(ctx->readback);
     if ((rc = check_hip(ctx, hipMemsetAsync(rb + RB_HBAD, 0, sizeof(int64_t), ctx->stream), "memset")))
         return rc;
-    k_hard_validate<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, off, idx, rb + RB_HBAD);
+    if (idx)
+        k_hard_validate<true><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, off, idx, rb + RB_HBAD);
+    else
+        k_hard_validate<false><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, off, idx, rb + RB_HBAD);
     if ((rc = check_hip(ctx, hipGetLastError(), "list check"))) return rc;
     if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + RB_HBAD, rb + RB_HBAD, sizeof(int64_t),
                                             hipMemcpyDeviceToHost, ctx->stream), "readback")))
@@ -1174,7 +1181,7 @@ static int validate_lists(p3t_ctx *ctx, int64_t n, const int64_t *off, const int
     if (ctx->hpin[RB_HBAD])
         return set_error(ctx, P3T_EINVAL,
                          "neighbour lists malformed (bad offsets, index out of range, self entry, "
-                         "or not symmetric)");
+                         "not symmetric, or entries without an index array)");
     return P3T_OK;
 }
 
@@ -1263,7 +1270,7 @@ int launch_hard_force(p3t_ctx *ctx, int64_t n, const double *pos, const double *
                       double *pot) {
     int rc;
     if ((rc = ensure(ctx, ctx->readback, 64 * sizeof(int64_t)))) return rc;
-    if ((rc = validate_lists(ctx, n, off, idx))) return rc;
+    if ((rc = validate_csr(ctx, n, off, idx))) return rc;
     const HardConsts hc = hard_consts(p, kd, n);
     k_hard_force<<<blocks_for(n, kHardThreads), kHardThreads, 0, ctx->stream>>>(
         n, pos, vel, mass, off, idx, hc, acc, jerk, pot);
@@ -1279,7 +1286,7 @@ int launch_hermite(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const doub
     if ((rc = ensure(ctx, ctx->readback, 64 * sizeof(int64_t)))) return rc;
     if ((rc = aux_streams(ctx))) return rc;
     if ((rc = check_hip(ctx, hipEventRecord(ctx->ev[10], st), "event"))) return rc;
-    if ((rc = validate_lists(ctx, n, off, idx))) return rc;
+    if ((rc = validate_csr(ctx, n, off, idx))) return rc;
     // workspace: 7 per-particle int32 arrays, then per-slot state
     if ((rc = ensure(ctx, ctx->hard_ix, 7 * (size_t)(n + 1) * sizeof(int32_t)))) return rc;
     int32_t *par = ptr<int32_t>(ctx->hard_ix), *label = par + (n + 1), *ccount = label + (n + 1),

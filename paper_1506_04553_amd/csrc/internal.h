@@ -161,6 +161,11 @@ int launch_hermite(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const doub
                    const int64_t *off, const int32_t *idx, const p3t_params *p,
                    const p3t_kinds *kd, const p3t_hermite_params *hp, int32_t *nsteps,
                    p3t_hermite_stats *stats);
+// Checks a caller's symmetric neighbour CSR of n rows before any kernel walks it
+// (offsets non-decreasing from >= 0, entries in [0, n), no self entry, every
+// listed particle's own row non-empty); idx may be NULL only if every row is
+// empty.  P3T_OK or P3T_EINVAL (synchronises the stream).
+int validate_csr(p3t_ctx *ctx, int64_t n, const int64_t *off, const int32_t *idx);
 
 // Particle kinds (kinds.hip): soft sums of the pairs with a special particle,
 // and the neighbour lists of all particles with a radius per kind of pair.

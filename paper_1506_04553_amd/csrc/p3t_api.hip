@@ -349,6 +349,9 @@ extern "C" int p3t_kinds_neighbors(p3t_ctx *ctx, int64_t n, const double *pos,
         return set_error(ctx, P3T_EINVAL, "bad kinds-neighbour arguments");
     int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
     if (rc) return rc;
+    // the normal particles' lists come from the caller: check them first
+    const int64_t n_normal = n - kinds->n_special;
+    if (n_normal > 0 && (rc = validate_csr(ctx, n_normal, nn_off, nn_idx))) return rc;
     return launch_kinds_neighbors(ctx, n, pos, kinds, nn_off, nn_idx, off, idx, cap, nnz);
 }
 

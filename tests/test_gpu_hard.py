@@ -300,3 +300,59 @@ def test_p3t_energy_conservation(ctx):
     # at these steps the pairs cross the changeover band in a few soft steps, so the
     # error falls about linearly with dt_soft, not yet as dt_soft^2
     assert errs[0] < 1e-5 and errs[1] < 0.75 * errs[0]
+
+
+def test_null_index_array_through_the_abi(ctx):
+    """idx may be NULL only when every row is empty: then the hard force is zero
+    and the Hermite call drifts every particle; with a non-empty row the call is
+    rejected by the offsets-only check, before any kernel reads an entry.  The
+    kinds neighbour lists check the caller's normal lists the same way."""
+    import ctypes as C
+    import torch
+    from paper_1506_04553_amd.p3t import (HermiteParams, HermiteStats, Kinds, P3T_EINVAL, P3T_OK,
+                                          make_params)
+    L, h = ctx._L, ctx._h
+    rng = np.random.default_rng(71)
+    n = 40
+    pos, vel = _dev(rng.uniform(-1, 1, (n, 3))), _dev(rng.normal(size=(n, 3)))
+    mass = _dev(np.full(n, 1.0 / n))
+    p = make_params(**_params(0.01))
+    empty = _dev(np.zeros(n + 1, np.int64))
+    one = np.zeros(n + 1, np.int64)
+    one[1:] = 1
+    one = _dev(one)
+    acc = torch.full((n, 3), 7.0, dtype=torch.float64, device="cuda")
+    jerk = torch.full((n, 3), 7.0, dtype=torch.float64, device="cuda")
+    args = lambda off: (h, n, pos.data_ptr(), vel.data_ptr(), mass.data_ptr(), off.data_ptr(), None,
+                        C.byref(p), None, acc.data_ptr(), jerk.data_ptr(), None)
+    assert L.p3t_hard_force(*args(empty)) == P3T_OK
+    torch.cuda.synchronize()
+    assert not acc.any() and not jerk.any()
+    assert L.p3t_hard_force(*args(one)) == P3T_EINVAL
+    log(f"  NULL idx with an entry: {L.p3t_last_error(h).decode()}")
+    hp = HermiteParams(2.0 ** -7, 2.0 ** -9, 0.1, 0.01, 0.0, 0)
+    st = HermiteStats()
+    x0 = pos.clone()
+    assert L.p3t_hermite_hard(h, n, pos.data_ptr(), vel.data_ptr(), mass.data_ptr(),
+                              empty.data_ptr(), None, C.byref(p), None, C.byref(hp), None,
+                              C.byref(st)) == P3T_OK
+    torch.cuda.synchronize()
+    assert torch.equal(pos, x0 + 2.0 ** -7 * vel) and st.n_hard == 0
+    assert L.p3t_hermite_hard(h, n, pos.data_ptr(), vel.data_ptr(), mass.data_ptr(),
+                              one.data_ptr(), None, C.byref(p), None, C.byref(hp), None,
+                              C.byref(st)) == P3T_EINVAL
+    # kinds: the normal lists (first n - 2 rows) must be well formed
+    kd = Kinds(n_special=2, r_in_ns=0.001, r_out_ns=0.01, r_search_ns=0.011, eps_ns=1e-4,
+               split_ss=0, eta_sp=0.03, eta_s_sp=0.003)
+    out_off = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    out_idx = torch.empty(64, dtype=torch.int32, device="cuda")
+    nnz = C.c_int64(0)
+    nn_empty = _dev(np.zeros(n - 1, np.int64))
+    assert L.p3t_kinds_neighbors(h, n, pos.data_ptr(), C.byref(kd), nn_empty.data_ptr(), None,
+                                 out_off.data_ptr(), out_idx.data_ptr(), 64, C.byref(nnz)) == P3T_OK
+    asym = np.zeros(n - 1, np.int64)
+    asym[1:] = 1                             # 0 lists 1, 1 lists nothing
+    asym, bad = _dev(asym), _dev(np.array([1], np.int32))
+    assert L.p3t_kinds_neighbors(h, n, pos.data_ptr(), C.byref(kd), asym.data_ptr(),
+                                 bad.data_ptr(), out_off.data_ptr(), out_idx.data_ptr(), 64,
+                                 C.byref(nnz)) == P3T_EINVAL
