@@ -143,6 +143,15 @@ int p3t_neighbors(p3t_ctx *ctx, int64_t *offsets, int32_t *idx, int64_t cap, int
 int p3t_long_force_vjp(p3t_ctx *ctx, const double *w, const double *c, double *gpos,
                        double *gmass);
 
+/* Frees the interaction-list arrays of the last build (the largest part of a
+ * build's memory) and keeps the tree, moments and groups.  The next call that
+ * needs the lists (p3t_long_force, p3t_neighbors, p3t_long_force_vjp,
+ * p3t_copy_array of a list) walks the tree again first; the walk is
+ * deterministic, so the lists, forces and VJP are the same as without the
+ * release.  For a backward pass under memory pressure: release after the
+ * forward, recompute in the VJP.  Errors: ESTATE (no build), EHIP. */
+int p3t_release_lists(p3t_ctx *ctx);
+
 /* Leapfrog helpers of the shared-timestep soft step (Section 2.1, kick under
  * H_soft; drift): v += dt_kick * a, then x += dt_drift * v, elementwise over
  * [n][3] device arrays.  Errors: EINVAL, EHIP. */

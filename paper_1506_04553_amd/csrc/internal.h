@@ -79,6 +79,7 @@ struct p3t_ctx {
     char err[512] = {0};
 
     int built = 0;
+    int lists_released = 0;   // 1: the list arrays were freed; the next call that needs them walks again
     int64_t n = 0;
     p3t_params prm{};
     p3t::Changeover chg{};

@@ -199,6 +199,7 @@ extern "C" int p3t_build_tree(p3t_ctx *ctx, int64_t n, const double *pos, const 
     int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
     if (rc) return rc;
     ctx->built = 0;
+    ctx->lists_released = 0;
     ctx->n = n;
     ctx->prm = *p;
     ctx->chg = make_changeover(p->r_in, p->r_out);
@@ -220,12 +221,35 @@ extern "C" int p3t_build_tree(p3t_ctx *ctx, int64_t n, const double *pos, const 
     return P3T_OK;
 }
 
+// the lists of the current build, walked again if they were released
+static int ensure_lists(p3t_ctx *ctx) {
+    if (!ctx->lists_released) return P3T_OK;
+    const int rc = build_lists(ctx);
+    if (rc == P3T_OK) ctx->lists_released = 0;
+    return rc;
+}
+
+extern "C" int p3t_release_lists(p3t_ctx *ctx) {
+    if (!ctx) return P3T_EINVAL;
+    if (!ctx->built) return set_error(ctx, P3T_ESTATE, "p3t_release_lists before p3t_build_tree");
+    int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
+    if (rc) return rc;
+    // the stream's work may still read the lists: free only after it drains
+    if ((rc = check_hip(ctx, hipStreamSynchronize(ctx->stream), "sync"))) return rc;
+    release(ctx, ctx->c_idx);
+    release(ctx, ctx->p_idx);
+    release(ctx, ctx->n_idx);
+    ctx->lists_released = 1;
+    return P3T_OK;
+}
+
 extern "C" int p3t_long_force(p3t_ctx *ctx, double *acc, double *pot) {
     if (!ctx) return P3T_EINVAL;
     if (!ctx->built) return set_error(ctx, P3T_ESTATE, "p3t_long_force before p3t_build_tree");
     if (!acc) return set_error(ctx, P3T_EINVAL, "acc is NULL");
     int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
     if (rc) return rc;
+    if ((rc = ensure_lists(ctx))) return rc;
     if ((rc = mark(ctx, EV_FORCE))) return rc;
     if ((rc = launch_force(ctx, acc, pot))) return rc;
     if ((rc = mark(ctx, EV_FORCE + 1))) return rc;
@@ -240,6 +264,7 @@ extern "C" int p3t_neighbors(p3t_ctx *ctx, int64_t *offsets, int32_t *idx, int64
         return set_error(ctx, P3T_EINVAL, "bad neighbour buffers");
     int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
     if (rc) return rc;
+    if ((rc = ensure_lists(ctx))) return rc;
     if ((rc = mark(ctx, EV_NBR))) return rc;
     if ((rc = launch_neighbors(ctx, offsets, idx, cap, nnz))) return rc;
     if ((rc = mark(ctx, EV_NBR + 1))) return rc;
@@ -254,6 +279,7 @@ extern "C" int p3t_long_force_vjp(p3t_ctx *ctx, const double *w, const double *c
     if (!w || !gpos || !gmass) return set_error(ctx, P3T_EINVAL, "bad VJP buffers");
     int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
     if (rc) return rc;
+    if ((rc = ensure_lists(ctx))) return rc;
     if ((rc = mark(ctx, EV_VJP))) return rc;
     if ((rc = launch_vjp(ctx, w, c, gpos, gmass))) return rc;
     if ((rc = mark(ctx, EV_VJP + 1))) return rc;
@@ -470,6 +496,7 @@ extern "C" int p3t_copy_array(p3t_ctx *ctx, int which, void *dst, int64_t bytes)
     if (!ctx->built) return set_error(ctx, P3T_ESTATE, "no tree");
     int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
     if (rc) return rc;
+    if ((rc = ensure_lists(ctx))) return rc;
     if ((rc = check_hip(ctx, hipStreamSynchronize(ctx->stream), "sync"))) return rc;
     const int64_t n = ctx->n, nn = ctx->n_nodes, G = ctx->n_groups, stride = nn + 1;
     const void *src = nullptr;

@@ -80,7 +80,7 @@ EXPORTS = ("p3t_create", "p3t_destroy", "p3t_check_params", "p3t_build_tree", "p
            "p3t_neighbors", "p3t_long_force_vjp", "p3t_kick_drift", "p3t_get_stats",
            "p3t_copy_array", "p3t_status_string", "p3t_last_error", "p3t_hard_force",
            "p3t_hermite_hard", "p3t_step", "p3t_direct", "p3t_kinds_soft",
-           "p3t_kinds_neighbors")
+           "p3t_kinds_neighbors", "p3t_release_lists")
 
 DIRECT_MODES = {"newton": 0, "soft": 1, "hard": 2}
 
@@ -124,6 +124,7 @@ def load_library(path: str = LIB_PATH):
     L.p3t_long_force.argtypes = [V, V, V]
     L.p3t_neighbors.argtypes = [V, V, V, C.c_int64, C.POINTER(C.c_int64)]
     L.p3t_long_force_vjp.argtypes = [V, V, V, V, V]
+    L.p3t_release_lists.argtypes = [V]
     L.p3t_kick_drift.argtypes = [V, C.c_int64, V, V, V, C.c_double, C.c_double]
     L.p3t_get_stats.argtypes = [V, C.POINTER(Stats)]
     K = C.POINTER(Kinds)
@@ -267,6 +268,11 @@ class P3T:
                 continue
             self._check(rc)
             return off, idx[:nnz.value]
+
+    def release_lists(self):
+        """Free the last build's interaction lists; the next call that needs
+        them walks the tree again (same lists)."""
+        self._check(self._L.p3t_release_lists(self._h))
 
     def long_force_vjp(self, w: torch.Tensor, c: torch.Tensor | None = None):
         dev = torch.device("cuda", self.device)

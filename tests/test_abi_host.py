@@ -81,6 +81,7 @@ def test_null_context_and_status_strings(lib):
     assert lib.p3t_kinds_soft(None, 1, None, None, None, None, None, None) == -1
     assert lib.p3t_kinds_neighbors(None, 1, None, None, None, None, None, None, 0, None) == -1
     assert lib.p3t_direct(None, 1, None, None, None, 0, None, None) == -1
+    assert lib.p3t_release_lists(None) == -1
     lib.p3t_destroy(None)
     assert lib.p3t_status_string(0) == b"ok"
     assert lib.p3t_status_string(-3) == b"capacity exceeded"

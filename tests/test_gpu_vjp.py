@@ -206,3 +206,54 @@ def test_autograd_function_and_gradcheck(ctx):
     torch.autograd.gradcheck(f, (pos.detach().clone().requires_grad_(True),
                                  mass.detach().clone().requires_grad_(True)),
                              eps=1e-7, atol=1e-6, rtol=1e-5, nondet_tol=1e-12)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_released_lists_are_recomputed(ctx, precision):
+    """p3t_release_lists frees the interaction lists; the next force, neighbour
+    or VJP call walks the tree again.  The walk is deterministic, so forces and
+    neighbour lists are bit-identical and the VJP equal to rounding (its cell
+    adjoints are summed with atomics); the autograd function with
+    recompute_lists=True gives the same gradients."""
+    import torch
+    from paper_1506_04553_amd import long_force
+    c = make_cluster(WORKLOADS["plummer64k_salpeter"], seed=2, n=20000)
+    p = dict(WORKLOADS["plummer64k_salpeter"].params(precision=precision))
+    dev = torch.device("cuda", ctx.device)
+    pos, mass = torch.from_numpy(c.pos).to(dev), torch.from_numpy(c.mass).to(dev)
+    rng = np.random.default_rng(5)
+    w = torch.from_numpy(rng.normal(size=(len(c.mass), 3))).to(dev)
+    cw = torch.from_numpy(rng.normal(size=len(c.mass))).to(dev)
+    out = []
+    for release in (False, True):
+        ctx.build_tree(pos, mass, **p)
+        st0 = ctx.stats()
+        if release:
+            ctx.release_lists()
+            ctx.release_lists()   # twice is harmless
+        acc, pot = ctx.long_force()
+        if release:
+            ctx.release_lists()
+        off, idx = ctx.neighbors()
+        if release:
+            ctx.release_lists()
+        gp, gm = ctx.long_force_vjp(w, cw)
+        st1 = ctx.stats()
+        for k in ("n_cell_entries", "n_part_entries", "n_near_entries", "n_pc", "n_pp", "n_groups"):
+            assert st0[k] == st1[k], k
+        out.append([t.cpu().numpy() for t in (acc, pot, off, idx, gp, gm)])
+    a, b = out
+    for u, v in zip(a[:4], b[:4]):
+        assert np.array_equal(u, v)
+    assert rel_rms(b[4], a[4]) < 1e-13 and rel_rms(b[5], a[5]) < 1e-13
+    log(f"  recomputed lists ({precision}): forces and lists identical, "
+        f"VJP {rel_rms(b[4], a[4]):.1e}")
+    # the autograd function, with and without recomputation
+    grads = []
+    for rec in (False, True):
+        x = pos.clone().requires_grad_(True)
+        m = mass.clone().requires_grad_(True)
+        acc, pot = long_force(x, m, ctx, recompute_lists=rec, **p)
+        ((w * acc).sum() + (cw * pot).sum()).backward()
+        grads.append((x.grad.cpu().numpy(), m.grad.cpu().numpy()))
+    assert rel_rms(grads[1][0], grads[0][0]) < 1e-13 and rel_rms(grads[1][1], grads[0][1]) < 1e-13
