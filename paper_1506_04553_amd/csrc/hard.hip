@@ -1380,7 +1380,7 @@ int launch_hermite(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const doub
                 return rc;
         int32_t base_k = cls[0];
         if (cls[1] > 0)
-            k_hermite_lds<256, 4, 8192, 512><<<(unsigned)cls[1], 256, 0, ctx->aux[0]>>>(
+            k_hermite_lds<512, 2, 8192, 512><<<(unsigned)cls[1], 512, 0, ctx->aux[0]>>>(
                 cl_beg, cl_end, order, base_k, mem, off, lidx, mass, pos, vel, hk, hc2, nsteps, rbh);
         base_k += cls[1];
         if (cls[2] > 0)
