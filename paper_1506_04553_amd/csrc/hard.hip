@@ -964,18 +964,32 @@ __global__ __launch_bounds__(T) void k_hermite_lds(
 // sub-group runs its own block-step loop with the operations of k_hermite_lds
 // (its minimum of t + dt by shuffles inside the sub-group); the wavefront loops
 // until every sub-group is past t_end.  The list entries of a component with
-// fewer than 32 members always fit its share of the LDS area.
+// fewer than 32 members always fit its share of the LDS area.  With RP, a
+// block step spreads the active members' list entries over the sub-group's
+// lanes, SUB at a time, and each owner then adds its row's terms in list order
+// (the same sums as the loop over its own row), so that a member with many
+// neighbours no longer sets the length of the step alone.
 constexpr int kPackEdges = 2048;
 
-template <int SUB>
+template <bool RP>
+struct PackLds {
+    double xp[3 * kWave], vp[3 * kWave], m[kWave];
+    int32_t row[kWave + 16];
+    int32_t nb[kPackEdges];
+    int16_t ae[RP ? kPackEdges : 1];     // active entries of a step ...
+    int16_t aown[RP ? kPackEdges : 1];   // ... and their members
+    double term[RP ? 6 * kWave : 1];     // one chunk of terms per sub-group
+    int8_t sp[kWave];
+};
+
+template <int SUB, bool RP>
 __device__ __forceinline__ void hermite_sub(
     int slot, int32_t n_slots, const int32_t *__restrict__ cl_beg,
     const int32_t *__restrict__ cl_end, const int32_t *__restrict__ order, int32_t order_base,
     const int32_t *__restrict__ mem, const int64_t *__restrict__ off,
     const int32_t *__restrict__ lidx, const double *__restrict__ mass, double *__restrict__ pos,
     double *__restrict__ vel, const HardConsts &hc, const HermConsts &hp,
-    int32_t *__restrict__ nsteps_out, unsigned long long *rb, double *s_xp, double *s_vp,
-    double *s_m, int32_t *s_row, int32_t *s_nb, int8_t *s_sp) {
+    int32_t *__restrict__ nsteps_out, unsigned long long *rb, PackLds<RP> &L) {
     constexpr int P = kWave / SUB;           // components per wavefront
     constexpr int NBCAP = kPackEdges / P;    // list entries in LDS per component
     static_assert(SUB == kWave || SUB * (SUB - 1) <= NBCAP, "lists must fit");
@@ -985,9 +999,9 @@ __device__ __forceinline__ void hermite_sub(
     const int c = has ? order[order_base + cs] : 0;
     const int b = has ? cl_beg[c] : 0;
     const int nm = has ? cl_end[c] - b : 0;
-    double *xs = s_xp + 3 * SUB * sub, *vs = s_vp + 3 * SUB * sub, *sm = s_m + SUB * sub;
-    int8_t *ssp = s_sp + SUB * sub;
-    int32_t *row = s_row + (SUB + 1) * sub, *nb = s_nb + NBCAP * sub;
+    double *xs = L.xp + 3 * SUB * sub, *vs = L.vp + 3 * SUB * sub, *sm = L.m + SUB * sub;
+    int8_t *ssp = L.sp + SUB * sub;
+    int32_t *row = L.row + (SUB + 1) * sub, *nb = L.nb + NBCAP * sub;
     const bool mine = lt < nm;               // this lane owns member lt
     int32_t i = 0;
     if (mine) {
@@ -1051,9 +1065,55 @@ __device__ __forceinline__ void hermite_sub(
             }
         }
         __syncthreads();
-        if (live && mine && t + dt == t_next) {
-            double a1[3], j1[3], a2[3], a3[3];
+        const bool act = live && mine && t + dt == t_next;
+        double a1[3] = {0.0, 0.0, 0.0}, j1[3] = {0.0, 0.0, 0.0};
+        if (RP) {
+            // the active members' entries of this sub-group, gathered in row order
+            const bool par = in_lds;                 // the same on every lane of the sub-group
+            const int len = (act && par) ? row[lt + 1] - row[lt] : 0;
+            int incl = len;
+            for (int o = 1; o < SUB; o <<= 1) {
+                const int y = __shfl_up(incl, o, SUB);
+                if (lt >= o) incl += y;
+            }
+            const int base = incl - len;
+            const int n_act = __shfl(incl, SUB - 1, SUB);
+            int16_t *ae = L.ae + NBCAP * sub, *aown = L.aown + NBCAP * sub;
+            for (int q = 0; q < len; ++q) {
+                ae[base + q] = (int16_t)(row[lt] + q);
+                aown[base + q] = (int16_t)lt;
+            }
+            // chunks: as many as the longest sub-group of the wavefront needs
+            int chunks = (n_act + SUB - 1) / SUB;
+            for (int o = kWave / 2; o >= SUB; o >>= 1) chunks = max(chunks, __shfl_xor(chunks, o));
+            __syncthreads();
+            double *term = L.term + 6 * SUB * sub;
+            for (int k = 0; k < chunks; ++k) {
+                const int c0 = k * SUB, e = c0 + lt;
+                if (e < n_act) {
+                    double o[6];
+                    pair_terms(aown[e], nb[ae[e]], xs, vs, sm, ssp, hc, o);
+                    for (int q = 0; q < 6; ++q) term[6 * lt + q] = o[q];
+                }
+                __syncthreads();
+                const int r0 = max(base, c0), r1 = min(base + len, c0 + SUB);
+                for (int q = r0; q < r1; ++q) {
+                    const double *o = term + 6 * (q - c0);
+                    a1[0] += o[0];
+                    a1[1] += o[1];
+                    a1[2] += o[2];
+                    j1[0] += o[3];
+                    j1[1] += o[4];
+                    j1[2] += o[5];
+                }
+                __syncthreads();
+            }
+            if (act && !par) hard_sum_local(lt, xs, vs, sm, ssp, nbp, rowb, rowe, hc, a1, j1);
+        } else if (act) {
             hard_sum_local(lt, xs, vs, sm, ssp, nbp, rowb, rowe, hc, a1, j1);
+        }
+        if (act) {
+            double a2[3], a3[3];
             const double h = dt;
             for (int q = 0; q < 3; ++q) {
                 const double s2 = (-6.0 * (a[q] - a1[q]) - h * (4.0 * jk[q] + 2.0 * j1[q])) / (h * h);
@@ -1095,43 +1155,43 @@ __device__ __forceinline__ void hermite_sub(
     if (tid == 0 && mx) atomicMax(rb + (RB_HMAXBLK - RB_HBAD), mx);
 }
 
-// Counts of the five packings, largest components first, as laid out in
-// `order` from order_base: n[0] components on 64 lanes, n[1] on 32, n[2] on 16,
-// n[3] on 8, n[4] on 4; blocks [0, bs[0]) take the first, [bs[0], bs[1]) the
-// second, ...
+// The packings of one launch: n[k] components on 64 >> k lanes each, taken
+// from `order` at ob[k]; blocks [bs[k - 1], bs[k]) run packing k (bs[-1] = 0).
 constexpr int kPacks = 5;
 struct PackPlan {
     int32_t n[kPacks];
+    int32_t ob[kPacks];
     int32_t bs[kPacks];
 };
 
+template <bool RP>
 __global__ __launch_bounds__(kWave) void k_hermite_pack(
     PackPlan pp, const int32_t *__restrict__ cl_beg, const int32_t *__restrict__ cl_end,
-    const int32_t *__restrict__ order, int32_t order_base, const int32_t *__restrict__ mem,
+    const int32_t *__restrict__ order, const int32_t *__restrict__ mem,
     const int64_t *__restrict__ off, const int32_t *__restrict__ lidx,
     const double *__restrict__ mass, double *__restrict__ pos, double *__restrict__ vel,
     HardConsts hc, HermConsts hp, int32_t *__restrict__ nsteps_out, unsigned long long *rb) {
-    __shared__ double s_xp[3 * kWave], s_vp[3 * kWave], s_m[kWave];
-    __shared__ int32_t s_row[kWave + 16];
-    __shared__ int32_t s_nb[kPackEdges];
-    __shared__ int8_t s_sp[kWave];
+    __shared__ PackLds<RP> L;
     const int bx = blockIdx.x;
-    const int32_t o1 = order_base + pp.n[0], o2 = o1 + pp.n[1], o3 = o2 + pp.n[2], o4 = o3 + pp.n[3];
-    if (bx < pp.bs[0])
-        hermite_sub<64>(bx, pp.n[0], cl_beg, cl_end, order, order_base, mem, off, lidx, mass,
-                        pos, vel, hc, hp, nsteps_out, rb, s_xp, s_vp, s_m, s_row, s_nb, s_sp);
-    else if (bx < pp.bs[1])
-        hermite_sub<32>(bx - pp.bs[0], pp.n[1], cl_beg, cl_end, order, o1, mem, off, lidx, mass,
-                        pos, vel, hc, hp, nsteps_out, rb, s_xp, s_vp, s_m, s_row, s_nb, s_sp);
-    else if (bx < pp.bs[2])
-        hermite_sub<16>(bx - pp.bs[1], pp.n[2], cl_beg, cl_end, order, o2, mem, off, lidx, mass,
-                        pos, vel, hc, hp, nsteps_out, rb, s_xp, s_vp, s_m, s_row, s_nb, s_sp);
-    else if (bx < pp.bs[3])
-        hermite_sub<8>(bx - pp.bs[2], pp.n[3], cl_beg, cl_end, order, o3, mem, off, lidx, mass,
-                       pos, vel, hc, hp, nsteps_out, rb, s_xp, s_vp, s_m, s_row, s_nb, s_sp);
-    else
-        hermite_sub<4>(bx - pp.bs[3], pp.n[4], cl_beg, cl_end, order, o4, mem, off, lidx, mass,
-                       pos, vel, hc, hp, nsteps_out, rb, s_xp, s_vp, s_m, s_row, s_nb, s_sp);
+#define P3T_PACK_ARGS cl_beg, cl_end, order, pp.ob[K], mem, off, lidx, mass, pos, vel, hc, hp, \
+                      nsteps_out, rb, L
+    if (bx < pp.bs[0]) {
+        constexpr int K = 0;
+        hermite_sub<64, RP>(bx, pp.n[K], P3T_PACK_ARGS);
+    } else if (bx < pp.bs[1]) {
+        constexpr int K = 1;
+        hermite_sub<32, RP>(bx - pp.bs[0], pp.n[K], P3T_PACK_ARGS);
+    } else if (bx < pp.bs[2]) {
+        constexpr int K = 2;
+        hermite_sub<16, RP>(bx - pp.bs[1], pp.n[K], P3T_PACK_ARGS);
+    } else if (bx < pp.bs[3]) {
+        constexpr int K = 3;
+        hermite_sub<8, RP>(bx - pp.bs[2], pp.n[K], P3T_PACK_ARGS);
+    } else {
+        constexpr int K = 4;
+        hermite_sub<4, RP>(bx - pp.bs[3], pp.n[K], P3T_PACK_ARGS);
+    }
+#undef P3T_PACK_ARGS
 }
 
 // ---------------------------------------------------------------------------
@@ -1388,16 +1448,28 @@ int launch_hermite(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const doub
                 cl_beg, cl_end, order, base_k, mem, off, lidx, mass, pos, vel, hk, hc2, nsteps, rbh);
         base_k += cls[2];
         if (cls[3] > 0) {
-            PackPlan pp;
-            int32_t nbk = 0;
+            // the packings of 16 to 64 lanes (components of 8 to 63 members) with
+            // their terms spread over the lanes, on the context stream; those of
+            // 4 and 8 lanes on their own stream
+            PackPlan wide{}, narrow{};
+            int32_t ob = base_k, nw = 0, nn = 0;
             for (int k = 0; k < kPacks; ++k) {
                 const int per = 1 << k;   // components per block: 1, 2, 4, 8, 16
-                pp.n[k] = sub[k];
-                nbk += (sub[k] + per - 1) / per;
-                pp.bs[k] = nbk;
+                const int32_t blocks = (sub[k] + per - 1) / per;
+                PackPlan &pl = k < 3 ? wide : narrow;
+                int32_t &nb = k < 3 ? nw : nn;
+                pl.n[k] = sub[k];
+                pl.ob[k] = ob;
+                nb += blocks;
+                ob += sub[k];
+                for (int q = k; q < kPacks; ++q) pl.bs[q] = nb;
             }
-            k_hermite_pack<<<(unsigned)nbk, kWave, 0, ctx->aux[2]>>>(
-                pp, cl_beg, cl_end, order, base_k, mem, off, lidx, mass, pos, vel, hk, hc2, nsteps, rbh);
+            if (nn > 0)
+                k_hermite_pack<false><<<(unsigned)nn, kWave, 0, ctx->aux[2]>>>(
+                    narrow, cl_beg, cl_end, order, mem, off, lidx, mass, pos, vel, hk, hc2, nsteps, rbh);
+            if (nw > 0)
+                k_hermite_pack<true><<<(unsigned)nw, kWave, 0, st>>>(
+                    wide, cl_beg, cl_end, order, mem, off, lidx, mass, pos, vel, hk, hc2, nsteps, rbh);
         }
 
         if ((rc = check_hip(ctx, hipGetLastError(), "hermite"))) return rc;
