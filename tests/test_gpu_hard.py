@@ -356,3 +356,42 @@ def test_null_index_array_through_the_abi(ctx):
     assert L.p3t_kinds_neighbors(h, n, pos.data_ptr(), C.byref(kd), asym.data_ptr(),
                                  bad.data_ptr(), out_off.data_ptr(), out_idx.data_ptr(), 64,
                                  C.byref(nnz)) == P3T_EINVAL
+
+
+def test_hermite_every_packing(ctx):
+    """Components of every packing of the small-component kernels, bit for bit
+    against the oracle: about 40 members (one per 64 lanes, list in LDS, terms
+    spread over the lanes), 20 (two per wavefront), 10 (four), 5 (eight) and 2
+    (sixteen), with counts that leave the last wavefront of each packing partly
+    empty, so that finished and idle lane groups step beside live ones."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+    rng = np.random.default_rng(91)
+    parts, k = [], 0
+    for members, count, rad in ((40, 3, 0.012), (20, 5, 0.008), (10, 9, 0.006), (5, 17, 0.004),
+                                (2, 33, 0.003)):
+        for _ in range(count):
+            d = rng.normal(size=(members, 3))
+            d *= (rad * rng.uniform(0, 1, members) ** (1 / 3) / np.linalg.norm(d, axis=1))[:, None]
+            parts.append(np.array([k * 0.5, 0.0, 0.0]) + d)
+            k += 1
+    pos = np.concatenate(parts)
+    n = len(pos)
+    vel = rng.normal(scale=0.05, size=(n, 3))
+    mass = np.full(n, 1e-6)
+    p = dict(eps=1e-4, r_in=0.001, r_out=0.01, theta=0.5, r_search=0.011, n_crit=64, n_leaf=16)
+    off, idx = direct.brute_neighbors(pos, p["r_search"])
+    hard = np.diff(off) > 0
+    _, lab = connected_components(csr_matrix((np.ones(len(idx)), idx, off), shape=(n, n)),
+                                  directed=False)
+    sizes = np.bincount(lab[hard])
+    sizes = sizes[sizes > 0]
+    for lo, hi in ((2, 4), (4, 8), (8, 16), (16, 32), (32, 64)):
+        assert ((sizes >= lo) & (sizes < hi)).any(), (lo, hi)
+    hk = _hermite_kw(p["r_out"], mass, dt_soft=2.0 ** -6)
+    x, v, ns, st = _run_hermite(ctx, pos, vel, mass, off, idx, p, hk)
+    ox, ov, ons, _ = oracle.hermite(pos, vel, mass, off, idx, p["eps"], p["r_in"], p["r_out"],
+                                    **_okw(hk))
+    log(f"every packing: {st}; sizes {np.bincount(np.minimum(sizes, 64))[1:].tolist()}")
+    assert np.array_equal(ns, ons)
+    assert np.array_equal(x, ox) and np.array_equal(v, ov)
