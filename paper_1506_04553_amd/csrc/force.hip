@@ -231,12 +231,13 @@ __device__ __forceinline__ void pc_term(Slot<R> &q, const CJ<R> &c, R eps2, R ro
 
 // Per-tile loops of one wavefront over its slice of the staged entries, for
 // one or two active i-slots (TWO), so that the loop bodies carry no branch on
-// the slot count.
+// the slot count.  The FP64 loops are unrolled deeper (four entries): their
+// pipe otherwise waits on FP64 latencies.
 // Trip counts are wave-uniform: lanes past the end of a tile read the padding
 // entries (zero mass, far away), whose terms are exactly zero.
 template <class R, bool TWO>
 __device__ __forceinline__ void far_tile(Slot<R> *q, const PJ<R> *sp, int iters, int ns, R eps2) {
-#pragma unroll 2
+#pragma unroll(sizeof(R) == 8 ? 4 : 2)
     for (int it = 0; it < iters; ++it, sp += ns) {
         const PJ<R> pj = *sp;
         pp_fast<R>(q[0], pj, eps2);
@@ -269,7 +270,7 @@ __device__ __forceinline__ void near_tile(Slot<R> *q, const PJ<R> *sp, const int
 template <class R, bool QUAD, bool CHECK_K, bool TWO>
 __device__ __forceinline__ void cell_tile(Slot<R> *q, const CJ<R> *sc, int iters, int ns, R eps2,
                                           R rout2, const ForceParams &fp) {
-#pragma unroll 2
+#pragma unroll(sizeof(R) == 8 ? 4 : 2)
     for (int it = 0; it < iters; ++it, sc += ns) {
         const CJ<R> cj = *sc;
         pc_term<R, QUAD, CHECK_K>(q[0], cj, eps2, rout2, fp);
