@@ -250,11 +250,16 @@ __device__ __forceinline__ void near_tile(Slot<R> *q, const PJ<R> *sp, const int
                                           int ns, R eps2, R rout2, const ForceParams &fp) {
     for (int it = 0; it < iters; ++it, sp += ns, sj += ns) {
         const PJ<R> pj = *sp;
+        // the changeover path where s < r_out, and for a particle's own pair
+        // (zero offset: s^2 = eps^2 exactly), which only that path discards, also
+        // when the softening reaches beyond r_out
         const R dx0 = pj.x - q[0].x, dy0 = pj.y - q[0].y, dz0 = pj.z - q[0].z;
-        bool nr = fmaR(dx0, dx0, fmaR(dy0, dy0, fmaR(dz0, dz0, eps2))) < rout2;
+        const R r20 = fmaR(dx0, dx0, fmaR(dy0, dy0, fmaR(dz0, dz0, eps2)));
+        bool nr = (r20 < rout2) | (r20 == eps2);
         if (TWO) {
             const R dx1 = pj.x - q[1].x, dy1 = pj.y - q[1].y, dz1 = pj.z - q[1].z;
-            nr = nr | (fmaR(dx1, dx1, fmaR(dy1, dy1, fmaR(dz1, dz1, eps2))) < rout2);
+            const R r21 = fmaR(dx1, dx1, fmaR(dy1, dy1, fmaR(dz1, dz1, eps2)));
+            nr = nr | (r21 < rout2) | (r21 == eps2);
         }
         if (ballot(nr)) {
             const int32_t jid = *sj;

@@ -162,6 +162,10 @@ def _edge_cases():
     cases["large_theta"] = (plummer(3000, 18).pos, np.full(3000, 1 / 3000), dict(base, theta=1.5))
     # zero softening: every pair distance is positive except a particle's own
     cases["eps0"] = (plummer(2000, 19).pos, np.full(2000, 1 / 2000), dict(base, eps=0.0))
+    # softening beyond r_out: no pair reaches inside r_out, the own pair (s = eps)
+    # must still be left out of the potential
+    cases["eps_beyond_rout"] = (plummer(1500, 20).pos, np.full(1500, 1 / 1500),
+                                dict(base, eps=0.03))
     return cases
 
 
