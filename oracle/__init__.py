@@ -10,6 +10,7 @@ reduces to.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -64,49 +65,69 @@ def _kinds(kinds):
 _lib = None
 
 
+def _open(path: str):
+    """Load a build of the oracle's C sources and declare its signatures."""
+    L = C.CDLL(path)
+    P = C.c_void_p
+    L.or_build.argtypes = [C.c_int64, P, P, C.POINTER(_Params), C.POINTER(C.c_void_p)]
+    L.or_build.restype = C.c_int
+    L.or_build_ex.argtypes = [C.c_int64, P, P, C.POINTER(_Params), C.c_int64, C.POINTER(C.c_void_p)]
+    L.or_build_ex.restype = C.c_int
+    L.or_free.argtypes = [P]
+    L.or_force.argtypes = [P, P, P]
+    L.or_neighbors.argtypes = [P, P, P]
+    L.or_vjp.argtypes = [P, P, P, P, P]
+    L.or_refresh.argtypes = [P, P, P]
+    L.or_force_groups.argtypes = [P, P, C.c_int64, P, P]
+    for f in ("or_n_nodes", "or_n_groups"):
+        getattr(L, f).argtypes = [P]
+        getattr(L, f).restype = C.c_int64
+    L.or_root.argtypes = [P, P]
+    L.or_counts.argtypes = [P, P]
+    L.or_get_keys.argtypes = [P, P, P]
+    L.or_get_nodes.argtypes = [P] * 8
+    L.or_get_moments.argtypes = [P] * 7
+    L.or_get_groups.argtypes = [P, P]
+    L.or_get_lists.argtypes = [P] * 5
+    for f in ("or_K", "or_dK", "or_W", "or_W_over_y"):
+        getattr(L, f).argtypes = [C.c_double, C.c_double]
+        getattr(L, f).restype = C.c_double
+    L.or_C.argtypes = [C.c_double]
+    L.or_C.restype = C.c_double
+    L.or_morton.argtypes = [C.c_double, C.c_double, C.c_double, P, C.c_double]
+    L.or_morton.restype = C.c_uint64
+    L.or_num_threads.restype = C.c_int
+    L.or_set_threads.argtypes = [C.c_int]
+    L.or_set_threads.restype = None
+    L.or_hard_force.argtypes = [C.c_int64, P, P, P, P, P, C.c_double, C.c_double,
+                                C.c_double, C.POINTER(_Kinds), P, P, P]
+    L.or_hermite.argtypes = [C.c_int64, P, P, P, P, P, C.c_double, C.c_double, C.c_double,
+                             C.POINTER(_HermiteParams), C.POINTER(_Kinds), P, P]
+    L.or_hermite.restype = C.c_int
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         build(force=False)
-        L = C.CDLL(_LIB)
-        P = C.c_void_p
-        L.or_build.argtypes = [C.c_int64, P, P, C.POINTER(_Params), C.POINTER(C.c_void_p)]
-        L.or_build.restype = C.c_int
-        L.or_build_ex.argtypes = [C.c_int64, P, P, C.POINTER(_Params), C.c_int64, C.POINTER(C.c_void_p)]
-        L.or_build_ex.restype = C.c_int
-        L.or_free.argtypes = [P]
-        L.or_force.argtypes = [P, P, P]
-        L.or_neighbors.argtypes = [P, P, P]
-        L.or_vjp.argtypes = [P, P, P, P, P]
-        L.or_refresh.argtypes = [P, P, P]
-        L.or_force_groups.argtypes = [P, P, C.c_int64, P, P]
-        for f in ("or_n_nodes", "or_n_groups"):
-            getattr(L, f).argtypes = [P]
-            getattr(L, f).restype = C.c_int64
-        L.or_root.argtypes = [P, P]
-        L.or_counts.argtypes = [P, P]
-        L.or_get_keys.argtypes = [P, P, P]
-        L.or_get_nodes.argtypes = [P] * 8
-        L.or_get_moments.argtypes = [P] * 7
-        L.or_get_groups.argtypes = [P, P]
-        L.or_get_lists.argtypes = [P] * 5
-        for f in ("or_K", "or_dK", "or_W", "or_W_over_y"):
-            getattr(L, f).argtypes = [C.c_double, C.c_double]
-            getattr(L, f).restype = C.c_double
-        L.or_C.argtypes = [C.c_double]
-        L.or_C.restype = C.c_double
-        L.or_morton.argtypes = [C.c_double, C.c_double, C.c_double, P, C.c_double]
-        L.or_morton.restype = C.c_uint64
-        L.or_num_threads.restype = C.c_int
-        L.or_set_threads.argtypes = [C.c_int]
-        L.or_set_threads.restype = None
-        L.or_hard_force.argtypes = [C.c_int64, P, P, P, P, P, C.c_double, C.c_double,
-                                    C.c_double, C.POINTER(_Kinds), P, P, P]
-        L.or_hermite.argtypes = [C.c_int64, P, P, P, P, P, C.c_double, C.c_double, C.c_double,
-                                 C.POINTER(_HermiteParams), C.POINTER(_Kinds), P, P]
-        L.or_hermite.restype = C.c_int
-        _lib = L
+        _lib = _open(_LIB)
     return _lib
+
+
+@contextlib.contextmanager
+def swapped_library(path: str):
+    """Run this module's functions on another build of the oracle's sources
+    inside the ``with`` block.  The tests build copies with a planted mistake
+    to show that the pins catch it; free every Tree made inside the block
+    before it ends."""
+    global _lib
+    old = lib()
+    _lib = _open(path)
+    try:
+        yield
+    finally:
+        _lib = old
 
 
 def _ptr(a: np.ndarray):
