@@ -146,7 +146,7 @@ int p3t_long_force_vjp(p3t_ctx *ctx, const double *w, const double *c, double *g
 /* Frees the interaction-list arrays of the last build (the largest part of a
  * build's memory) and keeps the tree, moments and groups.  The next call that
  * needs the lists (p3t_long_force, p3t_neighbors, p3t_long_force_vjp,
- * p3t_copy_array of a list) walks the tree again first; the walk is
+ * p3t_step, p3t_copy_array of a list) walks the tree again first; the walk is
  * deterministic, so the lists, forces and VJP are the same as without the
  * release.  For a backward pass under memory pressure: release after the
  * forward, recompute in the VJP.  Errors: ESTATE (no build), EHIP. */
@@ -158,7 +158,7 @@ int p3t_release_lists(p3t_ctx *ctx);
 int p3t_kick_drift(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const double *acc,
                    double dt_kick, double dt_drift);
 
-/* Particle kinds (Section 3.3, the SMBH runs): the last n_special particles
+/* Particle kinds (Section 3.2.2, the SMBH runs): the last n_special particles
  * of the arrays are special.  A normal-special pair takes its own cutoffs,
  * softening and neighbour radius; a special-special pair its own softening and,
  * with split_ss = 0, no soft part at all (K = W = 0: the pair is integrated
@@ -276,6 +276,10 @@ int p3t_hermite_hard(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const do
  * part and soft sums take each pair's own parameters.
  *   pos, vel device [n][3]; mass device [n]; acc device [n][3] in/out;
  *   pot device [n] out or NULL; stats: the hard part's, host out or NULL.
+ * The neighbour radius must reach the outer cutoff (Section 2.2: h = r_cut plus
+ * a buffer): r_search >= r_out, and with kinds r_search_ns >= r_out_ns (and
+ * r_search_ss >= r_out_ss when split_ss = 1); otherwise the pairs between h and
+ * r_out would lose their hard force, and the call returns EINVAL.
  * Errors: ESTATE, EINVAL, ENOMEM, ELIMIT, EHIP. */
 int p3t_step(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const double *mass, double *acc,
              double *pot, const p3t_params *p, const p3t_kinds *kinds,

@@ -12,7 +12,7 @@ Everything here is written directly from the definitions, in numpy FP64:
 * neighbour sets "within distance h" (Section 2.2) by testing every pair with
   dx*dx + dy*dy + dz*dz < h*h;
 * the gradient of L = sum w.a + sum c.phi of the direct soft sum;
-* particle kinds (Section 3.3, the SMBH runs): the soft sum of the pairs that
+* particle kinds (Section 3.2.2, the SMBH runs): the soft sum of the pairs that
   involve a special particle, each pair with its own parameters, and the
   neighbour sets with a radius per kind of pair.
 """
@@ -199,7 +199,7 @@ def plummer_accel(r, a=3.0 * math.pi / 16.0):
 
 def _kind_pair(n_total, n_special, i, j, eps, r_in, r_out, kinds):
     """(eps, r_in, r_out, split) of the pair (i, j) by kinds: the last
-    n_special particles are special (Section 3.3)."""
+    n_special particles are special (Section 3.2.2)."""
     first = n_total - n_special
     si, sj = i >= first, j >= first
     if si and sj:

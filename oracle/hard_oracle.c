@@ -47,7 +47,7 @@
  *   a0          the softening term of the criteria is passed in (alpha m / r_cut^2
  *               with m chosen by the caller);
  *   kinds       optionally the last n_special particles are special (the SMBHs of
- *               Section 3.3): a normal-special pair takes its own r_in, r_cut and
+ *               Section 3.2.2): a normal-special pair takes its own r_in, r_cut and
  *               softening, a special-special pair its own softening and, when it
  *               is not split, K = W = 0 (the pair is wholly hard: no soft force);
  *               special particles take their own eta and eta_s.

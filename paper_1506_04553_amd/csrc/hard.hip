@@ -183,8 +183,10 @@ __device__ inline void hard_sum(int64_t i, int64_t si, const double *__restrict_
 
 // Rows must be well formed before any kernel walks them: offsets non-decreasing
 // from a non-negative start, entries in [0, n), not the row's own particle, and
-// every listed particle's own row non-empty (symmetric lists).  Without an
-// index array (HAS_IDX false) every row must be empty and nothing else is read.
+// symmetric (i is on the row of every j on i's row; the components of the
+// neighbour graph are joined from one end of each edge, and the integrators
+// index a neighbour inside its component).  Without an index array (HAS_IDX
+// false) every row must be empty and nothing else is read.
 template <bool HAS_IDX>
 __global__ void k_hard_validate(int64_t n, const int64_t *__restrict__ off,
                                 const int32_t *__restrict__ idx, int64_t *bad) {
@@ -196,7 +198,11 @@ __global__ void k_hard_validate(int64_t n, const int64_t *__restrict__ off,
     for (int64_t k = b; k < e; ++k) {
         const int32_t j = idx[k];
         if (j < 0 || j >= n || j == i) { atomicOr((unsigned long long *)bad, 1ull); return; }
-        if (off[j + 1] <= off[j]) { atomicOr((unsigned long long *)bad, 1ull); return; }
+        const int64_t jb = off[j], je = off[j + 1];
+        if (jb < 0 || je < jb) { atomicOr((unsigned long long *)bad, 1ull); return; }
+        bool back = false;   // rows need not be sorted: a linear search of j's row
+        for (int64_t t = jb; t < je && !back; ++t) back = idx[t] == (int32_t)i;
+        if (!back) { atomicOr((unsigned long long *)bad, 1ull); return; }
     }
 }
 

@@ -1,4 +1,4 @@
-// kinds.hip -- particle kinds for the SMBH runs (Section 3.3): the last
+// kinds.hip -- particle kinds for the SMBH runs (Section 3.2.2): the last
 // n_special particles of the arrays are special; a pair of a normal and a
 // special particle takes its own cutoff radii, softening and neighbour radius,
 // and a pair of two special particles its own softening and, when it is not

@@ -384,6 +384,8 @@ extern "C" int p3t_kinds_neighbors(p3t_ctx *ctx, int64_t n, const double *pos,
 // neighbour lists of the current build into buf_off/buf_idx, grown as needed
 static int step_neighbors(p3t_ctx *ctx, int64_t n_rows, int64_t *nnz) {
     int rc;
+    // the search reads the build's near lists: walk again if they were released
+    if ((rc = ensure_lists(ctx))) return rc;
     if ((rc = ensure(ctx, ctx->step_off, (size_t)(n_rows + 1) * sizeof(int64_t)))) return rc;
     int64_t cap = (int64_t)(ctx->step_idx.bytes / sizeof(int32_t));
     if (cap < 1) {
@@ -406,6 +408,13 @@ extern "C" int p3t_step(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const
     if (!pos || !vel || !mass || !acc || p3t_check_params(p) != P3T_OK || !hermite_params_ok(hp) ||
         n < 1 || !kinds_ok(kinds, n))
         return set_error(ctx, P3T_EINVAL, "bad step arguments");
+    // Section 2.2: the neighbour radius is r_cut plus a buffer, so every pair
+    // with a hard part (s < r_out) is on the lists the step integrates; a
+    // smaller radius would drop the (1 - K) force of the pairs between h and r_out
+    if (p->r_search < p->r_out ||
+        (has_special(kinds) && (kinds->r_search_ns < kinds->r_out_ns ||
+                                (kinds->split_ss && kinds->r_search_ss < kinds->r_out_ss))))
+        return set_error(ctx, P3T_EINVAL, "p3t_step needs r_search >= r_out for every kind of pair");
     const int64_t n_sp = has_special(kinds) ? kinds->n_special : 0, n_tree = n - n_sp;
     if (!ctx->built || ctx->n != n_tree || n_tree < 1)
         return set_error(ctx, P3T_ESTATE, "p3t_step needs a build of the normal particles");

@@ -150,7 +150,8 @@ def load_library(path: str = LIB_PATH):
 
 
 def make_params(eps, r_in, r_out, theta, r_search, n_crit=64, n_leaf=16, use_quadrupole=1,
-                precision=PREC_FP64, **_ignored) -> Params:
+                precision=PREC_FP64) -> Params:
+    """The p3t_params struct; an unknown or misspelt name raises TypeError."""
     if isinstance(precision, str):
         precision = {"fp64": PREC_FP64, "mixed": PREC_MIXED}[precision]
     return Params(float(eps), float(r_in), float(r_out), float(theta), float(r_search),

@@ -21,6 +21,31 @@ def rel_rms(a, b):
     return float(np.sqrt(((a - b) ** 2).sum() / den)) if den > 0 else float(np.abs(a - b).max())
 
 
+# Per-row bounds: the error of a particle's acceleration (vector norm) or
+# potential, over the larger of its own magnitude and 1e-3 of the RMS
+# magnitude (rows whose terms nearly cancel are held to the RMS scale).  The
+# FP64 path sums the same terms as the oracle in another order (about 1e-16
+# per term); the mixed path rounds each term to FP32 (about 6e-8) on offsets
+# from the group's centre.
+ROW_TOL = {"fp64": 1e-11, "mixed": 1e-3}
+
+
+def row_errors(a, ref):
+    """Largest per-row relative error of a [n,3] or [n] array against ref."""
+    a = np.asarray(a, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    if ref.ndim == 1:
+        a, ref = a[:, None], ref[:, None]
+    if len(ref) == 0:
+        return 0.0
+    mag = np.sqrt((ref ** 2).sum(1))
+    floor = 1e-3 * float(np.sqrt((mag ** 2).mean()))
+    if floor == 0.0:
+        return float(np.abs(a - ref).max())
+    err = np.sqrt(((a - ref) ** 2).sum(1))
+    return float((err / np.maximum(mag, floor)).max())
+
+
 def gpu_run(ctx, pos, mass, params, want_neighbors=True, want_arrays=True):
     """Build + force (+ neighbours) on the GPU; returns host numpy results."""
     import torch

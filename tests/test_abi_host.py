@@ -98,3 +98,14 @@ def test_create_rejects_bad_arguments(lib):
     assert rc == -1 and not h.value
     rc = lib.p3t_create(C.byref(h), -1, None, ALLOC_FN(0), FREE_FN(0), None)
     assert rc == -1 and not h.value
+
+
+def test_make_params_rejects_unknown_names():
+    """A misspelt parameter name must not be dropped silently."""
+    from paper_1506_04553_amd import make_params
+    d = dict(eps=1e-3, r_in=1e-3, r_out=1e-2, theta=0.5, r_search=1.1e-2)
+    make_params(**d)
+    with pytest.raises(TypeError):
+        make_params(**d, n_crti=64)
+    with pytest.raises(TypeError):
+        make_params(**d, quadrupole=1)

@@ -8,6 +8,8 @@ must agree bit for bit, and so must the Hermite trajectories and step counts
 built from them.  The potential uses the device logarithm in the changeover
 region and is compared to 1e-14 relative.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -265,41 +267,53 @@ def test_p3t_step_matches_oracle_composition(ctx):
 
 
 def test_p3t_energy_conservation(ctx):
-    """Whole P3T steps of a Plummer cluster (N = 2048): the total energy,
-    kinetic plus the full softened Newton potential from the direct sum, is
-    conserved to the scheme's error, which falls as the soft step falls."""
-    import torch
-    n = 2048
+    """Whole P3T steps of a Plummer cluster (N = 512) over 1/8 time unit: the
+    total energy (kinetic plus the softened Newton potential of the direct
+    sum) is conserved to the splitting error of the scheme, which is second
+    order (Section 2.1: half kick, Hermite, half kick), so each halving of
+    the soft step cuts the error four-fold.  theta = 0 makes the soft force
+    exact, eta = 0.01 puts the Hermite error far below the splitting error,
+    r_out = 0.1 keeps dt_soft sigma / r_cut small (0.03 - 0.11) and the buffer
+    is 3 sigma dt_soft (Section 3.1.1).  The errors match those of the same
+    steps composed from oracle pieces."""
+    from tests.test_oracle_hard import p3t_energy_errors
+    n = 512
     c = plummer(n, 91)
-    # theta = 0: the soft force is exact, so only the integration error remains
-    p = dict(eps=1.0 / 256, r_in=0.002, r_out=0.02, theta=0.0, r_search=0.03, n_crit=64,
-             n_leaf=16, precision="fp64")
+    r_out, eta = 0.1, 0.01
     mass = _dev(c.mass)
+    dts = (2.0 ** -6, 2.0 ** -7, 2.0 ** -8)
 
-    def energy(pos, vel):
+    def energy(pos, vel, p):
         _, ph = ctx.direct(pos, mass, "newton", **p)
         return float(0.5 * (mass * (vel * vel).sum(1)).sum() + 0.5 * (mass * ph).sum())
 
     errs = []
-    for dt in (2.0 ** -7, 2.0 ** -8):
+    for dt in dts:
+        p = dict(eps=1.0 / 256, r_in=0.1 * r_out, r_out=r_out, theta=0.0,
+                 r_search=r_out + 3.0 / math.sqrt(2.0) * dt, n_crit=64, n_leaf=16,
+                 precision="fp64")
         pos, vel = _dev(c.pos), _dev(c.vel)
-        e0 = energy(pos, vel)
+        e0 = energy(pos, vel, p)
         ctx.build_tree(pos, mass, **p)
         acc, _ = ctx.long_force(want_pot=False)
-        hk = dict(dt_soft=dt, dt_max=dt / 4, eta=0.1, eta_s=0.01,
-                  a0=0.1 * float(c.mass.mean()) / p["r_out"] ** 2, max_block_steps=200000)
+        hk = dict(dt_soft=dt, dt_max=dt / 4, eta=eta, eta_s=eta / 10,
+                  a0=0.1 * float(c.mass.mean()) / r_out ** 2, max_block_steps=200000)
         steps = int(round(0.125 / dt))
         n_hard = 0
         for _ in range(steps):
             st = ctx.step(pos, vel, mass, acc, hk, **p)
             n_hard = max(n_hard, st["n_hard"])
-        errs.append(abs(energy(pos, vel) - e0) / abs(e0))
+        errs.append(abs(energy(pos, vel, p) - e0) / abs(e0))
         log(f"p3t energy: dt_soft {dt:g}, {steps} steps, up to {n_hard} hard particles, "
-            f"|dE/E| {errs[-1]:.2e}")
+            f"|dE/E| {errs[-1]:.3e}")
         assert n_hard > 0
-    # at these steps the pairs cross the changeover band in a few soft steps, so the
-    # error falls about linearly with dt_soft, not yet as dt_soft^2
-    assert errs[0] < 1e-5 and errs[1] < 0.75 * errs[0]
+    ref = p3t_energy_errors(oracle, dts, n=n, r_out=r_out, eta=eta)
+    log(f"  oracle composition: {['%.3e' % e for e in ref]}; ratios "
+        f"{errs[1] / errs[0]:.3f} {errs[2] / errs[1]:.3f}")
+    assert errs[0] < 1e-4
+    assert errs[1] < 0.35 * errs[0] and errs[2] < 0.35 * errs[1], errs
+    for g, o in zip(errs, ref):
+        assert abs(g - o) <= 0.01 * o, (errs, ref)
 
 
 def test_null_index_array_through_the_abi(ctx):
@@ -395,3 +409,105 @@ def test_hermite_every_packing(ctx):
     log(f"every packing: {st}; sizes {np.bincount(np.minimum(sizes, 64))[1:].tolist()}")
     assert np.array_equal(ns, ons)
     assert np.array_equal(x, ox) and np.array_equal(v, ov)
+
+
+def test_asymmetric_lists_are_rejected(ctx):
+    """Every row non-empty but the lists not symmetric (2 lists 0, 0 does not
+    list 2): the hard force, the Hermite integration and the kinds neighbour
+    merge must reject them with EINVAL before any kernel uses them, and leave
+    the outputs untouched."""
+    import ctypes as C
+    import torch
+    from paper_1506_04553_amd.p3t import (HermiteParams, HermiteStats, Kinds, P3T_EINVAL, P3T_OK,
+                                          make_params)
+    L, h = ctx._L, ctx._h
+    rng = np.random.default_rng(72)
+    n = 4
+    pos, vel = _dev(rng.uniform(-0.002, 0.002, (n, 3))), _dev(rng.normal(size=(n, 3)))
+    mass = _dev(np.full(n, 1.0 / n))
+    p = make_params(**_params(0.01))
+    # rows: 0 -> {1}, 1 -> {0, 3}, 2 -> {0}, 3 -> {1}
+    off = _dev(np.array([0, 1, 3, 4, 5], np.int64))
+    idx = _dev(np.array([1, 0, 3, 0, 1], np.int32))
+    acc = torch.full((n, 3), 7.0, dtype=torch.float64, device="cuda")
+    jerk = torch.full((n, 3), 7.0, dtype=torch.float64, device="cuda")
+    rc = L.p3t_hard_force(h, n, pos.data_ptr(), vel.data_ptr(), mass.data_ptr(), off.data_ptr(),
+                          idx.data_ptr(), C.byref(p), None, acc.data_ptr(), jerk.data_ptr(), None)
+    assert rc == P3T_EINVAL, rc
+    log(f"  asymmetric lists: {L.p3t_last_error(h).decode()}")
+    torch.cuda.synchronize()
+    assert bool((acc == 7.0).all()) and bool((jerk == 7.0).all())
+    hp = HermiteParams(2.0 ** -7, 2.0 ** -9, 0.1, 0.01, 0.0, 0)
+    st = HermiteStats()
+    x0 = pos.clone()
+    assert L.p3t_hermite_hard(h, n, pos.data_ptr(), vel.data_ptr(), mass.data_ptr(),
+                              off.data_ptr(), idx.data_ptr(), C.byref(p), None, C.byref(hp), None,
+                              C.byref(st)) == P3T_EINVAL
+    torch.cuda.synchronize()
+    assert torch.equal(pos, x0)
+    # the same lists made symmetric (0 also lists 2) are accepted
+    off_s = _dev(np.array([0, 2, 4, 5, 6], np.int64))
+    idx_s = _dev(np.array([1, 2, 0, 3, 0, 1], np.int32))
+    rc = L.p3t_hard_force(h, n, pos.data_ptr(), vel.data_ptr(), mass.data_ptr(),
+                          off_s.data_ptr(), idx_s.data_ptr(), C.byref(p), None, acc.data_ptr(),
+                          jerk.data_ptr(), None)
+    assert rc == P3T_OK, rc
+    # kinds: the same asymmetric rows as the normal particles' lists of six
+    # particles, the last two special
+    kd = Kinds(n_special=2, r_in_ns=0.001, r_out_ns=0.01, r_search_ns=0.011, eps_ns=1e-4,
+               split_ss=0, eta_sp=0.03, eta_s_sp=0.003)
+    pos6 = _dev(rng.uniform(-0.002, 0.002, (6, 3)))
+    out_off = torch.full((7,), -7, dtype=torch.int64, device="cuda")
+    out_idx = torch.empty(64, dtype=torch.int32, device="cuda")
+    nnz = C.c_int64(0)
+    assert L.p3t_kinds_neighbors(h, 6, pos6.data_ptr(), C.byref(kd), off.data_ptr(),
+                                 idx.data_ptr(), out_off.data_ptr(), out_idx.data_ptr(), 64,
+                                 C.byref(nnz)) == P3T_EINVAL
+    torch.cuda.synchronize()
+    assert bool((out_off == -7).all())
+    assert L.p3t_kinds_neighbors(h, 6, pos6.data_ptr(), C.byref(kd), off_s.data_ptr(),
+                                 idx_s.data_ptr(), out_off.data_ptr(), out_idx.data_ptr(), 64,
+                                 C.byref(nnz)) == P3T_OK
+
+
+def test_step_after_released_lists(ctx):
+    """p3t_step reads the build's near lists for its neighbour search: after
+    p3t_release_lists it must walk the tree again first, and give bit for bit
+    the step it gives without the release."""
+    n = 4096
+    c = plummer(n, 82)
+    p = dict(eps=4.0 / n, r_in=0.003, r_out=0.03, theta=0.5, r_search=0.04, n_crit=64,
+             n_leaf=16, precision="mixed")
+    hk = _hermite_kw(p["r_out"], c.mass, dt_soft=2.0 ** -6)
+    out = []
+    for release in (False, True):
+        pos, vel, mass = _dev(c.pos), _dev(c.vel), _dev(c.mass)
+        ctx.build_tree(pos, mass, **p)
+        acc, _ = ctx.long_force()
+        if release:
+            ctx.release_lists()
+        st = ctx.step(pos, vel, mass, acc, hk, **p)
+        out.append([t.cpu().numpy() for t in (pos, vel, acc)] + [st["n_hard"], st["steps"]])
+    a, b = out
+    assert all(np.array_equal(u, v) for u, v in zip(a[:3], b[:3]))
+    assert a[3:] == b[3:] and a[3] > 0
+    log(f"  step after release: identical ({a[3]} hard particles, {a[4]} Hermite steps)")
+
+
+def test_step_rejects_search_radius_below_r_out(ctx):
+    """The step's lists must hold every pair inside r_out (h = r_cut + a buffer,
+    Section 2.2): r_search < r_out is EINVAL, positions untouched."""
+    from paper_1506_04553_amd import P3TError
+    from paper_1506_04553_amd.p3t import P3T_EINVAL
+    n = 1024
+    c = plummer(n, 83)
+    p = dict(eps=4.0 / n, r_in=0.003, r_out=0.03, theta=0.5, r_search=0.02, n_crit=64,
+             n_leaf=16, precision="fp64")
+    hk = _hermite_kw(p["r_out"], c.mass, dt_soft=2.0 ** -6)
+    pos, vel, mass = _dev(c.pos), _dev(c.vel), _dev(c.mass)
+    ctx.build_tree(pos, mass, **p)
+    acc, _ = ctx.long_force()
+    with pytest.raises(P3TError) as e:
+        ctx.step(pos, vel, mass, acc, hk, **p)
+    assert e.value.status == P3T_EINVAL
+    assert np.array_equal(pos.cpu().numpy(), c.pos) and np.array_equal(vel.cpu().numpy(), c.vel)

@@ -1,4 +1,4 @@
-"""GPU particle kinds (Section 3.3, the SMBH runs) against the oracle: two
+"""GPU particle kinds (Section 3.2.2, the SMBH runs) against the oracle: two
 SMBH particles of 1 % of the galaxy mass each at (+-0.5, 0, 0) with velocities
 (0, +-0.5, 0) in a Plummer galaxy; r_cut between field stars 1/256, between an
 SMBH and a field star 1/32; softening 1e-4 except between the SMBHs (none, and

@@ -3,14 +3,17 @@
 Keys, order, topology, centres of mass, boxes, groups, interaction lists and
 neighbour lists must match bit for bit.  Forces: the FP64 path within 1e-12
 relative RMS (the terms are the same; only rsqrt rounding and summation order
-differ, ~1e-16 per term), the mixed path within the 1e-4 relative RMS bar.
+differ, ~1e-16 per term), the mixed path within the 1e-4 relative RMS bar;
+and every row (acceleration and potential) within 1e-11 (FP64) or 1e-3
+(mixed) of its own magnitude, floored at 1e-3 of the RMS magnitude.
 """
 import numpy as np
 import pytest
 
 import oracle
 from inputs import WORKLOADS, make_cluster, plummer
-from tests.gpu_cases import compare_neighbors, compare_tree, gpu_run, log, rel_rms
+from tests.gpu_cases import (ROW_TOL, compare_neighbors, compare_tree, gpu_run, log, rel_rms,
+                             row_errors)
 
 pytestmark = pytest.mark.gpu
 
@@ -34,12 +37,17 @@ def _params(w, **over):
 
 
 def _check_forces(g, acc, pot, tol, label, rows=None):
+    """Relative RMS over all rows within tol, and every row within the per-row
+    bound of its precision."""
     ga, gp = g["acc"], g["pot"]
     if rows is not None:
         ga, gp, acc, pot = ga[rows], gp[rows], acc[rows], pot[rows]
     ea, ep = rel_rms(ga, acc), rel_rms(gp, pot)
-    log(f"{label}: acc rel-RMS {ea:.3e}  pot rel-RMS {ep:.3e}")
+    ra, rp = row_errors(ga, acc), row_errors(gp, pot)
+    rtol = ROW_TOL["fp64" if tol <= FP64_TOL else "mixed"]
+    log(f"{label}: acc rel-RMS {ea:.3e} max row {ra:.3e}  pot rel-RMS {ep:.3e} max row {rp:.3e}")
     assert ea <= tol and ep <= tol, (ea, ep)
+    assert ra <= rtol and rp <= rtol, (ra, rp)
     return ea, ep
 
 
@@ -114,16 +122,28 @@ def test_large_sampled(ctx, name, prec):
     np.testing.assert_array_equal(a, b)
 
 
-@pytest.mark.parametrize("theta,n_crit", [(0.5, 128), (0.3, 64)])
+_P4M = {}
+
+
+def _plummer4m():
+    if "c" not in _P4M:
+        _P4M["c"] = make_cluster(WORKLOADS["plummer4m_salpeter"], seed=1)
+    return _P4M["c"]
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.5, 0.7])
+@pytest.mark.parametrize("n_crit", [64, 128, 256, 512])
 def test_plummer4m_sampled(ctx, theta, n_crit):
-    """The 2^22-particle Salpeter workload: whole tree bit-exact, lists of every
-    997th group (the oracle walks only those), forces of 96 of them."""
+    """The 2^22-particle Salpeter workload at every theta x n_crit setting of
+    its sweep: whole tree bit-exact, lists of every 997th group (the oracle
+    walks only those), forces of 96 of them in both precisions."""
     w = WORKLOADS["plummer4m_salpeter"]
-    c = make_cluster(w, seed=1)
+    c = _plummer4m()
     log(f"case plummer4m theta={theta} n_crit={n_crit}")
     for prec in ("mixed", "fp64"):
         p = _params(w, theta=theta, n_crit=n_crit, precision=prec)
-        g = gpu_run(ctx, c.pos, c.mass, p, want_neighbors=(prec == "mixed"))
+        g = gpu_run(ctx, c.pos, c.mass, p, want_neighbors=(prec == "mixed"),
+                    want_arrays=(prec == "mixed"))
         if prec == "mixed":
             t = oracle.Tree(c.pos, c.mass, p, walk_stride=997)
             compare_tree(g, t)
@@ -132,6 +152,7 @@ def test_plummer4m_sampled(ctx, theta, n_crit):
             sample = rng.choice(walked, min(96, len(walked)), replace=False)
             acc, pot = t.force_groups(sample)
             rows = np.nonzero(~np.isnan(pot))[0]
+            del t
         _check_forces(g, acc, pot, FP64_TOL if prec == "fp64" else MIXED_TOL,
                       f"plummer4m theta={theta} n_crit={n_crit} {prec}", rows)
 
@@ -187,6 +208,47 @@ def test_edge_cases(ctx, name, prec):
         assert np.all(g["acc"] == 0) and np.all(g["pot"] == 0)
     else:
         _check_forces(g, acc, pot, tol, f"{name} {prec}")
+    compare_neighbors(g, t)
+
+
+def _band_cases():
+    """Neighbour radius below r_out, so that accepted cells lie inside the
+    changeover band and their K(y_c), W(y_c) differ from 1: eight particles
+    whose accepted cells are single particles (the tree sum is then the direct
+    sum), a Plummer sphere with the band across the cluster, and the 2^16
+    Salpeter workload with h = r_out / 2."""
+    from tests.test_oracle_cells_in_band import CORNER_CASES, _band_tree, _corner_setup
+    cases = {}
+    for name in CORNER_CASES:
+        cases["corners_" + name] = _corner_setup(name)
+    cases["corners_band_monopole"] = _corner_setup("band", quad=0)
+    cases["plummer3000_band"] = _band_tree(0.5)
+    w = WORKLOADS["plummer64k_salpeter"]
+    c = make_cluster(w, seed=3)
+    cases["plummer64k_h_half_rout"] = (c.pos, c.mass, w.params(r_search=0.5 * w.r_out))
+    return cases
+
+
+BAND = _band_cases()
+
+
+@pytest.mark.parametrize("name", list(BAND))
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_cells_in_band(ctx, name, prec):
+    """Accepted cells inside r_out (h < r_out): the kernels' cell-term
+    changeover path against the oracle, lists and neighbours bit-exact."""
+    from tests.test_oracle_cells_in_band import band_pairs
+    pos, mass, p = BAND[name]
+    p = dict(p, precision=prec)
+    log(f"band case {name} {prec} n={len(mass)}")
+    g = gpu_run(ctx, pos, mass, p)
+    t = oracle.Tree(pos, mass, p)
+    nb = band_pairs(t, pos, p)
+    log(f"  {nb} (member, cell) pairs inside r_out")
+    assert nb > 0
+    compare_tree(g, t)
+    acc, pot = t.force()
+    _check_forces(g, acc, pot, FP64_TOL if prec == "fp64" else MIXED_TOL, f"{name} {prec}")
     compare_neighbors(g, t)
 
 
@@ -374,3 +436,101 @@ def test_kick_drift(ctx):
     v2 = v + 0.125 * a
     x2 = x + 0.25 * v2
     assert np.array_equal(tv.cpu().numpy(), v2) and np.array_equal(tx.cpu().numpy(), x2)
+
+
+def test_allocator_failure_is_enomem():
+    """Every device workspace of a build, force, neighbour search and VJP comes
+    from the context's allocator.  When its k-th allocation fails (for every k
+    that the sequence reaches), the call returns P3T_ENOMEM and leaves the
+    caller's outputs untouched; with the allocator working again the same
+    context gives the same forces, lists and VJP as an unfailing context."""
+    import ctypes as C
+    import torch
+    from paper_1506_04553_amd import P3T
+    from paper_1506_04553_amd.p3t import (ALLOC_FN, FREE_FN, P3T_ENOMEM, P3T_OK, P3TError,
+                                          load_library)
+    L = load_library()
+    c = plummer(3000, 23)
+    p = dict(eps=1e-3, r_in=0.005, r_out=0.05, theta=0.5, r_search=0.055, n_crit=64, n_leaf=16,
+             precision="mixed")
+    st = torch.cuda.current_stream(0)
+    state = {"count": 0, "fail_at": 0}
+
+    def _alloc(nbytes, _user):
+        state["count"] += 1
+        if state["count"] == state["fail_at"]:
+            return None
+        return torch.cuda.caching_allocator_alloc(int(nbytes), 0, st)
+
+    def _free(ptr, _user):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    acb, fcb = ALLOC_FN(_alloc), FREE_FN(_free)
+
+    def new_ctx():
+        obj = P3T.__new__(P3T)
+        obj._L, obj.device, obj.stream, obj._allocs = L, 0, st, {}
+        obj._alloc_cb, obj._free_cb = acb, fcb
+        h = C.c_void_p()
+        assert L.p3t_create(C.byref(h), 0, C.c_void_p(st.cuda_stream), acb, fcb, None) == P3T_OK
+        obj._h, obj.n, obj.params, obj.build_id = h, 0, None, 0
+        return obj
+
+    n = len(c.mass)
+    pos, mass = torch.from_numpy(c.pos).cuda(), torch.from_numpy(c.mass).cuda()
+    rng = np.random.default_rng(24)
+    w = torch.from_numpy(rng.normal(size=(n, 3))).cuda()
+    cw = torch.from_numpy(rng.normal(size=n)).cuda()
+    SENT = -7.0
+
+    def sequence(ctx_):
+        """Build, force, neighbours, VJP; returns (results, status of the
+        failing call or OK, whether that call left its outputs untouched)."""
+        try:
+            ctx_.build_tree(pos, mass, **p)
+        except P3TError as e:
+            return None, e.status, True
+        acc = torch.full((n, 3), SENT, dtype=torch.float64, device="cuda")
+        pot = torch.full((n,), SENT, dtype=torch.float64, device="cuda")
+        rc = L.p3t_long_force(ctx_._h, C.c_void_p(acc.data_ptr()), C.c_void_p(pot.data_ptr()))
+        torch.cuda.synchronize()
+        if rc != P3T_OK:
+            return None, rc, bool((acc == SENT).all() and (pot == SENT).all())
+        off = torch.full((n + 1,), -7, dtype=torch.int64, device="cuda")
+        idx = torch.full((n * 8,), -7, dtype=torch.int32, device="cuda")
+        nnz = C.c_int64(0)
+        rc = L.p3t_neighbors(ctx_._h, C.c_void_p(off.data_ptr()), C.c_void_p(idx.data_ptr()),
+                             n * 8, C.byref(nnz))
+        torch.cuda.synchronize()
+        if rc != P3T_OK:
+            return None, rc, bool((off == -7).all() and (idx == -7).all())
+        gp = torch.full((n, 3), SENT, dtype=torch.float64, device="cuda")
+        gm = torch.full((n,), SENT, dtype=torch.float64, device="cuda")
+        rc = L.p3t_long_force_vjp(ctx_._h, C.c_void_p(w.data_ptr()), C.c_void_p(cw.data_ptr()),
+                                  C.c_void_p(gp.data_ptr()), C.c_void_p(gm.data_ptr()))
+        torch.cuda.synchronize()
+        if rc != P3T_OK:
+            return None, rc, bool((gp == SENT).all() and (gm == SENT).all())
+        res = [t.cpu().numpy() for t in (acc, pot, off, idx[:nnz.value], gp, gm)]
+        return res, P3T_OK, True
+
+    ref_ctx = new_ctx()
+    ref, rc, _ = sequence(ref_ctx)
+    assert rc == P3T_OK
+    total = state["count"]
+    ref_ctx.close()
+    log(f"  {total} allocations in build, force, neighbours and VJP")
+    assert total > 10
+    for k in range(1, total + 1):
+        state["count"], state["fail_at"] = 0, k
+        ctx_ = new_ctx()
+        res, rc, untouched = sequence(ctx_)
+        assert rc == P3T_ENOMEM, (k, rc)
+        assert untouched, k
+        state["fail_at"] = 0
+        res, rc, _ = sequence(ctx_)
+        assert rc == P3T_OK, (k, rc)
+        for u, v in zip(res[:4], ref[:4]):
+            assert np.array_equal(u, v), k
+        assert rel_rms(res[4], ref[4]) < 1e-13 and rel_rms(res[5], ref[5]) < 1e-13, k
+        ctx_.close()

@@ -1,4 +1,4 @@
-"""Pins of the oracle's particle kinds (Section 3.3, the SMBH runs: a cutoff
+"""Pins of the oracle's particle kinds (Section 3.2.2, the SMBH runs: a cutoff
 radius and a softening per kind of pair; between SMBHs no split and no
 softening; a timestep accuracy per kind).
 
