@@ -127,9 +127,17 @@ struct Slot {
     R ax, ay, az, ph;
     Sum<R> sx, sy, sz, sp;
     int32_t i;
+    // FP32: fold the tile partials into the compensated sums; FP64: the
+    // partials are the sums (no second set of registers)
     __device__ __forceinline__ void flush() {
+        if (sizeof(R) == 8) return;
         sx.add(ax); sy.add(ay); sz.add(az); sp.add(ph);
         ax = ay = az = ph = R(0);
+    }
+    __device__ __forceinline__ double total(int c) const {
+        if (sizeof(R) == 8)
+            return c == 0 ? (double)ax : c == 1 ? (double)ay : c == 2 ? (double)az : (double)ph;
+        return c == 0 ? sx.value() : c == 1 ? sy.value() : c == 2 ? sz.value() : sp.value();
     }
 };
 
@@ -286,8 +294,7 @@ __device__ __forceinline__ void cell_tile(Slot<R> *q, const CJ<R> *sc, int iters
 template <class R, bool QUAD, bool CHECK_K>
 __global__ __launch_bounds__(kForceThreads)
 __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 4 : 1))) void k_force(
-    const GroupInfo *__restrict__ grp, ListsDev L, const double *__restrict__ x,
-    const double *__restrict__ y, const double *__restrict__ z, const double *__restrict__ m,
+    const GroupInfo *__restrict__ grp, ListsDev L, const PosMass *__restrict__ xm,
     const NodeMP *__restrict__ mp, const int32_t *__restrict__ perm, ForceParams fp,
     double *__restrict__ acc, double *__restrict__ pot) {
     // tile + padding read by lanes past the tile end (zero mass, far away)
@@ -331,11 +338,12 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 4 : 1))) void k_force(
             const int li = (v0 + kForceWaves * k + w) * nw + il;
             const bool valid = (k == 0 ? act0 : act1) && li < gi.count;
             const int32_t i = gi.first + (valid ? li : 0);
+            const PosMass pi = xm[i];
             q[k].i = valid ? i : -1;
             // padding lanes sit far away: every term stays finite and is discarded
-            q[k].x = valid ? (R)(x[i] - gcx) : R(1e18);
-            q[k].y = valid ? (R)(y[i] - gcy) : R(1e18);
-            q[k].z = valid ? (R)(z[i] - gcz) : R(1e18);
+            q[k].x = valid ? (R)(pi.x - gcx) : R(1e18);
+            q[k].y = valid ? (R)(pi.y - gcy) : R(1e18);
+            q[k].z = valid ? (R)(pi.z - gcz) : R(1e18);
             q[k].ax = q[k].ay = q[k].az = q[k].ph = R(0);
         }
         // FP32 partials are folded into the compensated sums every >= 64 iterations
@@ -352,12 +360,16 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 4 : 1))) void k_force(
         // ---- particle-particle terms: tiles staged through LDS by the whole
         //      block, the next tile fetched into registers while the current one
         //      is consumed ----
+        // a list particle shifted to the group centre (FP64), then rounded to R
+        auto stage = [&](const PosMass &pj) {
+            return PJ<R>{(R)(pj.x - gcx), (R)(pj.y - gcy), (R)(pj.z - gcz), (R)pj.m};
+        };
         auto stream_particles = [&](const int32_t *list, int64_t b, int64_t e, auto &&consume) {
             PJ<R> pre = zero_p;
             int32_t prej = -2;
             if (b + tid < e) {
                 prej = list[b + tid];
-                pre = PJ<R>{(R)(x[prej] - gcx), (R)(y[prej] - gcy), (R)(z[prej] - gcz), (R)m[prej]};
+                pre = stage(xm[prej]);
             }
             for (int64_t t0 = b; t0 < e; t0 += kTile) {
                 const int tl = (int)min<int64_t>(kTile, e - t0);
@@ -367,8 +379,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 4 : 1))) void k_force(
                 __syncthreads();
                 if (t0 + kTile + tid < e) {
                     prej = list[t0 + kTile + tid];
-                    pre = PJ<R>{(R)(x[prej] - gcx), (R)(y[prej] - gcy), (R)(z[prej] - gcz),
-                                (R)m[prej]};
+                    pre = stage(xm[prej]);
                 } else {
                     pre = zero_p;
                     prej = -2;
@@ -420,8 +431,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 4 : 1))) void k_force(
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             if (!(k == 0 ? act0 : act1)) continue;
-            double r0 = q[k].sx.value(), r1 = q[k].sy.value(), r2 = q[k].sz.value(),
-                   r3 = q[k].sp.value();
+            double r0 = q[k].total(0), r1 = q[k].total(1), r2 = q[k].total(2),
+                   r3 = q[k].total(3);
             for (int d = nw; d < kWave; d <<= 1) {
                 r0 += __shfl_xor(r0, d, kWave);
                 r1 += __shfl_xor(r1, d, kWave);
@@ -457,9 +468,7 @@ static ForceParams force_params(const p3t_ctx *ctx) {
 template <class R, bool QUAD, bool CHECK_K>
 static void launch_force_t(p3t_ctx *ctx, const ForceParams &fp, double *acc, double *pot) {
     k_force<R, QUAD, CHECK_K><<<(unsigned)ctx->n_groups, kForceThreads, 0, ctx->stream>>>(
-        ptr<GroupInfo>(ctx->grp), lists_dev(ctx), ptr<double>(ctx->x), ptr<double>(ctx->y),
-        ptr<double>(ctx->z),
-        ptr<double>(ctx->m), ptr<NodeMP>(ctx->node_mp), ptr<int32_t>(ctx->vals[0]), fp, acc, pot);
+        ptr<GroupInfo>(ctx->grp), lists_dev(ctx), ptr<PosMass>(ctx->xm), ptr<NodeMP>(ctx->node_mp), ptr<int32_t>(ctx->vals[0]), fp, acc, pot);
 }
 
 template <class R>

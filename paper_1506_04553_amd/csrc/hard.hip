@@ -1231,7 +1231,7 @@ static HardConsts hard_consts(const p3t_params *p, const p3t_kinds *kd, int64_t 
 
 int validate_csr(p3t_ctx *ctx, int64_t n, const int64_t *off, const int32_t *idx) {
     int rc;
-    if ((rc = ensure(ctx, ctx->readback, 64 * sizeof(int64_t)))) return rc;
+    if ((rc = ensure_readback(ctx))) return rc;
     int64_t *rb = ptr<int64_t>(ctx->readback);
     if ((rc = check_hip(ctx, hipMemsetAsync(rb + RB_HBAD, 0, sizeof(int64_t), ctx->stream), "memset")))
         return rc;
@@ -1335,7 +1335,7 @@ int launch_hard_force(p3t_ctx *ctx, int64_t n, const double *pos, const double *
                       const p3t_params *p, const p3t_kinds *kd, double *acc, double *jerk,
                       double *pot) {
     int rc;
-    if ((rc = ensure(ctx, ctx->readback, 64 * sizeof(int64_t)))) return rc;
+    if ((rc = ensure_readback(ctx))) return rc;
     if ((rc = validate_csr(ctx, n, off, idx))) return rc;
     const HardConsts hc = hard_consts(p, kd, n);
     k_hard_force<<<blocks_for(n, kHardThreads), kHardThreads, 0, ctx->stream>>>(
@@ -1349,7 +1349,7 @@ int launch_hermite(p3t_ctx *ctx, int64_t n, double *pos, double *vel, const doub
                    p3t_hermite_stats *stats) {
     int rc;
     hipStream_t st = ctx->stream;
-    if ((rc = ensure(ctx, ctx->readback, 64 * sizeof(int64_t)))) return rc;
+    if ((rc = ensure_readback(ctx))) return rc;
     if ((rc = aux_streams(ctx))) return rc;
     if ((rc = check_hip(ctx, hipEventRecord(ctx->ev[10], st), "event"))) return rc;
     if ((rc = validate_csr(ctx, n, off, idx))) return rc;

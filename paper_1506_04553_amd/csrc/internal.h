@@ -21,6 +21,12 @@ struct RootInfo {
     int32_t pad;
 };
 
+// Sorted particle record: position and mass in one aligned 32-byte line
+// segment, so that a gathered list entry costs one read.
+struct alignas(32) PosMass {
+    double x, y, z, m;
+};
+
 // Per-node record read by the tree walk (96 bytes, one read per visit).
 struct NodeWalk {
     double cx, cy, cz;      // centre of mass
@@ -96,17 +102,18 @@ struct p3t_ctx {
     int64_t hint_groups = 0, hint_max[3] = {0, 0, 0};
     int32_t hint_n_crit = -1;
     int32_t nbr_cap = 0;   // neighbour row slot size for the next p3t_neighbors (0: default)
+    unsigned long long nbr_tag = 0;   // number of neighbour searches so far (tags their readback words)
     double ms_build = 0, ms_walk = 0, ms_force = 0, ms_nbr = 0, ms_vjp = 0;
     hipEvent_t ev[12] = {nullptr};  // start/end pairs: build, force, neighbours, vjp, walk, hermite
     int64_t *hpin = nullptr;      // pinned host readback area (64 int64)
 
-    p3t::DevBuf root, keys[2], vals[2], hist, histc, x, y, z, m;
+    p3t::DevBuf root, keys[2], vals[2], hist, histc, rs_tot, xm;
     p3t::DevBuf lvlrange, tblk, tblk_off;
     p3t::DevBuf node_level, node_first, node_count, node_child, node_nchild, node_parent,
         node_prefix, node_S, node_walk, node_mp;
     p3t::DevBuf gflag, gscan, grp;
     p3t::DevBuf cnt, off, c_idx, p_idx, n_idx;
-    p3t::DevBuf wstack, dflags, readback, scan_tmp, nbr_cnt, nbr_slots;
+    p3t::DevBuf wstack, readback, scan_tmp, nbr_cnt, nbr_slots;
     p3t::DevBuf vjp_gx, vjp_gm, vjp_cell, bbox;
     p3t::DevBuf seg_end, gorder, grank, ghist;
     p3t::DevBuf hard_ix, hard_state;   // hard part: components and integrator state
@@ -123,6 +130,10 @@ namespace p3t {
 
 // Allocation helpers (context allocator or hipMalloc); return 0 or P3T_ENOMEM.
 int ensure(p3t_ctx *ctx, DevBuf &b, size_t bytes);
+// The device readback area (kReadbackWords int64 words), allocated and cleared
+// on first use.
+constexpr int kReadbackWords = 64;
+int ensure_readback(p3t_ctx *ctx);
 void release(p3t_ctx *ctx, DevBuf &b);
 int set_error(p3t_ctx *ctx, int status, const char *fmt, ...);
 int check_hip(p3t_ctx *ctx, hipError_t e, const char *what);
@@ -131,17 +142,33 @@ int check_hip(p3t_ctx *ctx, hipError_t e, const char *what);
 // null) receives the sum of all n inputs.
 int scan_exclusive_i64(p3t_ctx *ctx, const int64_t *in, int64_t *out, int64_t n, int64_t *total);
 int scan_exclusive_i32(p3t_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, int32_t *total);
+// Exclusive prefix sum of each row of a [rows][cols] array (one block per
+// row, one launch); totals[r] receives the sum of row r.
+int scan_rows_i32(p3t_ctx *ctx, const int32_t *in, int32_t *out, int32_t *totals, int rows,
+                  int64_t cols);
+
+// Readback slots (int64 words of ctx->readback / ctx->hpin) written during a
+// build: the node count of each level (kLevels int32), then the input check.
+constexpr int kRbTopoBad = kLevels + 1;
+// The walk's statistics from this slot on (kRbWalkWords words, cleared by the
+// group selection before every walk of a build).
+constexpr int kRbWalk = 24;
+constexpr int kRbWalkWords = 13;
+// The root-cube kernel's block counter (zero between builds).
+constexpr int kRbBboxDone = kRbWalk + kRbWalkWords;
 
 // Tree build stages (tree.hip).
-int build_root_keys(p3t_ctx *ctx, const double *pos, const double *mass, int64_t n);
-int radix_sort_keys(p3t_ctx *ctx, int64_t n);   // sorts keys[0]/vals[0] -> keys[0]/vals[0]
-int gather_sorted(p3t_ctx *ctx, const double *pos, const double *mass, int64_t n);
+// root cube, Morton keys, stable sort (keys[0] / vals[0]) and the sorted
+// particle records xm
+int build_sorted(p3t_ctx *ctx, const double *pos, const double *mass, int64_t n);
 int build_topology(p3t_ctx *ctx, int64_t n);    // sets ctx->n_nodes, level_start, depth
 int build_moments(p3t_ctx *ctx);
 int build_groups(p3t_ctx *ctx);                 // sets ctx->n_groups
 
 // Walk (walk.hip): lists and their statistics; sets n_groups and list sizes.
-int build_lists(p3t_ctx *ctx);
+// stats_cleared: the walk's statistics slots are already zero (a build clears
+// them in the group selection); a walk after p3t_release_lists clears them.
+int build_lists(p3t_ctx *ctx, bool stats_cleared);
 
 // Interactions (force.hip).
 int launch_force(p3t_ctx *ctx, double *acc, double *pot);
@@ -149,8 +176,12 @@ int launch_force(p3t_ctx *ctx, double *acc, double *pot);
 // Neighbour lists (neighbors.hip).
 int launch_neighbors(p3t_ctx *ctx, int64_t *offsets, int32_t *idx, int64_t cap, int64_t *nnz);
 
-// VJP (vjp.hip).
+// VJP (vjp.hip).  launch_vjp takes its workspaces from the context;
+// launch_vjp_ws from the caller: gx [3 n], gm [n] and cadj [10 n_nodes] doubles
+// (gx and gm are written before they are read, cadj is cleared first).
 int launch_vjp(p3t_ctx *ctx, const double *w, const double *c, double *gpos, double *gmass);
+int launch_vjp_ws(p3t_ctx *ctx, const double *w, const double *c, double *gpos, double *gmass,
+                  double *gx, double *gm, double *cadj);
 
 // Hard part (hard.hip): force and jerk over neighbour lists; Hermite block-step
 // integration over one soft step.

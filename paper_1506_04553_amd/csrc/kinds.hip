@@ -239,7 +239,7 @@ int launch_kinds_neighbors(p3t_ctx *ctx, int64_t n, const double *pos, const p3t
                            int32_t *idx, int64_t cap, int64_t *nnz) {
     int rc;
     hipStream_t st = ctx->stream;
-    if ((rc = ensure(ctx, ctx->readback, 64 * sizeof(int64_t)))) return rc;
+    if ((rc = ensure_readback(ctx))) return rc;
     if ((rc = ensure(ctx, ctx->kinds_cnt, (size_t)(n + 1) * sizeof(int64_t)))) return rc;
     int64_t *cnt = ptr<int64_t>(ctx->kinds_cnt), *rb = ptr<int64_t>(ctx->readback);
     KindsNbr kn;

@@ -36,14 +36,18 @@ __device__ __forceinline__ double axis_gap(double v, double lo, double hi) {
     return b > t ? b : t;
 }
 
-// CSR = false: rows into slots of `cap` entries, counts into cnt, flag on overflow.
+// CSR = false: rows into slots of `cap` entries, counts into cnt (cnt[n] = 0
+// for the scan), and, tagged with this call's number `tag` so that no word
+// has to be cleared first: the longest row into *longest as
+// max(tag << 32 | length), and *overflow = max(tag) if a row outgrew its slot.
 // CSR = true: rows straight into out at the offsets off (cnt, cap unused).
 template <bool CSR>
 __global__ __launch_bounds__(kNbrThreads) void k_neighbors(
-    const GroupInfo *__restrict__ grp, ListsDev L, const double *__restrict__ x,
-    const double *__restrict__ y, const double *__restrict__ z, const int32_t *__restrict__ perm,
+    const GroupInfo *__restrict__ grp, ListsDev L, const PosMass *__restrict__ xm,
+    const int32_t *__restrict__ perm,
     double h2, int32_t cap, int32_t *__restrict__ out, const int64_t *__restrict__ off,
-    int64_t *__restrict__ cnt, int32_t *__restrict__ overflow) {
+    int64_t *__restrict__ cnt, int64_t n, unsigned long long tag,
+    unsigned long long *__restrict__ longest, unsigned long long *__restrict__ overflow) {
     __shared__ double s_x[kNbrTile], s_y[kNbrTile], s_z[kNbrTile];
     __shared__ int32_t s_j[kNbrTile];
     __shared__ int32_t s_wn[kNbrWaves];
@@ -52,11 +56,14 @@ __global__ __launch_bounds__(kNbrThreads) void k_neighbors(
     const GroupInfo gi = grp[g];
     const int64_t nb = L.beg[2][g], ne = L.end[2][g];   // near particles
     const int32_t *__restrict__ n_idx = L.idx[2];
+    if (!CSR && blockIdx.x == 0 && tid == 0) cnt[n] = 0;
+    int kmax = 0;
 
     for (int m0 = 0; m0 < gi.count; m0 += kNbrThreads) {
         const bool valid = m0 + tid < gi.count;
         const int32_t i = gi.first + (valid ? m0 + tid : 0);
-        const double xi = x[i], yi = y[i], zi = z[i];
+        const PosMass pi = xm[i];
+        const double xi = pi.x, yi = pi.y, zi = pi.z;
         const int64_t o = perm[i];
         int32_t *row = CSR ? out + (valid ? off[o] : 0) : out + o * (int64_t)cap;
         int k = 0;
@@ -67,9 +74,10 @@ __global__ __launch_bounds__(kNbrThreads) void k_neighbors(
             double xj = 0.0, yj = 0.0, zj = 0.0;
             if (t0 + tid < ne) {
                 j = n_idx[t0 + tid];
-                xj = x[j];
-                yj = y[j];
-                zj = z[j];
+                const PosMass pj = xm[j];
+                xj = pj.x;
+                yj = pj.y;
+                zj = pj.z;
                 const double tx = axis_gap(xj, gi.lo[0], gi.hi[0]);
                 const double ty = axis_gap(yj, gi.lo[1], gi.hi[1]);
                 const double tz = axis_gap(zj, gi.lo[2], gi.hi[2]);
@@ -105,31 +113,26 @@ __global__ __launch_bounds__(kNbrThreads) void k_neighbors(
         }
         if (!CSR && valid) {
             cnt[o] = k;
-            if (k > cap) atomicOr(overflow, 1);
+            kmax = k > kmax ? k : kmax;
         }
     }
-}
-
-// Longest row (one update per block of 256).
-__global__ __launch_bounds__(256) void k_row_max(int64_t n, int64_t *__restrict__ cnt,
-                                                  unsigned long long *__restrict__ out) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) cnt[n] = 0;
-    unsigned long long mx = 0;
-    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n;
-         o += (int64_t)gridDim.x * blockDim.x) {
-        const unsigned long long c = (unsigned long long)cnt[o];
-        mx = c > mx ? c : mx;
-    }
+    if (CSR) return;
+    // longest row of the block: one update per block
     for (int d = kWave / 2; d > 0; d >>= 1) {
-        const unsigned long long v = __shfl_xor(mx, d, kWave);
-        mx = v > mx ? v : mx;
+        const int v = __shfl_xor(kmax, d, kWave);
+        kmax = v > kmax ? v : kmax;
     }
-    __shared__ unsigned long long s_mx[4];
-    if (lane_id() == 0) s_mx[threadIdx.x / kWave] = mx;
+    __syncthreads();   // s_wn is free: every wave is past its last tile
+    if (lane == 0) s_wn[w] = kmax;
     __syncthreads();
-    if (threadIdx.x == 0) {   // one update per block
-        for (int q = 1; q < 4; ++q) mx = s_mx[q] > mx ? s_mx[q] : mx;
-        atomicMax(out, mx);
+    if (tid == 0) {
+        for (int q = 1; q < kNbrWaves; ++q) kmax = s_wn[q] > kmax ? s_wn[q] : kmax;
+        // one word for the whole grid: only blocks that would raise it update
+        // it (most blocks' longest rows are below the maximum already seen)
+        const unsigned long long v = (tag << 32) | (unsigned long long)kmax;
+        if (v > __hip_atomic_load(longest, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(longest, v);
+        if (kmax > cap) atomicMax(overflow, tag);
     }
 }
 
@@ -191,27 +194,26 @@ int launch_neighbors(p3t_ctx *ctx, int64_t *offsets, int32_t *idx, int64_t cap, 
     const unsigned grid = (unsigned)ctx->n_groups;
     const int32_t row_cap = ctx->nbr_cap > 0 ? ctx->nbr_cap : kNbrFirstCap;
     if ((rc = ensure(ctx, ctx->nbr_slots, (size_t)n * row_cap * sizeof(int32_t) + 4))) return rc;
-    // every particle's count is written (groups partition the particles); the
-    // entry past the last one, which takes part in the scan, is zeroed by k_row_max
-    if ((rc = check_hip(ctx, hipMemsetAsync(rb + RB_NNZ, 0, 3 * sizeof(int64_t), st), "memset")))
-        return rc;
-    if (grid) {
-        k_neighbors<false><<<grid, kNbrThreads, 0, st>>>(
-            ptr<GroupInfo>(ctx->grp), L, ptr<double>(ctx->x), ptr<double>(ctx->y),
-            ptr<double>(ctx->z), ptr<int32_t>(ctx->vals[0]), h2, row_cap,
-            ptr<int32_t>(ctx->nbr_slots), nullptr, cnt, reinterpret_cast<int32_t *>(rb + RB_NOVF));
-        if ((rc = check_hip(ctx, hipGetLastError(), "neighbours"))) return rc;
-    }
-    k_row_max<<<256, 256, 0, st>>>(n, cnt, reinterpret_cast<unsigned long long *>(rb + RB_NMAX));
-    if ((rc = check_hip(ctx, hipGetLastError(), "neighbour row max"))) return rc;
+    // every particle's count is written (groups partition the particles), and
+    // the entry past the last one, which takes part in the scan, is zeroed;
+    // the longest row and the overflow flag carry this call's tag (the slots
+    // were cleared once, when the readback area was allocated)
+    const unsigned long long tag = ++ctx->nbr_tag;
+    auto *rbu = reinterpret_cast<unsigned long long *>(rb);
+    if (grid == 0) return set_error(ctx, P3T_ESTATE, "no groups");
+    k_neighbors<false><<<grid, kNbrThreads, 0, st>>>(
+        ptr<GroupInfo>(ctx->grp), L, ptr<PosMass>(ctx->xm), ptr<int32_t>(ctx->vals[0]), h2, row_cap,
+        ptr<int32_t>(ctx->nbr_slots), nullptr, cnt, n, tag, rbu + RB_NMAX, rbu + RB_NOVF);
+    if ((rc = check_hip(ctx, hipGetLastError(), "neighbours"))) return rc;
     if ((rc = scan_exclusive_i64(ctx, cnt, cnt, n + 1, rb + RB_NNZ))) return rc;
     if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + RB_NNZ, rb + RB_NNZ, 3 * sizeof(int64_t),
                                             hipMemcpyDeviceToHost, st), "readback")))
         return rc;
     if ((rc = check_hip(ctx, hipStreamSynchronize(st), "sync"))) return rc;
     const int64_t total = ctx->hpin[RB_NNZ];
-    const bool over = *reinterpret_cast<int32_t *>(ctx->hpin + RB_NOVF) != 0;
-    const int64_t longest = ctx->hpin[RB_NMAX];
+    const auto *hu = reinterpret_cast<const unsigned long long *>(ctx->hpin);
+    const bool over = hu[RB_NOVF] == tag;
+    const int64_t longest = (hu[RB_NMAX] >> 32) == tag ? (int64_t)(hu[RB_NMAX] & 0xffffffffull) : 0;
     // next call: room for rows a little longer than the longest seen, within
     // a workspace of at most 1 GiB
     int64_t want = longest + longest / 4 + 8;
@@ -232,8 +234,8 @@ int launch_neighbors(p3t_ctx *ctx, int64_t *offsets, int32_t *idx, int64_t cap, 
     // some row did not fit its slot: write the rows straight into the CSR
     if (grid) {
         k_neighbors<true><<<grid, kNbrThreads, 0, st>>>(
-            ptr<GroupInfo>(ctx->grp), L, ptr<double>(ctx->x), ptr<double>(ctx->y),
-            ptr<double>(ctx->z), ptr<int32_t>(ctx->vals[0]), h2, 0, idx, cnt, nullptr, nullptr);
+            ptr<GroupInfo>(ctx->grp), L, ptr<PosMass>(ctx->xm), ptr<int32_t>(ctx->vals[0]), h2, 0,
+            idx, cnt, nullptr, n, tag, nullptr, nullptr);
         if ((rc = check_hip(ctx, hipGetLastError(), "neighbours (CSR)"))) return rc;
     }
     k_sort_rows<<<blocks_for(n + 1, 256), 256, 0, st>>>(n, cnt, offsets, idx);

@@ -10,6 +10,7 @@
 
 using namespace p3t;
 
+
 namespace p3t {
 
 int set_error(p3t_ctx *ctx, int status, const char *fmt, ...) {
@@ -47,6 +48,15 @@ int ensure(p3t_ctx *ctx, DevBuf &b, size_t bytes) {
     b.p = p;
     b.bytes = cap;
     return P3T_OK;
+}
+
+int ensure_readback(p3t_ctx *ctx) {
+    if (ctx->readback.p) return P3T_OK;
+    int rc = ensure(ctx, ctx->readback, kReadbackWords * sizeof(int64_t));
+    if (rc) return rc;
+    // cleared once, when allocated: the neighbour search's tagged words rely on it
+    return check_hip(ctx, hipMemsetAsync(ctx->readback.p, 0, ctx->readback.bytes, ctx->stream),
+                     "memset");
 }
 
 void release(p3t_ctx *ctx, DevBuf &b) {
@@ -150,12 +160,12 @@ extern "C" void p3t_destroy(p3t_ctx *ctx) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
     DevBuf *bufs[] = {&ctx->root, &ctx->keys[0], &ctx->keys[1], &ctx->vals[0], &ctx->vals[1],
-                      &ctx->hist, &ctx->histc, &ctx->x, &ctx->y, &ctx->z, &ctx->m, &ctx->lvlrange,
+                      &ctx->hist, &ctx->histc, &ctx->rs_tot, &ctx->xm, &ctx->lvlrange,
                       &ctx->tblk, &ctx->tblk_off, &ctx->node_level, &ctx->node_first,
                       &ctx->node_count, &ctx->node_child, &ctx->node_nchild, &ctx->node_parent,
                       &ctx->node_prefix, &ctx->node_S, &ctx->node_walk, &ctx->node_mp, &ctx->gflag,
                       &ctx->gscan, &ctx->grp, &ctx->cnt, &ctx->off, &ctx->c_idx, &ctx->p_idx,
-                      &ctx->n_idx, &ctx->wstack, &ctx->dflags, &ctx->readback, &ctx->scan_tmp,
+                      &ctx->n_idx, &ctx->wstack, &ctx->readback, &ctx->scan_tmp,
                       &ctx->nbr_cnt, &ctx->nbr_slots, &ctx->vjp_gx, &ctx->vjp_gm, &ctx->vjp_cell, &ctx->bbox,
                       &ctx->seg_end, &ctx->gorder, &ctx->grank, &ctx->ghist, &ctx->hard_ix,
                       &ctx->hard_state, &ctx->step_off, &ctx->step_idx, &ctx->step_off2,
@@ -203,16 +213,14 @@ extern "C" int p3t_build_tree(p3t_ctx *ctx, int64_t n, const double *pos, const 
     ctx->n = n;
     ctx->prm = *p;
     ctx->chg = make_changeover(p->r_in, p->r_out);
-    if ((rc = ensure(ctx, ctx->readback, 64 * sizeof(int64_t)))) return rc;
+    if ((rc = ensure_readback(ctx))) return rc;
     if ((rc = mark(ctx, EV_BUILD))) return rc;
-    if ((rc = build_root_keys(ctx, pos, mass, n))) return rc;
-    if ((rc = radix_sort_keys(ctx, n))) return rc;
-    if ((rc = gather_sorted(ctx, pos, mass, n))) return rc;
+    if ((rc = build_sorted(ctx, pos, mass, n))) return rc;
     if ((rc = build_topology(ctx, n))) return rc;
     if ((rc = build_moments(ctx))) return rc;
     if ((rc = build_groups(ctx))) return rc;
     if ((rc = mark(ctx, EV_WALK))) return rc;
-    if ((rc = build_lists(ctx))) return rc;
+    if ((rc = build_lists(ctx, true))) return rc;
     if ((rc = mark(ctx, EV_WALK + 1))) return rc;
     if ((rc = mark(ctx, EV_BUILD + 1))) return rc;
     ctx->ms_build = ctx->ms_walk = -1.0;   // resolved lazily by p3t_get_stats
@@ -224,7 +232,7 @@ extern "C" int p3t_build_tree(p3t_ctx *ctx, int64_t n, const double *pos, const 
 // the lists of the current build, walked again if they were released
 static int ensure_lists(p3t_ctx *ctx) {
     if (!ctx->lists_released) return P3T_OK;
-    const int rc = build_lists(ctx);
+    const int rc = build_lists(ctx, false);
     if (rc == P3T_OK) ctx->lists_released = 0;
     return rc;
 }

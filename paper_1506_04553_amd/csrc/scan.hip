@@ -80,8 +80,90 @@ static int scan_rec(p3t_ctx *ctx, const T *in, T *out, int64_t n, T *total, T *t
     return check_hip(ctx, hipGetLastError(), "scan add");
 }
 
+// Two launches for up to kScan2MaxTiles tiles of kScan2Tile elements: the tile
+// sums, then every block adds up the sums of the tiles before its own and
+// scans its tile from there.
+constexpr int kScan2Items = 16;
+constexpr int kScan2Tile = kScanThreads * kScan2Items;
+constexpr int64_t kScan2MaxTiles = 4096;
+
+template <class T>
+__global__ __launch_bounds__(kScanThreads) void k_scan2_sums(const T *__restrict__ in, int64_t n,
+                                                             T *__restrict__ tile_sums) {
+    __shared__ T wsum[kScanThreads / kWave];
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScan2Tile;
+    T run = 0;
+#pragma unroll
+    for (int k = 0; k < kScan2Items; ++k) {
+        const int64_t i = base + (int64_t)k * kScanThreads + tid;   // coalesced
+        if (i < n) run += in[i];
+    }
+    run = wave_sum(run);
+    if (tid % kWave == 0) wsum[tid / kWave] = run;
+    __syncthreads();
+    if (tid == 0) {
+        T s = 0;
+        for (int k = 0; k < kScanThreads / kWave; ++k) s += wsum[k];
+        tile_sums[blockIdx.x] = s;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(kScanThreads) void k_scan2_tiles(const T *in, T *out, int64_t n,
+                                                              const T *__restrict__ tile_sums,
+                                                              T *total) {
+    __shared__ T wsum[kScanThreads / kWave];
+    __shared__ T s_base;
+    const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+    // this tile's offset: the sum of the tiles before it
+    T before = 0;
+    for (int64_t b = tid; b < blockIdx.x; b += kScanThreads) before += tile_sums[b];
+    before = wave_sum(before);
+    if (lane == 0) wsum[w] = before;
+    __syncthreads();
+    if (tid == 0) {
+        T s = 0;
+        for (int k = 0; k < kScanThreads / kWave; ++k) s += wsum[k];
+        s_base = s;
+        if (total && blockIdx.x == gridDim.x - 1) *total = s + tile_sums[blockIdx.x];
+    }
+    __syncthreads();
+    // the tile: each thread scans kScan2Items consecutive elements
+    const int64_t base = (int64_t)blockIdx.x * kScan2Tile + (int64_t)tid * kScan2Items;
+    T v[kScan2Items];
+    T run = 0;
+#pragma unroll
+    for (int k = 0; k < kScan2Items; ++k) {
+        const int64_t i = base + k;
+        v[k] = (i < n) ? in[i] : T(0);
+        run += v[k];
+    }
+    const T incl = wave_incl_scan(run);
+    __syncthreads();   // wsum is reused
+    if (lane == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    T excl = s_base + incl - run;
+    for (int k = 0; k < w; ++k) excl += wsum[k];
+#pragma unroll
+    for (int k = 0; k < kScan2Items; ++k) {
+        const int64_t i = base + k;
+        if (i < n) out[i] = excl;
+        excl += v[k];
+    }
+}
+
 template <class T>
 static int scan_any(p3t_ctx *ctx, const T *in, T *out, int64_t n, T *total) {
+    const int64_t tiles = (n + kScan2Tile - 1) / kScan2Tile;
+    if (n > 0 && tiles <= kScan2MaxTiles) {
+        int rc = ensure(ctx, ctx->scan_tmp, (size_t)(tiles + 1) * sizeof(int64_t));
+        if (rc) return rc;
+        T *sums = ptr<T>(ctx->scan_tmp);
+        k_scan2_sums<T><<<(unsigned)tiles, kScanThreads, 0, ctx->stream>>>(in, n, sums);
+        k_scan2_tiles<T><<<(unsigned)tiles, kScanThreads, 0, ctx->stream>>>(in, out, n, sums, total);
+        return check_hip(ctx, hipGetLastError(), "scan");
+    }
     // scratch: sum over recursion levels of the block counts
     int64_t need = 0, m = n;
     while (m > kScanTile) {
@@ -91,6 +173,40 @@ static int scan_any(p3t_ctx *ctx, const T *in, T *out, int64_t n, T *total) {
     int rc = ensure(ctx, ctx->scan_tmp, (size_t)(need + 1) * sizeof(int64_t));
     if (rc) return rc;
     return scan_rec<T>(ctx, in, out, n, total, ptr<T>(ctx->scan_tmp));
+}
+
+// Block r: exclusive scan of row r in chunks of kScanThreads with a running carry.
+__global__ __launch_bounds__(kScanThreads) void k_scan_rows(const int32_t *__restrict__ in,
+                                                            int32_t *__restrict__ out,
+                                                            int32_t *__restrict__ totals,
+                                                            int64_t cols) {
+    __shared__ int32_t s_wsum[kScanThreads / kWave];
+    const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+    const int64_t row = (int64_t)blockIdx.x * cols;
+    int32_t carry = 0;
+    for (int64_t c0 = 0; c0 < cols; c0 += kScanThreads) {
+        const int64_t c = c0 + tid;
+        const int32_t v = c < cols ? in[row + c] : 0;
+        const int32_t incl = wave_incl_scan(v);
+        if (lane == kWave - 1) s_wsum[w] = incl;
+        __syncthreads();
+        int32_t wb = 0, tot = 0;
+        for (int k = 0; k < kScanThreads / kWave; ++k) {
+            wb += k < w ? s_wsum[k] : 0;
+            tot += s_wsum[k];
+        }
+        if (c < cols) out[row + c] = carry + wb + incl - v;
+        carry += tot;
+        __syncthreads();   // s_wsum is rewritten by the next chunk
+    }
+    if (tid == 0) totals[blockIdx.x] = carry;
+}
+
+int scan_rows_i32(p3t_ctx *ctx, const int32_t *in, int32_t *out, int32_t *totals, int rows,
+                  int64_t cols) {
+    if (rows <= 0) return P3T_OK;
+    k_scan_rows<<<rows, kScanThreads, 0, ctx->stream>>>(in, out, totals, cols);
+    return check_hip(ctx, hipGetLastError(), "row scan");
 }
 
 int scan_exclusive_i64(p3t_ctx *ctx, const int64_t *in, int64_t *out, int64_t n, int64_t *total) {

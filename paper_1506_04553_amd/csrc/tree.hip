@@ -1,7 +1,7 @@
 // tree.hip -- octree construction on the GPU: root cube, Morton keys, LSD
-// radix sort, sorted SoA gather, particle-parallel octree topology, bottom-up
-// moments (monopole + quadrupole, Section 2.2 "up to the quadrupole moment")
-// and group selection.
+// radix sort (its last pass writes the sorted particle records),
+// particle-parallel octree topology, bottom-up moments (monopole + quadrupole,
+// Section 2.2 "up to the quadrupole moment") and group selection.
 //
 // Every quantity that feeds a discrete decision (keys, node boundaries,
 // centre of mass, boxes) is a fixed IEEE FP64 operation sequence: this file is
@@ -30,10 +30,17 @@ namespace p3t {
 // ---------------------------------------------------------------------------
 constexpr int kRedThreads = 256;
 
-__global__ __launch_bounds__(kRedThreads) void k_bbox_partial(const double *__restrict__ pos,
-                                                              const double *__restrict__ mass,
-                                                              int64_t n, double *partial,
-                                                              int32_t *bad) {
+// per block: lo xyz, hi xyz, and 1 if some input of the block is invalid
+constexpr int kBboxRec = 7;
+
+// Root cube and input check in one launch: every block reduces its share of
+// the particles to a record (lo xyz, hi xyz, invalid-input flag); the last
+// block to finish (agent-scope acquire-release counter, reset by that block)
+// reduces the records to the root cube, root->bad_input and *bad_rb.
+__global__ __launch_bounds__(kRedThreads) void k_bbox(const double *__restrict__ pos,
+                                                      const double *__restrict__ mass, int64_t n,
+                                                      double *partial, RootInfo *root,
+                                                      int64_t *bad_rb, unsigned int *done) {
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     int flag = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -73,36 +80,54 @@ __global__ __launch_bounds__(kRedThreads) void k_bbox_partial(const double *__re
             }
             sf[0] |= sf[k];
         }
-        for (int a = 0; a < 6; ++a) partial[6 * blockIdx.x + a] = s[0][a];
-        if (sf[0]) atomicOr(bad, 1);
+        for (int a = 0; a < 6; ++a) partial[kBboxRec * blockIdx.x + a] = s[0][a];
+        partial[kBboxRec * blockIdx.x + 6] = sf[0] ? 1.0 : 0.0;
     }
-}
-
-__global__ __launch_bounds__(kRedThreads) void k_bbox_final(const double *partial, int nb,
-                                                            const int32_t *bad, RootInfo *root) {
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int b = threadIdx.x; b < nb; b += blockDim.x)
+    __shared__ bool s_last;
+    if (threadIdx.x == 0) {
+        const unsigned int prev =
+            __hip_atomic_fetch_add(done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // every block's record is visible
+    const int nb = (int)gridDim.x;
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = INFINITY;
+        hi[a] = -INFINITY;
+    }
+    double bad = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
         for (int a = 0; a < 3; ++a) {
-            lo[a] = fmin(lo[a], partial[6 * b + a]);
-            hi[a] = fmax(hi[a], partial[6 * b + 3 + a]);
+            lo[a] = fmin(lo[a], partial[kBboxRec * b + a]);
+            hi[a] = fmax(hi[a], partial[kBboxRec * b + 3 + a]);
         }
+        bad = fmax(bad, partial[kBboxRec * b + 6]);
+    }
 #pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1)
+    for (int d = kWave / 2; d > 0; d >>= 1) {
         for (int a = 0; a < 3; ++a) {
             lo[a] = fmin(lo[a], __shfl_xor(lo[a], d, kWave));
             hi[a] = fmax(hi[a], __shfl_xor(hi[a], d, kWave));
         }
-    __shared__ double s[kRedThreads / kWave][6];
-    const int w = threadIdx.x / kWave;
-    if (threadIdx.x % kWave == 0)
-        for (int a = 0; a < 3; ++a) { s[w][a] = lo[a]; s[w][3 + a] = hi[a]; }
+        bad = fmax(bad, __shfl_xor(bad, d, kWave));
+    }
+    __shared__ double s7[kRedThreads / kWave][7];
+    if (threadIdx.x % kWave == 0) {
+        for (int a = 0; a < 3; ++a) { s7[w][a] = lo[a]; s7[w][3 + a] = hi[a]; }
+        s7[w][6] = bad;
+    }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    for (int k = 1; k < kRedThreads / kWave; ++k)
+    *done = 0;   // for the next build
+    for (int k = 1; k < kRedThreads / kWave; ++k) {
         for (int a = 0; a < 3; ++a) {
-            lo[a] = fmin(lo[a], s[k][a]);
-            hi[a] = fmax(hi[a], s[k][3 + a]);
+            lo[a] = fmin(lo[a], s7[k][a]);
+            hi[a] = fmax(hi[a], s7[k][3 + a]);
         }
+        bad = fmax(bad, s7[k][6]);
+    }
     double ext = 0.0;
     for (int a = 0; a < 3; ++a) {
         double e = hi[a] - lo[a];
@@ -117,7 +142,8 @@ __global__ __launch_bounds__(kRedThreads) void k_bbox_final(const double *partia
     for (int a = 0; a < 3; ++a) root->lo[a] = lo[a];
     root->L = L;
     root->scale = ldexp(1.0, kMaxLevel) / L;
-    root->bad_input = *bad;
+    root->bad_input = bad != 0.0 ? 1 : 0;
+    *bad_rb = bad != 0.0 ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -133,101 +159,145 @@ __device__ __forceinline__ uint64_t spread_bits3(uint64_t v) {
     return v;
 }
 
-__global__ void k_keys(const double *__restrict__ pos, int64_t n, const RootInfo *__restrict__ root,
-                       uint64_t *__restrict__ keys, int32_t *__restrict__ idx) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double scale = root->scale;
-    uint64_t q[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        double t = floor((pos[3 * i + a] - root->lo[a]) * scale);
-        uint64_t v = (uint64_t)t;
-        q[a] = v > 0x1fffffull ? 0x1fffffull : v;
-    }
-    keys[i] = (spread_bits3(q[0]) << 2) | (spread_bits3(q[1]) << 1) | spread_bits3(q[2]);
-    idx[i] = (int32_t)i;
-}
-
-int build_root_keys(p3t_ctx *ctx, const double *pos, const double *mass, int64_t n) {
-    int rc;
-    const int nb = (int)std::min<int64_t>(1024, (n + kRedThreads - 1) / kRedThreads);
-    if ((rc = ensure(ctx, ctx->root, sizeof(RootInfo)))) return rc;
-    if ((rc = ensure(ctx, ctx->dflags, 16 * sizeof(int32_t)))) return rc;
-    if ((rc = ensure(ctx, ctx->bbox, 6 * nb * sizeof(double)))) return rc;
-    if ((rc = ensure(ctx, ctx->keys[0], n * sizeof(uint64_t)))) return rc;
-    if ((rc = ensure(ctx, ctx->keys[1], n * sizeof(uint64_t)))) return rc;
-    if ((rc = ensure(ctx, ctx->vals[0], n * sizeof(int32_t)))) return rc;
-    if ((rc = ensure(ctx, ctx->vals[1], n * sizeof(int32_t)))) return rc;
-    int32_t *flags = ptr<int32_t>(ctx->dflags);
-    if ((rc = check_hip(ctx, hipMemsetAsync(flags, 0, 16 * sizeof(int32_t), ctx->stream), "memset")))
-        return rc;
-    double *partial = ptr<double>(ctx->bbox);
-    k_bbox_partial<<<nb, kRedThreads, 0, ctx->stream>>>(pos, mass, n, partial, flags);
-    k_bbox_final<<<1, kRedThreads, 0, ctx->stream>>>(partial, nb, flags, ptr<RootInfo>(ctx->root));
-    k_keys<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(pos, n, ptr<RootInfo>(ctx->root),
-                                                         ptr<uint64_t>(ctx->keys[0]),
-                                                         ptr<int32_t>(ctx->vals[0]));
-    return check_hip(ctx, hipGetLastError(), "root/keys");
-}
-
 // ---------------------------------------------------------------------------
-// Stable LSD radix sort of (key, index), 8 passes of 8 bits.
+// Stable LSD radix sort of (key, index): kRsPasses passes of kRsBits bits.
 // ---------------------------------------------------------------------------
 constexpr int kRsThreads = 256;
 constexpr int kRsRounds = 8;
 constexpr int kRsTile = kRsThreads * kRsRounds;   // 2048 keys per block
 constexpr int kRsWaves = kRsThreads / kWave;
+constexpr int kRsBits = 8;                         // digit width: 8 passes cover the 63 key bits
+constexpr int kRsBins = 1 << kRsBits;
+constexpr int kRsPasses = (3 * kMaxLevel + kRsBits - 1) / kRsBits;
+constexpr int kRsPer = kRsBins / kRsThreads;       // digits per thread in the bookkeeping
+static_assert(kRsBins % kRsThreads == 0, "whole digits per thread");
+
+__device__ __forceinline__ int rs_digit(uint64_t key, int shift) {
+    return (int)((key >> shift) & (kRsBins - 1));
+}
 
 __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t *__restrict__ keys, int64_t n,
                                                         int shift, int32_t *__restrict__ counts,
                                                         int nb) {
-    __shared__ int32_t h[256];
-    h[threadIdx.x] = 0;
+    __shared__ int32_t h[kRsBins];
+    for (int d = threadIdx.x; d < kRsBins; d += kRsThreads) h[d] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kRsTile;
     for (int r = 0; r < kRsRounds; ++r) {
         int64_t i = base + r * kRsThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255], 1);
+        if (i < n) atomicAdd(&h[rs_digit(keys[i], shift)], 1);
     }
     __syncthreads();
-    counts[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+    for (int d = threadIdx.x; d < kRsBins; d += kRsThreads)
+        counts[(int64_t)d * nb + blockIdx.x] = h[d];
 }
 
+// Morton keys of the tile of kRsTile particles of this block, their indices,
+// and the tile's histogram of the first radix digit (the keys' low bits)
+__global__ __launch_bounds__(kRsThreads) void k_keys_hist(const double *__restrict__ pos, int64_t n,
+                                                          const RootInfo *__restrict__ root,
+                                                          uint64_t *__restrict__ keys,
+                                                          int32_t *__restrict__ idx,
+                                                          int32_t *__restrict__ counts, int nb) {
+    __shared__ int32_t h[kRsBins];
+    for (int d = threadIdx.x; d < kRsBins; d += kRsThreads) h[d] = 0;
+    __syncthreads();
+    const double scale = root->scale;
+    const double lo[3] = {root->lo[0], root->lo[1], root->lo[2]};
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    for (int r = 0; r < kRsRounds; ++r) {
+        const int64_t i = base + r * kRsThreads + threadIdx.x;
+        if (i >= n) break;
+        uint64_t q[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double t = floor((pos[3 * i + a] - lo[a]) * scale);
+            const uint64_t v = (uint64_t)t;
+            q[a] = v > 0x1fffffull ? 0x1fffffull : v;
+        }
+        const uint64_t key = (spread_bits3(q[0]) << 2) | (spread_bits3(q[1]) << 1) | spread_bits3(q[2]);
+        keys[i] = key;
+        idx[i] = (int32_t)i;
+        atomicAdd(&h[rs_digit(key, 0)], 1);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < kRsBins; d += kRsThreads)
+        counts[(int64_t)d * nb + blockIdx.x] = h[d];
+}
+
+// exclusive scan over the kRsBins digits, thread t holding digits
+// kRsPer t .. kRsPer t + kRsPer - 1 in v
+__device__ __forceinline__ void block_excl_scan_bins(int v[kRsPer], int32_t *s_wsum) {
+    const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+    int local = 0;
+#pragma unroll
+    for (int k = 0; k < kRsPer; ++k) local += v[k];
+    const int incl = wave_incl_scan(local);
+    if (lane == kWave - 1) s_wsum[w] = incl;
+    __syncthreads();
+    int run = incl - local;
+    for (int k = 0; k < w; ++k) run += s_wsum[k];
+#pragma unroll
+    for (int k = 0; k < kRsPer; ++k) {
+        const int c = v[k];
+        v[k] = run;
+        run += c;
+    }
+}
+
+// LAST: the final pass also writes the sorted particle records xm (from the
+// caller's positions and masses) and clears the n + 1 group-start flags.
+struct SortedOut {
+    const double *pos, *mass;
+    PosMass *xm;
+    int32_t *gflag;
+};
+
+template <bool LAST>
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
     const uint64_t *__restrict__ kin, const int32_t *__restrict__ vin, uint64_t *__restrict__ kout,
     int32_t *__restrict__ vout, int64_t n, int shift, const int32_t *__restrict__ counts,
-    const int32_t *__restrict__ offsets, int nb) {
+    const int32_t *__restrict__ offsets, const int32_t *__restrict__ totals, int nb, SortedOut so) {
     __shared__ uint64_t s_key[kRsTile];
     __shared__ int32_t s_val[kRsTile];
-    __shared__ int32_t s_start[256], s_run[256];
-    __shared__ int32_t s_wcnt[kRsWaves][256], s_woff[kRsWaves][256];
-    __shared__ int32_t s_wsum[kRsWaves];
+    __shared__ int32_t s_start[kRsBins], s_run[kRsBins], s_dbase[kRsBins];
+    __shared__ int32_t s_wcnt[kRsWaves][kRsBins], s_woff[kRsWaves][kRsBins];
+    __shared__ int32_t s_wsum[kRsWaves], s_wsum2[kRsWaves];
     const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
     const int64_t base = (int64_t)blockIdx.x * kRsTile;
     const int64_t tile_n = std::min<int64_t>(kRsTile, n - base);
 
-    // digit starts inside this tile: exclusive scan of the tile histogram
+    // digit starts inside this tile (exclusive scan of the tile histogram) and
+    // the first output position of each digit (exclusive scan of the totals)
     {
-        int c = counts[(int64_t)tid * nb + blockIdx.x];
-        int incl = wave_incl_scan(c);
-        if (lane == kWave - 1) s_wsum[w] = incl;
-        __syncthreads();
-        int wb = 0;
-        for (int k = 0; k < w; ++k) wb += s_wsum[k];
-        s_start[tid] = wb + incl - c;
-        s_run[tid] = 0;
+        int c[kRsPer], t[kRsPer];
+#pragma unroll
+        for (int k = 0; k < kRsPer; ++k) {
+            const int d = kRsPer * tid + k;
+            c[k] = counts[(int64_t)d * nb + blockIdx.x];
+            t[k] = totals[d];
+        }
+        block_excl_scan_bins(c, s_wsum);
+        block_excl_scan_bins(t, s_wsum2);
+#pragma unroll
+        for (int k = 0; k < kRsPer; ++k) {
+            const int d = kRsPer * tid + k;
+            s_start[d] = c[k];
+            s_dbase[d] = t[k];
+            s_run[d] = 0;
+        }
     }
     for (int r = 0; r < kRsRounds; ++r) {
-        for (int k = 0; k < kRsWaves; ++k) s_wcnt[k][tid] = 0;
+        for (int k = 0; k < kRsWaves; ++k)
+            for (int d = tid; d < kRsBins; d += kRsThreads) s_wcnt[k][d] = 0;
         __syncthreads();
         const int64_t i = base + r * kRsThreads + tid;
         const bool valid = i < n;
         const uint64_t key = valid ? kin[i] : 0ull;
-        const int d = (int)((key >> shift) & 255);
+        const int d = rs_digit(key, shift);
         uint64_t same = ballot(valid);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < kRsBits; ++b) {
             const bool bit = (d >> b) & 1;
             const uint64_t bb = ballot(bit);
             same &= bit ? bb : ~bb;
@@ -235,14 +305,14 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
         const int rank_w = count_below(same);
         if (valid && rank_w == 0) s_wcnt[w][d] = __popcll(same);
         __syncthreads();
-        {
-            int run = s_run[tid];
+        for (int e = tid; e < kRsBins; e += kRsThreads) {
+            int run = s_run[e];
 #pragma unroll
             for (int k = 0; k < kRsWaves; ++k) {
-                s_woff[k][tid] = run;
-                run += s_wcnt[k][tid];
+                s_woff[k][e] = run;
+                run += s_wcnt[k][e];
             }
-            s_run[tid] = run;
+            s_run[e] = run;
         }
         __syncthreads();
         if (valid) {
@@ -254,57 +324,73 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
     }
     for (int p = tid; p < tile_n; p += kRsThreads) {
         const uint64_t key = s_key[p];
-        const int d = (int)((key >> shift) & 255);
-        const int64_t o = (int64_t)offsets[(int64_t)d * nb + blockIdx.x] + (p - s_start[d]);
+        const int d = rs_digit(key, shift);
+        const int64_t o = (int64_t)s_dbase[d] + offsets[(int64_t)d * nb + blockIdx.x] +
+                          (p - s_start[d]);
+        const int32_t v = s_val[p];
         kout[o] = key;
-        vout[o] = s_val[p];
+        vout[o] = v;
+        if (LAST) {
+            so.xm[o] = PosMass{so.pos[3 * (int64_t)v], so.pos[3 * (int64_t)v + 1],
+                               so.pos[3 * (int64_t)v + 2], so.mass[v]};
+            so.gflag[o] = 0;
+        }
     }
+    if (LAST && blockIdx.x == 0 && tid == 0) so.gflag[n] = 0;
 }
 
-int radix_sort_keys(p3t_ctx *ctx, int64_t n) {
+// Root cube, keys, the kRsPasses radix passes, and the sorted particle
+// records: the first digit's histogram comes with the keys, the records with
+// the last pass.
+int build_sorted(p3t_ctx *ctx, const double *pos, const double *mass, int64_t n) {
     int rc;
+    const int nbb = (int)std::min<int64_t>(256, (n + kRedThreads - 1) / kRedThreads);
     const int nb = (int)((n + kRsTile - 1) / kRsTile);
-    if ((rc = ensure(ctx, ctx->hist, (size_t)256 * nb * sizeof(int32_t)))) return rc;
-    if ((rc = ensure(ctx, ctx->histc, (size_t)256 * nb * sizeof(int32_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->root, sizeof(RootInfo)))) return rc;
+    if ((rc = ensure(ctx, ctx->bbox, kBboxRec * nbb * sizeof(double)))) return rc;
+    for (p3t::DevBuf *b : {&ctx->keys[0], &ctx->keys[1]})
+        if ((rc = ensure(ctx, *b, n * sizeof(uint64_t)))) return rc;
+    for (p3t::DevBuf *b : {&ctx->vals[0], &ctx->vals[1]})
+        if ((rc = ensure(ctx, *b, n * sizeof(int32_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->hist, (size_t)kRsBins * nb * sizeof(int32_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->histc, (size_t)kRsBins * nb * sizeof(int32_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->rs_tot, kRsBins * sizeof(int32_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->xm, n * sizeof(PosMass)))) return rc;
+    if ((rc = ensure(ctx, ctx->gflag, (n + 1) * sizeof(int32_t)))) return rc;
+    double *partial = ptr<double>(ctx->bbox);
+    int64_t *rb = ptr<int64_t>(ctx->readback);
+    k_bbox<<<nbb, kRedThreads, 0, ctx->stream>>>(pos, mass, n, partial, ptr<RootInfo>(ctx->root),
+                                                 rb + kRbTopoBad,
+                                                 reinterpret_cast<unsigned int *>(rb + kRbBboxDone));
     int32_t *cnt = ptr<int32_t>(ctx->histc), *off = ptr<int32_t>(ctx->hist);
+    int32_t *tot = ptr<int32_t>(ctx->rs_tot);
+    k_keys_hist<<<nb, kRsThreads, 0, ctx->stream>>>(pos, n, ptr<RootInfo>(ctx->root),
+                                                     ptr<uint64_t>(ctx->keys[0]),
+                                                     ptr<int32_t>(ctx->vals[0]), cnt, nb);
+    if ((rc = check_hip(ctx, hipGetLastError(), "root/keys"))) return rc;
+    const SortedOut so{pos, mass, ptr<PosMass>(ctx->xm), ptr<int32_t>(ctx->gflag)};
     int src = 0;
-    for (int pass = 0; pass < 8; ++pass) {
-        const int shift = 8 * pass;
+    for (int pass = 0; pass < kRsPasses; ++pass) {
+        const int shift = kRsBits * pass;
         uint64_t *kin = ptr<uint64_t>(ctx->keys[src]), *kout = ptr<uint64_t>(ctx->keys[1 - src]);
         int32_t *vin = ptr<int32_t>(ctx->vals[src]), *vout = ptr<int32_t>(ctx->vals[1 - src]);
-        k_rs_hist<<<nb, kRsThreads, 0, ctx->stream>>>(kin, n, shift, cnt, nb);
-        if ((rc = check_hip(ctx, hipGetLastError(), "radix hist"))) return rc;
-        if ((rc = scan_exclusive_i32(ctx, cnt, off, (int64_t)256 * nb, nullptr))) return rc;
-        k_rs_scatter<<<nb, kRsThreads, 0, ctx->stream>>>(kin, vin, kout, vout, n, shift, cnt, off, nb);
+        if (pass > 0) {
+            k_rs_hist<<<nb, kRsThreads, 0, ctx->stream>>>(kin, n, shift, cnt, nb);
+            if ((rc = check_hip(ctx, hipGetLastError(), "radix hist"))) return rc;
+        }
+        if ((rc = scan_rows_i32(ctx, cnt, off, tot, kRsBins, nb))) return rc;
+        auto scatter = pass == kRsPasses - 1 ? k_rs_scatter<true> : k_rs_scatter<false>;
+        scatter<<<nb, kRsThreads, 0, ctx->stream>>>(kin, vin, kout, vout, n, shift, cnt, off, tot,
+                                                     nb, so);
         if ((rc = check_hip(ctx, hipGetLastError(), "radix scatter"))) return rc;
         src = 1 - src;
     }
-    return P3T_OK;  // 8 passes: the result is back in keys[0] / vals[0]
-}
-
-// ---------------------------------------------------------------------------
-// Sorted SoA copy of positions and masses
-// ---------------------------------------------------------------------------
-__global__ void k_gather(const double *__restrict__ pos, const double *__restrict__ mass,
-                         const int32_t *__restrict__ perm, int64_t n, double *__restrict__ x,
-                         double *__restrict__ y, double *__restrict__ z, double *__restrict__ m) {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int64_t o = perm[s];
-    x[s] = pos[3 * o];
-    y[s] = pos[3 * o + 1];
-    z[s] = pos[3 * o + 2];
-    m[s] = mass[o];
-}
-
-int gather_sorted(p3t_ctx *ctx, const double *pos, const double *mass, int64_t n) {
-    int rc;
-    for (p3t::DevBuf *b : {&ctx->x, &ctx->y, &ctx->z, &ctx->m})
-        if ((rc = ensure(ctx, *b, n * sizeof(double)))) return rc;
-    k_gather<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(pos, mass, ptr<int32_t>(ctx->vals[0]), n,
-                                                           ptr<double>(ctx->x), ptr<double>(ctx->y),
-                                                           ptr<double>(ctx->z), ptr<double>(ctx->m));
-    return check_hip(ctx, hipGetLastError(), "gather");
+    // the passes alternate between the two buffers: an odd count ends in the second
+    if (src == 1) {
+        std::swap(ctx->keys[0], ctx->keys[1]);
+        std::swap(ctx->vals[0], ctx->vals[1]);
+    }
+    return P3T_OK;  // the sorted keys and permutation are in keys[0] / vals[0]
 }
 
 // ---------------------------------------------------------------------------
@@ -396,16 +482,17 @@ __global__ __launch_bounds__(kTopoThreads) void k_topo_ranges(const uint64_t *__
     if (threadIdx.x < kLevels) blk[(int64_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
 }
 
-__global__ void k_topo_level_starts(const int32_t *__restrict__ blk_off, int nb, const int32_t *total,
-                                    int64_t *__restrict__ out) {
-    const int l = threadIdx.x;
-    if (l < kLevels) out[l] = blk_off[(int64_t)l * nb];
-    if (l == kLevels) out[l] = *total;
-}
+// first node id of every level, and the node count at [kLevels] (computed on
+// the host from the per-level node counts, passed by value)
+struct LevelStarts {
+    int64_t s[kLevels + 1];
+};
 
+// blk_off: per level, the exclusive scan of the node starts over the blocks
 __global__ __launch_bounds__(kTopoThreads) void k_topo_emit(
     const uint64_t *__restrict__ keys, int64_t n, const int32_t *__restrict__ range,
-    const int32_t *__restrict__ blk_off, int nb, int32_t *__restrict__ level, int32_t *__restrict__ first,
+    const int32_t *__restrict__ blk_off, const LevelStarts level_start, int nb,
+    int32_t *__restrict__ level, int32_t *__restrict__ first,
     int32_t *__restrict__ count, int32_t *__restrict__ child, int32_t *__restrict__ nchild,
     uint64_t *__restrict__ prefix) {
     __shared__ uint64_t s_ball[kLevels][kTopoWaves];
@@ -427,7 +514,7 @@ __global__ __launch_bounds__(kTopoThreads) void k_topo_emit(
     const uint64_t ka = keys[a];
     // number of level-l starts before position a, plus the level's first id
     auto rank_at = [&](int l) -> int32_t {
-        int base = blk_off[(int64_t)l * nb + blockIdx.x];
+        int base = (int)level_start.s[l] + blk_off[(int64_t)l * nb + blockIdx.x];
         for (int k = 0; k < w; ++k) base += s_wc[l][k];
         return base + count_below(s_ball[l][w]);
     };
@@ -451,13 +538,13 @@ __global__ __launch_bounds__(kTopoThreads) void k_topo_emit(
 // - (own first child); parents from the children ranges.
 __global__ void k_topo_links(int64_t n_nodes, const int32_t *__restrict__ level,
                              const int32_t *__restrict__ child, int32_t *__restrict__ nchild,
-                             int32_t *__restrict__ parent, const int64_t *__restrict__ level_start) {
+                             int32_t *__restrict__ parent, const LevelStarts level_start) {
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= n_nodes) return;
     if (id == 0) parent[0] = -1;
     if (nchild[id] != -1) return;
     const int l = level[id];
-    const int64_t next = (id + 1 < level_start[l + 1]) ? child[id + 1] : level_start[l + 2];
+    const int64_t next = (id + 1 < level_start.s[l + 1]) ? child[id + 1] : level_start.s[l + 2];
     const int32_t cf = child[id];
     const int32_t nc = (int32_t)(next - cf);
     nchild[id] = nc;
@@ -469,32 +556,35 @@ int build_topology(p3t_ctx *ctx, int64_t n) {
     const int nb = (int)((n + kTopoThreads - 1) / kTopoThreads);
     if ((rc = ensure(ctx, ctx->lvlrange, n * sizeof(int32_t)))) return rc;
     if ((rc = ensure(ctx, ctx->tblk, (size_t)kLevels * nb * sizeof(int32_t)))) return rc;
-    if ((rc = ensure(ctx, ctx->tblk_off, ((size_t)kLevels * nb + 1) * sizeof(int32_t)))) return rc;
-    if ((rc = ensure(ctx, ctx->readback, 64 * sizeof(int64_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->tblk_off, (size_t)kLevels * nb * sizeof(int32_t)))) return rc;
+    if ((rc = ensure_readback(ctx))) return rc;
     const uint64_t *keys = ptr<uint64_t>(ctx->keys[0]);
     int32_t *blk = ptr<int32_t>(ctx->tblk), *blk_off = ptr<int32_t>(ctx->tblk_off);
     int64_t *rb = ptr<int64_t>(ctx->readback);
     k_topo_ranges<<<nb, kTopoThreads, 0, ctx->stream>>>(keys, n, ctx->prm.n_leaf,
                                                         ptr<int32_t>(ctx->lvlrange), blk, nb);
     if ((rc = check_hip(ctx, hipGetLastError(), "topology ranges"))) return rc;
-    int32_t *total = blk_off + (size_t)kLevels * nb;
-    if ((rc = scan_exclusive_i32(ctx, blk, blk_off, (int64_t)kLevels * nb, total))) return rc;
-    k_topo_level_starts<<<1, 64, 0, ctx->stream>>>(blk_off, nb, total, rb);
-    if ((rc = check_hip(ctx, hipGetLastError(), "topology level starts"))) return rc;
-    // one read-back: node count, level starts and the input check
-    if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin, rb, (kLevels + 1) * sizeof(int64_t),
+    // the per-level node counts go straight to the readback area (int32, in
+    // the words before the input check)
+    static_assert(kLevels * sizeof(int32_t) <= kRbTopoBad * sizeof(int64_t), "readback layout");
+    int32_t *level_total = reinterpret_cast<int32_t *>(rb);
+    if ((rc = scan_rows_i32(ctx, blk, blk_off, level_total, kLevels, nb))) return rc;
+    // one read-back: node counts per level and the input check
+    if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin, rb, (kRbTopoBad + 1) * sizeof(int64_t),
                                             hipMemcpyDeviceToHost, ctx->stream), "readback")))
         return rc;
-    if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + 32, (const char *)ctx->root.p +
-                                                offsetof(RootInfo, bad_input),
-                                            sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream),
-                        "readback")))
-        return rc;
     if ((rc = check_hip(ctx, hipStreamSynchronize(ctx->stream), "sync"))) return rc;
-    if (*(int32_t *)(ctx->hpin + 32))
+    if (ctx->hpin[kRbTopoBad])
         return set_error(ctx, P3T_EINVAL, "non-finite position or non-positive/non-finite mass");
-    for (int l = 0; l <= kLevels; ++l) ctx->level_start[l] = ctx->hpin[l];
-    ctx->n_nodes = ctx->level_start[kLevels];
+    LevelStarts ls;
+    const int32_t *hl = reinterpret_cast<const int32_t *>(ctx->hpin);
+    int64_t run = 0;
+    for (int l = 0; l < kLevels; ++l) {
+        ls.s[l] = ctx->level_start[l] = run;
+        run += hl[l];
+    }
+    ls.s[kLevels] = ctx->level_start[kLevels] = run;
+    ctx->n_nodes = run;
     ctx->depth = 0;
     for (int l = 0; l < kLevels; ++l)
         if (ctx->level_start[l + 1] > ctx->level_start[l]) ctx->depth = l;
@@ -504,152 +594,171 @@ int build_topology(p3t_ctx *ctx, int64_t n) {
         if ((rc = ensure(ctx, *b, nn * sizeof(int32_t)))) return rc;
     if ((rc = ensure(ctx, ctx->node_prefix, nn * sizeof(uint64_t)))) return rc;
     k_topo_emit<<<nb, kTopoThreads, 0, ctx->stream>>>(
-        keys, n, ptr<int32_t>(ctx->lvlrange), blk_off, nb, ptr<int32_t>(ctx->node_level),
+        keys, n, ptr<int32_t>(ctx->lvlrange), blk_off, ls, nb, ptr<int32_t>(ctx->node_level),
         ptr<int32_t>(ctx->node_first), ptr<int32_t>(ctx->node_count), ptr<int32_t>(ctx->node_child),
         ptr<int32_t>(ctx->node_nchild), ptr<uint64_t>(ctx->node_prefix));
     if ((rc = check_hip(ctx, hipGetLastError(), "topology emit"))) return rc;
     k_topo_links<<<blocks_for(nn, 256), 256, 0, ctx->stream>>>(
         nn, ptr<int32_t>(ctx->node_level), ptr<int32_t>(ctx->node_child),
-        ptr<int32_t>(ctx->node_nchild), ptr<int32_t>(ctx->node_parent), rb);
+        ptr<int32_t>(ctx->node_nchild), ptr<int32_t>(ctx->node_parent), ls);
     return check_hip(ctx, hipGetLastError(), "topology links");
 }
 
 // ---------------------------------------------------------------------------
-// Moments, one launch per level from the deepest up.
+// Moments, bottom up: every leaf in one launch (a thread per node), then the
+// internal nodes level by level from the deepest, one launch per level.  The
+// folds are the same IEEE operation sequences in the same order (members in
+// sorted order, children in octant order) whichever thread performs them.
 // ---------------------------------------------------------------------------
-// MODE 1: every leaf of the tree (leaves depend on particles only);
-// MODE 2: the internal nodes of one level (their children are complete).
-template <int MODE>
-__global__ __launch_bounds__(128) void k_moments_level(int64_t begin, int64_t end, int lev,
-                                const int32_t *__restrict__ level, const RootInfo *__restrict__ root,
-                                const double *__restrict__ x, const double *__restrict__ y,
-                                const double *__restrict__ z, const double *__restrict__ m,
-                                const int32_t *__restrict__ first, const int32_t *__restrict__ count,
-                                const int32_t *__restrict__ child, const int32_t *__restrict__ nchild,
-                                double *__restrict__ S, NodeWalk *__restrict__ nw,
-                                NodeMP *__restrict__ mp, int64_t n_nodes) {
-    const int64_t id = begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= end) return;
-    const int nc = nchild[id];
-    if ((MODE == 1) != (nc == 0)) return;
-    if (MODE == 1) lev = level[id];
-    const int32_t f = first[id], cnt = count[id];
-    double M = 0.0, Sx = 0.0, Sy = 0.0, Sz = 0.0;
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    double q[6] = {0, 0, 0, 0, 0, 0};
-    if (MODE == 1) {
-        // particles in chunks of 8, loaded together (clamped to the last
-        // member), folded in order
-        const int32_t e = f + cnt;
-        for (int32_t k0 = f; k0 < e; k0 += 8) {
-            double cm[8], cx8[8], cy8[8], cz8[8];
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const int32_t k = k0 + c < e ? k0 + c : e - 1;
-                cm[c] = m[k]; cx8[c] = x[k]; cy8[c] = y[k]; cz8[c] = z[k];
-            }
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                if (k0 + c >= e) continue;
-                const double mk = cm[c], xk = cx8[c], yk = cy8[c], zk = cz8[c];
-                M = M + mk;
-                Sx = Sx + mk * xk;
-                Sy = Sy + mk * yk;
-                Sz = Sz + mk * zk;
-                lo[0] = fmin(lo[0], xk); lo[1] = fmin(lo[1], yk); lo[2] = fmin(lo[2], zk);
-                hi[0] = fmax(hi[0], xk); hi[1] = fmax(hi[1], yk); hi[2] = fmax(hi[2], zk);
-            }
-        }
-        const double cx = Sx / M, cy = Sy / M, cz = Sz / M;
-        for (int32_t k0 = f; k0 < e; k0 += 8) {
-            double cm[8], cx8[8], cy8[8], cz8[8];
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const int32_t k = k0 + c < e ? k0 + c : e - 1;
-                cm[c] = m[k]; cx8[c] = x[k]; cy8[c] = y[k]; cz8[c] = z[k];
-            }
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                if (k0 + c >= e) continue;
-                const double mk = cm[c];
-                const double dx = cx8[c] - cx, dy = cy8[c] - cy, dz = cz8[c] - cz;
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                q[0] += mk * (3.0 * dx * dx - r2);
-                q[1] += mk * (3.0 * dy * dy - r2);
-                q[2] += mk * (3.0 * dz * dz - r2);
-                q[3] += mk * 3.0 * dx * dy;
-                q[4] += mk * 3.0 * dx * dz;
-                q[5] += mk * 3.0 * dy * dz;
-            }
-        }
-    } else {
-        const int32_t cf = child[id];
-        // at most 8 children: every child slot is loaded (clamped to the last
-        // child) so that the loads issue together; the folds keep child order
-        // and skip the slots past nc
-        double cM[8], cS[8][3], clo[8][3], chi[8][3];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const int k = cf + (c < nc ? c : nc - 1);
-            cM[c] = mp[k].M;
-            cS[c][0] = S[k];
-            cS[c][1] = S[n_nodes + k];
-            cS[c][2] = S[2 * n_nodes + k];
-            for (int a = 0; a < 3; ++a) {
-                clo[c][a] = nw[k].lo[a];
-                chi[c][a] = nw[k].hi[a];
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            if (c < nc) {
-                M = M + cM[c];
-                Sx = Sx + cS[c][0];
-                Sy = Sy + cS[c][1];
-                Sz = Sz + cS[c][2];
-                for (int a = 0; a < 3; ++a) {
-                    lo[a] = fmin(lo[a], clo[c][a]);
-                    hi[a] = fmax(hi[a], chi[c][a]);
-                }
-            }
-        }
-        const double cx = Sx / M, cy = Sy / M, cz = Sz / M;
-        // parallel-axis shift of the children's quadrupoles to this centre
-        NodeMP cm[8];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) cm[c] = mp[cf + (c < nc ? c : nc - 1)];
-#pragma unroll
-        for (int cc = 0; cc < 8; ++cc) {
-            if (cc >= nc) continue;
-            const NodeMP c = cm[cc];
-            const double dx = c.cx - cx, dy = c.cy - cy, dz = c.cz - cz;
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            q[0] += c.q[0] + c.M * (3.0 * dx * dx - r2);
-            q[1] += c.q[1] + c.M * (3.0 * dy * dy - r2);
-            q[2] += c.q[2] + c.M * (3.0 * dz * dz - r2);
-            q[3] += c.q[3] + c.M * 3.0 * dx * dy;
-            q[4] += c.q[4] + c.M * 3.0 * dx * dz;
-            q[5] += c.q[5] + c.M * 3.0 * dy * dz;
-        }
-    }
+struct MomentArrays {
+    const int32_t *level, *first, *count, *child, *nchild, *parent;
+    const RootInfo *root;
+    const PosMass *xm;
+    double *S;
+    NodeWalk *nw;
+    NodeMP *mp;
+    int64_t n_nodes;
+};
+
+__device__ __forceinline__ void store_node(const MomentArrays &A, int64_t id, int lev, int nc,
+                                           int32_t f, int32_t cnt, double M, double Sx,
+                                           double Sy, double Sz, const double lo[3],
+                                           const double hi[3], const double q[6]) {
     const double cx = Sx / M, cy = Sy / M, cz = Sz / M;
-    S[id] = Sx;
-    S[n_nodes + id] = Sy;
-    S[2 * n_nodes + id] = Sz;
-    const double side = ldexp(root->L, -lev);
+    A.S[id] = Sx;
+    A.S[A.n_nodes + id] = Sy;
+    A.S[2 * A.n_nodes + id] = Sz;
+    const double side = ldexp(A.root->L, -lev);
     NodeWalk o;
     o.cx = cx; o.cy = cy; o.cz = cz;
     o.l2 = side * side;
     for (int a = 0; a < 3; ++a) { o.lo[a] = lo[a]; o.hi[a] = hi[a]; }
-    o.child_first = nc ? child[id] : -1;
+    o.child_first = nc ? A.child[id] : -1;
     o.n_child = nc;
     o.first = f;
     o.count = cnt;
-    nw[id] = o;
+    A.nw[id] = o;
     NodeMP p;
     p.cx = cx; p.cy = cy; p.cz = cz; p.M = M;
     for (int a = 0; a < 6; ++a) p.q[a] = q[a];
-    mp[id] = p;
+    A.mp[id] = p;
+}
+
+// fold of a leaf's members in sorted order: M, S = sum m x (left folds),
+// box, and the quadrupole about com = S / M
+__device__ __forceinline__ void leaf_moments(const MomentArrays &A, int64_t id) {
+    constexpr int kChunk = 8;    // members held in registers at once
+    const int32_t f = A.first[id], cnt = A.count[id], e = f + cnt;
+    double M = 0.0, Sx = 0.0, Sy = 0.0, Sz = 0.0;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double q[6] = {0, 0, 0, 0, 0, 0};
+    PosMass pk[kChunk];
+    // the members, loaded together (clamped to the last member) kChunk at a
+    // time; a leaf of at most kChunk members is read once for both folds
+    auto load = [&](int32_t k0) {
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c) pk[c] = A.xm[k0 + c < e ? k0 + c : e - 1];
+    };
+    for (int32_t k0 = f; k0 < e; k0 += kChunk) {
+        load(k0);
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c) {
+            if (k0 + c >= e) continue;
+            const double mk = pk[c].m, xk = pk[c].x, yk = pk[c].y, zk = pk[c].z;
+            M = M + mk;
+            Sx = Sx + mk * xk;
+            Sy = Sy + mk * yk;
+            Sz = Sz + mk * zk;
+            lo[0] = fmin(lo[0], xk); lo[1] = fmin(lo[1], yk); lo[2] = fmin(lo[2], zk);
+            hi[0] = fmax(hi[0], xk); hi[1] = fmax(hi[1], yk); hi[2] = fmax(hi[2], zk);
+        }
+    }
+    const double cx = Sx / M, cy = Sy / M, cz = Sz / M;
+    for (int32_t k0 = f; k0 < e; k0 += kChunk) {
+        if (cnt > kChunk) load(k0);
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c) {
+            if (k0 + c >= e) continue;
+            const double mk = pk[c].m;
+            const double dx = pk[c].x - cx, dy = pk[c].y - cy, dz = pk[c].z - cz;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            q[0] += mk * (3.0 * dx * dx - r2);
+            q[1] += mk * (3.0 * dy * dy - r2);
+            q[2] += mk * (3.0 * dz * dz - r2);
+            q[3] += mk * 3.0 * dx * dy;
+            q[4] += mk * 3.0 * dx * dz;
+            q[5] += mk * 3.0 * dy * dz;
+        }
+    }
+    store_node(A, id, A.level[id], 0, f, cnt, M, Sx, Sy, Sz, lo, hi, q);
+}
+
+// fold of an internal node's (at most 8) children in octant order, the
+// children's quadrupoles shifted to the node's centre of mass
+__device__ __forceinline__ void internal_moments(const MomentArrays &A, int64_t id) {
+    const int nc = A.nchild[id];
+    const int32_t cf = A.child[id];
+    double M = 0.0, Sx = 0.0, Sy = 0.0, Sz = 0.0;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double q[6] = {0, 0, 0, 0, 0, 0};
+    // every child slot is loaded (clamped to the last child) so that all the
+    // loads issue together; the folds keep child order and skip the slots
+    // past nc
+    NodeMP cm[8];
+    double cS[8][3], clo[8][3], chi[8][3];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int k = cf + (c < nc ? c : nc - 1);
+        cm[c] = A.mp[k];
+        cS[c][0] = A.S[k];
+        cS[c][1] = A.S[A.n_nodes + k];
+        cS[c][2] = A.S[2 * A.n_nodes + k];
+        for (int a = 0; a < 3; ++a) {
+            clo[c][a] = A.nw[k].lo[a];
+            chi[c][a] = A.nw[k].hi[a];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if (c < nc) {
+            M = M + cm[c].M;
+            Sx = Sx + cS[c][0];
+            Sy = Sy + cS[c][1];
+            Sz = Sz + cS[c][2];
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = fmin(lo[a], clo[c][a]);
+                hi[a] = fmax(hi[a], chi[c][a]);
+            }
+        }
+    }
+    const double cx = Sx / M, cy = Sy / M, cz = Sz / M;
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) {
+        if (cc >= nc) continue;
+        const NodeMP c = cm[cc];
+        const double dx = c.cx - cx, dy = c.cy - cy, dz = c.cz - cz;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        q[0] += c.q[0] + c.M * (3.0 * dx * dx - r2);
+        q[1] += c.q[1] + c.M * (3.0 * dy * dy - r2);
+        q[2] += c.q[2] + c.M * (3.0 * dz * dz - r2);
+        q[3] += c.q[3] + c.M * 3.0 * dx * dy;
+        q[4] += c.q[4] + c.M * 3.0 * dx * dz;
+        q[5] += c.q[5] + c.M * 3.0 * dy * dz;
+    }
+    store_node(A, id, A.level[id], nc, A.first[id], A.count[id], M, Sx, Sy, Sz, lo, hi, q);
+}
+
+__global__ __launch_bounds__(128) void k_moments_leaves(MomentArrays A) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= A.n_nodes || A.nchild[id] != 0) return;
+    leaf_moments(A, id);
+}
+
+// the internal nodes with ids in [begin, end) (one level)
+__global__ __launch_bounds__(128) void k_moments_level(MomentArrays A, int64_t begin, int64_t end) {
+    const int64_t id = begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= end || A.nchild[id] == 0) return;
+    internal_moments(A, id);
 }
 
 int build_moments(p3t_ctx *ctx) {
@@ -658,21 +767,25 @@ int build_moments(p3t_ctx *ctx) {
     if ((rc = ensure(ctx, ctx->node_S, 3 * nn * sizeof(double)))) return rc;
     if ((rc = ensure(ctx, ctx->node_walk, nn * sizeof(NodeWalk)))) return rc;
     if ((rc = ensure(ctx, ctx->node_mp, nn * sizeof(NodeMP)))) return rc;
-    for (int l = kLevels; l >= 0; --l) {
-        // l == kLevels: one launch over all leaves; then internal nodes level by level
-        const bool leaves = l == kLevels;
-        const int64_t b = leaves ? 0 : ctx->level_start[l];
-        const int64_t e = leaves ? nn : ctx->level_start[l + 1];
-        if (e <= b || l == kMaxLevel) continue;   // level 21 holds leaves only
-        auto kern = leaves ? k_moments_level<1> : k_moments_level<2>;
-        kern<<<blocks_for(e - b, 128), 128, 0, ctx->stream>>>(
-            b, e, l, ptr<int32_t>(ctx->node_level), ptr<RootInfo>(ctx->root),
-            ptr<double>(ctx->x), ptr<double>(ctx->y),
-            ptr<double>(ctx->z), ptr<double>(ctx->m), ptr<int32_t>(ctx->node_first),
-            ptr<int32_t>(ctx->node_count), ptr<int32_t>(ctx->node_child),
-            ptr<int32_t>(ctx->node_nchild), ptr<double>(ctx->node_S), ptr<NodeWalk>(ctx->node_walk),
-            ptr<NodeMP>(ctx->node_mp), nn);
-        if ((rc = check_hip(ctx, hipGetLastError(), "moments"))) return rc;
+    MomentArrays A;
+    A.level = ptr<int32_t>(ctx->node_level);
+    A.first = ptr<int32_t>(ctx->node_first);
+    A.count = ptr<int32_t>(ctx->node_count);
+    A.child = ptr<int32_t>(ctx->node_child);
+    A.nchild = ptr<int32_t>(ctx->node_nchild);
+    A.parent = ptr<int32_t>(ctx->node_parent);
+    A.root = ptr<RootInfo>(ctx->root);
+    A.xm = ptr<PosMass>(ctx->xm);
+    A.S = ptr<double>(ctx->node_S);
+    A.nw = ptr<NodeWalk>(ctx->node_walk);
+    A.mp = ptr<NodeMP>(ctx->node_mp);
+    A.n_nodes = nn;
+    k_moments_leaves<<<blocks_for(nn, 128), 128, 0, ctx->stream>>>(A);
+    if ((rc = check_hip(ctx, hipGetLastError(), "moments (leaves)"))) return rc;
+    for (int l = (int)ctx->depth - 1; l >= 0; --l) {   // the deepest level holds leaves only
+        const int64_t b = ctx->level_start[l], e = ctx->level_start[l + 1];
+        k_moments_level<<<blocks_for(e - b, 128), 128, 0, ctx->stream>>>(A, b, e);
+        if ((rc = check_hip(ctx, hipGetLastError(), "moments (level)"))) return rc;
     }
     return P3T_OK;
 }
@@ -694,10 +807,13 @@ __global__ void k_group_mark(int64_t n_nodes, const int32_t *__restrict__ count,
     }
 }
 
+// also clears the walk's statistics words (zero, nz of them)
 __global__ void k_group_compact(int64_t n, const int32_t *__restrict__ flag,
                                 const int32_t *__restrict__ slot, const int32_t *__restrict__ node_at,
-                                const NodeWalk *__restrict__ nw, GroupInfo *__restrict__ grp) {
+                                const NodeWalk *__restrict__ nw, GroupInfo *__restrict__ grp,
+                                int64_t *__restrict__ zero, int nz) {
     int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < nz) zero[a] = 0;
     if (a >= n || !flag[a]) return;
     const int32_t id = node_at[a];
     const NodeWalk nd = nw[id];
@@ -723,16 +839,16 @@ int build_groups(p3t_ctx *ctx) {
     if ((rc = ensure(ctx, ctx->grp, (nn + 1) * sizeof(GroupInfo)))) return rc;
     int32_t *flag = ptr<int32_t>(ctx->gflag), *slot = ptr<int32_t>(ctx->gscan);
     int32_t *node_at = ptr<int32_t>(ctx->lvlrange);
-    if ((rc = check_hip(ctx, hipMemsetAsync(flag, 0, (n + 1) * sizeof(int32_t), ctx->stream), "memset")))
-        return rc;
+    // the flags were cleared by the last radix pass
     k_group_mark<<<blocks_for(nn, 256), 256, 0, ctx->stream>>>(
         nn, ptr<int32_t>(ctx->node_count), ptr<int32_t>(ctx->node_nchild),
         ptr<int32_t>(ctx->node_parent), ptr<int32_t>(ctx->node_first), ctx->prm.n_crit, flag, node_at);
     if ((rc = check_hip(ctx, hipGetLastError(), "group mark"))) return rc;
     // slot[n] = number of groups (device), read back together with the list sizes
     if ((rc = scan_exclusive_i32(ctx, flag, slot, n + 1, nullptr))) return rc;
-    k_group_compact<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(
-        n, flag, slot, node_at, ptr<NodeWalk>(ctx->node_walk), ptr<GroupInfo>(ctx->grp));
+    k_group_compact<<<blocks_for(n > kRbWalkWords ? n : kRbWalkWords, 256), 256, 0, ctx->stream>>>(
+        n, flag, slot, node_at, ptr<NodeWalk>(ctx->node_walk), ptr<GroupInfo>(ctx->grp),
+        ptr<int64_t>(ctx->readback) + kRbWalk, kRbWalkWords);
     return check_hip(ctx, hipGetLastError(), "group compact");
 }
 

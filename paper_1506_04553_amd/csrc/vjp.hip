@@ -233,9 +233,8 @@ __device__ __forceinline__ void vjp_i_pp_tile(const VjpPart<R> *sp, const int32_
 // CELL_K: accepted cells may lie within r_out of a member (h < r_out)
 template <class R, bool CELL_K>
 __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
-    const GroupInfo *__restrict__ grp, ListsDev L, const double *__restrict__ x,
-    const double *__restrict__ y,
-    const double *__restrict__ z, const double *__restrict__ m, const NodeMP *__restrict__ mp,
+    const GroupInfo *__restrict__ grp, ListsDev L, const PosMass *__restrict__ xm,
+    const NodeMP *__restrict__ mp,
     const int32_t *__restrict__ perm, const double *__restrict__ wv, const double *__restrict__ cv,
     VjpParams vp, double *__restrict__ gx, double *__restrict__ gm, int64_t n) {
     __shared__ VjpPart<R> s_p[kVjpTile];
@@ -260,7 +259,8 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
         const int li = tid & (pad - 1), slice = tid >> lg;
         const int32_t i = gi.first + chunk + li;
         const int64_t o = perm[i];
-        const R xi = (R)(x[i] - sh[0]), yi = (R)(y[i] - sh[1]), zi = (R)(z[i] - sh[2]);
+        const PosMass pi = xm[i];
+        const R xi = (R)(pi.x - sh[0]), yi = (R)(pi.y - sh[1]), zi = (R)(pi.z - sh[2]);
         const R wx = (R)wv[3 * o], wy = (R)wv[3 * o + 1], wz = (R)wv[3 * o + 2];
         const R ci = vp.has_c ? (R)cv[o] : R(0);
         double g0 = 0, g1 = 0, g2 = 0;
@@ -273,8 +273,9 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
                 __syncthreads();
                 if (tid < tl) {
                     const int32_t j = idxs[t0 + tid];
-                    s_p[tid] = VjpPart<R>{(R)(x[j] - sh[0]), (R)(y[j] - sh[1]), (R)(z[j] - sh[2]),
-                                          (R)m[j]};
+                    const PosMass pj = xm[j];
+                    s_p[tid] = VjpPart<R>{(R)(pj.x - sh[0]), (R)(pj.y - sh[1]), (R)(pj.z - sh[2]),
+                                          (R)pj.m};
                     s_j[tid] = j;
                 }
                 __syncthreads();
@@ -352,9 +353,8 @@ __device__ __forceinline__ void vjp_scatter_pp(const VjpMember<R> *si, const int
 
 template <class R, bool CELL_K>
 __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
-    const GroupInfo *__restrict__ grp, ListsDev L, const double *__restrict__ x,
-    const double *__restrict__ y,
-    const double *__restrict__ z, const double *__restrict__ m, const NodeMP *__restrict__ mp,
+    const GroupInfo *__restrict__ grp, ListsDev L, const PosMass *__restrict__ xm,
+    const NodeMP *__restrict__ mp,
     const int32_t *__restrict__ perm, const double *__restrict__ wv, const double *__restrict__ cv,
     VjpParams vp, double *__restrict__ gx, double *__restrict__ gm, double *__restrict__ cadj,
     int64_t n, int64_t n_nodes) {
@@ -378,7 +378,8 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
         if (tid < nc) {
             const int32_t i = gi.first + chunk + tid;
             const int64_t o = perm[i];
-            s_i[tid] = VjpMember<R>{(R)(x[i] - sh[0]), (R)(y[i] - sh[1]), (R)(z[i] - sh[2]),
+            const PosMass pi = xm[i];
+            s_i[tid] = VjpMember<R>{(R)(pi.x - sh[0]), (R)(pi.y - sh[1]), (R)(pi.z - sh[2]),
                                     vp.has_c ? (R)cv[o] : R(0), (R)wv[3 * o], (R)wv[3 * o + 1],
                                     (R)wv[3 * o + 2], R(0)};
             s_id[tid] = i;
@@ -387,8 +388,9 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
         for (int64_t e = tid; e < np; e += kVjpThreads) {
             const bool far = e < nf;
             const int32_t j = far ? p_idx[fb + e] : n_idx[nb + (e - nf)];
-            const R xj = (R)(x[j] - sh[0]), yj = (R)(y[j] - sh[1]), zj = (R)(z[j] - sh[2]);
-            const R mj = (R)m[j];
+            const PosMass pj = xm[j];
+            const R xj = (R)(pj.x - sh[0]), yj = (R)(pj.y - sh[1]), zj = (R)(pj.z - sh[2]);
+            const R mj = (R)pj.m;
             double acc[4] = {0, 0, 0, 0};
             if (far)   // K = W = 1, never a member
                 vjp_scatter_pp<R, false>(s_i, s_id, nc, j, xj, yj, zj, mj, vp, acc);
@@ -467,8 +469,7 @@ __device__ __forceinline__ void form_shift(Form &f, const double e[3]) {
 __global__ void k_vjp_down(int64_t n_nodes, const int32_t *__restrict__ nchild,
                            const int32_t *__restrict__ parent, const NodeMP *__restrict__ mp,
                            const NodeWalk *__restrict__ nw, const double *__restrict__ cadj,
-                           const double *__restrict__ x, const double *__restrict__ y,
-                           const double *__restrict__ z, const double *__restrict__ m,
+                           const PosMass *__restrict__ xm,
                            double *__restrict__ gx, double *__restrict__ gm, int64_t n) {
     const int64_t leaf = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (leaf >= n_nodes || nchild[leaf] != 0) return;
@@ -488,12 +489,13 @@ __global__ void k_vjp_down(int64_t n_nodes, const int32_t *__restrict__ nchild,
     const double cx = mp[leaf].cx, cy = mp[leaf].cy, cz = mp[leaf].cz;
     const int32_t first = nw[leaf].first, cnt = nw[leaf].count;
     for (int32_t k = first; k < first + cnt; ++k) {
-        const double d[3] = {x[k] - cx, y[k] - cy, z[k] - cz};
+        const PosMass pk = xm[k];
+        const double d[3] = {pk.x - cx, pk.y - cy, pk.z - cz};
         double Bd[3];
         Bmul(f.B, d, Bd);
         gm[k] += d[0] * Bd[0] + d[1] * Bd[1] + d[2] * Bd[2] + f.b[0] * d[0] + f.b[1] * d[1] +
                  f.b[2] * d[2] + f.g;
-        const double mk = m[k];
+        const double mk = pk.m;
         gx[k] += mk * (2.0 * Bd[0] + f.b[0]);
         gx[n + k] += mk * (2.0 * Bd[1] + f.b[1]);
         gx[2 * n + k] += mk * (2.0 * Bd[2] + f.b[2]);
@@ -512,12 +514,25 @@ __global__ void k_vjp_unpermute(int64_t n, const int32_t *__restrict__ perm,
     gmass[o] = gm[s];
 }
 
+__global__ void k_vjp_zero(int64_t count, double *__restrict__ a) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < count) a[k] = 0.0;
+}
+
 int launch_vjp(p3t_ctx *ctx, const double *w, const double *c, double *gpos, double *gmass) {
     int rc;
     const int64_t n = ctx->n, nn = ctx->n_nodes;
     if ((rc = ensure(ctx, ctx->vjp_gx, 3 * n * sizeof(double)))) return rc;
     if ((rc = ensure(ctx, ctx->vjp_gm, n * sizeof(double)))) return rc;
     if ((rc = ensure(ctx, ctx->vjp_cell, 10 * nn * sizeof(double)))) return rc;
+    return launch_vjp_ws(ctx, w, c, gpos, gmass, ptr<double>(ctx->vjp_gx), ptr<double>(ctx->vjp_gm),
+                         ptr<double>(ctx->vjp_cell));
+}
+
+int launch_vjp_ws(p3t_ctx *ctx, const double *w, const double *c, double *gpos, double *gmass,
+                  double *gx, double *gm, double *cadj) {
+    int rc;
+    const int64_t n = ctx->n, nn = ctx->n_nodes;
     VjpParams vp{};
     vp.eps2 = ctx->prm.eps * ctx->prm.eps;
     vp.rout2 = ctx->prm.r_out * ctx->prm.r_out;
@@ -530,11 +545,11 @@ int launch_vjp(p3t_ctx *ctx, const double *w, const double *c, double *gpos, dou
     vp.wm = ctx->chg.wm;
     vp.use_quad = ctx->prm.use_quadrupole ? 1 : 0;
     vp.has_c = c != nullptr;
-    double *gx = ptr<double>(ctx->vjp_gx), *gm = ptr<double>(ctx->vjp_gm);
-    double *cadj = ptr<double>(ctx->vjp_cell);
     const ListsDev L = lists_dev(ctx);
-    if ((rc = check_hip(ctx, hipMemsetAsync(cadj, 0, 10 * nn * sizeof(double), ctx->stream), "memset")))
-        return rc;
+    // the cell adjoints are accumulated: clear them (a fill kernel, which a
+    // caller's graph capture records as an ordinary kernel node)
+    k_vjp_zero<<<blocks_for(10 * nn, 256), 256, 0, ctx->stream>>>(10 * nn, cadj);
+    if ((rc = check_hip(ctx, hipGetLastError(), "vjp clear"))) return rc;
     const unsigned G = (unsigned)ctx->n_groups;
     // accepted cells lie at least h from every member: K = W = 1 on them when h >= r_out
     const bool cell_k = ctx->prm.r_search < ctx->prm.r_out;
@@ -545,19 +560,16 @@ int launch_vjp(p3t_ctx *ctx, const double *w, const double *c, double *gpos, dou
     auto ks = mixed ? (cell_k ? k_vjp_scatter<float, true> : k_vjp_scatter<float, false>)
                     : (cell_k ? k_vjp_scatter<double, true> : k_vjp_scatter<double, false>);
     ki<<<G, kVjpThreads, 0, ctx->stream>>>(
-        ptr<GroupInfo>(ctx->grp), L, ptr<double>(ctx->x), ptr<double>(ctx->y), ptr<double>(ctx->z),
-        ptr<double>(ctx->m), ptr<NodeMP>(ctx->node_mp), ptr<int32_t>(ctx->vals[0]), w, c, vp, gx, gm,
+        ptr<GroupInfo>(ctx->grp), L, ptr<PosMass>(ctx->xm), ptr<NodeMP>(ctx->node_mp), ptr<int32_t>(ctx->vals[0]), w, c, vp, gx, gm,
         n);
     if ((rc = check_hip(ctx, hipGetLastError(), "vjp i-side"))) return rc;
     ks<<<G, kVjpThreads, 0, ctx->stream>>>(
-        ptr<GroupInfo>(ctx->grp), L, ptr<double>(ctx->x), ptr<double>(ctx->y), ptr<double>(ctx->z),
-        ptr<double>(ctx->m), ptr<NodeMP>(ctx->node_mp), ptr<int32_t>(ctx->vals[0]), w, c, vp, gx, gm,
+        ptr<GroupInfo>(ctx->grp), L, ptr<PosMass>(ctx->xm), ptr<NodeMP>(ctx->node_mp), ptr<int32_t>(ctx->vals[0]), w, c, vp, gx, gm,
         cadj, n, nn);
     if ((rc = check_hip(ctx, hipGetLastError(), "vjp scatter"))) return rc;
     k_vjp_down<<<blocks_for(nn, 128), 128, 0, ctx->stream>>>(
         nn, ptr<int32_t>(ctx->node_nchild), ptr<int32_t>(ctx->node_parent), ptr<NodeMP>(ctx->node_mp),
-        ptr<NodeWalk>(ctx->node_walk), cadj, ptr<double>(ctx->x), ptr<double>(ctx->y),
-        ptr<double>(ctx->z), ptr<double>(ctx->m), gx, gm, n);
+        ptr<NodeWalk>(ctx->node_walk), cadj, ptr<PosMass>(ctx->xm), gx, gm, n);
     if ((rc = check_hip(ctx, hipGetLastError(), "vjp push-down"))) return rc;
     k_vjp_unpermute<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, ptr<int32_t>(ctx->vals[0]), gx,
                                                                  gm, gpos, gmass);

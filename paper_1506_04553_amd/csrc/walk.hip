@@ -206,14 +206,21 @@ struct WalkStats {
     int32_t spilled, pad;          // groups that needed the global stack
 };
 
-// Statistics from the per-group counts, and the leaf count of the tree.
+static_assert(sizeof(WalkStats) == kRbWalkWords * 8, "walk statistics slots");
+
+constexpr int kOrderBins = 128;   // launch-order buckets (see below)
+
+// Statistics from the per-group counts, and the leaf count of the tree; also
+// clears the launch-order bucket counts.
 __global__ __launch_bounds__(1024) void k_walk_stats(const GroupInfo *__restrict__ grp,
                                                     const int32_t *__restrict__ n_groups_dev,
                                                     const int64_t *__restrict__ cnt, int64_t S,
                                                     const int32_t *__restrict__ nchild,
-                                                    int64_t n_nodes, WalkStats *__restrict__ out) {
+                                                    int64_t n_nodes, WalkStats *__restrict__ out,
+                                                    uint32_t *__restrict__ order_hist) {
     const int G = *n_groups_dev;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t0 < kOrderBins) order_hist[t0] = 0;
     const int64_t nt = (int64_t)gridDim.x * blockDim.x;
     unsigned long long tot[3] = {0, 0, 0}, mx[3] = {0, 0, 0}, pc = 0, pp = 0, ppn = 0, lv = 0;
     for (int64_t g = t0; g < G; g += nt) {
@@ -283,8 +290,6 @@ ListsDev lists_dev(const p3t_ctx *ctx) {
 // instruction count), largest first; the order inside a bucket is arbitrary
 // (it decides only which block runs which group).
 // ---------------------------------------------------------------------------
-constexpr int kOrderBins = 128;
-
 __device__ __forceinline__ int order_bin(const GroupInfo &gi, const int64_t *cnt, int64_t S, int g) {
     const float cost = (float)gi.count * (35.0f * (float)cnt[g] +
                                           15.0f * (float)(cnt[S + g] + cnt[2 * S + g]));
@@ -315,23 +320,25 @@ __global__ __launch_bounds__(256) void k_order_count(const GroupInfo *__restrict
     if (valid) rank[g] = (b << 24) | (int32_t)(base + count_below(same));
 }
 
-__global__ __launch_bounds__(kOrderBins) void k_order_scan(uint32_t *__restrict__ hist) {
-    __shared__ uint32_t s[kOrderBins];
-    const int t = threadIdx.x;
-    s[t] = hist[t];
-    __syncthreads();
-    uint32_t e = 0;
-    for (int k = 0; k < t; ++k) e += s[k];
-    hist[kOrderBins + t] = e;   // bucket starts
-}
-
+// each block takes the bucket starts (exclusive scan of the counts) itself
 __global__ __launch_bounds__(256) void k_order_place(int64_t G, const int32_t *__restrict__ rank,
                                                      const uint32_t *__restrict__ hist,
                                                      int32_t *__restrict__ order) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    static_assert(kOrderBins <= 256, "one thread per bucket");
+    __shared__ uint32_t s_cnt[kOrderBins], s_start[kOrderBins];
+    const int t = threadIdx.x;
+    if (t < kOrderBins) s_cnt[t] = hist[t];
+    __syncthreads();
+    if (t < kOrderBins) {
+        uint32_t e = 0;
+        for (int k = 0; k < t; ++k) e += s_cnt[k];
+        s_start[t] = e;
+    }
+    __syncthreads();
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + t;
     if (g >= G) return;
     const int32_t r = rank[g];
-    order[hist[kOrderBins + (r >> 24)] + (r & 0xffffff)] = (int32_t)g;
+    order[s_start[r >> 24] + (r & 0xffffff)] = (int32_t)g;
 }
 
 __global__ void k_order_identity(int64_t G, int32_t *__restrict__ order) {
@@ -344,32 +351,26 @@ static int build_order(p3t_ctx *ctx, int64_t stride) {
     const int64_t G = ctx->n_groups;
     if ((rc = ensure(ctx, ctx->gorder, (G + 1) * sizeof(int32_t)))) return rc;
     if ((rc = ensure(ctx, ctx->grank, (G + 1) * sizeof(int32_t)))) return rc;
-    if ((rc = ensure(ctx, ctx->ghist, 2 * kOrderBins * sizeof(uint32_t)))) return rc;
     if (G <= 0) return P3T_OK;
     if (G >= (1 << 24)) {   // ranks are packed in 24 bits: keep the group order
         k_order_identity<<<blocks_for(G, 256), 256, 0, ctx->stream>>>(G, ptr<int32_t>(ctx->gorder));
         return check_hip(ctx, hipGetLastError(), "group order");
     }
+    // the bucket counts were cleared by the walk statistics
     uint32_t *hist = ptr<uint32_t>(ctx->ghist);
-    if ((rc = check_hip(ctx, hipMemsetAsync(hist, 0, kOrderBins * sizeof(uint32_t), ctx->stream),
-                        "memset")))
-        return rc;
     k_order_count<<<blocks_for(G, 256), 256, 0, ctx->stream>>>(
         ptr<GroupInfo>(ctx->grp), G, ptr<int64_t>(ctx->cnt), stride, hist, ptr<int32_t>(ctx->grank));
-    k_order_scan<<<1, kOrderBins, 0, ctx->stream>>>(hist);
     k_order_place<<<blocks_for(G, 256), 256, 0, ctx->stream>>>(G, ptr<int32_t>(ctx->grank), hist,
                                                               ptr<int32_t>(ctx->gorder));
     return check_hip(ctx, hipGetLastError(), "group order");
 }
 
-// the walk's results sit in the readback area from this int64 slot on
-constexpr int kRbWalk = 24;
-
 static int run_walk_stats(p3t_ctx *ctx, const int32_t *G_dev, int64_t stride, WalkStats *ws) {
     // few large blocks: the block results meet in same-address atomics
     k_walk_stats<<<32, 1024, 0, ctx->stream>>>(ptr<GroupInfo>(ctx->grp), G_dev,
                                               ptr<int64_t>(ctx->cnt), stride,
-                                              ptr<int32_t>(ctx->node_nchild), ctx->n_nodes, ws);
+                                              ptr<int32_t>(ctx->node_nchild), ctx->n_nodes, ws,
+                                              ptr<uint32_t>(ctx->ghist));
     int rc = check_hip(ctx, hipGetLastError(), "walk stats");
     if (rc) return rc;
     if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + kRbWalk, ws, sizeof(WalkStats),
@@ -378,7 +379,7 @@ static int run_walk_stats(p3t_ctx *ctx, const int32_t *G_dev, int64_t stride, Wa
     return check_hip(ctx, hipStreamSynchronize(ctx->stream), "sync");
 }
 
-int build_lists(p3t_ctx *ctx) {
+int build_lists(p3t_ctx *ctx, bool stats_cleared) {
     static_assert(kRbWalk * 8 + sizeof(WalkStats) <= 40 * 8, "walk readback overlaps other slots");
     int rc;
     const int64_t nn = ctx->n_nodes;   // bound on the number of groups
@@ -386,6 +387,8 @@ int build_lists(p3t_ctx *ctx) {
     if ((rc = ensure(ctx, ctx->cnt, 3 * stride * sizeof(int64_t)))) return rc;
     if ((rc = ensure(ctx, ctx->off, 3 * stride * sizeof(int64_t)))) return rc;
     if ((rc = ensure(ctx, ctx->seg_end, 3 * stride * sizeof(int64_t)))) return rc;
+    // launch-order bucket counts, cleared by the walk statistics
+    if ((rc = ensure(ctx, ctx->ghist, kOrderBins * sizeof(uint32_t)))) return rc;
     int64_t *cnt = ptr<int64_t>(ctx->cnt), *off = ptr<int64_t>(ctx->off);
     int64_t *end = ptr<int64_t>(ctx->seg_end);
     WalkStats *ws = reinterpret_cast<WalkStats *>(ptr<int64_t>(ctx->readback) + kRbWalk);
@@ -449,7 +452,7 @@ int build_lists(p3t_ctx *ctx) {
                 if ((rc = ensure(ctx, *lbuf[k], (gcap * wo.cap[k] + 1) * sizeof(int32_t)))) return rc;
                 wo.idx[k] = ptr<int32_t>(*lbuf[k]);
             }
-            if ((rc = reset())) return rc;
+            if (!stats_cleared && (rc = reset())) return rc;
             k_walk<kFixed><<<grid, kWalkThreads, 0, st>>>(ptr<GroupInfo>(ctx->grp), G_dev,
                                                            ptr<NodeWalk>(ctx->node_walk), wp, wo,
                                                            gstack, lds_cap);

@@ -180,16 +180,19 @@ class P3T:
         self._allocs = {}
         if use_torch_allocator:
             dev, st = self.device, self.stream
+            # bound now: a context released at interpreter exit still frees its
+            # workspaces after the module globals are gone
+            alloc, delete = torch.cuda.caching_allocator_alloc, torch.cuda.caching_allocator_delete
 
             def _alloc(nbytes, _user):
                 try:
-                    p = torch.cuda.caching_allocator_alloc(int(nbytes), dev, st)
+                    p = alloc(int(nbytes), dev, st)
                 except Exception:       # out of memory: the library reports ENOMEM
                     return None
                 return p
 
             def _free(p, _user):
-                torch.cuda.caching_allocator_delete(int(p))
+                delete(int(p))
 
             self._alloc_cb, self._free_cb = ALLOC_FN(_alloc), FREE_FN(_free)
         else:

@@ -31,6 +31,8 @@ def test_summarize_rates_and_flops():
     flops = ((1000 * bench.F_PP + 2000 * bench.F_PC_QUAD) + (3000 * bench.F_PP + 4000 * bench.F_PC_QUAD)) / 2
     assert s["flops_per_launch"] == flops
     assert s["force_tflops"] == pytest.approx(flops / 3e-3 / 1e12)
+    survey = ((1000 * 37 + 2000 * 75) + (3000 * 37 + 4000 * 75)) / 2
+    assert s["force_tflops_survey"] == pytest.approx(survey / 3e-3 / 1e12)
     mono = bench.summarize(rec, seconds=0.5, steps=2, quad=False)
     assert mono["flops_per_launch"] < flops      # the monopole cell term counts fewer flops
 

@@ -216,7 +216,10 @@ def _band_cases():
     changeover band and their K(y_c), W(y_c) differ from 1: eight particles
     whose accepted cells are single particles (the tree sum is then the direct
     sum), a Plummer sphere with the band across the cluster, and the 2^16
-    Salpeter workload with h = r_out / 2."""
+    Salpeter workload with r_out = 0.1 and h = r_out / 2 (at the workload's own
+    r_out = 0.005 no accepted cell lies within r_out of a member: cells that
+    close are far smaller than the particle spacing; at 0.1 about 8 000
+    (member, cell) pairs do)."""
     from tests.test_oracle_cells_in_band import CORNER_CASES, _band_tree, _corner_setup
     cases = {}
     for name in CORNER_CASES:
@@ -225,7 +228,8 @@ def _band_cases():
     cases["plummer3000_band"] = _band_tree(0.5)
     w = WORKLOADS["plummer64k_salpeter"]
     c = make_cluster(w, seed=3)
-    cases["plummer64k_h_half_rout"] = (c.pos, c.mass, w.params(r_search=0.5 * w.r_out))
+    cases["plummer64k_h_half_rout"] = (c.pos, c.mass, w.params(r_out=0.1, r_in=0.01,
+                                                                r_search=0.05))
     return cases
 
 
