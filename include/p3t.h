@@ -143,6 +143,26 @@ int p3t_neighbors(p3t_ctx *ctx, int64_t *offsets, int32_t *idx, int64_t cap, int
 int p3t_long_force_vjp(p3t_ctx *ctx, const double *w, const double *c, double *gpos,
                        double *gmass);
 
+/* p3t_long_force_vjp for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same result, from the same kernels, with every workspace
+ * taken from a static 64 MiB array that the library holds on each device until
+ * the process ends (its device address is resolved by p3t_create).  The call
+ * itself allocates nothing and does not synchronise the stream.
+ *   workspace: 4 n + 10 n_nodes doubles (n_nodes from p3t_get_stats), each of
+ *   the two per-particle parts rounded up to 256 bytes; larger builds return
+ *   ECAPACITY (about n = 2^20 with up to 4 * 10^5 nodes fits).
+ * All calls on one device share that array and leave their intermediate
+ * values in it: two calls that may run at the same time on one device (from
+ * two contexts, or on different streams) race and give wrong results; calls
+ * ordered on one stream are safe.  The build's lists must be present: after
+ * p3t_release_lists the call returns ESTATE (walking again would allocate);
+ * p3t_long_force or p3t_long_force_vjp restores them.
+ * Arguments and outputs as p3t_long_force_vjp.
+ * Errors: ESTATE, EINVAL, ECAPACITY, EHIP. */
+int p3t_long_force_vjp_noalloc(p3t_ctx *ctx, const double *w, const double *c, double *gpos,
+                               double *gmass);
+
 /* Frees the interaction-list arrays of the last build (the largest part of a
  * build's memory) and keeps the tree, moments and groups.  The next call that
  * needs the lists (p3t_long_force, p3t_neighbors, p3t_long_force_vjp,

@@ -106,6 +106,7 @@ struct p3t_ctx {
     double ms_build = 0, ms_walk = 0, ms_force = 0, ms_nbr = 0, ms_vjp = 0;
     hipEvent_t ev[12] = {nullptr};  // start/end pairs: build, force, neighbours, vjp, walk, hermite
     int64_t *hpin = nullptr;      // pinned host readback area (64 int64)
+    void *scratch = nullptr;      // device address of the library's static workspace on this device
 
     p3t::DevBuf root, keys[2], vals[2], hist, histc, rs_tot, xm;
     p3t::DevBuf lvlrange, tblk, tblk_off;

@@ -6,10 +6,22 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "internal.h"
 
 using namespace p3t;
 
+// Static workspace of p3t_long_force_vjp_noalloc: one array per device, part
+// of the library's code object, so that call allocates nothing.  Host code
+// never uses the array's name as an address: p3t_create resolves its device
+// address once per device (with that device current) and every use goes
+// through that pointer.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
 
 namespace p3t {
 
@@ -144,6 +156,24 @@ extern "C" int p3t_create(p3t_ctx **out, int device, void *hip_stream, p3t_alloc
     ctx->user = alloc_user;
     // P3T_WALK_LDS_STACK=k (k >= 64) caps the walk's on-chip stack at k entries
     if (const char *ev = getenv("P3T_WALK_LDS_STACK")) ctx->walk_lds_cap = atoi(ev);
+    if (device >= kMaxDevices) {
+        delete ctx;
+        return P3T_EINVAL;
+    }
+    {
+        // the static workspace's address on this device (the device is current)
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[device]) {
+            void *sp = nullptr;
+            if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp) {
+                (void)hipGetLastError();
+                delete ctx;
+                return P3T_EHIP;
+            }
+            g_scratch_ptr[device] = sp;
+        }
+        ctx->scratch = g_scratch_ptr[device];
+    }
     hipError_t e = hipHostMalloc((void **)&ctx->hpin, 64 * sizeof(int64_t), hipHostMallocDefault);
     for (int k = 0; k < 12 && e == hipSuccess; ++k) e = hipEventCreate(&ctx->ev[k]);
     if (e != hipSuccess) {
@@ -290,6 +320,36 @@ extern "C" int p3t_long_force_vjp(p3t_ctx *ctx, const double *w, const double *c
     if ((rc = ensure_lists(ctx))) return rc;
     if ((rc = mark(ctx, EV_VJP))) return rc;
     if ((rc = launch_vjp(ctx, w, c, gpos, gmass))) return rc;
+    if ((rc = mark(ctx, EV_VJP + 1))) return rc;
+    ctx->ms_vjp = -1.0;
+    return P3T_OK;
+}
+
+extern "C" int p3t_long_force_vjp_noalloc(p3t_ctx *ctx, const double *w, const double *c,
+                                          double *gpos, double *gmass) {
+    if (!ctx) return P3T_EINVAL;
+    if (!ctx->built)
+        return set_error(ctx, P3T_ESTATE, "p3t_long_force_vjp_noalloc before p3t_build_tree");
+    // walking the tree again would allocate the lists
+    if (ctx->lists_released)
+        return set_error(ctx, P3T_ESTATE,
+                         "p3t_long_force_vjp_noalloc needs the build's lists; they were released");
+    if (!w || !gpos || !gmass) return set_error(ctx, P3T_EINVAL, "bad VJP buffers");
+    const int64_t n = ctx->n, nn = ctx->n_nodes;
+    // gx [3 n], gm [n], cell adjoints [10 n_nodes], each 256-byte aligned
+    const size_t a = 256 / sizeof(double);
+    const size_t ngx = (3 * (size_t)n + a - 1) / a * a, ngm = ((size_t)n + a - 1) / a * a;
+    const size_t need = (ngx + ngm + 10 * (size_t)nn) * sizeof(double);
+    if (need > kScratchBytes)
+        return set_error(ctx, P3T_ECAPACITY,
+                         "p3t_long_force_vjp_noalloc needs %zu bytes of workspace for n = %lld and "
+                         "%lld nodes (4 n + 10 n_nodes doubles); its static workspace holds %zu",
+                         need, (long long)n, (long long)nn, kScratchBytes);
+    int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
+    if (rc) return rc;
+    double *gx = static_cast<double *>(ctx->scratch), *gm = gx + ngx, *cadj = gm + ngm;
+    if ((rc = mark(ctx, EV_VJP))) return rc;
+    if ((rc = launch_vjp_ws(ctx, w, c, gpos, gmass, gx, gm, cadj))) return rc;
     if ((rc = mark(ctx, EV_VJP + 1))) return rc;
     ctx->ms_vjp = -1.0;
     return P3T_OK;

@@ -80,7 +80,7 @@ EXPORTS = ("p3t_create", "p3t_destroy", "p3t_check_params", "p3t_build_tree", "p
            "p3t_neighbors", "p3t_long_force_vjp", "p3t_kick_drift", "p3t_get_stats",
            "p3t_copy_array", "p3t_status_string", "p3t_last_error", "p3t_hard_force",
            "p3t_hermite_hard", "p3t_step", "p3t_direct", "p3t_kinds_soft",
-           "p3t_kinds_neighbors", "p3t_release_lists")
+           "p3t_kinds_neighbors", "p3t_release_lists", "p3t_long_force_vjp_noalloc")
 
 DIRECT_MODES = {"newton": 0, "soft": 1, "hard": 2}
 
@@ -124,6 +124,7 @@ def load_library(path: str = LIB_PATH):
     L.p3t_long_force.argtypes = [V, V, V]
     L.p3t_neighbors.argtypes = [V, V, V, C.c_int64, C.POINTER(C.c_int64)]
     L.p3t_long_force_vjp.argtypes = [V, V, V, V, V]
+    L.p3t_long_force_vjp_noalloc.argtypes = [V, V, V, V, V]
     L.p3t_release_lists.argtypes = [V]
     L.p3t_kick_drift.argtypes = [V, C.c_int64, V, V, V, C.c_double, C.c_double]
     L.p3t_get_stats.argtypes = [V, C.POINTER(Stats)]
@@ -287,6 +288,19 @@ class P3T:
         gmass = torch.empty((self.n,), dtype=torch.float64, device=dev)
         self._check(self._L.p3t_long_force_vjp(self._h, _dptr(w), _dptr(c), _dptr(gpos),
                                                _dptr(gmass)))
+        return gpos, gmass
+
+    def long_force_vjp_noalloc(self, w: torch.Tensor, c: torch.Tensor | None,
+                               gpos: torch.Tensor, gmass: torch.Tensor):
+        """p3t_long_force_vjp_noalloc into the caller's gpos [n,3] and gmass [n]:
+        the library allocates nothing (static per-device workspace)."""
+        self._tensor(w, (self.n, 3), "w")
+        if c is not None:
+            self._tensor(c, (self.n,), "c")
+        self._tensor(gpos, (self.n, 3), "gpos")
+        self._tensor(gmass, (self.n,), "gmass")
+        self._check(self._L.p3t_long_force_vjp_noalloc(self._h, _dptr(w), _dptr(c), _dptr(gpos),
+                                                       _dptr(gmass)))
         return gpos, gmass
 
     def kick_drift(self, pos, vel, acc, dt_kick: float, dt_drift: float):
