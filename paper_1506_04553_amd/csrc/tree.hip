@@ -32,6 +32,9 @@ constexpr int kRedThreads = 256;
 
 // per block: lo xyz, hi xyz, and 1 if some input of the block is invalid
 constexpr int kBboxRec = 7;
+constexpr int kBboxUnroll = 4;
+// few blocks: each ends with an agent-scope release, which is costly
+constexpr int kBboxMaxBlocks = 256;
 
 // Root cube and input check in one launch: every block reduces its share of
 // the particles to a record (lo xyz, hi xyz, invalid-input flag); the last
@@ -43,17 +46,29 @@ __global__ __launch_bounds__(kRedThreads) void k_bbox(const double *__restrict__
                                                       int64_t *bad_rb, unsigned int *done) {
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     int flag = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    // kBboxUnroll particles per thread and round, loaded together
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < n;
+         i0 += kBboxUnroll * stride) {
+        PosMass r[kBboxUnroll];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            double v = pos[3 * i + a];
-            flag |= !isfinite(v);
-            lo[a] = fmin(lo[a], v);
-            hi[a] = fmax(hi[a], v);
+        for (int j = 0; j < kBboxUnroll; ++j) {
+            const int64_t i = i0 + j * stride;
+            if (i < n) r[j] = PosMass{pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], mass[i]};
         }
-        double mm = mass[i];
-        flag |= !(isfinite(mm) && mm > 0.0);
+#pragma unroll
+        for (int j = 0; j < kBboxUnroll; ++j) {
+            const int64_t i = i0 + j * stride;
+            if (i >= n) continue;
+            const double v[3] = {r[j].x, r[j].y, r[j].z};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                flag |= !isfinite(v[a]);
+                lo[a] = fmin(lo[a], v[a]);
+                hi[a] = fmax(hi[a], v[a]);
+            }
+            flag |= !(isfinite(r[j].m) && r[j].m > 0.0);
+        }
     }
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) {
@@ -183,21 +198,30 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t *__restri
     for (int d = threadIdx.x; d < kRsBins; d += kRsThreads) h[d] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    uint64_t k[kRsRounds];
+#pragma unroll
     for (int r = 0; r < kRsRounds; ++r) {
-        int64_t i = base + r * kRsThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[rs_digit(keys[i], shift)], 1);
+        const int64_t i = base + r * kRsThreads + threadIdx.x;
+        k[r] = i < n ? keys[i] : 0ull;
     }
+#pragma unroll
+    for (int r = 0; r < kRsRounds; ++r)
+        if (base + r * kRsThreads + threadIdx.x < n) atomicAdd(&h[rs_digit(k[r], shift)], 1);
     __syncthreads();
     for (int d = threadIdx.x; d < kRsBins; d += kRsThreads)
         counts[(int64_t)d * nb + blockIdx.x] = h[d];
 }
 
 // Morton keys of the tile of kRsTile particles of this block, their indices,
-// and the tile's histogram of the first radix digit (the keys' low bits)
-__global__ __launch_bounds__(kRsThreads) void k_keys_hist(const double *__restrict__ pos, int64_t n,
+// the tile's histogram of the first radix digit (the keys' low bits), and each
+// particle's position and mass packed in one 32-byte record (xm_in, input
+// order) for the sort's final gather
+__global__ __launch_bounds__(kRsThreads) void k_keys_hist(const double *__restrict__ pos,
+                                                          const double *__restrict__ mass, int64_t n,
                                                           const RootInfo *__restrict__ root,
                                                           uint64_t *__restrict__ keys,
                                                           int32_t *__restrict__ idx,
+                                                          PosMass *__restrict__ xm_in,
                                                           int32_t *__restrict__ counts, int nb) {
     __shared__ int32_t h[kRsBins];
     for (int d = threadIdx.x; d < kRsBins; d += kRsThreads) h[d] = 0;
@@ -205,19 +229,28 @@ __global__ __launch_bounds__(kRsThreads) void k_keys_hist(const double *__restri
     const double scale = root->scale;
     const double lo[3] = {root->lo[0], root->lo[1], root->lo[2]};
     const int64_t base = (int64_t)blockIdx.x * kRsTile;
-    for (int r = 0; r < kRsRounds; ++r) {
-        const int64_t i = base + r * kRsThreads + threadIdx.x;
+    PosMass r[kRsRounds];
+#pragma unroll
+    for (int k = 0; k < kRsRounds; ++k) {
+        const int64_t i = base + k * kRsThreads + threadIdx.x;
+        if (i < n) r[k] = PosMass{pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], mass[i]};
+    }
+#pragma unroll
+    for (int k = 0; k < kRsRounds; ++k) {
+        const int64_t i = base + k * kRsThreads + threadIdx.x;
         if (i >= n) break;
+        const double x[3] = {r[k].x, r[k].y, r[k].z};
         uint64_t q[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const double t = floor((pos[3 * i + a] - lo[a]) * scale);
+            const double t = floor((x[a] - lo[a]) * scale);
             const uint64_t v = (uint64_t)t;
             q[a] = v > 0x1fffffull ? 0x1fffffull : v;
         }
         const uint64_t key = (spread_bits3(q[0]) << 2) | (spread_bits3(q[1]) << 1) | spread_bits3(q[2]);
         keys[i] = key;
         idx[i] = (int32_t)i;
+        xm_in[i] = r[k];
         atomicAdd(&h[rs_digit(key, 0)], 1);
     }
     __syncthreads();
@@ -245,10 +278,10 @@ __device__ __forceinline__ void block_excl_scan_bins(int v[kRsPer], int32_t *s_w
     }
 }
 
-// LAST: the final pass also writes the sorted particle records xm (from the
-// caller's positions and masses) and clears the n + 1 group-start flags.
+// LAST: the final pass also writes the sorted particle records xm (gathered
+// from the packed input records) and clears the n + 1 group-start flags.
 struct SortedOut {
-    const double *pos, *mass;
+    const PosMass *xm_in;
     PosMass *xm;
     int32_t *gflag;
 };
@@ -256,25 +289,65 @@ struct SortedOut {
 template <bool LAST>
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
     const uint64_t *__restrict__ kin, const int32_t *__restrict__ vin, uint64_t *__restrict__ kout,
-    int32_t *__restrict__ vout, int64_t n, int shift, const int32_t *__restrict__ counts,
-    const int32_t *__restrict__ offsets, const int32_t *__restrict__ totals, int nb, SortedOut so) {
+    int32_t *__restrict__ vout, int64_t n, int shift, const int32_t *__restrict__ offsets,
+    const int32_t *__restrict__ totals, int nb, SortedOut so) {
     __shared__ uint64_t s_key[kRsTile];
     __shared__ int32_t s_val[kRsTile];
-    __shared__ int32_t s_start[kRsBins], s_run[kRsBins], s_dbase[kRsBins];
-    __shared__ int32_t s_wcnt[kRsWaves][kRsBins], s_woff[kRsWaves][kRsBins];
+    __shared__ int32_t s_start[kRsBins], s_gbase[kRsBins];
+    __shared__ int32_t s_wcnt[kRsWaves][kRsBins];
     __shared__ int32_t s_wsum[kRsWaves], s_wsum2[kRsWaves];
     const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
     const int64_t base = (int64_t)blockIdx.x * kRsTile;
     const int64_t tile_n = std::min<int64_t>(kRsTile, n - base);
-
-    // digit starts inside this tile (exclusive scan of the tile histogram) and
-    // the first output position of each digit (exclusive scan of the totals)
+    // wavefront w ranks the kRsRounds * 64 consecutive keys from wbase; its
+    // per-digit running counts live in its own row of s_wcnt
+    constexpr int kPerWave = kRsRounds * kWave;
+    const int64_t wbase = base + (int64_t)w * kPerWave;
+    for (int d = lane; d < kRsBins; d += kWave) s_wcnt[w][d] = 0;
+    uint64_t key[kRsRounds];
+    int32_t val[kRsRounds];
+#pragma unroll
+    for (int r = 0; r < kRsRounds; ++r) {
+        const int64_t i = wbase + r * kWave + lane;
+        key[r] = i < n ? kin[i] : 0ull;
+        val[r] = i < n ? vin[i] : 0;
+    }
+    int dig[kRsRounds], rank[kRsRounds];
+#pragma unroll
+    for (int r = 0; r < kRsRounds; ++r) {
+        const bool valid = wbase + r * kWave + lane < n;
+        const int d = rs_digit(key[r], shift);
+        uint64_t same = ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kRsBits; ++b) {
+            const bool bit = (d >> b) & 1;
+            const uint64_t bb = ballot(bit);
+            same &= bit ? bb : ~bb;
+        }
+        const int below = count_below(same);
+        // earlier keys of this digit in the wavefront's chunk, then this round's
+        // (the row is this wavefront's alone, and its LDS accesses are in order)
+        const int prior = s_wcnt[w][d];
+        if (valid && below == 0) s_wcnt[w][d] = prior + __popcll(same);
+        dig[r] = d;
+        rank[r] = prior + below;
+    }
+    __syncthreads();
+    // per digit: the wavefronts' offsets inside the digit, the digit's start
+    // in the tile, and its first output position
     {
         int c[kRsPer], t[kRsPer];
 #pragma unroll
         for (int k = 0; k < kRsPer; ++k) {
             const int d = kRsPer * tid + k;
-            c[k] = counts[(int64_t)d * nb + blockIdx.x];
+            int run = 0;
+#pragma unroll
+            for (int v = 0; v < kRsWaves; ++v) {
+                const int x = s_wcnt[v][d];
+                s_wcnt[v][d] = run;
+                run += x;
+            }
+            c[k] = run;
             t[k] = totals[d];
         }
         block_excl_scan_bins(c, s_wsum);
@@ -283,56 +356,28 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
         for (int k = 0; k < kRsPer; ++k) {
             const int d = kRsPer * tid + k;
             s_start[d] = c[k];
-            s_dbase[d] = t[k];
-            s_run[d] = 0;
+            s_gbase[d] = t[k] + offsets[(int64_t)d * nb + blockIdx.x] - c[k];
         }
     }
+    __syncthreads();
+#pragma unroll
     for (int r = 0; r < kRsRounds; ++r) {
-        for (int k = 0; k < kRsWaves; ++k)
-            for (int d = tid; d < kRsBins; d += kRsThreads) s_wcnt[k][d] = 0;
-        __syncthreads();
-        const int64_t i = base + r * kRsThreads + tid;
-        const bool valid = i < n;
-        const uint64_t key = valid ? kin[i] : 0ull;
-        const int d = rs_digit(key, shift);
-        uint64_t same = ballot(valid);
-#pragma unroll
-        for (int b = 0; b < kRsBits; ++b) {
-            const bool bit = (d >> b) & 1;
-            const uint64_t bb = ballot(bit);
-            same &= bit ? bb : ~bb;
+        if (wbase + r * kWave + lane < n) {
+            const int d = dig[r];
+            const int p = s_start[d] + s_wcnt[w][d] + rank[r];
+            s_key[p] = key[r];
+            s_val[p] = val[r];
         }
-        const int rank_w = count_below(same);
-        if (valid && rank_w == 0) s_wcnt[w][d] = __popcll(same);
-        __syncthreads();
-        for (int e = tid; e < kRsBins; e += kRsThreads) {
-            int run = s_run[e];
-#pragma unroll
-            for (int k = 0; k < kRsWaves; ++k) {
-                s_woff[k][e] = run;
-                run += s_wcnt[k][e];
-            }
-            s_run[e] = run;
-        }
-        __syncthreads();
-        if (valid) {
-            const int p = s_start[d] + s_woff[w][d] + rank_w;
-            s_key[p] = key;
-            s_val[p] = vin[i];
-        }
-        __syncthreads();
     }
+    __syncthreads();
     for (int p = tid; p < tile_n; p += kRsThreads) {
-        const uint64_t key = s_key[p];
-        const int d = rs_digit(key, shift);
-        const int64_t o = (int64_t)s_dbase[d] + offsets[(int64_t)d * nb + blockIdx.x] +
-                          (p - s_start[d]);
+        const uint64_t k = s_key[p];
+        const int64_t o = (int64_t)s_gbase[rs_digit(k, shift)] + p;
         const int32_t v = s_val[p];
-        kout[o] = key;
+        kout[o] = k;
         vout[o] = v;
         if (LAST) {
-            so.xm[o] = PosMass{so.pos[3 * (int64_t)v], so.pos[3 * (int64_t)v + 1],
-                               so.pos[3 * (int64_t)v + 2], so.mass[v]};
+            so.xm[o] = so.xm_in[v];
             so.gflag[o] = 0;
         }
     }
@@ -344,7 +389,8 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
 // the last pass.
 int build_sorted(p3t_ctx *ctx, const double *pos, const double *mass, int64_t n) {
     int rc;
-    const int nbb = (int)std::min<int64_t>(256, (n + kRedThreads - 1) / kRedThreads);
+    const int nbb = (int)std::min<int64_t>(
+        kBboxMaxBlocks, (n + (int64_t)kRedThreads * kBboxUnroll - 1) / ((int64_t)kRedThreads * kBboxUnroll));
     const int nb = (int)((n + kRsTile - 1) / kRsTile);
     if ((rc = ensure(ctx, ctx->root, sizeof(RootInfo)))) return rc;
     if ((rc = ensure(ctx, ctx->bbox, kBboxRec * nbb * sizeof(double)))) return rc;
@@ -356,6 +402,7 @@ int build_sorted(p3t_ctx *ctx, const double *pos, const double *mass, int64_t n)
     if ((rc = ensure(ctx, ctx->histc, (size_t)kRsBins * nb * sizeof(int32_t)))) return rc;
     if ((rc = ensure(ctx, ctx->rs_tot, kRsBins * sizeof(int32_t)))) return rc;
     if ((rc = ensure(ctx, ctx->xm, n * sizeof(PosMass)))) return rc;
+    if ((rc = ensure(ctx, ctx->xm_in, n * sizeof(PosMass)))) return rc;
     if ((rc = ensure(ctx, ctx->gflag, (n + 1) * sizeof(int32_t)))) return rc;
     double *partial = ptr<double>(ctx->bbox);
     int64_t *rb = ptr<int64_t>(ctx->readback);
@@ -364,11 +411,12 @@ int build_sorted(p3t_ctx *ctx, const double *pos, const double *mass, int64_t n)
                                                  reinterpret_cast<unsigned int *>(rb + kRbBboxDone));
     int32_t *cnt = ptr<int32_t>(ctx->histc), *off = ptr<int32_t>(ctx->hist);
     int32_t *tot = ptr<int32_t>(ctx->rs_tot);
-    k_keys_hist<<<nb, kRsThreads, 0, ctx->stream>>>(pos, n, ptr<RootInfo>(ctx->root),
+    k_keys_hist<<<nb, kRsThreads, 0, ctx->stream>>>(pos, mass, n, ptr<RootInfo>(ctx->root),
                                                      ptr<uint64_t>(ctx->keys[0]),
-                                                     ptr<int32_t>(ctx->vals[0]), cnt, nb);
+                                                     ptr<int32_t>(ctx->vals[0]),
+                                                     ptr<PosMass>(ctx->xm_in), cnt, nb);
     if ((rc = check_hip(ctx, hipGetLastError(), "root/keys"))) return rc;
-    const SortedOut so{pos, mass, ptr<PosMass>(ctx->xm), ptr<int32_t>(ctx->gflag)};
+    const SortedOut so{ptr<PosMass>(ctx->xm_in), ptr<PosMass>(ctx->xm), ptr<int32_t>(ctx->gflag)};
     int src = 0;
     for (int pass = 0; pass < kRsPasses; ++pass) {
         const int shift = kRsBits * pass;
@@ -380,8 +428,8 @@ int build_sorted(p3t_ctx *ctx, const double *pos, const double *mass, int64_t n)
         }
         if ((rc = scan_rows_i32(ctx, cnt, off, tot, kRsBins, nb))) return rc;
         auto scatter = pass == kRsPasses - 1 ? k_rs_scatter<true> : k_rs_scatter<false>;
-        scatter<<<nb, kRsThreads, 0, ctx->stream>>>(kin, vin, kout, vout, n, shift, cnt, off, tot,
-                                                     nb, so);
+        scatter<<<nb, kRsThreads, 0, ctx->stream>>>(kin, vin, kout, vout, n, shift, off, tot, nb,
+                                                     so);
         if ((rc = check_hip(ctx, hipGetLastError(), "radix scatter"))) return rc;
         src = 1 - src;
     }
@@ -445,24 +493,57 @@ __device__ __forceinline__ int64_t upper_bound_key(const uint64_t *keys, int64_t
 }
 
 // range code: lo | hi << 8, or -1 when no node starts at a
+// Up to this leaf size the topology kernels read their keys from an on-chip
+// window (the block's keys and n_leaf on either side) instead of searching.
+constexpr int kTopoWin = 64;
+// stands for positions outside [0, n): its prefix at every level differs from
+// that of every key (keys have 63 bits)
+constexpr uint64_t kNoKey = ~0ull;
+
+// keys base - before .. base + kTopoThreads + after - 1 of the block into s_k
+__device__ __forceinline__ void load_key_window(uint64_t *s_k, const uint64_t *keys, int64_t n,
+                                                int64_t base, int before, int after) {
+    for (int t = threadIdx.x; t < kTopoThreads + before + after; t += kTopoThreads) {
+        const int64_t i = base - before + t;
+        s_k[t] = (i >= 0 && i < n) ? keys[i] : kNoKey;
+    }
+}
+
 __global__ __launch_bounds__(kTopoThreads) void k_topo_ranges(const uint64_t *__restrict__ keys,
                                                               int64_t n, int n_leaf,
                                                               int32_t *__restrict__ range,
                                                               int32_t *__restrict__ blk, int nb) {
     __shared__ int32_t cnt[kLevels];
+    __shared__ uint64_t s_k[kTopoThreads + 2 * kTopoWin];
     if (threadIdx.x < kLevels) cnt[threadIdx.x] = 0;
+    const int64_t base = (int64_t)blockIdx.x * kTopoThreads;
+    const bool win = n_leaf <= kTopoWin;
+    if (win) load_key_window(s_k, keys, n, base, n_leaf, n_leaf);
     __syncthreads();
-    const int64_t a = (int64_t)blockIdx.x * kTopoThreads + threadIdx.x;
+    const int64_t a = base + threadIdx.x;
+    const int o = threadIdx.x + n_leaf;   // a's slot in the window
     int lo = 1, hi = 0;
     if (a < n) {
-        const uint64_t ka = keys[a];
-        const int c = (a == 0) ? -1 : common_levels(keys[a - 1], ka);
-        const int m = (a + n_leaf < n) ? common_levels(ka, keys[a + n_leaf]) : -1;
+        const uint64_t ka = win ? s_k[o] : keys[a];
+        const int c = (a == 0) ? -1 : common_levels(win ? s_k[o - 1] : keys[a - 1], ka);
+        const int m = (a + n_leaf < n)
+                          ? common_levels(ka, win ? s_k[o + n_leaf] : keys[a + n_leaf])
+                          : -1;
         bool exists;
         if (a == 0) {
             exists = true;
         } else if (c >= kMaxLevel) {
             exists = false;   // duplicate key: no node starts here
+        } else if (win) {
+            // the level-c node holding a (a contiguous run of keys) has more
+            // than n_leaf members iff at least n_leaf of the n_leaf keys on
+            // either side of a share a's level-c prefix
+            const int sh = 3 * (kMaxLevel - c);
+            const uint64_t P = ka >> sh;
+            int same = 0;
+            for (int k = 1; k <= n_leaf; ++k)
+                same += (int)((s_k[o - k] >> sh) == P) + (int)((s_k[o + k] >> sh) == P);
+            exists = same >= n_leaf;
         } else {
             // the level-c node containing a must have more than n_leaf particles
             const int sh = 3 * (kMaxLevel - c);
@@ -490,15 +571,18 @@ struct LevelStarts {
 
 // blk_off: per level, the exclusive scan of the node starts over the blocks
 __global__ __launch_bounds__(kTopoThreads) void k_topo_emit(
-    const uint64_t *__restrict__ keys, int64_t n, const int32_t *__restrict__ range,
+    const uint64_t *__restrict__ keys, int64_t n, int n_leaf, const int32_t *__restrict__ range,
     const int32_t *__restrict__ blk_off, const LevelStarts level_start, int nb,
     int32_t *__restrict__ level, int32_t *__restrict__ first,
     int32_t *__restrict__ count, int32_t *__restrict__ child, int32_t *__restrict__ nchild,
     uint64_t *__restrict__ prefix) {
     __shared__ uint64_t s_ball[kLevels][kTopoWaves];
     __shared__ int32_t s_wc[kLevels][kTopoWaves];
+    __shared__ uint64_t s_k[kTopoThreads + kTopoWin];
     const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
     const int64_t a = (int64_t)blockIdx.x * kTopoThreads + tid;
+    const bool win = n_leaf <= kTopoWin;
+    if (win) load_key_window(s_k, keys, n, (int64_t)blockIdx.x * kTopoThreads, 0, n_leaf);
     const int32_t code = (a < n) ? range[a] : -1;
     const int lo = code < 0 ? 1 : (code & 255), hi = code < 0 ? 0 : (code >> 8);
     // all lanes: per-level membership masks of this wave
@@ -511,7 +595,7 @@ __global__ __launch_bounds__(kTopoThreads) void k_topo_emit(
     }
     __syncthreads();
     if (code < 0) return;
-    const uint64_t ka = keys[a];
+    const uint64_t ka = win ? s_k[tid] : keys[a];
     // number of level-l starts before position a, plus the level's first id
     auto rank_at = [&](int l) -> int32_t {
         int base = (int)level_start.s[l] + blk_off[(int64_t)l * nb + blockIdx.x];
@@ -522,11 +606,23 @@ __global__ __launch_bounds__(kTopoThreads) void k_topo_emit(
     for (int l = lo; l <= hi; ++l) {
         const int32_t next = (l < kMaxLevel) ? rank_at(l + 1) : 0;
         const int sh = 3 * (kMaxLevel - l);
-        const uint64_t kmax = ka | ((sh >= 64) ? ~0ull : ((1ull << sh) - 1ull));
-        const int64_t ub = gallop_upper_key(keys, a + 1, n, kmax);
+        if (l == hi) {
+            // a leaf: at most n_leaf members unless at the deepest level
+            // (equal keys); internal nodes are counted by the moments fold
+            int cnt = n_leaf + 1;
+            if (win) {
+                const uint64_t P = ka >> sh;
+                cnt = 1;
+                for (int k = 1; k <= n_leaf; ++k) cnt += (int)((s_k[tid + k] >> sh) == P);
+            }
+            if (cnt > n_leaf) {
+                const uint64_t kmax = ka | ((sh >= 64) ? ~0ull : ((1ull << sh) - 1ull));
+                cnt = (int)(gallop_upper_key(keys, a + 1, n, kmax) - a);
+            }
+            count[id] = cnt;
+        }
         level[id] = l;
         first[id] = (int32_t)a;
-        count[id] = (int32_t)(ub - a);
         child[id] = next;
         nchild[id] = (l == hi) ? 0 : -1;
         prefix[id] = (sh >= 64) ? 0ull : (ka >> sh);
@@ -594,7 +690,7 @@ int build_topology(p3t_ctx *ctx, int64_t n) {
         if ((rc = ensure(ctx, *b, nn * sizeof(int32_t)))) return rc;
     if ((rc = ensure(ctx, ctx->node_prefix, nn * sizeof(uint64_t)))) return rc;
     k_topo_emit<<<nb, kTopoThreads, 0, ctx->stream>>>(
-        keys, n, ptr<int32_t>(ctx->lvlrange), blk_off, ls, nb, ptr<int32_t>(ctx->node_level),
+        keys, n, ctx->prm.n_leaf, ptr<int32_t>(ctx->lvlrange), blk_off, ls, nb, ptr<int32_t>(ctx->node_level),
         ptr<int32_t>(ctx->node_first), ptr<int32_t>(ctx->node_count), ptr<int32_t>(ctx->node_child),
         ptr<int32_t>(ctx->node_nchild), ptr<uint64_t>(ctx->node_prefix));
     if ((rc = check_hip(ctx, hipGetLastError(), "topology emit"))) return rc;
@@ -611,7 +707,8 @@ int build_topology(p3t_ctx *ctx, int64_t n) {
 // sorted order, children in octant order) whichever thread performs them.
 // ---------------------------------------------------------------------------
 struct MomentArrays {
-    const int32_t *level, *first, *count, *child, *nchild, *parent;
+    const int32_t *level, *first, *child, *nchild, *parent;
+    int32_t *count;                 // leaves' counts in; internal nodes' counts out
     const RootInfo *root;
     const PosMass *xm;
     double *S;
@@ -621,7 +718,7 @@ struct MomentArrays {
 };
 
 __device__ __forceinline__ void store_node(const MomentArrays &A, int64_t id, int lev, int nc,
-                                           int32_t f, int32_t cnt, double M, double Sx,
+                                           int32_t child_first, int32_t f, int32_t cnt, double M, double Sx,
                                            double Sy, double Sz, const double lo[3],
                                            const double hi[3], const double q[6]) {
     const double cx = Sx / M, cy = Sy / M, cz = Sz / M;
@@ -633,7 +730,7 @@ __device__ __forceinline__ void store_node(const MomentArrays &A, int64_t id, in
     o.cx = cx; o.cy = cy; o.cz = cz;
     o.l2 = side * side;
     for (int a = 0; a < 3; ++a) { o.lo[a] = lo[a]; o.hi[a] = hi[a]; }
-    o.child_first = nc ? A.child[id] : -1;
+    o.child_first = nc ? child_first : -1;
     o.n_child = nc;
     o.first = f;
     o.count = cnt;
@@ -690,62 +787,73 @@ __device__ __forceinline__ void leaf_moments(const MomentArrays &A, int64_t id) 
             q[5] += mk * 3.0 * dy * dz;
         }
     }
-    store_node(A, id, A.level[id], 0, f, cnt, M, Sx, Sy, Sz, lo, hi, q);
+    store_node(A, id, A.level[id], 0, -1, f, cnt, M, Sx, Sy, Sz, lo, hi, q);
 }
 
-// fold of an internal node's (at most 8) children in octant order, the
-// children's quadrupoles shifted to the node's centre of mass
-__device__ __forceinline__ void internal_moments(const MomentArrays &A, int64_t id) {
-    const int nc = A.nchild[id];
-    const int32_t cf = A.child[id];
+// What a parent's fold reads of each child, staged in LDS.
+struct ChildRec {
+    double M, Sx, Sy, Sz, cx, cy, cz;
+    double q[6];
+    double lo[3], hi[3];
+    int32_t count, pad;
+};
+
+__device__ __forceinline__ ChildRec load_child(const MomentArrays &A, int64_t k) {
+    const NodeMP m = A.mp[k];
+    const NodeWalk &w = A.nw[k];
+    ChildRec r;
+    r.M = m.M;
+    r.Sx = A.S[k];
+    r.Sy = A.S[A.n_nodes + k];
+    r.Sz = A.S[2 * A.n_nodes + k];
+    r.cx = m.cx; r.cy = m.cy; r.cz = m.cz;
+    for (int a = 0; a < 6; ++a) r.q[a] = m.q[a];
+    for (int a = 0; a < 3; ++a) {
+        r.lo[a] = w.lo[a];
+        r.hi[a] = w.hi[a];
+    }
+    r.count = w.count;
+    r.pad = 0;
+    return r;
+}
+
+// fold of an internal node's nc (at most 8) children child(0 .. nc-1) in octant
+// order, the children's quadrupoles shifted to the node's centre of mass; the
+// node's count is the sum of its children's
+template <class Child>
+__device__ __forceinline__ void internal_moments(const MomentArrays &A, int64_t id, int lev,
+                                                 int32_t first_child, const Child &child, int nc) {
     double M = 0.0, Sx = 0.0, Sy = 0.0, Sz = 0.0;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     double q[6] = {0, 0, 0, 0, 0, 0};
-    // every child slot is loaded (clamped to the last child) so that all the
-    // loads issue together; the folds keep child order and skip the slots
-    // past nc
-    NodeMP cm[8];
-    double cS[8][3], clo[8][3], chi[8][3];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const int k = cf + (c < nc ? c : nc - 1);
-        cm[c] = A.mp[k];
-        cS[c][0] = A.S[k];
-        cS[c][1] = A.S[A.n_nodes + k];
-        cS[c][2] = A.S[2 * A.n_nodes + k];
+    int32_t cnt = 0;
+    for (int k = 0; k < nc; ++k) {
+        const ChildRec c = child(k);
+        cnt += c.count;
+        M = M + c.M;
+        Sx = Sx + c.Sx;
+        Sy = Sy + c.Sy;
+        Sz = Sz + c.Sz;
         for (int a = 0; a < 3; ++a) {
-            clo[c][a] = A.nw[k].lo[a];
-            chi[c][a] = A.nw[k].hi[a];
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        if (c < nc) {
-            M = M + cm[c].M;
-            Sx = Sx + cS[c][0];
-            Sy = Sy + cS[c][1];
-            Sz = Sz + cS[c][2];
-            for (int a = 0; a < 3; ++a) {
-                lo[a] = fmin(lo[a], clo[c][a]);
-                hi[a] = fmax(hi[a], chi[c][a]);
-            }
+            lo[a] = fmin(lo[a], c.lo[a]);
+            hi[a] = fmax(hi[a], c.hi[a]);
         }
     }
     const double cx = Sx / M, cy = Sy / M, cz = Sz / M;
-#pragma unroll
-    for (int cc = 0; cc < 8; ++cc) {
-        if (cc >= nc) continue;
-        const NodeMP c = cm[cc];
+    for (int k = 0; k < nc; ++k) {
+        const ChildRec c = child(k);
         const double dx = c.cx - cx, dy = c.cy - cy, dz = c.cz - cz;
         const double r2 = dx * dx + dy * dy + dz * dz;
-        q[0] += c.q[0] + c.M * (3.0 * dx * dx - r2);
-        q[1] += c.q[1] + c.M * (3.0 * dy * dy - r2);
-        q[2] += c.q[2] + c.M * (3.0 * dz * dz - r2);
-        q[3] += c.q[3] + c.M * 3.0 * dx * dy;
-        q[4] += c.q[4] + c.M * 3.0 * dx * dz;
-        q[5] += c.q[5] + c.M * 3.0 * dy * dz;
+        const double Mk = c.M;
+        q[0] += c.q[0] + Mk * (3.0 * dx * dx - r2);
+        q[1] += c.q[1] + Mk * (3.0 * dy * dy - r2);
+        q[2] += c.q[2] + Mk * (3.0 * dz * dz - r2);
+        q[3] += c.q[3] + Mk * 3.0 * dx * dy;
+        q[4] += c.q[4] + Mk * 3.0 * dx * dz;
+        q[5] += c.q[5] + Mk * 3.0 * dy * dz;
     }
-    store_node(A, id, A.level[id], nc, A.first[id], A.count[id], M, Sx, Sy, Sz, lo, hi, q);
+    A.count[id] = cnt;
+    store_node(A, id, lev, nc, first_child, A.first[id], cnt, M, Sx, Sy, Sz, lo, hi, q);
 }
 
 __global__ __launch_bounds__(128) void k_moments_leaves(MomentArrays A) {
@@ -754,11 +862,56 @@ __global__ __launch_bounds__(128) void k_moments_leaves(MomentArrays A) {
     leaf_moments(A, id);
 }
 
-// the internal nodes with ids in [begin, end) (one level)
-__global__ __launch_bounds__(128) void k_moments_level(MomentArrays A, int64_t begin, int64_t end) {
-    const int64_t id = begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= end || A.nchild[id] == 0) return;
-    internal_moments(A, id);
+// The internal nodes of level lev from the children level [cb, ce): a lane
+// per child stages that child's record in LDS (consecutive lanes, consecutive
+// records); the lane of each parent's first child folds the parent.  A block
+// also stages the 7 children past its end, so every parent whose first child
+// it holds has all its children on chip.
+constexpr int kMomThreads = 256;
+__global__ __launch_bounds__(kMomThreads) void k_moments_level(MomentArrays A, int lev, int64_t cb,
+                                                               int64_t ce) {
+    __shared__ ChildRec s_c[kMomThreads + 7];
+    __shared__ int32_t s_par[kMomThreads + 7];
+    const int64_t k0 = cb + (int64_t)blockIdx.x * kMomThreads;
+    for (int t = threadIdx.x; t < kMomThreads + 7; t += kMomThreads) {
+        const int64_t k = k0 + t;
+        if (k < ce) {
+            s_c[t] = load_child(A, k);
+            s_par[t] = A.parent[k];
+        } else {
+            s_par[t] = -1;
+        }
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    const int64_t k = k0 + t;
+    if (k >= ce) return;
+    const int32_t p = s_par[t];
+    // a parent's children are consecutive; the level's first node starts one
+    const int32_t before = (k == cb) ? -1 : (t > 0 ? s_par[t - 1] : A.parent[k - 1]);
+    if (before == p) return;
+    int nc = 1;
+    while (nc < 8 && s_par[t + nc] == p) ++nc;
+    const ChildRec *c = s_c + t;
+    internal_moments(A, p, lev, (int32_t)k, [c](int j) { return c[j]; }, nc);
+}
+
+// The top levels top .. 0 (each of at most kMomTopThreads nodes) in one block,
+// a thread per parent reading its children from memory; the block's barrier
+// orders each level after the one below it (one compute unit: the block sees
+// its own writes).
+constexpr int kMomTopThreads = 1024;
+__global__ __launch_bounds__(kMomTopThreads) void k_moments_top(MomentArrays A, int top,
+                                                               LevelStarts ls) {
+    for (int l = top; l >= 0; --l) {
+        for (int64_t id = ls.s[l] + threadIdx.x; id < ls.s[l + 1]; id += kMomTopThreads) {
+            const int nc = A.nchild[id];
+            if (nc == 0) continue;
+            const int32_t cf = A.child[id];
+            internal_moments(A, id, l, cf, [&A, cf](int j) { return load_child(A, cf + j); }, nc);
+        }
+        __syncthreads();
+    }
 }
 
 int build_moments(p3t_ctx *ctx) {
@@ -782,10 +935,22 @@ int build_moments(p3t_ctx *ctx) {
     A.n_nodes = nn;
     k_moments_leaves<<<blocks_for(nn, 128), 128, 0, ctx->stream>>>(A);
     if ((rc = check_hip(ctx, hipGetLastError(), "moments (leaves)"))) return rc;
-    for (int l = (int)ctx->depth - 1; l >= 0; --l) {   // the deepest level holds leaves only
-        const int64_t b = ctx->level_start[l], e = ctx->level_start[l + 1];
-        k_moments_level<<<blocks_for(e - b, 128), 128, 0, ctx->stream>>>(A, b, e);
+    // the levels 0 .. top of at most kMomTopThreads nodes each go to one block
+    int top = -1;
+    while (top + 1 <= (int)ctx->depth - 1 &&
+           ctx->level_start[top + 2] - ctx->level_start[top + 1] <= kMomTopThreads)
+        ++top;
+    for (int l = (int)ctx->depth - 1; l > top; --l) {   // the deepest level holds leaves only
+        const int64_t cb = ctx->level_start[l + 1], ce = ctx->level_start[l + 2];
+        k_moments_level<<<blocks_for(ce - cb, kMomThreads), kMomThreads, 0, ctx->stream>>>(
+            A, l, cb, ce);
         if ((rc = check_hip(ctx, hipGetLastError(), "moments (level)"))) return rc;
+    }
+    if (top >= 0) {
+        LevelStarts ls;
+        for (int l = 0; l <= kLevels; ++l) ls.s[l] = ctx->level_start[l];
+        k_moments_top<<<1, kMomTopThreads, 0, ctx->stream>>>(A, top, ls);
+        if ((rc = check_hip(ctx, hipGetLastError(), "moments (top levels)"))) return rc;
     }
     return P3T_OK;
 }

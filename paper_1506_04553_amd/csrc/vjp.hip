@@ -22,8 +22,14 @@
 //
 // The adjoint arithmetic takes no decisions (the lists are frozen), so unlike
 // the rest of the library it lets the compiler fuse multiply-adds.  Runs of at
-// most 32 terms are summed in R before each run's sum joins an FP64 sum.
+// most 32 terms are summed in R before each run's sum joins an FP64 sum; a
+// member's cell terms are summed in R over the 64 entries of a wavefront (a
+// fixed tree) before joining an FP64 sum.
 //
+// Two passes over each group's lists: the first sums the particle-list terms
+// of each member; the second sums, for each list entry, the terms of all
+// members and scatters them, and evaluates each (member, cell) term only once,
+// for both sides.
 // The pair and cell terms are evaluated in the precision of the forward pass
 // (R = double, or R = float on offsets from the group's centre taken in FP64,
 // as in the interaction kernel; K and W themselves are evaluated in FP64) and
@@ -127,7 +133,7 @@ struct VjpCell {
     R x, y, z, M, q[6];
 };
 
-template <class R, bool CHG>
+template <class R, bool CHG, bool QUAD>
 __device__ __forceinline__ void cell_grad(R rx, R ry, R rz, R M, const R q[6], R wx, R wy, R wz,
                                           R ci, const VjpParams &vp, CellGrad<R> &o) {
 #pragma clang fp contract(fast)
@@ -139,7 +145,7 @@ __device__ __forceinline__ void cell_grad(R rx, R ry, R rz, R M, const R q[6], R
     const Chg c = CHG ? changeover_ds((double)s, vp) : changeover_unit();
     const R K = (R)c.K, Ks = (R)c.Ks, W = (R)c.W, Ws = (R)c.Ws;
     R Qr[3] = {0, 0, 0}, Qw[3] = {0, 0, 0}, qq = 0;
-    if (vp.use_quad) {
+    if (QUAD) {
         Qr[0] = q[0] * rx + q[3] * ry + q[4] * rz;
         Qr[1] = q[3] * rx + q[1] * ry + q[5] * rz;
         Qr[2] = q[4] * rx + q[5] * ry + q[2] * rz;
@@ -164,7 +170,7 @@ __device__ __forceinline__ void cell_grad(R rx, R ry, R rz, R M, const R q[6], R
     const R radial = (Ks * wA + ci * Ws * Phi) * inv;
     for (int a = 0; a < 3; ++a) o.gr[a] = radial * r[a] - K * Hw[a] - ci * W * A[a];
     o.gM = -K * rw * inv3 - ci * W * inv;
-    if (vp.use_quad) {
+    if (QUAD) {
         const R k5 = R(0.5) * K * inv5, k7 = R(-2.5) * K * rw * inv7, cwq = R(-0.5) * ci * W * inv5;
         const R rr = k7 + cwq;
         o.S[0] = R(2) * k5 * wx * rx + rr * rx * rx;
@@ -176,6 +182,59 @@ __device__ __forceinline__ void cell_grad(R rx, R ry, R rz, R M, const R q[6], R
     } else {
         for (int a = 0; a < 6; ++a) o.S[a] = R(0);
     }
+}
+
+// The same terms for a cell at least r_out from the member (K = W = 1, dK/ds =
+// dW/ds = 0), rearranged: with cw = M/s^3 + 5/2 qq/s^7 (qq = r.Q.r),
+//   dl/dr = -cw w + Q w/s^5 + (c cw - cr) r - (cq + c/s^5) Q r,
+//   cr = -3 M (r.w)/s^5 + 5 (r.Q.w)/s^7 - 35/2 qq (r.w)/s^9,  cq = 5 (r.w)/s^7,
+// and dl/dQ = (w r^T + r w^T)/(2 s^5) + rr r r^T, rr = -5/2 (r.w)/s^7 - c/(2 s^5).
+// Outputs: g = dl/dr, gM = dl/dM, S = dl/dQ (xx yy zz xy xz yz; zero without
+// the quadrupole).
+template <class R, bool QUAD>
+__device__ __forceinline__ void cell_grad_far(R rx, R ry, R rz, R M, const R q[6], R wx, R wy,
+                                              R wz, R ci, R eps2, R g[3], R &gM, R S[6]) {
+#pragma clang fp contract(fast)
+    const R s2 = rx * rx + ry * ry + rz * rz + eps2;
+    const R inv = vrsq(s2);
+    const R inv2 = inv * inv, inv3 = inv2 * inv, inv5 = inv3 * inv2;
+    const R rw = rx * wx + ry * wy + rz * wz;
+    gM = -rw * inv3 - ci * inv;
+    if (!QUAD) {
+        const R cw = M * inv3;
+        const R b = ci * cw + R(3) * M * rw * inv5;   // c cw - cr, cr = -3 M (r.w)/s^5
+        g[0] = b * rx - cw * wx;
+        g[1] = b * ry - cw * wy;
+        g[2] = b * rz - cw * wz;
+        for (int a = 0; a < 6; ++a) S[a] = R(0);
+        return;
+    }
+    const R inv7 = inv5 * inv2, inv9 = inv7 * inv2;
+    const R Qr0 = q[0] * rx + q[3] * ry + q[4] * rz;
+    const R Qr1 = q[3] * rx + q[1] * ry + q[5] * rz;
+    const R Qr2 = q[4] * rx + q[5] * ry + q[2] * rz;
+    const R Qw0 = q[0] * wx + q[3] * wy + q[4] * wz;
+    const R Qw1 = q[3] * wx + q[1] * wy + q[5] * wz;
+    const R Qw2 = q[4] * wx + q[5] * wy + q[2] * wz;
+    const R qq = rx * Qr0 + ry * Qr1 + rz * Qr2;
+    const R Qrw = Qr0 * wx + Qr1 * wy + Qr2 * wz;
+    const R cw = M * inv3 + R(2.5) * qq * inv7;
+    const R cr = R(-3) * M * rw * inv5 + R(5) * Qrw * inv7 - R(17.5) * qq * rw * inv9;
+    const R b = ci * cw - cr;
+    const R gq = -(R(5) * rw * inv7 + ci * inv5);
+    g[0] = b * rx - cw * wx + inv5 * Qw0 + gq * Qr0;
+    g[1] = b * ry - cw * wy + inv5 * Qw1 + gq * Qr1;
+    g[2] = b * rz - cw * wz + inv5 * Qw2 + gq * Qr2;
+    const R rr = R(-2.5) * rw * inv7 - R(0.5) * ci * inv5;
+    const R k5 = R(0.5) * inv5;
+    const R ux = k5 * wx, uy = k5 * wy, uz = k5 * wz;
+    const R vx = rr * rx, vy = rr * ry, vz = rr * rz;
+    S[0] = rx * (R(2) * ux + vx);
+    S[1] = ry * (R(2) * uy + vy);
+    S[2] = rz * (R(2) * uz + vz);
+    S[3] = ry * (ux + vx) + rx * uy;
+    S[4] = rz * (ux + vx) + rx * uz;
+    S[5] = rz * (uy + vy) + ry * uz;
 }
 
 // coordinates are taken relative to `shift` in FP64 before rounding to R: the
@@ -197,11 +256,12 @@ __device__ __forceinline__ VjpCell<R> stage_cell(const NodeMP &c, const double s
 }
 
 // ---------------------------------------------------------------------------
-// Pass 1: per particle i (one group per block), the i-side terms.
+// Pass 1: per particle i (one group per block), the i-side particle-list terms.
 // ---------------------------------------------------------------------------
 // Terms are summed in R over runs of at most kFold and each run's sum is added
 // to an FP64 accumulator.
 constexpr int kFold = 32;
+static_assert(kFold <= kWave, "a run of member terms is parked one lane per member");
 
 // a list particle as staged in LDS: position (shifted) and mass
 template <class R>
@@ -230,8 +290,7 @@ __device__ __forceinline__ void vjp_i_pp_tile(const VjpPart<R> *sp, const int32_
     }
 }
 
-// CELL_K: accepted cells may lie within r_out of a member (h < r_out)
-template <class R, bool CELL_K>
+template <class R>
 __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
     const GroupInfo *__restrict__ grp, ListsDev L, const PosMass *__restrict__ xm,
     const NodeMP *__restrict__ mp,
@@ -239,15 +298,12 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
     VjpParams vp, double *__restrict__ gx, double *__restrict__ gm, int64_t n) {
     __shared__ VjpPart<R> s_p[kVjpTile];
     __shared__ int32_t s_j[kVjpTile];
-    __shared__ VjpCell<R> s_c[kVjpTile];
     __shared__ double s_red[3][kVjpThreads];
     const int tid = threadIdx.x;
     const int g = L.order[blockIdx.x];
     const GroupInfo gi = grp[g];
     double sh[3];
     group_shift<R>(gi, sh);
-    const int64_t cb = L.beg[0][g], ce = L.end[0][g];
-    const int32_t *__restrict__ c_idx = L.idx[0];
     // members in chunks of the largest power of two that fits (at most 256),
     // so that a chunk fills its lanes: 74 members run as 64 + 8 + 2
     for (int chunk = 0, nc = 0; chunk < gi.count; chunk += nc) {
@@ -287,24 +343,6 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
                                            wz, ci, vp, g0, g1, g2);
             }
         }
-        for (int64_t t0 = cb; t0 < ce; t0 += kVjpTile) {
-            const int tl = (int)min<int64_t>(kVjpTile, ce - t0);
-            __syncthreads();
-            if (tid < tl) s_c[tid] = stage_cell<R>(mp[c_idx[t0 + tid]], sh);
-            __syncthreads();
-            for (int k0 = slice; k0 < tl; k0 += kFold * nslice) {
-                const int k1 = min(tl, k0 + kFold * nslice);
-                R p0 = 0, p1 = 0, p2 = 0;
-                for (int k = k0; k < k1; k += nslice) {
-                    const VjpCell<R> c = s_c[k];
-                    CellGrad<R> cg;
-                    cell_grad<R, CELL_K>(xi - c.x, yi - c.y, zi - c.z, c.M, c.q, wx, wy, wz, ci,
-                                         vp, cg);
-                    p0 += cg.gr[0]; p1 += cg.gr[1]; p2 += cg.gr[2];
-                }
-                g0 += (double)p0; g1 += (double)p1; g2 += (double)p2;
-            }
-        }
         __syncthreads();
         s_red[0][tid] = g0; s_red[1][tid] = g1; s_red[2][tid] = g2;
         __syncthreads();
@@ -322,7 +360,8 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
 
 // ---------------------------------------------------------------------------
 // Pass 2: per list entry (particle j or cell c), the sum over the group's
-// members, scattered with one atomic add per component.  Cell adjoints are
+// members, scattered with one atomic add per component; the cell terms also
+// give the members their i-side cell terms.  Cell adjoints are
 // component-major: component a of cell c at cadj[a * n_nodes + c].
 // ---------------------------------------------------------------------------
 // a group member as staged in LDS: position (shifted), w and c
@@ -351,7 +390,7 @@ __device__ __forceinline__ void vjp_scatter_pp(const VjpMember<R> *si, const int
     }
 }
 
-template <class R, bool CELL_K>
+template <class R, bool CELL_K, bool QUAD>
 __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
     const GroupInfo *__restrict__ grp, ListsDev L, const PosMass *__restrict__ xm,
     const NodeMP *__restrict__ mp,
@@ -360,7 +399,9 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
     int64_t n, int64_t n_nodes) {
     __shared__ VjpMember<R> s_i[kVjpThreads];
     __shared__ int32_t s_id[kVjpThreads];
-    const int tid = threadIdx.x;
+    // per wavefront and member: the member's cell terms dl/dr (FP64 partials)
+    __shared__ double s_gr[kVjpThreads / kWave][kVjpThreads][3];
+    const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
     const int g = L.order[blockIdx.x];
     const GroupInfo gi = grp[g];
     double sh[3];
@@ -385,6 +426,7 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
             s_id[tid] = i;
         }
         __syncthreads();
+        for (int k = lane; k < nc; k += kWave) s_gr[w][k][0] = s_gr[w][k][1] = s_gr[w][k][2] = 0.0;
         for (int64_t e = tid; e < np; e += kVjpThreads) {
             const bool far = e < nf;
             const int32_t j = far ? p_idx[fb + e] : n_idx[nb + (e - nf)];
@@ -401,26 +443,70 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
             atomicAdd(&gx[2 * n + j], acc[2]);
             atomicAdd(&gm[j], acc[3]);
         }
-        for (int64_t e = cb + tid; e < ce; e += kVjpThreads) {
-            const int32_t cid = c_idx[e];
-            const VjpCell<R> c = stage_cell<R>(mp[cid], sh);
+        // cells: a lane per entry, the members from LDS.  Each pair's dl/dr
+        // counts for both sides: the cell's sums stay in the lane; the
+        // member's are summed over the wavefront's 64 entries (a fixed tree),
+        // parked in lane k - k0 of mg[] for the run of members k0 .. k1 - 1,
+        // and added to the wavefront's FP64 partials in s_gr after the run.
+        // Lanes past the end hold a massless cell far away and add zero.
+        const int64_t ncell = ce - cb;
+        for (int64_t e0 = (int64_t)w * kWave; e0 < ncell; e0 += kVjpThreads) {
+            const bool valid = e0 + lane < ncell;
+            const int32_t cid = valid ? c_idx[cb + e0 + lane] : 0;
+            VjpCell<R> c = stage_cell<R>(mp[cid], sh);
+            if (!valid) {
+                c.x = c.y = c.z = R(1e18);
+                c.M = R(0);
+                for (int a = 0; a < 6; ++a) c.q[a] = R(0);
+            }
             double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
             for (int k0 = 0; k0 < nc; k0 += kFold) {
                 const int k1 = min(nc, k0 + kFold);
                 R p[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+                R mg[3] = {0, 0, 0};
                 for (int k = k0; k < k1; ++k) {
                     const VjpMember<R> q = s_i[k];
-                    CellGrad<R> cg;
-                    cell_grad<R, CELL_K>(q.x - c.x, q.y - c.y, q.z - c.z, c.M, c.q, q.wx, q.wy,
-                                         q.wz, q.c, vp, cg);
-                    p[0] -= cg.gr[0]; p[1] -= cg.gr[1]; p[2] -= cg.gr[2];
-                    p[3] += cg.gM;
-                    for (int a = 0; a < 6; ++a) p[4 + a] += cg.S[a];
+                    R gr[3], gM, S[6];
+                    if (CELL_K) {
+                        CellGrad<R> cg;
+                        cell_grad<R, true, QUAD>(q.x - c.x, q.y - c.y, q.z - c.z, c.M, c.q, q.wx,
+                                                 q.wy, q.wz, q.c, vp, cg);
+                        for (int a = 0; a < 3; ++a) gr[a] = cg.gr[a];
+                        gM = cg.gM;
+                        for (int a = 0; a < 6; ++a) S[a] = cg.S[a];
+                    } else {
+                        cell_grad_far<R, QUAD>(q.x - c.x, q.y - c.y, q.z - c.z, c.M, c.q, q.wx,
+                                               q.wy, q.wz, q.c, (R)vp.eps2, gr, gM, S);
+                    }
+                    p[0] -= gr[0]; p[1] -= gr[1]; p[2] -= gr[2];
+                    p[3] += gM;
+                    if (QUAD)
+                        for (int a = 0; a < 6; ++a) p[4 + a] += S[a];
+                    const bool mine = lane == k - k0;
+                    for (int a = 0; a < 3; ++a) {
+                        const R t = last_lane(wave_sum_last(valid ? gr[a] : R(0)));
+                        mg[a] = mine ? t : mg[a];
+                    }
                 }
                 for (int a = 0; a < 10; ++a) acc[a] += (double)p[a];
+                if (lane < k1 - k0)
+                    for (int a = 0; a < 3; ++a) s_gr[w][k0 + lane][a] += (double)mg[a];
             }
-            for (int a = 0; a < 10; ++a)
-                if (acc[a] != 0.0) atomicAdd(&cadj[a * n_nodes + cid], acc[a]);
+            if (valid)
+                for (int a = 0; a < 10; ++a)
+                    if (acc[a] != 0.0) atomicAdd(&cadj[a * n_nodes + cid], acc[a]);
+        }
+        __syncthreads();
+        // the members' cell terms, wavefront partials in a fixed order (another
+        // group may be adding to the same particle as a list entry)
+        if (tid < nc) {
+            const int32_t i = s_id[tid];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                double r = 0.0;
+                for (int v = 0; v < kVjpThreads / kWave; ++v) r += s_gr[v][tid][a];
+                atomicAdd(&gx[a * n + i], r);
+            }
         }
     }
 }
@@ -555,10 +641,16 @@ int launch_vjp_ws(p3t_ctx *ctx, const double *w, const double *c, double *gpos, 
     const bool cell_k = ctx->prm.r_search < ctx->prm.r_out;
     // the adjoint terms follow the forward pass's precision
     const bool mixed = ctx->prm.precision == P3T_PREC_MIXED;
-    auto ki = mixed ? (cell_k ? k_vjp_i<float, true> : k_vjp_i<float, false>)
-                    : (cell_k ? k_vjp_i<double, true> : k_vjp_i<double, false>);
-    auto ks = mixed ? (cell_k ? k_vjp_scatter<float, true> : k_vjp_scatter<float, false>)
-                    : (cell_k ? k_vjp_scatter<double, true> : k_vjp_scatter<double, false>);
+    auto ki = mixed ? k_vjp_i<float> : k_vjp_i<double>;
+    const bool quad = vp.use_quad != 0;
+    auto ks = mixed ? (cell_k ? (quad ? k_vjp_scatter<float, true, true>
+                                      : k_vjp_scatter<float, true, false>)
+                              : (quad ? k_vjp_scatter<float, false, true>
+                                      : k_vjp_scatter<float, false, false>))
+                    : (cell_k ? (quad ? k_vjp_scatter<double, true, true>
+                                      : k_vjp_scatter<double, true, false>)
+                              : (quad ? k_vjp_scatter<double, false, true>
+                                      : k_vjp_scatter<double, false, false>));
     ki<<<G, kVjpThreads, 0, ctx->stream>>>(
         ptr<GroupInfo>(ctx->grp), L, ptr<PosMass>(ctx->xm), ptr<NodeMP>(ctx->node_mp), ptr<int32_t>(ctx->vals[0]), w, c, vp, gx, gm,
         n);

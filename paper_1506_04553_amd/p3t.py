@@ -9,8 +9,11 @@ If the library is missing this module raises; there is no fallback path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
+import weakref
 
 import numpy as np
 import torch
@@ -164,6 +167,18 @@ def check_params(**kw) -> int:
     return int(load_library().p3t_check_params(C.byref(p)))
 
 
+# Contexts still open at interpreter exit are closed by an exit handler, while
+# torch (whose allocator holds their workspaces) is still whole: this module is
+# imported after torch, so its handler runs before torch's.
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for ctx in list(_LIVE):
+        ctx.close()
+
+
 def _dptr(t: torch.Tensor | None):
     return None if t is None else C.c_void_p(t.data_ptr())
 
@@ -193,6 +208,8 @@ class P3T:
                 return p
 
             def _free(p, _user):
+                if sys.is_finalizing():   # torch's allocator may be gone; the process ends
+                    return
                 delete(int(p))
 
             self._alloc_cb, self._free_cb = ALLOC_FN(_alloc), FREE_FN(_free)
@@ -204,6 +221,7 @@ class P3T:
         if rc != P3T_OK:
             raise P3TError(rc, "p3t_create failed")
         self._h = h
+        _LIVE.add(self)
         self.n = 0
         self.params = None
         self.build_id = 0
