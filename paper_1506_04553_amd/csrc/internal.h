@@ -109,7 +109,7 @@ struct p3t_ctx {
     void *scratch = nullptr;      // device address of the library's static workspace on this device
 
     p3t::DevBuf root, keys[2], vals[2], hist, histc, rs_tot, xm, xm_in;
-    p3t::DevBuf lvlrange, tblk, tblk_off;
+    p3t::DevBuf lvlrange, tblk, tblk_off, gtile;
     p3t::DevBuf node_level, node_first, node_count, node_child, node_nchild, node_parent,
         node_prefix, node_S, node_walk, node_mp;
     p3t::DevBuf gflag, gscan, grp;

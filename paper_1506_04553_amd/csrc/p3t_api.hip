@@ -191,7 +191,7 @@ extern "C" void p3t_destroy(p3t_ctx *ctx) {
     else (void)hipDeviceSynchronize();
     DevBuf *bufs[] = {&ctx->root, &ctx->keys[0], &ctx->keys[1], &ctx->vals[0], &ctx->vals[1],
                       &ctx->hist, &ctx->histc, &ctx->rs_tot, &ctx->xm, &ctx->xm_in, &ctx->lvlrange,
-                      &ctx->tblk, &ctx->tblk_off, &ctx->node_level, &ctx->node_first,
+                      &ctx->tblk, &ctx->tblk_off, &ctx->gtile, &ctx->node_level, &ctx->node_first,
                       &ctx->node_count, &ctx->node_child, &ctx->node_nchild, &ctx->node_parent,
                       &ctx->node_prefix, &ctx->node_S, &ctx->node_walk, &ctx->node_mp, &ctx->gflag,
                       &ctx->gscan, &ctx->grp, &ctx->cnt, &ctx->off, &ctx->c_idx, &ctx->p_idx,

@@ -5,6 +5,7 @@
 
 #include "device_util.h"
 #include "internal.h"
+#include "scan_tiles.h"
 
 namespace p3t {
 
@@ -80,79 +81,6 @@ static int scan_rec(p3t_ctx *ctx, const T *in, T *out, int64_t n, T *total, T *t
     return check_hip(ctx, hipGetLastError(), "scan add");
 }
 
-// Two launches for up to kScan2MaxTiles tiles of kScan2Tile elements: the tile
-// sums, then every block adds up the sums of the tiles before its own and
-// scans its tile from there.
-constexpr int kScan2Items = 16;
-constexpr int kScan2Tile = kScanThreads * kScan2Items;
-constexpr int64_t kScan2MaxTiles = 4096;
-
-template <class T>
-__global__ __launch_bounds__(kScanThreads) void k_scan2_sums(const T *__restrict__ in, int64_t n,
-                                                             T *__restrict__ tile_sums) {
-    __shared__ T wsum[kScanThreads / kWave];
-    const int tid = threadIdx.x;
-    const int64_t base = (int64_t)blockIdx.x * kScan2Tile;
-    T run = 0;
-#pragma unroll
-    for (int k = 0; k < kScan2Items; ++k) {
-        const int64_t i = base + (int64_t)k * kScanThreads + tid;   // coalesced
-        if (i < n) run += in[i];
-    }
-    run = wave_sum(run);
-    if (tid % kWave == 0) wsum[tid / kWave] = run;
-    __syncthreads();
-    if (tid == 0) {
-        T s = 0;
-        for (int k = 0; k < kScanThreads / kWave; ++k) s += wsum[k];
-        tile_sums[blockIdx.x] = s;
-    }
-}
-
-template <class T>
-__global__ __launch_bounds__(kScanThreads) void k_scan2_tiles(const T *in, T *out, int64_t n,
-                                                              const T *__restrict__ tile_sums,
-                                                              T *total) {
-    __shared__ T wsum[kScanThreads / kWave];
-    __shared__ T s_base;
-    const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
-    // this tile's offset: the sum of the tiles before it
-    T before = 0;
-    for (int64_t b = tid; b < blockIdx.x; b += kScanThreads) before += tile_sums[b];
-    before = wave_sum(before);
-    if (lane == 0) wsum[w] = before;
-    __syncthreads();
-    if (tid == 0) {
-        T s = 0;
-        for (int k = 0; k < kScanThreads / kWave; ++k) s += wsum[k];
-        s_base = s;
-        if (total && blockIdx.x == gridDim.x - 1) *total = s + tile_sums[blockIdx.x];
-    }
-    __syncthreads();
-    // the tile: each thread scans kScan2Items consecutive elements
-    const int64_t base = (int64_t)blockIdx.x * kScan2Tile + (int64_t)tid * kScan2Items;
-    T v[kScan2Items];
-    T run = 0;
-#pragma unroll
-    for (int k = 0; k < kScan2Items; ++k) {
-        const int64_t i = base + k;
-        v[k] = (i < n) ? in[i] : T(0);
-        run += v[k];
-    }
-    const T incl = wave_incl_scan(run);
-    __syncthreads();   // wsum is reused
-    if (lane == kWave - 1) wsum[w] = incl;
-    __syncthreads();
-    T excl = s_base + incl - run;
-    for (int k = 0; k < w; ++k) excl += wsum[k];
-#pragma unroll
-    for (int k = 0; k < kScan2Items; ++k) {
-        const int64_t i = base + k;
-        if (i < n) out[i] = excl;
-        excl += v[k];
-    }
-}
-
 template <class T>
 static int scan_any(p3t_ctx *ctx, const T *in, T *out, int64_t n, T *total) {
     const int64_t tiles = (n + kScan2Tile - 1) / kScan2Tile;
@@ -161,7 +89,8 @@ static int scan_any(p3t_ctx *ctx, const T *in, T *out, int64_t n, T *total) {
         if (rc) return rc;
         T *sums = ptr<T>(ctx->scan_tmp);
         k_scan2_sums<T><<<(unsigned)tiles, kScanThreads, 0, ctx->stream>>>(in, n, sums);
-        k_scan2_tiles<T><<<(unsigned)tiles, kScanThreads, 0, ctx->stream>>>(in, out, n, sums, total);
+        k_scan2_tiles<T><<<(unsigned)tiles, kScanThreads, 0, ctx->stream>>>(
+            in, n, sums, total, StoreExclusive<T>{out});
         return check_hip(ctx, hipGetLastError(), "scan");
     }
     // scratch: sum over recursion levels of the block counts

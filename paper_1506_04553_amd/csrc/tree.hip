@@ -22,6 +22,7 @@
 
 #include "device_util.h"
 #include "internal.h"
+#include "scan_tiles.h"
 
 namespace p3t {
 
@@ -406,8 +407,10 @@ int build_sorted(p3t_ctx *ctx, const double *pos, const double *mass, int64_t n)
     if ((rc = ensure(ctx, ctx->gflag, (n + 1) * sizeof(int32_t)))) return rc;
     double *partial = ptr<double>(ctx->bbox);
     int64_t *rb = ptr<int64_t>(ctx->readback);
+    // the input check goes straight to the pinned host words (read after the
+    // topology's synchronisation)
     k_bbox<<<nbb, kRedThreads, 0, ctx->stream>>>(pos, mass, n, partial, ptr<RootInfo>(ctx->root),
-                                                 rb + kRbTopoBad,
+                                                 ctx->hpin + kRbTopoBad,
                                                  reinterpret_cast<unsigned int *>(rb + kRbBboxDone));
     int32_t *cnt = ptr<int32_t>(ctx->histc), *off = ptr<int32_t>(ctx->hist);
     int32_t *tot = ptr<int32_t>(ctx->rs_tot);
@@ -509,13 +512,18 @@ __device__ __forceinline__ void load_key_window(uint64_t *s_k, const uint64_t *k
     }
 }
 
+// (block 0 also clears the n_gtile group counters of the moments folds)
 __global__ __launch_bounds__(kTopoThreads) void k_topo_ranges(const uint64_t *__restrict__ keys,
                                                               int64_t n, int n_leaf,
                                                               int32_t *__restrict__ range,
-                                                              int32_t *__restrict__ blk, int nb) {
+                                                              int32_t *__restrict__ blk, int nb,
+                                                              int32_t *__restrict__ gtile,
+                                                              int n_gtile) {
     __shared__ int32_t cnt[kLevels];
     __shared__ uint64_t s_k[kTopoThreads + 2 * kTopoWin];
     if (threadIdx.x < kLevels) cnt[threadIdx.x] = 0;
+    if (blockIdx.x == 0)
+        for (int t = threadIdx.x; t < n_gtile; t += kTopoThreads) gtile[t] = 0;
     const int64_t base = (int64_t)blockIdx.x * kTopoThreads;
     const bool win = n_leaf <= kTopoWin;
     if (win) load_key_window(s_k, keys, n, base, n_leaf, n_leaf);
@@ -631,14 +639,13 @@ __global__ __launch_bounds__(kTopoThreads) void k_topo_emit(
 }
 
 // children are contiguous: n_child = (first child of the next node at this level)
-// - (own first child); parents from the children ranges.
-__global__ void k_topo_links(int64_t n_nodes, const int32_t *__restrict__ level,
-                             const int32_t *__restrict__ child, int32_t *__restrict__ nchild,
-                             int32_t *__restrict__ parent, const LevelStarts level_start) {
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= n_nodes) return;
-    if (id == 0) parent[0] = -1;
-    if (nchild[id] != -1) return;
+// - (own first child); parents from the children ranges.  Run by the leaf
+// moments kernel for the internal nodes.
+__device__ __forceinline__ void topo_links(int64_t id, const int32_t *__restrict__ level,
+                                           const int32_t *__restrict__ child,
+                                           int32_t *__restrict__ nchild,
+                                           int32_t *__restrict__ parent,
+                                           const LevelStarts &level_start) {
     const int l = level[id];
     const int64_t next = (id + 1 < level_start.s[l + 1]) ? child[id + 1] : level_start.s[l + 2];
     const int32_t cf = child[id];
@@ -650,25 +657,27 @@ __global__ void k_topo_links(int64_t n_nodes, const int32_t *__restrict__ level,
 int build_topology(p3t_ctx *ctx, int64_t n) {
     int rc;
     const int nb = (int)((n + kTopoThreads - 1) / kTopoThreads);
-    if ((rc = ensure(ctx, ctx->lvlrange, n * sizeof(int32_t)))) return rc;
+    // n + 1: the array later holds the groups' node_at
+    if ((rc = ensure(ctx, ctx->lvlrange, (n + 1) * sizeof(int32_t)))) return rc;
     if ((rc = ensure(ctx, ctx->tblk, (size_t)kLevels * nb * sizeof(int32_t)))) return rc;
     if ((rc = ensure(ctx, ctx->tblk_off, (size_t)kLevels * nb * sizeof(int32_t)))) return rc;
     if ((rc = ensure_readback(ctx))) return rc;
     const uint64_t *keys = ptr<uint64_t>(ctx->keys[0]);
     int32_t *blk = ptr<int32_t>(ctx->tblk), *blk_off = ptr<int32_t>(ctx->tblk_off);
-    int64_t *rb = ptr<int64_t>(ctx->readback);
-    k_topo_ranges<<<nb, kTopoThreads, 0, ctx->stream>>>(keys, n, ctx->prm.n_leaf,
-                                                        ptr<int32_t>(ctx->lvlrange), blk, nb);
+    // the groups' per-tile counts (for the compaction's scan), when it fits one
+    const int64_t n_gtile = (n + 1 + kScan2Tile - 1) / kScan2Tile;
+    const bool gcount = n_gtile <= kScan2MaxTiles;
+    if (gcount && (rc = ensure(ctx, ctx->gtile, n_gtile * sizeof(int32_t)))) return rc;
+    k_topo_ranges<<<nb, kTopoThreads, 0, ctx->stream>>>(
+        keys, n, ctx->prm.n_leaf, ptr<int32_t>(ctx->lvlrange), blk, nb,
+        gcount ? ptr<int32_t>(ctx->gtile) : nullptr, gcount ? (int)n_gtile : 0);
     if ((rc = check_hip(ctx, hipGetLastError(), "topology ranges"))) return rc;
-    // the per-level node counts go straight to the readback area (int32, in
-    // the words before the input check)
+    // the per-level node counts (int32, in the words before the input check) go
+    // straight to the pinned host words; one synchronisation makes them and the
+    // input check visible
     static_assert(kLevels * sizeof(int32_t) <= kRbTopoBad * sizeof(int64_t), "readback layout");
-    int32_t *level_total = reinterpret_cast<int32_t *>(rb);
+    int32_t *level_total = reinterpret_cast<int32_t *>(ctx->hpin);
     if ((rc = scan_rows_i32(ctx, blk, blk_off, level_total, kLevels, nb))) return rc;
-    // one read-back: node counts per level and the input check
-    if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin, rb, (kRbTopoBad + 1) * sizeof(int64_t),
-                                            hipMemcpyDeviceToHost, ctx->stream), "readback")))
-        return rc;
     if ((rc = check_hip(ctx, hipStreamSynchronize(ctx->stream), "sync"))) return rc;
     if (ctx->hpin[kRbTopoBad])
         return set_error(ctx, P3T_EINVAL, "non-finite position or non-positive/non-finite mass");
@@ -693,11 +702,7 @@ int build_topology(p3t_ctx *ctx, int64_t n) {
         keys, n, ctx->prm.n_leaf, ptr<int32_t>(ctx->lvlrange), blk_off, ls, nb, ptr<int32_t>(ctx->node_level),
         ptr<int32_t>(ctx->node_first), ptr<int32_t>(ctx->node_count), ptr<int32_t>(ctx->node_child),
         ptr<int32_t>(ctx->node_nchild), ptr<uint64_t>(ctx->node_prefix));
-    if ((rc = check_hip(ctx, hipGetLastError(), "topology emit"))) return rc;
-    k_topo_links<<<blocks_for(nn, 256), 256, 0, ctx->stream>>>(
-        nn, ptr<int32_t>(ctx->node_level), ptr<int32_t>(ctx->node_child),
-        ptr<int32_t>(ctx->node_nchild), ptr<int32_t>(ctx->node_parent), ls);
-    return check_hip(ctx, hipGetLastError(), "topology links");
+    return check_hip(ctx, hipGetLastError(), "topology emit");
 }
 
 // ---------------------------------------------------------------------------
@@ -715,17 +720,60 @@ struct MomentArrays {
     NodeWalk *nw;
     NodeMP *mp;
     int64_t n_nodes;
+    // groups: the highest nodes with at most n_crit members, or leaves; each
+    // flags its first particle (gflag) and is recorded there (node_at)
+    int n_crit;
+    int32_t *gflag, *node_at;
+    int32_t *gtile;                 // groups per kScan2Tile particles (null: not counted)
+    int64_t *walk_zero;             // the walk's statistics words, cleared here
 };
 
-__device__ __forceinline__ void store_node(const MomentArrays &A, int64_t id, int lev, int nc,
-                                           int32_t child_first, int32_t f, int32_t cnt, double M, double Sx,
-                                           double Sy, double Sz, const double lo[3],
-                                           const double hi[3], const double q[6]) {
+// Group counts per particle tile, gathered per lane (one open tile) and added
+// to gtile per wavefront and tile.
+struct TileCount {
+    int32_t tile = -1, count = 0;
+};
+
+__device__ __forceinline__ void mark_group(const MomentArrays &A, int32_t node, int32_t first,
+                                           TileCount &tc) {
+    A.gflag[first] = 1;
+    A.node_at[first] = node;
+    if (!A.gtile) return;
+    const int32_t t = first / kScan2Tile;
+    if (tc.count == 0 || tc.tile == t) {
+        tc.tile = t;
+        ++tc.count;
+    } else {
+        atomicAdd(&A.gtile[t], 1);   // the lane's groups straddle a tile boundary
+    }
+}
+
+// all lanes of the wavefront: one atomic add per distinct open tile
+__device__ __forceinline__ void flush_tile_counts(const MomentArrays &A, const TileCount &tc) {
+    if (!A.gtile) return;
+    const bool has = tc.count > 0;
+    uint64_t todo = ballot(has);
+    while (todo) {
+        const int lead = __builtin_ctzll(todo);
+        const int32_t t = __shfl(tc.tile, lead, kWave);
+        const bool same = has && tc.tile == t;
+        const int32_t sum = wave_sum(same ? tc.count : 0);
+        if (lane_id() == lead) atomicAdd(&A.gtile[t], sum);
+        todo &= ~ballot(same);
+    }
+}
+
+// L: the root cell's side
+__device__ __forceinline__ void store_node(const MomentArrays &A, double L, int64_t id, int lev,
+                                           int nc, int32_t child_first, int32_t f, int32_t cnt,
+                                           double M, double Sx, double Sy, double Sz,
+                                           const double lo[3], const double hi[3],
+                                           const double q[6]) {
     const double cx = Sx / M, cy = Sy / M, cz = Sz / M;
     A.S[id] = Sx;
     A.S[A.n_nodes + id] = Sy;
     A.S[2 * A.n_nodes + id] = Sz;
-    const double side = ldexp(A.root->L, -lev);
+    const double side = ldexp(L, -lev);
     NodeWalk o;
     o.cx = cx; o.cy = cy; o.cz = cz;
     o.l2 = side * side;
@@ -787,15 +835,23 @@ __device__ __forceinline__ void leaf_moments(const MomentArrays &A, int64_t id) 
             q[5] += mk * 3.0 * dy * dz;
         }
     }
-    store_node(A, id, A.level[id], 0, -1, f, cnt, M, Sx, Sy, Sz, lo, hi, q);
+    store_node(A, A.root->L, id, A.level[id], 0, -1, f, cnt, M, Sx, Sy, Sz, lo, hi, q);
 }
+
+// Internal nodes are folded from their children staged in LDS in chunks of
+// kMomChunk children (see fold_chunk).
+constexpr int kMomChunk = 256;
+constexpr int kMomChildMax = 8;
+constexpr int kMomStage = kMomChunk + kMomChildMax - 1;
+constexpr int kMomThreads = 320;   // >= kMomStage: one staging round
+static_assert(kMomThreads >= kMomStage, "one staging round");
 
 // What a parent's fold reads of each child, staged in LDS.
 struct ChildRec {
     double M, Sx, Sy, Sz, cx, cy, cz;
     double q[6];
     double lo[3], hi[3];
-    int32_t count, pad;
+    int32_t count, first, n_child, pad;
 };
 
 __device__ __forceinline__ ChildRec load_child(const MomentArrays &A, int64_t k) {
@@ -813,6 +869,8 @@ __device__ __forceinline__ ChildRec load_child(const MomentArrays &A, int64_t k)
         r.hi[a] = w.hi[a];
     }
     r.count = w.count;
+    r.first = w.first;
+    r.n_child = w.n_child;
     r.pad = 0;
     return r;
 }
@@ -821,8 +879,9 @@ __device__ __forceinline__ ChildRec load_child(const MomentArrays &A, int64_t k)
 // order, the children's quadrupoles shifted to the node's centre of mass; the
 // node's count is the sum of its children's
 template <class Child>
-__device__ __forceinline__ void internal_moments(const MomentArrays &A, int64_t id, int lev,
-                                                 int32_t first_child, const Child &child, int nc) {
+__device__ __forceinline__ void internal_moments(const MomentArrays &A, double L, int64_t id, int lev,
+                                                 int32_t first_child, const Child &child, int nc,
+                                                 TileCount &tc) {
     double M = 0.0, Sx = 0.0, Sy = 0.0, Sz = 0.0;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     double q[6] = {0, 0, 0, 0, 0, 0};
@@ -853,64 +912,103 @@ __device__ __forceinline__ void internal_moments(const MomentArrays &A, int64_t 
         q[5] += c.q[5] + Mk * 3.0 * dy * dz;
     }
     A.count[id] = cnt;
-    store_node(A, id, lev, nc, first_child, A.first[id], cnt, M, Sx, Sy, Sz, lo, hi, q);
+    const int32_t f = child(0).first;   // the node's first particle is its first child's
+    store_node(A, L, id, lev, nc, first_child, f, cnt, M, Sx, Sy, Sz, lo, hi, q);
+    // groups among the children (this node has more than n_crit members), or
+    // the root itself
+    if (cnt > A.n_crit) {
+        for (int k = 0; k < nc; ++k) {
+            const ChildRec c = child(k);
+            if (c.count <= A.n_crit || c.n_child == 0) mark_group(A, first_child + k, c.first, tc);
+        }
+    } else if (lev == 0) {
+        mark_group(A, (int32_t)id, f, tc);
+    }
 }
 
-__global__ __launch_bounds__(128) void k_moments_leaves(MomentArrays A) {
+// every leaf's moments; every internal node's child count and its children's
+// parent links (the topology's last step)
+__global__ __launch_bounds__(128) void k_moments_leaves(MomentArrays A, int32_t *__restrict__ nchild,
+                                                        int32_t *__restrict__ parent,
+                                                        LevelStarts ls) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= A.n_nodes || A.nchild[id] != 0) return;
-    leaf_moments(A, id);
-}
-
-// The internal nodes of level lev from the children level [cb, ce): a lane
-// per child stages that child's record in LDS (consecutive lanes, consecutive
-// records); the lane of each parent's first child folds the parent.  A block
-// also stages the 7 children past its end, so every parent whose first child
-// it holds has all its children on chip.
-constexpr int kMomThreads = 256;
-__global__ __launch_bounds__(kMomThreads) void k_moments_level(MomentArrays A, int lev, int64_t cb,
-                                                               int64_t ce) {
-    __shared__ ChildRec s_c[kMomThreads + 7];
-    __shared__ int32_t s_par[kMomThreads + 7];
-    const int64_t k0 = cb + (int64_t)blockIdx.x * kMomThreads;
-    for (int t = threadIdx.x; t < kMomThreads + 7; t += kMomThreads) {
-        const int64_t k = k0 + t;
-        if (k < ce) {
-            s_c[t] = load_child(A, k);
-            s_par[t] = A.parent[k];
-        } else {
-            s_par[t] = -1;
+    if (id < kRbWalkWords) A.walk_zero[id] = 0;
+    if (id >= A.n_nodes) return;
+    if (id == 0) parent[0] = -1;
+    if (nchild[id] != 0) {
+        topo_links(id, A.level, A.child, nchild, parent, ls);
+    } else {
+        leaf_moments(A, id);
+        if (id == 0) {   // a root that is a leaf: the only group
+            TileCount tc;
+            mark_group(A, 0, 0, tc);
+            if (A.gtile) atomicAdd(&A.gtile[0], tc.count);
         }
     }
-    __syncthreads();
-    const int t = threadIdx.x;
-    const int64_t k = k0 + t;
-    if (k >= ce) return;
-    const int32_t p = s_par[t];
-    // a parent's children are consecutive; the level's first node starts one
-    const int32_t before = (k == cb) ? -1 : (t > 0 ? s_par[t - 1] : A.parent[k - 1]);
-    if (before == p) return;
-    int nc = 1;
-    while (nc < 8 && s_par[t + nc] == p) ++nc;
-    const ChildRec *c = s_c + t;
-    internal_moments(A, p, lev, (int32_t)k, [c](int j) { return c[j]; }, nc);
 }
 
-// The top levels top .. 0 (each of at most kMomTopThreads nodes) in one block,
-// a thread per parent reading its children from memory; the block's barrier
-// orders each level after the one below it (one compute unit: the block sees
-// its own writes).
-constexpr int kMomTopThreads = 1024;
-__global__ __launch_bounds__(kMomTopThreads) void k_moments_top(MomentArrays A, int top,
-                                                               LevelStarts ls) {
-    for (int l = top; l >= 0; --l) {
-        for (int64_t id = ls.s[l] + threadIdx.x; id < ls.s[l + 1]; id += kMomTopThreads) {
-            const int nc = A.nchild[id];
-            if (nc == 0) continue;
-            const int32_t cf = A.child[id];
-            internal_moments(A, id, l, cf, [&A, cf](int j) { return load_child(A, cf + j); }, nc);
+// The internal nodes of level lev whose first child lies in the chunk of
+// children [k0, k0 + kMomChunk) of the children level [cb, ce): a thread per
+// child stages that child's record in LDS (consecutive threads, consecutive
+// records), with the kMomChildMax - 1 children past the chunk so that every
+// parent whose first child is in the chunk has all its children on chip; the
+// thread of each parent's first child folds the parent.
+
+struct MomStage {
+    ChildRec c[kMomStage];
+    int32_t par[kMomStage];
+    int32_t before;   // parent of the child before the chunk (-1 at the level's start)
+};
+
+__device__ __forceinline__ void fold_chunk(const MomentArrays &A, MomStage &st, int lev, int64_t cb,
+                                           int64_t ce, int64_t k0) {
+    const int t = threadIdx.x;
+    const double L = A.root->L;   // read while the stage fills
+    if (t < kMomStage) {
+        const int64_t k = k0 + t;
+        if (k < ce) {
+            st.c[t] = load_child(A, k);
+            st.par[t] = A.parent[k];
+        } else {
+            st.par[t] = -1;
         }
-        __syncthreads();
+    }
+    if (t == kMomStage) st.before = k0 > cb ? A.parent[k0 - 1] : -1;
+    __syncthreads();
+    TileCount tc;
+    if (t < kMomChunk && k0 + t < ce) {
+        const int32_t p = st.par[t];
+        // a parent's children are consecutive
+        const int32_t before = t > 0 ? st.par[t - 1] : st.before;
+        if (before != p) {
+            int nc = 1;
+            while (nc < kMomChildMax && st.par[t + nc] == p) ++nc;
+            const ChildRec *c = st.c + t;
+            internal_moments(A, L, p, lev, (int32_t)(k0 + t), [c](int j) { return c[j]; }, nc,
+                             tc);
+        }
+    }
+    flush_tile_counts(A, tc);
+    __syncthreads();   // the stage is reused
+}
+
+// one chunk per block
+__global__ __launch_bounds__(kMomThreads) void k_moments_level(MomentArrays A, int lev, int64_t cb,
+                                                               int64_t ce) {
+    __shared__ MomStage st;
+    fold_chunk(A, st, lev, cb, ce, cb + (int64_t)blockIdx.x * kMomChunk);
+}
+
+// The top levels top .. 0 (children levels of at most kMomTopChildren nodes)
+// in one block, chunk after chunk; the block's barriers order each level after
+// the one below it (one compute unit: the block sees its own writes).
+constexpr int64_t kMomTopChildren = 4 * kMomChunk;
+__global__ __launch_bounds__(kMomThreads) void k_moments_top(MomentArrays A, int top,
+                                                            LevelStarts ls) {
+    __shared__ MomStage st;
+    for (int l = top; l >= 0; --l) {
+        const int64_t cb = ls.s[l + 1], ce = ls.s[l + 2];
+        for (int64_t k0 = cb; k0 < ce; k0 += kMomChunk) fold_chunk(A, st, l, cb, ce, k0);
     }
 }
 
@@ -933,55 +1031,43 @@ int build_moments(p3t_ctx *ctx) {
     A.nw = ptr<NodeWalk>(ctx->node_walk);
     A.mp = ptr<NodeMP>(ctx->node_mp);
     A.n_nodes = nn;
-    k_moments_leaves<<<blocks_for(nn, 128), 128, 0, ctx->stream>>>(A);
+    A.n_crit = ctx->prm.n_crit;
+    // the group flags were cleared by the last radix pass; the topology's
+    // per-particle range codes are dead and their array holds node_at
+    A.gflag = ptr<int32_t>(ctx->gflag);
+    A.node_at = ptr<int32_t>(ctx->lvlrange);
+    A.gtile = (ctx->n + 1 + kScan2Tile - 1) / kScan2Tile <= kScan2MaxTiles ? ptr<int32_t>(ctx->gtile)
+                                                                          : nullptr;
+    A.walk_zero = ptr<int64_t>(ctx->readback) + kRbWalk;
+    LevelStarts ls;
+    for (int l = 0; l <= kLevels; ++l) ls.s[l] = ctx->level_start[l];
+    k_moments_leaves<<<blocks_for(nn, 128), 128, 0, ctx->stream>>>(
+        A, ptr<int32_t>(ctx->node_nchild), ptr<int32_t>(ctx->node_parent), ls);
     if ((rc = check_hip(ctx, hipGetLastError(), "moments (leaves)"))) return rc;
-    // the levels 0 .. top of at most kMomTopThreads nodes each go to one block
+    // the levels 0 .. top whose children levels hold at most kMomTopChildren
+    // nodes go to one block
     int top = -1;
     while (top + 1 <= (int)ctx->depth - 1 &&
-           ctx->level_start[top + 2] - ctx->level_start[top + 1] <= kMomTopThreads)
+           ctx->level_start[top + 3] - ctx->level_start[top + 2] <= kMomTopChildren)
         ++top;
     for (int l = (int)ctx->depth - 1; l > top; --l) {   // the deepest level holds leaves only
         const int64_t cb = ctx->level_start[l + 1], ce = ctx->level_start[l + 2];
-        k_moments_level<<<blocks_for(ce - cb, kMomThreads), kMomThreads, 0, ctx->stream>>>(
+        k_moments_level<<<blocks_for(ce - cb, kMomChunk), kMomThreads, 0, ctx->stream>>>(
             A, l, cb, ce);
         if ((rc = check_hip(ctx, hipGetLastError(), "moments (level)"))) return rc;
     }
     if (top >= 0) {
-        LevelStarts ls;
-        for (int l = 0; l <= kLevels; ++l) ls.s[l] = ctx->level_start[l];
-        k_moments_top<<<1, kMomTopThreads, 0, ctx->stream>>>(A, top, ls);
+        k_moments_top<<<1, kMomThreads, 0, ctx->stream>>>(A, top, ls);
         if ((rc = check_hip(ctx, hipGetLastError(), "moments (top levels)"))) return rc;
     }
     return P3T_OK;
 }
 
 // ---------------------------------------------------------------------------
-// Groups: flag the first particle of every group node, compact in particle order.
+// Groups: the moments folds flag the first particle of every group node; the
+// flagged particles are compacted in particle order.
 // ---------------------------------------------------------------------------
-__global__ void k_group_mark(int64_t n_nodes, const int32_t *__restrict__ count,
-                             const int32_t *__restrict__ nchild, const int32_t *__restrict__ parent,
-                             const int32_t *__restrict__ first, int n_crit, int32_t *__restrict__ flag,
-                             int32_t *__restrict__ node_at) {
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= n_nodes) return;
-    const bool cand = count[id] <= n_crit || nchild[id] == 0;
-    const bool top = (id == 0) || count[parent[id]] > n_crit;
-    if (cand && top) {
-        flag[first[id]] = 1;
-        node_at[first[id]] = (int32_t)id;
-    }
-}
-
-// also clears the walk's statistics words (zero, nz of them)
-__global__ void k_group_compact(int64_t n, const int32_t *__restrict__ flag,
-                                const int32_t *__restrict__ slot, const int32_t *__restrict__ node_at,
-                                const NodeWalk *__restrict__ nw, GroupInfo *__restrict__ grp,
-                                int64_t *__restrict__ zero, int nz) {
-    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a < nz) zero[a] = 0;
-    if (a >= n || !flag[a]) return;
-    const int32_t id = node_at[a];
-    const NodeWalk nd = nw[id];
+__device__ __forceinline__ GroupInfo group_info(const NodeWalk &nd, int32_t id) {
     GroupInfo g;
     for (int k = 0; k < 3; ++k) {
         g.lo[k] = nd.lo[k];
@@ -992,7 +1078,32 @@ __global__ void k_group_compact(int64_t n, const int32_t *__restrict__ flag,
     g.count = nd.count;
     g.node = id;
     g.pad = 0;
-    grp[slot[a]] = g;
+    return g;
+}
+
+// the group record of a flagged particle, at its rank among the flags
+struct GroupSink {
+    const int32_t *node_at;
+    const NodeWalk *nw;
+    GroupInfo *grp;
+    __device__ __forceinline__ void operator()(int64_t a, int32_t slot, int32_t flag) const {
+        if (!flag) return;
+        const int32_t id = node_at[a];
+        grp[slot] = group_info(nw[id], id);
+    }
+};
+
+// (more than kScan2MaxTiles tiles of particles) also clears the walk's
+// statistics words (zero, nz of them)
+__global__ void k_group_compact(int64_t n, const int32_t *__restrict__ flag,
+                                const int32_t *__restrict__ slot, const int32_t *__restrict__ node_at,
+                                const NodeWalk *__restrict__ nw, GroupInfo *__restrict__ grp,
+                                int64_t *__restrict__ zero, int nz) {
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < nz) zero[a] = 0;
+    if (a >= n || !flag[a]) return;
+    const int32_t id = node_at[a];
+    grp[slot[a]] = group_info(nw[id], id);
 }
 
 int build_groups(p3t_ctx *ctx) {
@@ -1004,12 +1115,17 @@ int build_groups(p3t_ctx *ctx) {
     if ((rc = ensure(ctx, ctx->grp, (nn + 1) * sizeof(GroupInfo)))) return rc;
     int32_t *flag = ptr<int32_t>(ctx->gflag), *slot = ptr<int32_t>(ctx->gscan);
     int32_t *node_at = ptr<int32_t>(ctx->lvlrange);
-    // the flags were cleared by the last radix pass
-    k_group_mark<<<blocks_for(nn, 256), 256, 0, ctx->stream>>>(
-        nn, ptr<int32_t>(ctx->node_count), ptr<int32_t>(ctx->node_nchild),
-        ptr<int32_t>(ctx->node_parent), ptr<int32_t>(ctx->node_first), ctx->prm.n_crit, flag, node_at);
-    if ((rc = check_hip(ctx, hipGetLastError(), "group mark"))) return rc;
-    // slot[n] = number of groups (device), read back together with the list sizes
+    // the group nodes were flagged by the moments folds; slot[n] = number of
+    // groups (device), read back together with the list sizes
+    const int64_t tiles = (n + 1 + kScan2Tile - 1) / kScan2Tile;
+    if (tiles <= kScan2MaxTiles) {
+        // the folds counted the groups per tile; the scan places the group
+        // records itself
+        k_scan2_tiles<int32_t><<<(unsigned)tiles, kScan2Threads, 0, ctx->stream>>>(
+            flag, n + 1, ptr<int32_t>(ctx->gtile), slot + n,
+            GroupSink{node_at, ptr<NodeWalk>(ctx->node_walk), ptr<GroupInfo>(ctx->grp)});
+        return check_hip(ctx, hipGetLastError(), "groups");
+    }
     if ((rc = scan_exclusive_i32(ctx, flag, slot, n + 1, nullptr))) return rc;
     k_group_compact<<<blocks_for(n > kRbWalkWords ? n : kRbWalkWords, 256), 256, 0, ctx->stream>>>(
         n, flag, slot, node_at, ptr<NodeWalk>(ctx->node_walk), ptr<GroupInfo>(ctx->grp),
