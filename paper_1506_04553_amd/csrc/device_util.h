@@ -73,29 +73,15 @@ __device__ __forceinline__ double dpp_src(double v) {
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// Sum over the 64 lanes, complete in lane 63, by a fixed tree: pairs, quads,
-// half rows, rows of 16, then rows 0+1 and 2+3, then all four.
+// Sum over each row of 16 lanes, in every lane of the row, by a fixed tree:
+// pairs, quads, half rows, rows.
 template <class T>
-__device__ __forceinline__ T wave_sum_last(T v) {
-    v += dpp_src<0xB1>(v);         // quad_perm [1,0,3,2]
-    v += dpp_src<0x4E>(v);         // quad_perm [2,3,0,1]
-    v += dpp_src<0x141>(v);        // row_half_mirror
-    v += dpp_src<0x140>(v);        // row_mirror
-    v += dpp_src<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
-    v += dpp_src<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+__device__ __forceinline__ T row_sum(T v) {
+    v += dpp_src<0xB1>(v);     // quad_perm [1,0,3,2]
+    v += dpp_src<0x4E>(v);     // quad_perm [2,3,0,1]
+    v += dpp_src<0x141>(v);    // row_half_mirror
+    v += dpp_src<0x140>(v);    // row_mirror
     return v;
-}
-
-// v's value in lane 63, in every lane
-__device__ __forceinline__ float last_lane(float v) {
-    return __builtin_bit_cast(float,
-                              __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), kWave - 1));
-}
-__device__ __forceinline__ double last_lane(double v) {
-    const uint64_t b = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, kWave - 1);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), kWave - 1);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 template <class T>

@@ -261,7 +261,8 @@ __device__ __forceinline__ VjpCell<R> stage_cell(const NodeMP &c, const double s
 // Terms are summed in R over runs of at most kFold and each run's sum is added
 // to an FP64 accumulator.
 constexpr int kFold = 32;
-static_assert(kFold <= kWave, "a run of member terms is parked one lane per member");
+// a run of member terms is parked one lane per member and row, half a run at a time
+static_assert(kFold == 32, "two halves of 16 members");
 
 // a list particle as staged in LDS: position (shifted) and mass
 template <class R>
@@ -445,10 +446,12 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
         }
         // cells: a lane per entry, the members from LDS.  Each pair's dl/dr
         // counts for both sides: the cell's sums stay in the lane; the
-        // member's are summed over the wavefront's 64 entries (a fixed tree),
-        // parked in lane k - k0 of mg[] for the run of members k0 .. k1 - 1,
-        // and added to the wavefront's FP64 partials in s_gr after the run.
-        // Lanes past the end hold a massless cell far away and add zero.
+        // member's are summed over each row of 16 entries (a fixed tree) and
+        // parked in the row's lane (k - k0) mod 16 of mg[half] for the run of
+        // members k0 .. k1 - 1; after the run a butterfly over the four rows
+        // completes each member's sum, which joins the wavefront's FP64
+        // partials in s_gr.  Lanes past the end hold a massless cell far away
+        // and add zero.
         const int64_t ncell = ce - cb;
         for (int64_t e0 = (int64_t)w * kWave; e0 < ncell; e0 += kVjpThreads) {
             const bool valid = e0 + lane < ncell;
@@ -463,34 +466,51 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
             for (int k0 = 0; k0 < nc; k0 += kFold) {
                 const int k1 = min(nc, k0 + kFold);
                 R p[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-                R mg[3] = {0, 0, 0};
-                for (int k = k0; k < k1; ++k) {
-                    const VjpMember<R> q = s_i[k];
-                    R gr[3], gM, S[6];
-                    if (CELL_K) {
-                        CellGrad<R> cg;
-                        cell_grad<R, true, QUAD>(q.x - c.x, q.y - c.y, q.z - c.z, c.M, c.q, q.wx,
-                                                 q.wy, q.wz, q.c, vp, cg);
-                        for (int a = 0; a < 3; ++a) gr[a] = cg.gr[a];
-                        gM = cg.gM;
-                        for (int a = 0; a < 6; ++a) S[a] = cg.S[a];
-                    } else {
-                        cell_grad_far<R, QUAD>(q.x - c.x, q.y - c.y, q.z - c.z, c.M, c.q, q.wx,
-                                               q.wy, q.wz, q.c, (R)vp.eps2, gr, gM, S);
-                    }
-                    p[0] -= gr[0]; p[1] -= gr[1]; p[2] -= gr[2];
-                    p[3] += gM;
-                    if (QUAD)
-                        for (int a = 0; a < 6; ++a) p[4 + a] += S[a];
-                    const bool mine = lane == k - k0;
-                    for (int a = 0; a < 3; ++a) {
-                        const R t = last_lane(wave_sum_last(valid ? gr[a] : R(0)));
-                        mg[a] = mine ? t : mg[a];
+                R mg[2][3] = {{0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int kh = min(k1, k0 + 16 * (h + 1));
+                    for (int k = k0 + 16 * h; k < kh; ++k) {
+                        const VjpMember<R> q = s_i[k];
+                        R gr[3], gM, S[6];
+                        if (CELL_K) {
+                            CellGrad<R> cg;
+                            cell_grad<R, true, QUAD>(q.x - c.x, q.y - c.y, q.z - c.z, c.M, c.q,
+                                                     q.wx, q.wy, q.wz, q.c, vp, cg);
+                            for (int a = 0; a < 3; ++a) gr[a] = cg.gr[a];
+                            gM = cg.gM;
+                            for (int a = 0; a < 6; ++a) S[a] = cg.S[a];
+                        } else {
+                            cell_grad_far<R, QUAD>(q.x - c.x, q.y - c.y, q.z - c.z, c.M, c.q, q.wx,
+                                                   q.wy, q.wz, q.c, (R)vp.eps2, gr, gM, S);
+                        }
+                        p[0] -= gr[0]; p[1] -= gr[1]; p[2] -= gr[2];
+                        p[3] += gM;
+                        if (QUAD)
+                            for (int a = 0; a < 6; ++a) p[4 + a] += S[a];
+                        // (a massless padding cell gives dl/dr = 0 exactly)
+                        const bool mine = (lane & 15) == ((k - k0) & 15);
+                        for (int a = 0; a < 3; ++a) {
+                            const R t = row_sum(gr[a]);
+                            mg[h][a] = mine ? t : mg[h][a];
+                        }
                     }
                 }
                 for (int a = 0; a < 10; ++a) acc[a] += (double)p[a];
-                if (lane < k1 - k0)
-                    for (int a = 0; a < 3; ++a) s_gr[w][k0 + lane][a] += (double)mg[a];
+                // the four rows' parts of each member's sum: lane j of row 0
+                // then holds member k0 + 16 h + j's
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    for (int a = 0; a < 3; ++a) {
+                        R t = mg[h][a];
+                        t += __shfl_xor(t, 16, kWave);
+                        t += __shfl_xor(t, 32, kWave);
+                        mg[h][a] = t;
+                    }
+                    if (lane < 16 && k0 + 16 * h + lane < k1)
+                        for (int a = 0; a < 3; ++a)
+                            s_gr[w][k0 + 16 * h + lane][a] += (double)mg[h][a];
+                }
             }
             if (valid)
                 for (int a = 0; a < 10; ++a)
