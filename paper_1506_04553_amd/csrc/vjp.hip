@@ -23,13 +23,14 @@
 // The adjoint arithmetic takes no decisions (the lists are frozen), so unlike
 // the rest of the library it lets the compiler fuse multiply-adds.  Runs of at
 // most 32 terms are summed in R before each run's sum joins an FP64 sum; a
-// member's cell terms are summed in R over the 64 entries of a wavefront (a
-// fixed tree) before joining an FP64 sum.
+// member's cell and far-particle terms are summed in R over the 64 entries of
+// a wavefront (a fixed tree) before joining an FP64 sum.
 //
-// Two passes over each group's lists: the first sums the particle-list terms
+// Two passes over each group's lists: the first sums the near-particle terms
 // of each member; the second sums, for each list entry, the terms of all
-// members and scatters them, and evaluates each (member, cell) term only once,
-// for both sides.
+// members and scatters them, and evaluates each (member, cell) and (member,
+// far particle) term only once, for both sides.
+//
 // The pair and cell terms are evaluated in the precision of the forward pass
 // (R = double, or R = float on offsets from the group's centre taken in FP64,
 // as in the interaction kernel; K and W themselves are evaluated in FP64) and
@@ -256,7 +257,7 @@ __device__ __forceinline__ VjpCell<R> stage_cell(const NodeMP &c, const double s
 }
 
 // ---------------------------------------------------------------------------
-// Pass 1: per particle i (one group per block), the i-side particle-list terms.
+// Pass 1: per particle i (one group per block), the i-side near-particle terms.
 // ---------------------------------------------------------------------------
 // Terms are summed in R over runs of at most kFold and each run's sum is added
 // to an FP64 accumulator.
@@ -321,10 +322,10 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
         const R wx = (R)wv[3 * o], wy = (R)wv[3 * o + 1], wz = (R)wv[3 * o + 2];
         const R ci = vp.has_c ? (R)cv[o] : R(0);
         double g0 = 0, g1 = 0, g2 = 0;
-        for (int list = 0; list < 2; ++list) {        // far and near particles
-            const int32_t *idxs = L.idx[1 + list];
-            const int64_t pb = L.beg[1 + list][g];
-            const int64_t pe = L.end[1 + list][g];
+        {   // near particles (the far ones are summed by the list-entry pass)
+            const int32_t *idxs = L.idx[2];
+            const int64_t pb = L.beg[2][g];
+            const int64_t pe = L.end[2][g];
             for (int64_t t0 = pb; t0 < pe; t0 += kVjpTile) {
                 const int tl = (int)min<int64_t>(kVjpTile, pe - t0);
                 __syncthreads();
@@ -336,12 +337,8 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_i(
                     s_j[tid] = j;
                 }
                 __syncthreads();
-                if (list == 0)   // far particles: K = W = 1, never a member
-                    vjp_i_pp_tile<R, false>(s_p, s_j, tl, slice, nslice, i, xi, yi, zi, wx, wy,
-                                            wz, ci, vp, g0, g1, g2);
-                else
-                    vjp_i_pp_tile<R, true>(s_p, s_j, tl, slice, nslice, i, xi, yi, zi, wx, wy,
-                                           wz, ci, vp, g0, g1, g2);
+                vjp_i_pp_tile<R, true>(s_p, s_j, tl, slice, nslice, i, xi, yi, zi, wx, wy, wz, ci,
+                                       vp, g0, g1, g2);
             }
         }
         __syncthreads();
@@ -428,17 +425,68 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_scatter(
         }
         __syncthreads();
         for (int k = lane; k < nc; k += kWave) s_gr[w][k][0] = s_gr[w][k][1] = s_gr[w][k][2] = 0.0;
-        for (int64_t e = tid; e < np; e += kVjpThreads) {
-            const bool far = e < nf;
-            const int32_t j = far ? p_idx[fb + e] : n_idx[nb + (e - nf)];
+        // far particles (K = W = 1, never a member): a lane per entry, the
+        // members from LDS; each pair's term counts for both sides, the
+        // members' parts gathered as for the cells below.  Lanes past the end
+        // hold a massless particle far away, whose terms are exactly zero.
+        for (int64_t e0 = (int64_t)w * kWave; e0 < nf; e0 += kVjpThreads) {
+            const bool valid = e0 + lane < nf;
+            const int32_t j = valid ? p_idx[fb + e0 + lane] : 0;
+            const PosMass pj = xm[j];
+            const R xj = valid ? (R)(pj.x - sh[0]) : R(1e18), yj = valid ? (R)(pj.y - sh[1]) : R(1e18),
+                    zj = valid ? (R)(pj.z - sh[2]) : R(1e18);
+            const R mj = valid ? (R)pj.m : R(0);
+            double acc[4] = {0, 0, 0, 0};
+            for (int k0 = 0; k0 < nc; k0 += kFold) {
+                const int k1 = min(nc, k0 + kFold);
+                R p[4] = {0, 0, 0, 0};
+                R mg[2][3] = {{0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int kh = min(k1, k0 + 16 * (h + 1));
+                    for (int k = k0 + 16 * h; k < kh; ++k) {
+                        const VjpMember<R> q = s_i[k];
+                        R gd[3], gmj;
+                        pair_grad<R, false>(xj - q.x, yj - q.y, zj - q.z, mj, q.wx, q.wy, q.wz, q.c,
+                                            vp, gd, gmj);
+                        p[0] += gd[0]; p[1] += gd[1]; p[2] += gd[2]; p[3] += gmj;
+                        const bool mine = (lane & 15) == ((k - k0) & 15);
+                        for (int a = 0; a < 3; ++a) {
+                            const R t = row_sum(gd[a]);
+                            mg[h][a] = mine ? t : mg[h][a];
+                        }
+                    }
+                }
+                for (int a = 0; a < 4; ++a) acc[a] += (double)p[a];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    for (int a = 0; a < 3; ++a) {
+                        R t = mg[h][a];
+                        t += __shfl_xor(t, 16, kWave);
+                        t += __shfl_xor(t, 32, kWave);
+                        mg[h][a] = t;
+                    }
+                    if (lane < 16 && k0 + 16 * h + lane < k1)   // the member's part: -dl/dd
+                        for (int a = 0; a < 3; ++a)
+                            s_gr[w][k0 + 16 * h + lane][a] -= (double)mg[h][a];
+                }
+            }
+            if (valid) {
+                atomicAdd(&gx[j], acc[0]);
+                atomicAdd(&gx[n + j], acc[1]);
+                atomicAdd(&gx[2 * n + j], acc[2]);
+                atomicAdd(&gm[j], acc[3]);
+            }
+        }
+        // near particles (the list may hold a member): a lane per entry, this
+        // side only
+        for (int64_t e = nf + tid; e < np; e += kVjpThreads) {
+            const int32_t j = n_idx[nb + (e - nf)];
             const PosMass pj = xm[j];
             const R xj = (R)(pj.x - sh[0]), yj = (R)(pj.y - sh[1]), zj = (R)(pj.z - sh[2]);
             const R mj = (R)pj.m;
             double acc[4] = {0, 0, 0, 0};
-            if (far)   // K = W = 1, never a member
-                vjp_scatter_pp<R, false>(s_i, s_id, nc, j, xj, yj, zj, mj, vp, acc);
-            else
-                vjp_scatter_pp<R, true>(s_i, s_id, nc, j, xj, yj, zj, mj, vp, acc);
+            vjp_scatter_pp<R, true>(s_i, s_id, nc, j, xj, yj, zj, mj, vp, acc);
             atomicAdd(&gx[j], acc[0]);
             atomicAdd(&gx[n + j], acc[1]);
             atomicAdd(&gx[2 * n + j], acc[2]);
