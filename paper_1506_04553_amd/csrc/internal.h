@@ -97,6 +97,7 @@ struct p3t_ctx {
     int64_t level_start[p3t::kLevels + 2] = {0};
     int walk_global = 0, walk_fixed = 0;
     int32_t walk_lds_cap = 0;   // entries of the walk's LDS stack to use (0: all of it)
+    bool groups_generic = false;  // groups compacted by a plain scan (as for the largest n)
     // sizes seen by the last two-pass or fixed-stride walk, used to reserve
     // fixed-stride list segments on the next build
     int64_t hint_groups = 0, hint_max[3] = {0, 0, 0};

@@ -156,6 +156,9 @@ extern "C" int p3t_create(p3t_ctx **out, int device, void *hip_stream, p3t_alloc
     ctx->user = alloc_user;
     // P3T_WALK_LDS_STACK=k (k >= 64) caps the walk's on-chip stack at k entries
     if (const char *ev = getenv("P3T_WALK_LDS_STACK")) ctx->walk_lds_cap = atoi(ev);
+    // P3T_GROUPS_GENERIC=1 takes the group compaction of the largest inputs
+    // (a plain scan of the flags, then the records) at any size
+    if (const char *ev = getenv("P3T_GROUPS_GENERIC")) ctx->groups_generic = atoi(ev) > 0;
     if (device >= kMaxDevices) {
         delete ctx;
         return P3T_EINVAL;

@@ -385,6 +385,12 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
     if (LAST && blockIdx.x == 0 && tid == 0) so.gflag[n] = 0;
 }
 
+// The moments folds count the groups per particle tile for the group scan when
+// the particles fit kScan2MaxTiles tiles (n + 1 flags).
+static bool group_tiles_counted(const p3t_ctx *ctx, int64_t n) {
+    return !ctx->groups_generic && (n + 1 + kScan2Tile - 1) / kScan2Tile <= kScan2MaxTiles;
+}
+
 // Root cube, keys, the kRsPasses radix passes, and the sorted particle
 // records: the first digit's histogram comes with the keys, the records with
 // the last pass.
@@ -666,7 +672,7 @@ int build_topology(p3t_ctx *ctx, int64_t n) {
     int32_t *blk = ptr<int32_t>(ctx->tblk), *blk_off = ptr<int32_t>(ctx->tblk_off);
     // the groups' per-tile counts (for the compaction's scan), when it fits one
     const int64_t n_gtile = (n + 1 + kScan2Tile - 1) / kScan2Tile;
-    const bool gcount = n_gtile <= kScan2MaxTiles;
+    const bool gcount = group_tiles_counted(ctx, n);
     if (gcount && (rc = ensure(ctx, ctx->gtile, n_gtile * sizeof(int32_t)))) return rc;
     k_topo_ranges<<<nb, kTopoThreads, 0, ctx->stream>>>(
         keys, n, ctx->prm.n_leaf, ptr<int32_t>(ctx->lvlrange), blk, nb,
@@ -1036,8 +1042,7 @@ int build_moments(p3t_ctx *ctx) {
     // per-particle range codes are dead and their array holds node_at
     A.gflag = ptr<int32_t>(ctx->gflag);
     A.node_at = ptr<int32_t>(ctx->lvlrange);
-    A.gtile = (ctx->n + 1 + kScan2Tile - 1) / kScan2Tile <= kScan2MaxTiles ? ptr<int32_t>(ctx->gtile)
-                                                                          : nullptr;
+    A.gtile = group_tiles_counted(ctx, ctx->n) ? ptr<int32_t>(ctx->gtile) : nullptr;
     A.walk_zero = ptr<int64_t>(ctx->readback) + kRbWalk;
     LevelStarts ls;
     for (int l = 0; l <= kLevels; ++l) ls.s[l] = ctx->level_start[l];
@@ -1118,7 +1123,7 @@ int build_groups(p3t_ctx *ctx) {
     // the group nodes were flagged by the moments folds; slot[n] = number of
     // groups (device), read back together with the list sizes
     const int64_t tiles = (n + 1 + kScan2Tile - 1) / kScan2Tile;
-    if (tiles <= kScan2MaxTiles) {
+    if (group_tiles_counted(ctx, n)) {
         // the folds counted the groups per tile; the scan places the group
         // records itself
         k_scan2_tiles<int32_t><<<(unsigned)tiles, kScan2Threads, 0, ctx->stream>>>(

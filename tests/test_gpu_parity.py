@@ -187,6 +187,12 @@ def _edge_cases():
     # must still be left out of the potential
     cases["eps_beyond_rout"] = (plummer(1500, 20).pos, np.full(1500, 1 / 1500),
                                 dict(base, eps=0.03))
+    # leaves of more than 64 particles: the topology searches the sorted keys
+    # instead of reading a window of them
+    cases["leaf100"] = (plummer(3000, 21).pos, np.full(3000, 1 / 3000),
+                        dict(base, n_crit=256, n_leaf=100))
+    cases["duplicates_leaf80"] = (dup, np.full(len(dup), 1.0 / len(dup)),
+                                  dict(base, n_crit=128, n_leaf=80))
     return cases
 
 
@@ -295,6 +301,28 @@ def test_walk_global_stack_path(monkeypatch):
         compare_neighbors(g, t)
         _check_forces(g, acc, pot, FP64_TOL, f"global stack walk {k}")
     small.close()
+
+
+def test_groups_generic_path(monkeypatch):
+    """The group compaction of the largest inputs (a plain scan of the group
+    flags, then the records), forced at a small size: groups, lists and forces
+    must still match the oracle, in both the two-pass and the fixed-stride walk."""
+    from paper_1506_04553_amd import P3T
+    w = WORKLOADS["plummer64k_salpeter"]
+    c = make_cluster(w, seed=7)
+    p = _params(w, precision="fp64")
+    t = oracle.Tree(c.pos, c.mass, p)
+    acc, pot = t.force()
+    monkeypatch.setenv("P3T_GROUPS_GENERIC", "1")
+    gen = P3T(0)
+    monkeypatch.delenv("P3T_GROUPS_GENERIC")
+    for k in range(2):
+        g = gpu_run(gen, c.pos, c.mass, p)
+        assert g["stats"]["walk_fixed_stride"] == k
+        compare_tree(g, t)
+        compare_neighbors(g, t)
+        _check_forces(g, acc, pot, FP64_TOL, f"generic group compaction {k}")
+    gen.close()
 
 
 def test_forward_is_deterministic(ctx):
