@@ -177,7 +177,9 @@ extern "C" int p3t_create(p3t_ctx **out, int device, void *hip_stream, p3t_alloc
         }
         ctx->scratch = g_scratch_ptr[device];
     }
-    hipError_t e = hipHostMalloc((void **)&ctx->hpin, 64 * sizeof(int64_t), hipHostMallocDefault);
+    // coherent: some kernels write their few result words straight into it,
+    // read by the host after the stream's synchronisation
+    hipError_t e = hipHostMalloc((void **)&ctx->hpin, 64 * sizeof(int64_t), hipHostMallocCoherent);
     for (int k = 0; k < 12 && e == hipSuccess; ++k) e = hipEventCreate(&ctx->ev[k]);
     if (e != hipSuccess) {
         p3t_destroy(ctx);

@@ -492,15 +492,6 @@ __device__ __forceinline__ int64_t gallop_upper_key(const uint64_t *keys, int64_
     return a;
 }
 
-__device__ __forceinline__ int64_t upper_bound_key(const uint64_t *keys, int64_t lo, int64_t hi,
-                                                   uint64_t v) {
-    while (lo < hi) {
-        int64_t mid = lo + ((hi - lo) >> 1);
-        if (keys[mid] <= v) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
 // range code: lo | hi << 8, or -1 when no node starts at a
 // Up to this leaf size the topology kernels read their keys from an on-chip
 // window (the block's keys and n_leaf on either side) instead of searching.
