@@ -241,12 +241,14 @@ __device__ __forceinline__ void pc_term(Slot<R> &q, const CJ<R> &c, R eps2, R ro
 // one or two active i-slots (TWO), so that the loop bodies carry no branch on
 // the slot count.  The FP64 loops are unrolled deeper (four entries): their
 // pipe otherwise waits on FP64 latencies.
+// A slice's entries are consecutive in LDS (the tile is stored slice by
+// slice), so unrolled iterations read at immediate offsets from one address.
 // Trip counts are wave-uniform: lanes past the end of a tile read the padding
 // entries (zero mass, far away), whose terms are exactly zero.
 template <class R, bool TWO>
-__device__ __forceinline__ void far_tile(Slot<R> *q, const PJ<R> *sp, int iters, int ns, R eps2) {
+__device__ __forceinline__ void far_tile(Slot<R> *q, const PJ<R> *sp, int iters, R eps2) {
 #pragma unroll(sizeof(R) == 8 ? 4 : 2)
-    for (int it = 0; it < iters; ++it, sp += ns) {
+    for (int it = 0; it < iters; ++it, ++sp) {
         const PJ<R> pj = *sp;
         pp_fast<R>(q[0], pj, eps2);
         if (TWO) pp_fast<R>(q[1], pj, eps2);
@@ -255,8 +257,8 @@ __device__ __forceinline__ void far_tile(Slot<R> *q, const PJ<R> *sp, int iters,
 
 template <class R, bool TWO>
 __device__ __forceinline__ void near_tile(Slot<R> *q, const PJ<R> *sp, const int32_t *sj, int iters,
-                                          int ns, R eps2, R rout2, const ForceParams &fp) {
-    for (int it = 0; it < iters; ++it, sp += ns, sj += ns) {
+                                          R eps2, R rout2, const ForceParams &fp) {
+    for (int it = 0; it < iters; ++it, ++sp, ++sj) {
         const PJ<R> pj = *sp;
         // the changeover path where s < r_out, and for a particle's own pair
         // (zero offset: s^2 = eps^2 exactly), which only that path discards, also
@@ -281,10 +283,10 @@ __device__ __forceinline__ void near_tile(Slot<R> *q, const PJ<R> *sp, const int
 }
 
 template <class R, bool QUAD, bool CHECK_K, bool TWO>
-__device__ __forceinline__ void cell_tile(Slot<R> *q, const CJ<R> *sc, int iters, int ns, R eps2,
-                                          R rout2, const ForceParams &fp) {
+__device__ __forceinline__ void cell_tile(Slot<R> *q, const CJ<R> *sc, int iters, R eps2, R rout2,
+                                          const ForceParams &fp) {
 #pragma unroll(sizeof(R) == 8 ? 4 : 2)
-    for (int it = 0; it < iters; ++it, sc += ns) {
+    for (int it = 0; it < iters; ++it, ++sc) {
         const CJ<R> cj = *sc;
         pc_term<R, QUAD, CHECK_K>(q[0], cj, eps2, rout2, fp);
         if (TWO) pc_term<R, QUAD, CHECK_K>(q[1], cj, eps2, rout2, fp);
@@ -297,7 +299,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 4 : 1))) void k_force(
     const GroupInfo *__restrict__ grp, ListsDev L, const PosMass *__restrict__ xm,
     const NodeMP *__restrict__ mp, const int32_t *__restrict__ perm, ForceParams fp,
     double *__restrict__ acc, double *__restrict__ pot) {
-    // tile + padding read by lanes past the tile end (zero mass, far away)
+    // one tile, stored slice by slice (see below)
     __shared__ PJ<R> s_p[kTile + kWave];
     __shared__ int32_t s_jid[kTile + kWave];
     __shared__ CJ<R> s_c[kTile + kWave];
@@ -318,16 +320,20 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 4 : 1))) void k_force(
     const int32_t *__restrict__ n_idx = L.idx[2];
     const R eps2 = (R)fp.eps2, rout2 = (R)fp.rout2;
 
-    if (w == 0) {
-        s_p[kTile + lane] = zero_p;
-        s_jid[kTile + lane] = -2;
-        s_c[kTile + lane] = zero_c;
-    }
     const int ls = choose_log2_slices(gi.count, 2 * kForceWaves);
     const int ns = 1 << ls;
     const int nw = kWave >> ls;                 // i-particles per virtual wavefront
     const int il = lane & (nw - 1), slice = lane >> (6 - ls);
     const int V = (gi.count + nw - 1) / nw;
+    // Tile entry e belongs to slice e mod ns, as its (e / ns)-th entry; it is
+    // stored at (e mod ns) S + e / ns, S = kTile / ns + 1, so each slice's
+    // entries are consecutive (one spare slot per slice staggers the slices
+    // over the LDS banks).  Entries past a tile's end are staged as padding,
+    // and no slice reads beyond kTile / ns entries, so every slot read holds
+    // an entry or padding; ns S <= kTile + kWave.
+    const int S = (kTile >> ls) + 1;
+    const int spos = (tid & (ns - 1)) * S + (tid >> ls);   // this thread's staging slot
+    const int sbase = slice * S;                            // this lane's slice
 
     for (int v0 = 0; v0 < V; v0 += 2 * kForceWaves) {
         // this wavefront's two virtual wavefronts (i-slots) in this round
@@ -374,8 +380,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 4 : 1))) void k_force(
             for (int64_t t0 = b; t0 < e; t0 += kTile) {
                 const int tl = (int)min<int64_t>(kTile, e - t0);
                 __syncthreads();
-                s_p[tid] = pre;
-                s_jid[tid] = prej;
+                s_p[spos] = pre;
+                s_jid[spos] = prej;
                 __syncthreads();
                 if (t0 + kTile + tid < e) {
                     prej = list[t0 + kTile + tid];
@@ -391,14 +397,14 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 4 : 1))) void k_force(
         };
         // far particles: K = W = 1 and j != i, plain softened terms
         stream_particles(p_idx, pb, pe, [&](int iters) {
-            if (act1) far_tile<R, true>(q, s_p + slice, iters, ns, eps2);
-            else if (act0) far_tile<R, false>(q, s_p + slice, iters, ns, eps2);
+            if (act1) far_tile<R, true>(q, s_p + sbase, iters, eps2);
+            else if (act0) far_tile<R, false>(q, s_p + sbase, iters, eps2);
         });
         // near particles: changeover and self exclusion where s < r_out
         stream_particles(n_idx, nb, ne, [&](int iters) {
-            if (act1) near_tile<R, true>(q, s_p + slice, s_jid + slice, iters, ns, eps2, rout2, fp);
+            if (act1) near_tile<R, true>(q, s_p + sbase, s_jid + sbase, iters, eps2, rout2, fp);
             else if (act0)
-                near_tile<R, false>(q, s_p + slice, s_jid + slice, iters, ns, eps2, rout2, fp);
+                near_tile<R, false>(q, s_p + sbase, s_jid + sbase, iters, eps2, rout2, fp);
         });
 
         // ---- particle-cell terms ----
@@ -415,14 +421,14 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 4 : 1))) void k_force(
             for (int64_t t0 = cb; t0 < ce; t0 += kTile) {
                 const int tl = (int)min<int64_t>(kTile, ce - t0);
                 __syncthreads();
-                s_c[tid] = pre;
+                s_c[spos] = pre;
                 __syncthreads();
                 pre = (t0 + kTile + tid < ce) ? load_cell(t0 + kTile + tid) : zero_c;
                 const int iters = (tl + ns - 1) >> ls;
                 if (act1)
-                    cell_tile<R, QUAD, CHECK_K, true>(q, s_c + slice, iters, ns, eps2, rout2, fp);
+                    cell_tile<R, QUAD, CHECK_K, true>(q, s_c + sbase, iters, eps2, rout2, fp);
                 else if (act0)
-                    cell_tile<R, QUAD, CHECK_K, false>(q, s_c + slice, iters, ns, eps2, rout2, fp);
+                    cell_tile<R, QUAD, CHECK_K, false>(q, s_c + sbase, iters, eps2, rout2, fp);
                 fold(iters, t0 + kTile >= ce);
             }
         }
