@@ -19,8 +19,10 @@
  *     on the context's device; "host" pointers are ordinary host memory;
  *   - positions/accelerations are row-major [n][3] float64, masses/potentials
  *     [n] float64, whatever the precision mode;
- *   - all work is enqueued on the context's stream; calls that must read a
- *     size back (p3t_build_tree, p3t_neighbors) synchronise that stream;
+ *   - all work is enqueued on the context's stream, except the neighbour
+ *     search of p3t_neighbors, which runs on a second stream of the context
+ *     (see there); calls that must read a size back (p3t_build_tree,
+ *     p3t_neighbors) synchronise;
  *   - a context is not thread-safe; use one per host thread;
  *   - every call returns P3T_OK (0) or a negative P3T_E* status; on error the
  *     caller's output buffers are left untouched and p3t_last_error() holds a
@@ -127,8 +129,13 @@ int p3t_long_force(p3t_ctx *ctx, double *acc, double *pot);
  * isolated iff offsets[i+1] == offsets[i].
  *   offsets  device [n+1] int64 out;  idx  device [cap] int32 out
  *   nnz      host out: number of pairs (set also when ECAPACITY is returned)
- * Synchronises the stream.  Errors: ESTATE, EINVAL, ECAPACITY (cap < nnz:
- * offsets and idx untouched), EHIP. */
+ * The search runs on a second stream of the context, from the point where the
+ * last build's lists were complete, beside whatever the context's stream is
+ * still running (it reads only the tree and the lists, and writes workspaces
+ * of its own); the call waits for the search alone, then writes offsets and
+ * idx on the context's stream, which runs everything queued after the call
+ * after the search.  Errors: ESTATE, EINVAL, ECAPACITY (cap < nnz: offsets and
+ * idx untouched), EHIP. */
 int p3t_neighbors(p3t_ctx *ctx, int64_t *offsets, int32_t *idx, int64_t cap, int64_t *nnz);
 
 /* Vector-Jacobian product of L = sum_i w_i . a_i + c_i phi_i with respect to

@@ -115,7 +115,7 @@ struct p3t_ctx {
         node_prefix, node_S, node_walk, node_mp;
     p3t::DevBuf gflag, gscan, grp;
     p3t::DevBuf cnt, off, c_idx, p_idx, n_idx;
-    p3t::DevBuf wstack, readback, scan_tmp, nbr_cnt, nbr_slots;
+    p3t::DevBuf wstack, readback, scan_tmp, nbr_cnt, nbr_slots, nbr_scan;
     p3t::DevBuf vjp_gx, vjp_gm, vjp_cell, bbox;
     p3t::DevBuf seg_end, gorder, grank, ghist;
     p3t::DevBuf hard_ix, hard_state;   // hard part: components and integrator state
@@ -123,6 +123,11 @@ struct p3t_ctx {
     hipStream_t aux[4] = {nullptr, nullptr, nullptr, nullptr};   // hard part's concurrent classes
     hipEvent_t aev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     int aux_ready = 0;
+    // The neighbour search runs on its own stream from the point where the
+    // lists are complete (ev_lists, recorded on `stream` by every walk), beside
+    // whatever the context's stream does meanwhile; ev_sync orders the two.
+    hipStream_t nbr_stream = nullptr;
+    hipEvent_t ev_lists = nullptr, ev_sync[2] = {nullptr, nullptr};
     p3t::DevBuf step_off, step_idx;    // neighbour CSR of p3t_step
     p3t::DevBuf step_off2, step_idx2;  // ... merged with the special particles' pairs
     p3t::DevBuf kinds_cnt;
@@ -144,6 +149,11 @@ int check_hip(p3t_ctx *ctx, hipError_t e, const char *what);
 // null) receives the sum of all n inputs.
 int scan_exclusive_i64(p3t_ctx *ctx, const int64_t *in, int64_t *out, int64_t n, int64_t *total);
 int scan_exclusive_i32(p3t_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, int32_t *total);
+// The same on stream st with the workspace tmp (at least scan_tmp_bytes(n)
+// bytes, so that the call allocates nothing).
+size_t scan_tmp_bytes(int64_t n);
+int scan_exclusive_i64_on(p3t_ctx *ctx, hipStream_t st, DevBuf &tmp, const int64_t *in,
+                          int64_t *out, int64_t n, int64_t *total);
 // Exclusive prefix sum of each row of a [rows][cols] array (one block per
 // row, one launch); totals[r] receives the sum of row r.
 int scan_rows_i32(p3t_ctx *ctx, const int32_t *in, int32_t *out, int32_t *totals, int rows,
@@ -175,8 +185,11 @@ int build_lists(p3t_ctx *ctx, bool stats_cleared);
 // Interactions (force.hip).
 int launch_force(p3t_ctx *ctx, double *acc, double *pot);
 
-// Neighbour lists (neighbors.hip).
-int launch_neighbors(p3t_ctx *ctx, int64_t *offsets, int32_t *idx, int64_t cap, int64_t *nnz);
+// Neighbour lists (neighbors.hip).  The search and the row count run on
+// ctx->nbr_stream, between the timing events t0 and t1 (either may be null);
+// the caller's arrays are written on ctx->stream after them.
+int launch_neighbors(p3t_ctx *ctx, int64_t *offsets, int32_t *idx, int64_t cap, int64_t *nnz,
+                     hipEvent_t t0, hipEvent_t t1);
 
 // VJP (vjp.hip).  launch_vjp takes its workspaces from the context;
 // launch_vjp_ws from the caller: gx [3 n], gm [n] and cadj [10 n_nodes] doubles

@@ -182,34 +182,59 @@ __global__ void k_sort_rows(int64_t n, const int64_t *__restrict__ off, int64_t 
 // readback slots (int64 units) used here: neighbour total, overflow flag, longest row
 enum { RB_NNZ = 40, RB_NOVF = 41, RB_NMAX = 42 };
 
-int launch_neighbors(p3t_ctx *ctx, int64_t *offsets, int32_t *idx, int64_t cap, int64_t *nnz) {
+// The search, the scan of the row lengths and their readback run on the
+// context's second stream as soon as the walk's lists are complete, beside the
+// interaction kernel or whatever else the context's stream runs meanwhile: it
+// only reads the tree and the lists and writes workspaces of its own.  The
+// host waits for that stream alone; the rows are then packed into the
+// caller's arrays on the context's stream, after the search.
+int launch_neighbors(p3t_ctx *ctx, int64_t *offsets, int32_t *idx, int64_t cap, int64_t *nnz,
+                     hipEvent_t t0, hipEvent_t t1) {
     int rc;
     const int64_t n = ctx->n;
-    hipStream_t st = ctx->stream;
+    hipStream_t st = ctx->stream, as = ctx->nbr_stream;
+    const unsigned grid = (unsigned)ctx->n_groups;
+    if (grid == 0) return set_error(ctx, P3T_ESTATE, "no groups");
+    const int32_t row_cap = ctx->nbr_cap > 0 ? ctx->nbr_cap : kNbrFirstCap;
+    // A workspace (re)allocated here may come from an allocator that hands out
+    // memory which work still queued on the context's stream uses: the search
+    // then also waits for that work.
+    void *const had[3] = {ctx->nbr_cnt.p, ctx->nbr_slots.p, ctx->nbr_scan.p};
     if ((rc = ensure(ctx, ctx->nbr_cnt, (n + 1) * sizeof(int64_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->nbr_slots, (size_t)n * row_cap * sizeof(int32_t) + 4))) return rc;
+    if ((rc = ensure(ctx, ctx->nbr_scan, scan_tmp_bytes(n + 1)))) return rc;
+    const bool fresh = had[0] != ctx->nbr_cnt.p || had[1] != ctx->nbr_slots.p ||
+                       had[2] != ctx->nbr_scan.p;
     int64_t *cnt = ptr<int64_t>(ctx->nbr_cnt);
     int64_t *rb = ptr<int64_t>(ctx->readback);
     const ListsDev L = lists_dev(ctx);
     const double h2 = ctx->prm.r_search * ctx->prm.r_search;
-    const unsigned grid = (unsigned)ctx->n_groups;
-    const int32_t row_cap = ctx->nbr_cap > 0 ? ctx->nbr_cap : kNbrFirstCap;
-    if ((rc = ensure(ctx, ctx->nbr_slots, (size_t)n * row_cap * sizeof(int32_t) + 4))) return rc;
     // every particle's count is written (groups partition the particles), and
     // the entry past the last one, which takes part in the scan, is zeroed;
     // the longest row and the overflow flag carry this call's tag (the slots
     // were cleared once, when the readback area was allocated)
     const unsigned long long tag = ++ctx->nbr_tag;
     auto *rbu = reinterpret_cast<unsigned long long *>(rb);
-    if (grid == 0) return set_error(ctx, P3T_ESTATE, "no groups");
-    k_neighbors<false><<<grid, kNbrThreads, 0, st>>>(
+    if ((rc = check_hip(ctx, hipStreamWaitEvent(as, ctx->ev_lists, 0), "wait"))) return rc;
+    if (fresh) {
+        if ((rc = check_hip(ctx, hipEventRecord(ctx->ev_sync[0], st), "event record"))) return rc;
+        if ((rc = check_hip(ctx, hipStreamWaitEvent(as, ctx->ev_sync[0], 0), "wait"))) return rc;
+    }
+    if (t0 && (rc = check_hip(ctx, hipEventRecord(t0, as), "event record"))) return rc;
+    k_neighbors<false><<<grid, kNbrThreads, 0, as>>>(
         ptr<GroupInfo>(ctx->grp), L, ptr<PosMass>(ctx->xm), ptr<int32_t>(ctx->vals[0]), h2, row_cap,
         ptr<int32_t>(ctx->nbr_slots), nullptr, cnt, n, tag, rbu + RB_NMAX, rbu + RB_NOVF);
     if ((rc = check_hip(ctx, hipGetLastError(), "neighbours"))) return rc;
-    if ((rc = scan_exclusive_i64(ctx, cnt, cnt, n + 1, rb + RB_NNZ))) return rc;
-    if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + RB_NNZ, rb + RB_NNZ, 3 * sizeof(int64_t),
-                                            hipMemcpyDeviceToHost, st), "readback")))
+    if ((rc = scan_exclusive_i64_on(ctx, as, ctx->nbr_scan, cnt, cnt, n + 1, rb + RB_NNZ)))
         return rc;
-    if ((rc = check_hip(ctx, hipStreamSynchronize(st), "sync"))) return rc;
+    if ((rc = check_hip(ctx, hipMemcpyAsync(ctx->hpin + RB_NNZ, rb + RB_NNZ, 3 * sizeof(int64_t),
+                                            hipMemcpyDeviceToHost, as), "readback")))
+        return rc;
+    if (t1 && (rc = check_hip(ctx, hipEventRecord(t1, as), "event record"))) return rc;
+    if ((rc = check_hip(ctx, hipEventRecord(ctx->ev_sync[1], as), "event record"))) return rc;
+    if ((rc = check_hip(ctx, hipStreamSynchronize(as), "sync"))) return rc;
+    // what follows on the context's stream comes after the search
+    if ((rc = check_hip(ctx, hipStreamWaitEvent(st, ctx->ev_sync[1], 0), "wait"))) return rc;
     const int64_t total = ctx->hpin[RB_NNZ];
     const auto *hu = reinterpret_cast<const unsigned long long *>(ctx->hpin);
     const bool over = hu[RB_NOVF] == tag;

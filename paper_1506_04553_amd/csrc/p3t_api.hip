@@ -181,6 +181,10 @@ extern "C" int p3t_create(p3t_ctx **out, int device, void *hip_stream, p3t_alloc
     // read by the host after the stream's synchronisation
     hipError_t e = hipHostMalloc((void **)&ctx->hpin, 64 * sizeof(int64_t), hipHostMallocCoherent);
     for (int k = 0; k < 12 && e == hipSuccess; ++k) e = hipEventCreate(&ctx->ev[k]);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->nbr_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_lists, hipEventDisableTiming);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k)
+        e = hipEventCreateWithFlags(&ctx->ev_sync[k], hipEventDisableTiming);
     if (e != hipSuccess) {
         p3t_destroy(ctx);
         return P3T_EHIP;
@@ -194,6 +198,7 @@ extern "C" void p3t_destroy(p3t_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
+    if (ctx->nbr_stream) (void)hipStreamSynchronize(ctx->nbr_stream);
     DevBuf *bufs[] = {&ctx->root, &ctx->keys[0], &ctx->keys[1], &ctx->vals[0], &ctx->vals[1],
                       &ctx->hist, &ctx->histc, &ctx->rs_tot, &ctx->xm, &ctx->xm_in, &ctx->lvlrange,
                       &ctx->tblk, &ctx->tblk_off, &ctx->gtile, &ctx->node_level, &ctx->node_first,
@@ -201,7 +206,7 @@ extern "C" void p3t_destroy(p3t_ctx *ctx) {
                       &ctx->node_prefix, &ctx->node_S, &ctx->node_walk, &ctx->node_mp, &ctx->gflag,
                       &ctx->gscan, &ctx->grp, &ctx->cnt, &ctx->off, &ctx->c_idx, &ctx->p_idx,
                       &ctx->n_idx, &ctx->wstack, &ctx->readback, &ctx->scan_tmp,
-                      &ctx->nbr_cnt, &ctx->nbr_slots, &ctx->vjp_gx, &ctx->vjp_gm, &ctx->vjp_cell, &ctx->bbox,
+                      &ctx->nbr_cnt, &ctx->nbr_slots, &ctx->nbr_scan, &ctx->vjp_gx, &ctx->vjp_gm, &ctx->vjp_cell, &ctx->bbox,
                       &ctx->seg_end, &ctx->gorder, &ctx->grank, &ctx->ghist, &ctx->hard_ix,
                       &ctx->hard_state, &ctx->step_off, &ctx->step_idx, &ctx->step_off2,
                       &ctx->step_idx2, &ctx->kinds_cnt, &ctx->hard_giant};
@@ -216,6 +221,10 @@ extern "C" void p3t_destroy(p3t_ctx *ctx) {
         }
     for (int k = 0; k < 5; ++k)
         if (ctx->aev[k]) (void)hipEventDestroy(ctx->aev[k]);
+    if (ctx->nbr_stream) (void)hipStreamDestroy(ctx->nbr_stream);
+    if (ctx->ev_lists) (void)hipEventDestroy(ctx->ev_lists);
+    for (int k = 0; k < 2; ++k)
+        if (ctx->ev_sync[k]) (void)hipEventDestroy(ctx->ev_sync[k]);
     delete ctx;
 }
 
@@ -308,9 +317,10 @@ extern "C" int p3t_neighbors(p3t_ctx *ctx, int64_t *offsets, int32_t *idx, int64
     int rc = check_hip(ctx, hipSetDevice(ctx->device), "set device");
     if (rc) return rc;
     if ((rc = ensure_lists(ctx))) return rc;
-    if ((rc = mark(ctx, EV_NBR))) return rc;
-    if ((rc = launch_neighbors(ctx, offsets, idx, cap, nnz))) return rc;
-    if ((rc = mark(ctx, EV_NBR + 1))) return rc;
+    // timed on the search's own stream (the packing into the caller's arrays,
+    // on the context's stream, is not included)
+    if ((rc = launch_neighbors(ctx, offsets, idx, cap, nnz, ctx->ev[EV_NBR], ctx->ev[EV_NBR + 1])))
+        return rc;
     ctx->ms_nbr = -1.0;
     return P3T_OK;
 }
@@ -465,11 +475,12 @@ static int step_neighbors(p3t_ctx *ctx, int64_t n_rows, int64_t *nnz) {
         if ((rc = ensure(ctx, ctx->step_idx, (size_t)n_rows * sizeof(int32_t)))) return rc;
         cap = (int64_t)(ctx->step_idx.bytes / sizeof(int32_t));
     }
-    rc = launch_neighbors(ctx, ptr<int64_t>(ctx->step_off), ptr<int32_t>(ctx->step_idx), cap, nnz);
+    rc = launch_neighbors(ctx, ptr<int64_t>(ctx->step_off), ptr<int32_t>(ctx->step_idx), cap, nnz,
+                          nullptr, nullptr);
     if (rc == P3T_ECAPACITY) {
         if ((rc = ensure(ctx, ctx->step_idx, (size_t)*nnz * sizeof(int32_t)))) return rc;
         rc = launch_neighbors(ctx, ptr<int64_t>(ctx->step_off), ptr<int32_t>(ctx->step_idx), *nnz,
-                              nnz);
+                              nnz, nullptr, nullptr);
     }
     return rc;
 }

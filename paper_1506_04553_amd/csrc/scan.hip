@@ -61,47 +61,56 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(T *out, int64_t n, co
 }
 
 template <class T>
-static int scan_rec(p3t_ctx *ctx, const T *in, T *out, int64_t n, T *total, T *tmp) {
+static int scan_rec(p3t_ctx *ctx, hipStream_t st, const T *in, T *out, int64_t n, T *total,
+                    T *tmp) {
     if (n <= 0) {
-        if (total) return check_hip(ctx, hipMemsetAsync(total, 0, sizeof(T), ctx->stream), "scan");
+        if (total) return check_hip(ctx, hipMemsetAsync(total, 0, sizeof(T), st), "scan");
         return P3T_OK;
     }
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     if (nb == 1) {
-        k_scan_tile<T><<<1, kScanThreads, 0, ctx->stream>>>(in, out, n, nullptr, total);
+        k_scan_tile<T><<<1, kScanThreads, 0, st>>>(in, out, n, nullptr, total);
         return check_hip(ctx, hipGetLastError(), "scan tile");
     }
     T *sums = tmp;
-    k_scan_tile<T><<<(unsigned)nb, kScanThreads, 0, ctx->stream>>>(in, out, n, sums, nullptr);
+    k_scan_tile<T><<<(unsigned)nb, kScanThreads, 0, st>>>(in, out, n, sums, nullptr);
     int rc = check_hip(ctx, hipGetLastError(), "scan tile");
     if (rc) return rc;
-    rc = scan_rec<T>(ctx, sums, sums, nb, total, tmp + nb);
+    rc = scan_rec<T>(ctx, st, sums, sums, nb, total, tmp + nb);
     if (rc) return rc;
-    k_scan_add<T><<<(unsigned)nb, kScanThreads, 0, ctx->stream>>>(out, n, sums);
+    k_scan_add<T><<<(unsigned)nb, kScanThreads, 0, st>>>(out, n, sums);
     return check_hip(ctx, hipGetLastError(), "scan add");
 }
 
-template <class T>
-static int scan_any(p3t_ctx *ctx, const T *in, T *out, int64_t n, T *total) {
-    const int64_t tiles = (n + kScan2Tile - 1) / kScan2Tile;
-    if (n > 0 && tiles <= kScan2MaxTiles) {
-        int rc = ensure(ctx, ctx->scan_tmp, (size_t)(tiles + 1) * sizeof(int64_t));
-        if (rc) return rc;
-        T *sums = ptr<T>(ctx->scan_tmp);
-        k_scan2_sums<T><<<(unsigned)tiles, kScanThreads, 0, ctx->stream>>>(in, n, sums);
-        k_scan2_tiles<T><<<(unsigned)tiles, kScanThreads, 0, ctx->stream>>>(
-            in, n, sums, total, StoreExclusive<T>{out});
-        return check_hip(ctx, hipGetLastError(), "scan");
-    }
-    // scratch: sum over recursion levels of the block counts
+static bool scan_two_pass(int64_t n) {
+    return n > 0 && (n + kScan2Tile - 1) / kScan2Tile <= kScan2MaxTiles;
+}
+
+size_t scan_tmp_bytes(int64_t n) {
+    if (scan_two_pass(n)) return (size_t)((n + kScan2Tile - 1) / kScan2Tile + 1) * sizeof(int64_t);
+    // the recursive scan: sum over recursion levels of the block counts
     int64_t need = 0, m = n;
     while (m > kScanTile) {
         m = (m + kScanTile - 1) / kScanTile;
         need += m;
     }
-    int rc = ensure(ctx, ctx->scan_tmp, (size_t)(need + 1) * sizeof(int64_t));
+    return (size_t)(need + 1) * sizeof(int64_t);
+}
+
+template <class T>
+static int scan_any(p3t_ctx *ctx, hipStream_t st, DevBuf &tmp, const T *in, T *out, int64_t n,
+                    T *total) {
+    int rc = ensure(ctx, tmp, scan_tmp_bytes(n));
     if (rc) return rc;
-    return scan_rec<T>(ctx, in, out, n, total, ptr<T>(ctx->scan_tmp));
+    if (scan_two_pass(n)) {
+        const unsigned tiles = (unsigned)((n + kScan2Tile - 1) / kScan2Tile);
+        T *sums = ptr<T>(tmp);
+        k_scan2_sums<T><<<tiles, kScanThreads, 0, st>>>(in, n, sums);
+        k_scan2_tiles<T><<<tiles, kScanThreads, 0, st>>>(in, n, sums, total,
+                                                         StoreExclusive<T>{out});
+        return check_hip(ctx, hipGetLastError(), "scan");
+    }
+    return scan_rec<T>(ctx, st, in, out, n, total, ptr<T>(tmp));
 }
 
 // Block r: exclusive scan of row r in chunks of kScanThreads with a running carry.
@@ -139,11 +148,16 @@ int scan_rows_i32(p3t_ctx *ctx, const int32_t *in, int32_t *out, int32_t *totals
 }
 
 int scan_exclusive_i64(p3t_ctx *ctx, const int64_t *in, int64_t *out, int64_t n, int64_t *total) {
-    return scan_any<int64_t>(ctx, in, out, n, total);
+    return scan_any<int64_t>(ctx, ctx->stream, ctx->scan_tmp, in, out, n, total);
 }
 
 int scan_exclusive_i32(p3t_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, int32_t *total) {
-    return scan_any<int32_t>(ctx, in, out, n, total);
+    return scan_any<int32_t>(ctx, ctx->stream, ctx->scan_tmp, in, out, n, total);
+}
+
+int scan_exclusive_i64_on(p3t_ctx *ctx, hipStream_t st, DevBuf &tmp, const int64_t *in,
+                          int64_t *out, int64_t n, int64_t *total) {
+    return scan_any<int64_t>(ctx, st, tmp, in, out, n, total);
 }
 
 }  // namespace p3t

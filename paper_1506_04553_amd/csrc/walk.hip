@@ -379,6 +379,13 @@ static int run_walk_stats(p3t_ctx *ctx, const int32_t *G_dev, int64_t stride, Wa
     return check_hip(ctx, hipStreamSynchronize(ctx->stream), "sync");
 }
 
+// the lists and their launch order are complete at this point of the
+// context's stream: work on other streams that reads them waits for ev_lists
+static int lists_done(p3t_ctx *ctx, int rc) {
+    if (rc) return rc;
+    return check_hip(ctx, hipEventRecord(ctx->ev_lists, ctx->stream), "event record");
+}
+
 int build_lists(p3t_ctx *ctx, bool stats_cleared) {
     static_assert(kRbWalk * 8 + sizeof(WalkStats) <= 40 * 8, "walk readback overlaps other slots");
     int rc;
@@ -461,7 +468,7 @@ int build_lists(p3t_ctx *ctx, bool stats_cleared) {
             if (hs->stack_ovf) return stack_error();
             if (!hs->cap_ovf) {
                 finish(true);
-                return build_order(ctx, stride);
+                return lists_done(ctx, build_order(ctx, stride));
             }
         }
     }
@@ -491,7 +498,7 @@ int build_lists(p3t_ctx *ctx, bool stats_cleared) {
                                                   ptr<NodeWalk>(ctx->node_walk), wp, wo, gstack,
                                                   lds_cap);
     if ((rc = check_hip(ctx, hipGetLastError(), "walk emit"))) return rc;
-    return build_order(ctx, stride);
+    return lists_done(ctx, build_order(ctx, stride));
 }
 
 }  // namespace p3t

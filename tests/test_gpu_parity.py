@@ -325,6 +325,43 @@ def test_groups_generic_path(monkeypatch):
     gen.close()
 
 
+def test_neighbors_beside_force():
+    """The neighbour search runs on the context's second stream while the
+    interaction kernel is still running on its first: neighbours called right
+    after the force launch (no synchronisation in between), on a fresh context
+    (whose first search allocates its workspaces) and on rebuilds, must match
+    the oracle's lists, and the forces those of a serial run, bit for bit."""
+    import torch
+    from paper_1506_04553_amd import P3T
+    w = WORKLOADS["plummer64k_salpeter"]
+    c = make_cluster(w, seed=9)
+    dev = torch.device("cuda", 0)
+    tp = torch.from_numpy(c.pos).to(dev)
+    tm = torch.from_numpy(c.mass).to(dev)
+    for prec in ("fp64", "mixed"):
+        p = _params(w, precision=prec)
+        if prec == "fp64":
+            t = oracle.Tree(c.pos, c.mass, p)
+        serial = P3T(0)
+        ref = gpu_run(serial, c.pos, c.mass, p, want_arrays=False)
+        serial.close()
+        compare_neighbors(ref, t)
+        ctx = P3T(0)
+        for rep in range(3):
+            log(f"neighbours beside the force: {prec} rep {rep}")
+            ctx.build_tree(tp, tm, **p)
+            acc, pot = ctx.long_force()
+            off, idx = ctx.neighbors()
+            # work queued on the caller's stream after the call sees the rows
+            total = int(off[-1].item())
+            g = {"nbr_off": off.cpu().numpy(), "nbr_idx": idx.cpu().numpy().astype(np.int64)}
+            assert total == len(g["nbr_idx"])
+            compare_neighbors(g, t)
+            assert np.array_equal(acc.cpu().numpy(), ref["acc"])
+            assert np.array_equal(pot.cpu().numpy(), ref["pot"])
+        ctx.close()
+
+
 def test_forward_is_deterministic(ctx):
     w = WORKLOADS["plummer64k_salpeter"]
     c = make_cluster(w, seed=2)
