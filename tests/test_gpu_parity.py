@@ -425,6 +425,31 @@ def test_fixed_stride_overflow_falls_back(ctx):
     assert np.array_equal(a["acc"], b["acc"]) and np.array_equal(a["pot"], b["pot"])
 
 
+def test_more_groups_than_reserved(ctx):
+    """A build with many more groups than the last one reserved room for: the
+    walk into fixed-stride segments flags the groups past the room and the
+    build walks again in two passes; lists, forces and neighbours equal those
+    of a fresh context."""
+    from paper_1506_04553_amd import P3T
+    w = WORKLOADS["plummer64k_salpeter"]
+    c = make_cluster(w, seed=6)
+    small = plummer(8192, 7)
+    for prec in ("fp64", "mixed"):
+        p = _params(w, precision=prec)
+        used = P3T(0)
+        gpu_run(used, small.pos, small.mass, p, want_arrays=False)
+        log(f"more groups than reserved: {prec}")
+        b = gpu_run(used, c.pos, c.mass, p)
+        used.close()
+        assert b["stats"]["walk_fixed_stride"] == 0
+        fresh = P3T(0)
+        a = gpu_run(fresh, c.pos, c.mass, p)
+        fresh.close()
+        _same_lists(a, b)
+        assert np.array_equal(a["acc"], b["acc"]) and np.array_equal(a["pot"], b["pot"])
+        assert np.array_equal(a["nbr_idx"], b["nbr_idx"])
+
+
 def test_reused_context_matches_fresh_context(ctx):
     """Workspaces left by a larger problem must not leak into a smaller one: a
     context that has just built a bigger tree gives the same lists (as per-group
