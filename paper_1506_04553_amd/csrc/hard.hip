@@ -1253,7 +1253,7 @@ int validate_csr(p3t_ctx *ctx, int64_t n, const int64_t *off, const int32_t *idx
 
 // kAux streams (default priority) and kAux + 1 events for the concurrent
 // classes, made on first use
-static int aux_streams(p3t_ctx *ctx) {
+int aux_streams(p3t_ctx *ctx) {
     if (ctx->aux_ready) return P3T_OK;
     int rc;
     for (int k = 0; k < kAux; ++k)

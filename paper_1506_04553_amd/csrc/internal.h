@@ -120,13 +120,14 @@ struct p3t_ctx {
     p3t::DevBuf seg_end, gorder, grank, ghist;
     p3t::DevBuf hard_ix, hard_state;   // hard part: components and integrator state
     p3t::DevBuf hard_giant;            // ... and the step bookkeeping of the largest components
-    hipStream_t aux[4] = {nullptr, nullptr, nullptr, nullptr};   // hard part's concurrent classes
+    // the hard part's concurrent classes (aux_streams); the neighbour search
+    // runs on aux[0] too, never at the same time (each host-synchronised)
+    hipStream_t aux[4] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t aev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     int aux_ready = 0;
-    // The neighbour search runs on its own stream from the point where the
-    // lists are complete (ev_lists, recorded on `stream` by every walk), beside
-    // whatever the context's stream does meanwhile; ev_sync orders the two.
-    hipStream_t nbr_stream = nullptr;
+    // The neighbour search runs on aux[0] from the point where the lists are
+    // complete (ev_lists, recorded on `stream` by every walk), beside whatever
+    // the context's stream does meanwhile; ev_sync orders the two.
     hipEvent_t ev_lists = nullptr, ev_sync[2] = {nullptr, nullptr};
     p3t::DevBuf step_off, step_idx;    // neighbour CSR of p3t_step
     p3t::DevBuf step_off2, step_idx2;  // ... merged with the special particles' pairs
@@ -185,9 +186,14 @@ int build_lists(p3t_ctx *ctx, bool stats_cleared);
 // Interactions (force.hip).
 int launch_force(p3t_ctx *ctx, double *acc, double *pot);
 
+// The hard part's auxiliary streams and their events, made on first use
+// (hard.hip); each takes a hardware queue of its own beside the context's
+// stream, so the context makes no other streams.
+int aux_streams(p3t_ctx *ctx);
+
 // Neighbour lists (neighbors.hip).  The search and the row count run on
-// ctx->nbr_stream, between the timing events t0 and t1 (either may be null);
-// the caller's arrays are written on ctx->stream after them.
+// ctx->aux[0], between the timing events t0 and t1 (either may be null); the
+// caller's arrays are written on ctx->stream after them.
 int launch_neighbors(p3t_ctx *ctx, int64_t *offsets, int32_t *idx, int64_t cap, int64_t *nnz,
                      hipEvent_t t0, hipEvent_t t1);
 

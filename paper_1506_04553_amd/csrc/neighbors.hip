@@ -182,17 +182,19 @@ __global__ void k_sort_rows(int64_t n, const int64_t *__restrict__ off, int64_t 
 // readback slots (int64 units) used here: neighbour total, overflow flag, longest row
 enum { RB_NNZ = 40, RB_NOVF = 41, RB_NMAX = 42 };
 
-// The search, the scan of the row lengths and their readback run on the
-// context's second stream as soon as the walk's lists are complete, beside the
-// interaction kernel or whatever else the context's stream runs meanwhile: it
-// only reads the tree and the lists and writes workspaces of its own.  The
-// host waits for that stream alone; the rows are then packed into the
-// caller's arrays on the context's stream, after the search.
+// The search, the scan of the row lengths and their readback run on a second
+// stream (the hard part's first auxiliary stream, idle outside its calls) as
+// soon as the walk's lists are complete, beside the interaction kernel or
+// whatever else the context's stream runs meanwhile: it only reads the tree
+// and the lists and writes workspaces of its own.  The host waits for that
+// stream alone; the rows are then packed into the caller's arrays on the
+// context's stream, after the search.
 int launch_neighbors(p3t_ctx *ctx, int64_t *offsets, int32_t *idx, int64_t cap, int64_t *nnz,
                      hipEvent_t t0, hipEvent_t t1) {
     int rc;
     const int64_t n = ctx->n;
-    hipStream_t st = ctx->stream, as = ctx->nbr_stream;
+    if ((rc = aux_streams(ctx))) return rc;
+    hipStream_t st = ctx->stream, as = ctx->aux[0];
     const unsigned grid = (unsigned)ctx->n_groups;
     if (grid == 0) return set_error(ctx, P3T_ESTATE, "no groups");
     const int32_t row_cap = ctx->nbr_cap > 0 ? ctx->nbr_cap : kNbrFirstCap;

@@ -181,7 +181,6 @@ extern "C" int p3t_create(p3t_ctx **out, int device, void *hip_stream, p3t_alloc
     // read by the host after the stream's synchronisation
     hipError_t e = hipHostMalloc((void **)&ctx->hpin, 64 * sizeof(int64_t), hipHostMallocCoherent);
     for (int k = 0; k < 12 && e == hipSuccess; ++k) e = hipEventCreate(&ctx->ev[k]);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->nbr_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_lists, hipEventDisableTiming);
     for (int k = 0; k < 2 && e == hipSuccess; ++k)
         e = hipEventCreateWithFlags(&ctx->ev_sync[k], hipEventDisableTiming);
@@ -198,7 +197,6 @@ extern "C" void p3t_destroy(p3t_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
-    if (ctx->nbr_stream) (void)hipStreamSynchronize(ctx->nbr_stream);
     DevBuf *bufs[] = {&ctx->root, &ctx->keys[0], &ctx->keys[1], &ctx->vals[0], &ctx->vals[1],
                       &ctx->hist, &ctx->histc, &ctx->rs_tot, &ctx->xm, &ctx->xm_in, &ctx->lvlrange,
                       &ctx->tblk, &ctx->tblk_off, &ctx->gtile, &ctx->node_level, &ctx->node_first,
@@ -221,7 +219,6 @@ extern "C" void p3t_destroy(p3t_ctx *ctx) {
         }
     for (int k = 0; k < 5; ++k)
         if (ctx->aev[k]) (void)hipEventDestroy(ctx->aev[k]);
-    if (ctx->nbr_stream) (void)hipStreamDestroy(ctx->nbr_stream);
     if (ctx->ev_lists) (void)hipEventDestroy(ctx->ev_lists);
     for (int k = 0; k < 2; ++k)
         if (ctx->ev_sync[k]) (void)hipEventDestroy(ctx->ev_sync[k]);
