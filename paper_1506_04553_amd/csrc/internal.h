@@ -167,8 +167,6 @@ constexpr int kRbTopoBad = kLevels + 1;
 // group selection before every walk of a build).
 constexpr int kRbWalk = 24;
 constexpr int kRbWalkWords = 13;
-// The root-cube kernel's block counter (zero between builds).
-constexpr int kRbBboxDone = kRbWalk + kRbWalkWords;
 
 // Tree build stages (tree.hip).
 // root cube, Morton keys, stable sort (keys[0] / vals[0]) and the sorted

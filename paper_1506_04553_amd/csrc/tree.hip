@@ -34,17 +34,15 @@ constexpr int kRedThreads = 256;
 // per block: lo xyz, hi xyz, and 1 if some input of the block is invalid
 constexpr int kBboxRec = 7;
 constexpr int kBboxUnroll = 4;
-// few blocks: each ends with an agent-scope release, which is costly
+// at most one record per thread of a keys block, which reduces them all
 constexpr int kBboxMaxBlocks = 256;
 
-// Root cube and input check in one launch: every block reduces its share of
-// the particles to a record (lo xyz, hi xyz, invalid-input flag); the last
-// block to finish (agent-scope acquire-release counter, reset by that block)
-// reduces the records to the root cube, root->bad_input and *bad_rb.
+// Bounding box and input check: every block reduces its share of the
+// particles to a record (lo xyz, hi xyz, invalid-input flag).  The keys
+// kernel reduces the records to the root cube (root_cube below).
 __global__ __launch_bounds__(kRedThreads) void k_bbox(const double *__restrict__ pos,
                                                       const double *__restrict__ mass, int64_t n,
-                                                      double *partial, RootInfo *root,
-                                                      int64_t *bad_rb, unsigned int *done) {
+                                                      double *__restrict__ partial) {
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     int flag = 0;
     // kBboxUnroll particles per thread and round, loaded together
@@ -99,67 +97,6 @@ __global__ __launch_bounds__(kRedThreads) void k_bbox(const double *__restrict__
         for (int a = 0; a < 6; ++a) partial[kBboxRec * blockIdx.x + a] = s[0][a];
         partial[kBboxRec * blockIdx.x + 6] = sf[0] ? 1.0 : 0.0;
     }
-    __shared__ bool s_last;
-    if (threadIdx.x == 0) {
-        const unsigned int prev =
-            __hip_atomic_fetch_add(done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = prev == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // every block's record is visible
-    const int nb = (int)gridDim.x;
-    for (int a = 0; a < 3; ++a) {
-        lo[a] = INFINITY;
-        hi[a] = -INFINITY;
-    }
-    double bad = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = fmin(lo[a], partial[kBboxRec * b + a]);
-            hi[a] = fmax(hi[a], partial[kBboxRec * b + 3 + a]);
-        }
-        bad = fmax(bad, partial[kBboxRec * b + 6]);
-    }
-#pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) {
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = fmin(lo[a], __shfl_xor(lo[a], d, kWave));
-            hi[a] = fmax(hi[a], __shfl_xor(hi[a], d, kWave));
-        }
-        bad = fmax(bad, __shfl_xor(bad, d, kWave));
-    }
-    __shared__ double s7[kRedThreads / kWave][7];
-    if (threadIdx.x % kWave == 0) {
-        for (int a = 0; a < 3; ++a) { s7[w][a] = lo[a]; s7[w][3 + a] = hi[a]; }
-        s7[w][6] = bad;
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    *done = 0;   // for the next build
-    for (int k = 1; k < kRedThreads / kWave; ++k) {
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = fmin(lo[a], s7[k][a]);
-            hi[a] = fmax(hi[a], s7[k][3 + a]);
-        }
-        bad = fmax(bad, s7[k][6]);
-    }
-    double ext = 0.0;
-    for (int a = 0; a < 3; ++a) {
-        double e = hi[a] - lo[a];
-        if (e > ext) ext = e;
-    }
-    double L = 1.0;
-    if (ext > 0.0) {
-        int e;
-        double f = frexp(ext, &e);
-        L = (f == 0.5) ? ldexp(1.0, e - 1) : ldexp(1.0, e);
-    }
-    for (int a = 0; a < 3; ++a) root->lo[a] = lo[a];
-    root->L = L;
-    root->scale = ldexp(1.0, kMaxLevel) / L;
-    root->bad_input = bad != 0.0 ? 1 : 0;
-    *bad_rb = bad != 0.0 ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -217,18 +154,79 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t *__restri
 // the tile's histogram of the first radix digit (the keys' low bits), and each
 // particle's position and mass packed in one 32-byte record (xm_in, input
 // order) for the sort's final gather
+// The root cube from the bounding box's nbb (<= kRsThreads) block records, by
+// every thread of the block alike (min and max are exact in any order): the
+// smallest power-of-two side that holds the box, from its low corner.  Block
+// 0 stores it, and the input check, for the kernels that follow.
+struct RootCube {
+    double lo[3], L, scale;
+    int bad;
+};
+
+__device__ __forceinline__ RootCube root_cube(const double *__restrict__ partial, int nbb,
+                                              RootInfo *__restrict__ root,
+                                              int64_t *__restrict__ bad_rb) {
+    static_assert(kBboxMaxBlocks <= kRsThreads, "a record per thread");
+    __shared__ double s7[kRsThreads / kWave][kBboxRec];
+    double v[kBboxRec] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0};
+    if ((int)threadIdx.x < nbb)
+        for (int a = 0; a < kBboxRec; ++a) v[a] = partial[kBboxRec * threadIdx.x + a];
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        for (int a = 0; a < 3; ++a) {
+            v[a] = fmin(v[a], __shfl_xor(v[a], d, kWave));
+            v[3 + a] = fmax(v[3 + a], __shfl_xor(v[3 + a], d, kWave));
+        }
+        v[6] = fmax(v[6], __shfl_xor(v[6], d, kWave));
+    }
+    const int w = threadIdx.x / kWave;
+    if (threadIdx.x % kWave == 0)
+        for (int a = 0; a < kBboxRec; ++a) s7[w][a] = v[a];
+    __syncthreads();
+    for (int k = 0; k < kRsThreads / kWave; ++k) {
+        for (int a = 0; a < 3; ++a) {
+            v[a] = fmin(v[a], s7[k][a]);
+            v[3 + a] = fmax(v[3 + a], s7[k][3 + a]);
+        }
+        v[6] = fmax(v[6], s7[k][6]);
+    }
+    RootCube c;
+    double ext = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        c.lo[a] = v[a];
+        const double e = v[3 + a] - v[a];
+        if (e > ext) ext = e;
+    }
+    c.L = 1.0;
+    if (ext > 0.0) {
+        int e;
+        const double f = frexp(ext, &e);
+        c.L = (f == 0.5) ? ldexp(1.0, e - 1) : ldexp(1.0, e);
+    }
+    c.scale = ldexp(1.0, kMaxLevel) / c.L;
+    c.bad = v[6] != 0.0 ? 1 : 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int a = 0; a < 3; ++a) root->lo[a] = c.lo[a];
+        root->L = c.L;
+        root->scale = c.scale;
+        root->bad_input = c.bad;
+        *bad_rb = c.bad;
+    }
+    return c;
+}
+
 __global__ __launch_bounds__(kRsThreads) void k_keys_hist(const double *__restrict__ pos,
                                                           const double *__restrict__ mass, int64_t n,
-                                                          const RootInfo *__restrict__ root,
+                                                          const double *__restrict__ partial,
+                                                          int nbb, RootInfo *__restrict__ root,
+                                                          int64_t *__restrict__ bad_rb,
                                                           uint64_t *__restrict__ keys,
                                                           int32_t *__restrict__ idx,
                                                           PosMass *__restrict__ xm_in,
                                                           int32_t *__restrict__ counts, int nb) {
     __shared__ int32_t h[kRsBins];
     for (int d = threadIdx.x; d < kRsBins; d += kRsThreads) h[d] = 0;
-    __syncthreads();
-    const double scale = root->scale;
-    const double lo[3] = {root->lo[0], root->lo[1], root->lo[2]};
+    // the tile's particles are on their way while the root cube is reduced
     const int64_t base = (int64_t)blockIdx.x * kRsTile;
     PosMass r[kRsRounds];
 #pragma unroll
@@ -236,6 +234,9 @@ __global__ __launch_bounds__(kRsThreads) void k_keys_hist(const double *__restri
         const int64_t i = base + k * kRsThreads + threadIdx.x;
         if (i < n) r[k] = PosMass{pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], mass[i]};
     }
+    const RootCube cube = root_cube(partial, nbb, root, bad_rb);   // its barrier also covers h
+    const double scale = cube.scale;
+    const double lo[3] = {cube.lo[0], cube.lo[1], cube.lo[2]};
 #pragma unroll
     for (int k = 0; k < kRsRounds; ++k) {
         const int64_t i = base + k * kRsThreads + threadIdx.x;
@@ -412,15 +413,14 @@ int build_sorted(p3t_ctx *ctx, const double *pos, const double *mass, int64_t n)
     if ((rc = ensure(ctx, ctx->xm_in, n * sizeof(PosMass)))) return rc;
     if ((rc = ensure(ctx, ctx->gflag, (n + 1) * sizeof(int32_t)))) return rc;
     double *partial = ptr<double>(ctx->bbox);
-    int64_t *rb = ptr<int64_t>(ctx->readback);
-    // the input check goes straight to the pinned host words (read after the
-    // topology's synchronisation)
-    k_bbox<<<nbb, kRedThreads, 0, ctx->stream>>>(pos, mass, n, partial, ptr<RootInfo>(ctx->root),
-                                                 ctx->hpin + kRbTopoBad,
-                                                 reinterpret_cast<unsigned int *>(rb + kRbBboxDone));
+    k_bbox<<<nbb, kRedThreads, 0, ctx->stream>>>(pos, mass, n, partial);
     int32_t *cnt = ptr<int32_t>(ctx->histc), *off = ptr<int32_t>(ctx->hist);
     int32_t *tot = ptr<int32_t>(ctx->rs_tot);
-    k_keys_hist<<<nb, kRsThreads, 0, ctx->stream>>>(pos, mass, n, ptr<RootInfo>(ctx->root),
+    // the input check goes straight to the pinned host words (read after the
+    // topology's synchronisation)
+    k_keys_hist<<<nb, kRsThreads, 0, ctx->stream>>>(pos, mass, n, partial, nbb,
+                                                     ptr<RootInfo>(ctx->root),
+                                                     ctx->hpin + kRbTopoBad,
                                                      ptr<uint64_t>(ctx->keys[0]),
                                                      ptr<int32_t>(ctx->vals[0]),
                                                      ptr<PosMass>(ctx->xm_in), cnt, nb);
