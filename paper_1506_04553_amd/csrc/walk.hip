@@ -59,6 +59,18 @@ struct WalkOut {
     int64_t stride;
 };
 
+// the c consecutive indices first .. first + c - 1 at d, four to a store (the
+// stores need only 4-byte alignment)
+typedef int32_t int4u __attribute__((ext_vector_type(4), aligned(4)));
+__device__ __forceinline__ void write_range(int32_t *d, int32_t first, int c) {
+    int t = 0;
+    for (; t + 4 <= c; t += 4) {
+        const int32_t f = first + t;
+        *reinterpret_cast<int4u *>(d + t) = int4u{f, f + 1, f + 2, f + 3};
+    }
+    for (; t < c; ++t) d[t] = first + t;
+}
+
 __device__ __forceinline__ double gap(double u, double v) {
     const double w = u > 0.0 ? u : 0.0;
     return v > w ? v : w;
@@ -144,15 +156,12 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(const GroupInfo *__restri
                     const int c = mine ? count : 0;
                     int tot;
                     const int excl = wave_excl_count(c, tot);
-                    if (MODE == kEmit && mine) {
-                        int32_t *d = dst[kk] + run[kk] + excl;
-                        for (int t = 0; t < c; ++t) d[t] = first + t;
-                    }
+                    if (MODE == kEmit && mine) write_range(dst[kk] + run[kk] + excl, first, c);
                     if (MODE == kFixed && mine) {
                         const int64_t pos = run[kk] + excl;
                         const int64_t lim = wo.cap[kk] - pos;
                         const int cc = lim < c ? (lim > 0 ? (int)lim : 0) : c;
-                        for (int t = 0; t < cc; ++t) dst[kk][pos + t] = first + t;
+                        write_range(dst[kk] + pos, first, cc);
                     }
                     run[kk] += tot;
                 }
