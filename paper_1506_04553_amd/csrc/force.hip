@@ -293,9 +293,13 @@ __device__ __forceinline__ void cell_tile(Slot<R> *q, const CJ<R> *sc, int iters
     }
 }
 
+// Occupancy: FP32, five wavefronts per SIMD (96 VGPRs; the hot loops keep
+// their registers, a few values of the near path and of the tile loop go to
+// scratch), which hides more latency than four of 118 VGPRs; FP64, four (128
+// VGPRs).
 template <class R, bool QUAD, bool CHECK_K>
 __global__ __launch_bounds__(kForceThreads)
-__attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 4 : 1))) void k_force(
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 4 : 5))) void k_force(
     const GroupInfo *__restrict__ grp, ListsDev L, const PosMass *__restrict__ xm,
     const NodeMP *__restrict__ mp, const int32_t *__restrict__ perm, ForceParams fp,
     double *__restrict__ acc, double *__restrict__ pot) {
